@@ -1,0 +1,255 @@
+/*
+ * l0cim.h -- C ABI of the MI355X (gfx950) MF-CIM solver for L0-regularised
+ * compressed sensing (L0RBCS).
+ *
+ * The method (Gunathilaka et al., "L0-regularized compressed sensing with
+ * Mean-field Coherent Ising Machines", arXiv:2405.00366) alternates two
+ * minimisations of the L0RBCS objective (eq. 3):
+ *   - sigma in {0,1}^N, by integrating the mean-field CIM with chaotic
+ *     amplitude control (MFZ-CIM, eq. 12-16) on the Ising form of the
+ *     objective (eq. 4), with couplings J = -(A^T A) o R R^T (zero diagonal)
+ *     and Zeeman term z = R o A^T y;
+ *   - R in R^N, by a classical digital processor (CDP): Jacobi relaxation
+ *     (Numerical experiments, parameter paragraph) or an FP64 least-squares
+ *     refit on the support;
+ * with the pump (eq. 21) and threshold (eq. 22) schedules of Algorithm 1.
+ *
+ * Conventions for every entry point
+ *   - Array pointers are DEVICE memory owned by the caller unless stated
+ *     otherwise; parameter structs are HOST memory, read during the call only.
+ *   - Matrices are row-major with an explicit leading dimension (in elements).
+ *   - `dtype` selects the arithmetic of the call: L0CIM_F32 or L0CIM_F64.
+ *     Every floating-point array of the call except J and row_scale has that
+ *     type (float* or double* passed as void*).
+ *   - Every call enqueues work on `stream` (a hipStream_t passed as void*,
+ *     NULL = the null stream) and returns without synchronising.  Outputs are
+ *     valid once the caller has synchronised the stream.
+ *   - No call allocates or frees device memory.  Scratch comes from the
+ *     caller's workspace `ws` of `ws_bytes` bytes (256-byte aligned); the
+ *     matching *_workspace_bytes() function returns the exact size needed.
+ *     A workspace may be reused by consecutive calls on one stream; calls that
+ *     overlap in time must use different workspaces.
+ *   - Errors the host can detect (NULL pointer, bad size or leading
+ *     dimension, unsupported dtype, workspace too small) return before
+ *     anything is enqueued and leave every output untouched.  Launch errors
+ *     return L0CIM_ERR_HIP.  l0cim_last_error() gives a thread-local message.
+ *   - Numerical failures are found on the device and reported through a
+ *     device-resident status word (bits L0CIM_ST_*), OR-ed in by the kernels.
+ */
+#ifndef L0CIM_H
+#define L0CIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define L0CIM_VERSION 100
+
+typedef enum {
+  L0CIM_OK = 0,
+  L0CIM_ERR_ARG = 1,          /* NULL pointer or out-of-range scalar */
+  L0CIM_ERR_SHAPE = 2,        /* bad size or leading dimension */
+  L0CIM_ERR_WORKSPACE = 3,    /* ws NULL or ws_bytes too small */
+  L0CIM_ERR_HIP = 4,          /* a HIP runtime call failed */
+  L0CIM_ERR_UNSUPPORTED = 5   /* dtype / field / method combination not built */
+} l0cim_status;
+
+typedef enum {
+  L0CIM_F32 = 0,
+  L0CIM_F64 = 1,
+  L0CIM_BF16 = 2,             /* coupling storage only */
+  L0CIM_FP8E4M3 = 3           /* coupling storage only (OCP e4m3, max 448) */
+} l0cim_dtype;
+
+typedef enum {
+  L0CIM_FIELD_CN = 0,         /* continuous local field, eq. 15 */
+  L0CIM_FIELD_BN = 1          /* binarised local field,  eq. 16 */
+} l0cim_field;
+
+typedef enum {
+  L0CIM_LAUNCH_AUTO = 0,
+  L0CIM_LAUNCH_RESIDENT = 1,
+  L0CIM_LAUNCH_STREAMED = 2
+} l0cim_launch;
+
+typedef enum {
+  L0CIM_CDP_JACOBI = 0,       /* damped Jacobi sweeps over all r */
+  L0CIM_CDP_CHOL_F64 = 1      /* FP64 Cholesky least squares on the support */
+} l0cim_cdp;
+
+/* Device status bits. */
+#define L0CIM_ST_NONFINITE  0x01  /* an amplitude or error variable is not finite */
+#define L0CIM_ST_BLOWUP     0x02  /* |c| > 1e3 at the end of a run */
+#define L0CIM_ST_CHOL_RIDGE 0x04  /* Cholesky pivot <= 1e-12 max diag: ridge added */
+#define L0CIM_ST_TINY_DIAG  0x08  /* some G_rr < 1e-12: that R_r held at 0 */
+#define L0CIM_ST_TIMEOUT    0x10  /* a bounded device wait gave up (run aborted) */
+
+/* MFZ-CIM dynamics: eq. 12-16 and the pump schedule eq. 21. */
+typedef struct {
+  double dt;          /* Euler increment (0.02) */
+  int32_t n_steps;    /* Euler steps per CIM run (1000 = 20 photon lifetimes) */
+  int32_t field;      /* l0cim_field */
+  double p_thr;       /* pump threshold (1) */
+  double d;           /* pump swing (0.4 random data, 0.6 MRI) */
+  double t_c, t_w;    /* sigmoid centre and width (4, 2) */
+  double K;           /* feedback strength (1 random data, 0.1 MRI) */
+  double j;           /* out-coupling rate (no value printed; default 0.2) */
+  double beta;        /* CAC rate (no value printed; default 0.3) */
+  double tau;         /* CAC target amplitude (1) */
+  double c0_std;      /* std of the initial amplitudes (1e-2: variance 1e-4) */
+  int32_t linear_j;   /* 1: linear term (-1 + p - j - c^2) (supporting info) */
+  int32_t launch;     /* 0: automatic; 1: resident (one persistent launch, J in LDS,
+                         error if it does not fit); 2: streamed (one launch per step) */
+  int64_t spin_limit; /* bound on polls of one device wait; 0 = default (2^22) */
+} l0cim_cim_params;
+
+/* Alternating minimisation (Algorithm 1), threshold schedule eq. 22, CDP. */
+typedef struct {
+  double eta_init, eta_end;  /* eta_i = max(eta_init (1 - i/velo), eta_end) */
+  int32_t velo;              /* schedule length (51 random data, 11 MRI) */
+  int32_t n_outer;           /* number of alternations performed */
+  int32_t cdp;               /* l0cim_cdp used inside the loop (JACOBI) */
+  int32_t cdp_iters;         /* Jacobi sweeps per alternation (100) */
+  double dtc;                /* Jacobi time increment (0.1) */
+  int32_t final_refit_f64;   /* 1: FP64 Cholesky refit of R on the final support */
+  int32_t replicas;          /* P >= 1 independent CIM trajectories */
+  uint64_t seed;             /* key of the initial-amplitude generator */
+  int32_t j_dtype;           /* coupling storage: F32 | F64 | BF16 | FP8E4M3 */
+  int32_t reserved0;
+} l0cim_solve_params;
+
+/* Per-solve report, written by the device into caller memory. */
+typedef struct {
+  int32_t status_bits;       /* OR of L0CIM_ST_* over the whole solve */
+  int32_t selected_replica;  /* replica kept in the last alternation */
+  int32_t support_size;      /* |sigma| returned */
+  int32_t n_outer_done;
+  double H;                  /* eq. 4 energy of the returned sigma (at the R of the last run) */
+  double E;                  /* eq. 3 objective of (sigma, R_out) at the last lambda */
+  int64_t spin_steps;        /* N * P * n_steps * n_outer */
+} l0cim_stats;
+
+int l0cim_version(void);
+const char* l0cim_status_string(l0cim_status s);
+const char* l0cim_last_error(void);
+
+/* Paper defaults for random data (Numerical experiments, parameter paragraph). */
+void l0cim_cim_params_default(l0cim_cim_params* p);
+void l0cim_solve_params_default(l0cim_solve_params* p);
+
+/*
+ * l0cim_gram -- G = A^T A (n x n, leading dim ldg) and b = A^T y (n).
+ * The couplings and Zeeman term of the Ising form are minus G and
+ * sqrt(tau) b (stated after eq. 11 and after eq. 15).
+ * A: m x n (lda >= n), y: m.  G is exactly symmetric.
+ */
+l0cim_status l0cim_gram(l0cim_dtype dtype, int32_t m, int32_t n, const void* A, int64_t lda,
+                        const void* y, void* G, int64_t ldg, void* b, void* stream);
+
+/*
+ * l0cim_build_couplings -- J_rr' = -G_rr' R_r R_r' (r != r'), J_rr = 0, and
+ * z_r = R_r b_r: the R-scaled couplings with which R_r h_r of eq. 15 is
+ * (J (c + sqrt(tau))/4)_r + (sqrt(tau)/2) z_r and R_r h^BN_r of eq. 16 is
+ * (sqrt(tau)/2)((J sigma)_r + z_r).
+ * J is written in j_dtype with leading dim ldj (>= n):
+ *   F32 (dtype F32) / F64 (dtype F64): exact elementwise product;
+ *   BF16 / FP8E4M3 (dtype F32): row_scale[r] = max_r' |J_rr'| / Q_max
+ *   (Q_max = 448 for FP8, 1 for BF16; 1 where the row is all zero) and the
+ *   stored value is RNE(J_rr' / row_scale[r]) (FP8 saturating).
+ * row_scale (float, n) is required for BF16/FP8 and ignored otherwise.
+ */
+l0cim_status l0cim_build_couplings(l0cim_dtype dtype, int32_t n, const void* G, int64_t ldg,
+                                   const void* b, const void* R, l0cim_dtype j_dtype, void* J,
+                                   int64_t ldj, float* row_scale, void* z, void* stream);
+
+/*
+ * l0cim_init_state -- initial CIM state for alternation `alt`:
+ * c[q][r] = c0_std * N(0,1) and e[q][r] = 1 (the vacuum-noise start stated
+ * after eq. 16 and in Algorithm 1).  The normal draw is counter-based:
+ * SplitMix64 outputs 2k+1 and 2k+2 of the stream keyed by `seed`, with
+ * k = (alt << 40) | (q << 24) | r, as two 53-bit uniforms u1, u2 and
+ * Box-Muller sqrt(-2 ln(1-u1)) cos(2 pi u2).  c, e: P x n, row stride n.
+ */
+l0cim_status l0cim_init_state(l0cim_dtype dtype, int32_t n, int32_t P, uint64_t seed, int32_t alt,
+                              double c0_std, void* c, void* e, void* stream);
+
+/*
+ * l0cim_mfcim_run -- integrate the MFZ-CIM (eq. 12-14 with the field of
+ * eq. 15 or 16 and the pump of eq. 21) for prm->n_steps forward-Euler steps
+ * of P independent replicas, all sharing J and z:
+ *   p_k  = (p_thr - d) + 2d / (1 + exp(-(k dt - t_c)/t_w))
+ *   phi  = R h  (CN: J (c + sqrt tau)/4 + (sqrt tau/2) z;  BN: (sqrt tau/2)(J H(c) + z))
+ *   c'   = c + dt [ (-1 + p_k - c^2) c + K j e (phi - eta^2 sqrt(tau)/4) ]
+ *   e'   = e + dt [ -beta (c^2 - tau) e ]
+ * c, e (P x n, row stride n) hold the initial state on entry and the final
+ * state on exit.  sigma (P x n, uint8) receives H(c) = [c > 0] at the end.
+ * H (P doubles, may be NULL) receives the eq. 4 energy of each sigma_q:
+ * -1/2 s^T J s - z^T s + lambda 1^T s with lambda = eta^2/2.
+ * trace (may be NULL): for k < trace_steps, trace[((k*2 + v)*P + q)*n + r] is
+ * variable v (0: c, 1: e) of replica q after k+1 steps.
+ * J: n x n in j_dtype (F32 or F64 matching dtype; BF16 / FP8 with row_scale,
+ * dtype F32).  status (int32, may be NULL) is OR-ed with L0CIM_ST_* bits.
+ */
+size_t l0cim_mfcim_run_workspace_bytes(l0cim_dtype dtype, int32_t n, int32_t P, l0cim_dtype j_dtype);
+l0cim_status l0cim_mfcim_run(l0cim_dtype dtype, int32_t n, int32_t P, l0cim_dtype j_dtype,
+                             const void* J, int64_t ldj, const float* row_scale, const void* z,
+                             double eta, const l0cim_cim_params* prm, void* c, void* e,
+                             uint8_t* sigma, double* H, void* trace, int32_t trace_steps,
+                             int32_t* status, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * l0cim_select_replica -- q* = argmin_q H[q] (lowest q on ties, NaN never
+ * chosen unless all are NaN) and sigma_out = sigma[q*] (n bytes).
+ * q_out (int32, may be NULL) receives q*.
+ */
+l0cim_status l0cim_select_replica(int32_t n, int32_t P, const double* H, const uint8_t* sigma,
+                                  uint8_t* sigma_out, int32_t* q_out, void* stream);
+
+/*
+ * l0cim_update_r -- the CDP step of Algorithm 1 on support sigma (n bytes).
+ *   L0CIM_CDP_JACOBI: `iters` synchronous sweeps over every r,
+ *     R_r <- R_r + dtc [ (b_r - sum_{r' != r} G_rr' sigma_r' R_r') / G_rr - R_r ];
+ *   L0CIM_CDP_CHOL_F64: R_S = G_SS^-1 b_S through an FP64 Cholesky factor
+ *     (ridge 1e-10 tr(G_SS)/|S| if a pivot is <= 1e-12 max diag, status bit
+ *     CHOL_RIDGE), and R_r = (b_r - G_rS R_S) / G_rr off the support.
+ * In both, r with G_rr < 1e-12 is held at 0 (status bit TINY_DIAG).
+ * R (n) is read as the starting point and overwritten.
+ */
+size_t l0cim_update_r_workspace_bytes(l0cim_dtype dtype, int32_t n, l0cim_cdp cdp);
+l0cim_status l0cim_update_r(l0cim_dtype dtype, int32_t n, const void* G, int64_t ldg, const void* b,
+                            const uint8_t* sigma, l0cim_cdp cdp, double dtc, int32_t iters,
+                            void* R, int32_t* status, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * l0cim_solve -- Algorithm 1 end to end on one instance:
+ *   G, b = gram(A, y);  R = R_init (or b_r / G_rr where R_init is NULL);
+ *   for i < n_outer: eta_i (eq. 22); J, z = couplings(G, b, R);
+ *     init_state(seed, i); mfcim_run; select_replica (lambda_i = eta_i^2/2);
+ *     update_r(JACOBI, dtc, cdp_iters);
+ *   optional FP64 Cholesky refit on the final support.
+ * Outputs R_out (n, dtype), sigma_out (n bytes) and *stats (device memory).
+ * A: m x n (lda >= n), y: m, R_init: n or NULL.
+ */
+size_t l0cim_solve_workspace_bytes(l0cim_dtype dtype, int32_t m, int32_t n,
+                                   const l0cim_cim_params* cim, const l0cim_solve_params* sp);
+l0cim_status l0cim_solve(l0cim_dtype dtype, int32_t m, int32_t n, const void* A, int64_t lda,
+                         const void* y, const void* R_init, const l0cim_cim_params* cim,
+                         const l0cim_solve_params* sp, void* R_out, uint8_t* sigma_out,
+                         l0cim_stats* stats, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Kernel timing for measurement.  Between l0cim_profile_begin() and
+ * l0cim_profile_end(), every launch of the CIM-run kernels made by this
+ * thread is bracketed by HIP events on its own stream.  profile_end waits for
+ * those events and returns the summed kernel time (ms) and launch count.
+ */
+l0cim_status l0cim_profile_begin(void);
+l0cim_status l0cim_profile_end(double* cim_ms, int64_t* cim_launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* L0CIM_H */

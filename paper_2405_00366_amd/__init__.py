@@ -1,0 +1,307 @@
+"""MI355X (gfx950) MF-CIM solver for L0-regularised compressed sensing.
+
+Thin Python binding of ``libl0cim.so`` (C ABI declared in include/l0cim.h).
+Every function has the name of the C entry point it calls and only marshals
+arguments: torch tensors supply device memory and the HIP stream, and all
+computation runs in the library's HIP kernels.  Importing works without a
+GPU; calling anything that launches work requires the built library and a
+visible device, and raises otherwise (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int, c_int32, c_int64, c_size_t, c_uint64, c_void_p
+
+import torch
+
+__all__ = [
+    "F32", "F64", "BF16", "FP8E4M3", "FIELD_CN", "FIELD_BN", "CDP_JACOBI", "CDP_CHOL_F64",
+    "CimParams", "SolveParams", "Stats", "L0cimError", "lib", "library_path",
+    "l0cim_version", "l0cim_gram", "l0cim_build_couplings", "l0cim_init_state",
+    "l0cim_mfcim_run", "l0cim_select_replica", "l0cim_update_r", "l0cim_solve",
+    "l0cim_mfcim_run_workspace_bytes", "l0cim_update_r_workspace_bytes",
+    "l0cim_solve_workspace_bytes", "l0cim_profile_begin", "l0cim_profile_end",
+    "cim_params", "solve_params",
+]
+
+F32, F64, BF16, FP8E4M3 = 0, 1, 2, 3
+FIELD_CN, FIELD_BN = 0, 1
+CDP_JACOBI, CDP_CHOL_F64 = 0, 1
+LAUNCH_AUTO, LAUNCH_RESIDENT, LAUNCH_STREAMED = 0, 1, 2
+
+ST_NONFINITE, ST_BLOWUP, ST_CHOL_RIDGE, ST_TINY_DIAG, ST_TIMEOUT = 1, 2, 4, 8, 16
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libl0cim.so")
+
+
+class CimParams(ctypes.Structure):
+    _fields_ = [
+        ("dt", c_double), ("n_steps", c_int32), ("field", c_int32),
+        ("p_thr", c_double), ("d", c_double), ("t_c", c_double), ("t_w", c_double),
+        ("K", c_double), ("j", c_double), ("beta", c_double), ("tau", c_double),
+        ("c0_std", c_double), ("linear_j", c_int32), ("launch", c_int32),
+        ("spin_limit", c_int64),
+    ]
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [
+        ("eta_init", c_double), ("eta_end", c_double), ("velo", c_int32), ("n_outer", c_int32),
+        ("cdp", c_int32), ("cdp_iters", c_int32), ("dtc", c_double),
+        ("final_refit_f64", c_int32), ("replicas", c_int32), ("seed", c_uint64),
+        ("j_dtype", c_int32), ("reserved0", c_int32),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("status_bits", c_int32), ("selected_replica", c_int32), ("support_size", c_int32),
+        ("n_outer_done", c_int32), ("H", c_double), ("E", c_double), ("spin_steps", c_int64),
+    ]
+
+
+STATS_BYTES = ctypes.sizeof(Stats)
+
+
+class L0cimError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status}: {detail}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (loaded on first use; raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(library_path):
+            raise L0cimError(-1, "load", f"{library_path} is missing: build it with "
+                                         "python paper_2405_00366_amd/build.py")
+        L = ctypes.CDLL(library_path)
+        st = c_int
+        vp = c_void_p
+        L.l0cim_version.restype = c_int
+        L.l0cim_status_string.restype = c_char_p
+        L.l0cim_status_string.argtypes = [c_int]
+        L.l0cim_last_error.restype = c_char_p
+        L.l0cim_cim_params_default.argtypes = [POINTER(CimParams)]
+        L.l0cim_cim_params_default.restype = None
+        L.l0cim_solve_params_default.argtypes = [POINTER(SolveParams)]
+        L.l0cim_solve_params_default.restype = None
+        L.l0cim_gram.argtypes = [c_int, c_int32, c_int32, vp, c_int64, vp, vp, c_int64, vp, vp]
+        L.l0cim_gram.restype = st
+        L.l0cim_build_couplings.argtypes = [c_int, c_int32, vp, c_int64, vp, vp, c_int, vp, c_int64,
+                                            vp, vp, vp]
+        L.l0cim_build_couplings.restype = st
+        L.l0cim_init_state.argtypes = [c_int, c_int32, c_int32, c_uint64, c_int32, c_double, vp, vp, vp]
+        L.l0cim_init_state.restype = st
+        L.l0cim_mfcim_run_workspace_bytes.argtypes = [c_int, c_int32, c_int32, c_int]
+        L.l0cim_mfcim_run_workspace_bytes.restype = c_size_t
+        L.l0cim_mfcim_run.argtypes = [c_int, c_int32, c_int32, c_int, vp, c_int64, vp, vp, c_double,
+                                      POINTER(CimParams), vp, vp, vp, vp, vp, c_int32, vp, vp,
+                                      c_size_t, vp]
+        L.l0cim_mfcim_run.restype = st
+        L.l0cim_select_replica.argtypes = [c_int32, c_int32, vp, vp, vp, vp, vp]
+        L.l0cim_select_replica.restype = st
+        L.l0cim_update_r_workspace_bytes.argtypes = [c_int, c_int32, c_int]
+        L.l0cim_update_r_workspace_bytes.restype = c_size_t
+        L.l0cim_update_r.argtypes = [c_int, c_int32, vp, c_int64, vp, vp, c_int, c_double, c_int32,
+                                     vp, vp, vp, c_size_t, vp]
+        L.l0cim_update_r.restype = st
+        L.l0cim_solve_workspace_bytes.argtypes = [c_int, c_int32, c_int32, POINTER(CimParams),
+                                                  POINTER(SolveParams)]
+        L.l0cim_solve_workspace_bytes.restype = c_size_t
+        L.l0cim_solve.argtypes = [c_int, c_int32, c_int32, vp, c_int64, vp, vp, POINTER(CimParams),
+                                  POINTER(SolveParams), vp, vp, vp, vp, c_size_t, vp]
+        L.l0cim_solve.restype = st
+        L.l0cim_profile_begin.restype = st
+        L.l0cim_profile_end.argtypes = [POINTER(c_double), POINTER(c_int64)]
+        L.l0cim_profile_end.restype = st
+        _lib = L
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        L = lib()
+        raise L0cimError(status, where, L.l0cim_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    return c_void_p(t.data_ptr())
+
+
+def _dtype_code(t) -> int:
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise ValueError(f"unsupported arithmetic dtype {t.dtype}")
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return c_void_p(stream.cuda_stream)
+
+
+def _ld(t) -> int:
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("matrix must be 2-D with unit column stride")
+    return t.stride(0)
+
+
+def _torch_jdtype(code: int):
+    return {F32: torch.float32, F64: torch.float64, BF16: torch.bfloat16,
+            FP8E4M3: torch.float8_e4m3fn}[code]
+
+
+def workspace(nbytes: int, device=None):
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device or "cuda")
+
+
+def cim_params(**kw) -> CimParams:
+    """Paper defaults (random data) with keyword overrides."""
+    p = CimParams()
+    lib().l0cim_cim_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        if k == "field" and isinstance(v, str):
+            v = FIELD_BN if v.upper() == "BN" else FIELD_CN
+        setattr(p, k, v)
+    return p
+
+
+def solve_params(**kw) -> SolveParams:
+    p = SolveParams()
+    lib().l0cim_solve_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+# ---------------------------------------------------------------------------
+# Entry points (same names as the C ABI)
+# ---------------------------------------------------------------------------
+
+def l0cim_version() -> int:
+    return lib().l0cim_version()
+
+
+def l0cim_gram(A, y, G=None, b=None, stream=None):
+    m, n = A.shape
+    dt = _dtype_code(A)
+    G = torch.empty((n, n), dtype=A.dtype, device=A.device) if G is None else G
+    b = torch.empty(n, dtype=A.dtype, device=A.device) if b is None else b
+    _check(lib().l0cim_gram(dt, m, n, _ptr(A), _ld(A), _ptr(y), _ptr(G), _ld(G), _ptr(b),
+                            _stream(stream)), "l0cim_gram")
+    return G, b
+
+
+def l0cim_build_couplings(G, b, R, j_dtype: int = None, J=None, row_scale=None, z=None, stream=None):
+    n = G.shape[0]
+    dt = _dtype_code(G)
+    if j_dtype is None:
+        j_dtype = dt
+    J = torch.empty((n, n), dtype=_torch_jdtype(j_dtype), device=G.device) if J is None else J
+    if j_dtype in (BF16, FP8E4M3) and row_scale is None:
+        row_scale = torch.empty(n, dtype=torch.float32, device=G.device)
+    z = torch.empty(n, dtype=G.dtype, device=G.device) if z is None else z
+    _check(lib().l0cim_build_couplings(dt, n, _ptr(G), _ld(G), _ptr(b), _ptr(R), j_dtype, _ptr(J),
+                                       _ld(J), _ptr(row_scale), _ptr(z), _stream(stream)),
+           "l0cim_build_couplings")
+    return J, row_scale, z
+
+
+def l0cim_init_state(n: int, P: int, seed: int, alt: int, c0_std: float, c, e, stream=None):
+    _check(lib().l0cim_init_state(_dtype_code(c), n, P, seed, alt, c0_std, _ptr(c), _ptr(e),
+                                  _stream(stream)), "l0cim_init_state")
+    return c, e
+
+
+def l0cim_mfcim_run_workspace_bytes(dtype: int, n: int, P: int, j_dtype: int) -> int:
+    return lib().l0cim_mfcim_run_workspace_bytes(dtype, n, P, j_dtype)
+
+
+def l0cim_mfcim_run(J, z, eta: float, prm: CimParams, c, e, sigma=None, H=None, trace=None,
+                    trace_steps: int = 0, row_scale=None, status=None, ws=None, j_dtype: int = None,
+                    stream=None):
+    P, n = c.shape
+    dt = _dtype_code(c)
+    if j_dtype is None:
+        j_dtype = {torch.float32: F32, torch.float64: F64, torch.bfloat16: BF16,
+                   torch.float8_e4m3fn: FP8E4M3}[J.dtype]
+    sigma = torch.empty((P, n), dtype=torch.uint8, device=c.device) if sigma is None else sigma
+    need = l0cim_mfcim_run_workspace_bytes(dt, n, P, j_dtype)
+    ws = workspace(need, c.device) if ws is None else ws
+    _check(lib().l0cim_mfcim_run(dt, n, P, j_dtype, _ptr(J), _ld(J), _ptr(row_scale), _ptr(z), eta,
+                                 ctypes.byref(prm), _ptr(c), _ptr(e), _ptr(sigma), _ptr(H),
+                                 _ptr(trace), trace_steps, _ptr(status), _ptr(ws), ws.numel(),
+                                 _stream(stream)), "l0cim_mfcim_run")
+    return sigma
+
+
+def l0cim_select_replica(H, sigma, sigma_out=None, q_out=None, stream=None):
+    P, n = sigma.shape
+    sigma_out = torch.empty(n, dtype=torch.uint8, device=sigma.device) if sigma_out is None else sigma_out
+    _check(lib().l0cim_select_replica(n, P, _ptr(H), _ptr(sigma), _ptr(sigma_out), _ptr(q_out),
+                                      _stream(stream)), "l0cim_select_replica")
+    return sigma_out
+
+
+def l0cim_update_r_workspace_bytes(dtype: int, n: int, cdp: int) -> int:
+    return lib().l0cim_update_r_workspace_bytes(dtype, n, cdp)
+
+
+def l0cim_update_r(G, b, sigma, R, cdp: int = CDP_JACOBI, dtc: float = 0.1, iters: int = 100,
+                   status=None, ws=None, stream=None):
+    n = G.shape[0]
+    dt = _dtype_code(G)
+    ws = workspace(l0cim_update_r_workspace_bytes(dt, n, cdp), G.device) if ws is None else ws
+    _check(lib().l0cim_update_r(dt, n, _ptr(G), _ld(G), _ptr(b), _ptr(sigma), cdp, dtc, iters, _ptr(R),
+                                _ptr(status), _ptr(ws), ws.numel(), _stream(stream)), "l0cim_update_r")
+    return R
+
+
+def l0cim_solve_workspace_bytes(dtype: int, m: int, n: int, cim: CimParams, sp: SolveParams) -> int:
+    return lib().l0cim_solve_workspace_bytes(dtype, m, n, ctypes.byref(cim), ctypes.byref(sp))
+
+
+def l0cim_solve(A, y, cim: CimParams, sp: SolveParams, R_init=None, R_out=None, sigma_out=None,
+                stats=None, ws=None, stream=None):
+    """Algorithm 1 on one instance.  Returns (R, sigma, stats_bytes_tensor)."""
+    m, n = A.shape
+    dt = _dtype_code(A)
+    R_out = torch.empty(n, dtype=A.dtype, device=A.device) if R_out is None else R_out
+    sigma_out = torch.empty(n, dtype=torch.uint8, device=A.device) if sigma_out is None else sigma_out
+    stats = torch.zeros(STATS_BYTES, dtype=torch.uint8, device=A.device) if stats is None else stats
+    need = l0cim_solve_workspace_bytes(dt, m, n, cim, sp)
+    ws = workspace(need, A.device) if ws is None else ws
+    _check(lib().l0cim_solve(dt, m, n, _ptr(A), _ld(A), _ptr(y), _ptr(R_init), ctypes.byref(cim),
+                             ctypes.byref(sp), _ptr(R_out), _ptr(sigma_out), _ptr(stats), _ptr(ws),
+                             ws.numel(), _stream(stream)), "l0cim_solve")
+    return R_out, sigma_out, stats
+
+
+def read_stats(stats_tensor) -> Stats:
+    """Copy a device stats block to the host (synchronises)."""
+    raw = bytes(stats_tensor.cpu().numpy().tobytes())
+    return Stats.from_buffer_copy(raw)
+
+
+def l0cim_profile_begin():
+    _check(lib().l0cim_profile_begin(), "l0cim_profile_begin")
+
+
+def l0cim_profile_end():
+    ms = c_double(0.0)
+    cnt = c_int64(0)
+    _check(lib().l0cim_profile_end(ctypes.byref(ms), ctypes.byref(cnt)), "l0cim_profile_end")
+    return ms.value, cnt.value

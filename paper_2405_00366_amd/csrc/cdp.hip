@@ -1,0 +1,482 @@
+// Classical digital processing (CDP): the R-minimisation of Algorithm 1.
+//  * Jacobi relaxation with time increment dtc over every r, synchronously
+//    (parameter paragraph of the numerical experiments: dtc = 0.1, 100
+//    iterations).  Resident form: rows of G stay in LDS and the vector
+//    s = sigma o R travels through flag-carrying words, as in the CIM run.
+//  * FP64 least-squares refit on the support through a Cholesky factor.
+//  * eq. 3 objective and the per-solve report.
+#include "kernels.h"
+
+namespace l0 {
+namespace {
+
+__host__ __device__ inline size_t a16(size_t x) { return (x + 15) & ~size_t(15); }
+
+template <typename T>
+__host__ __device__ inline size_t jacobi_lds(int n, int rpw) {
+  return a16(size_t(rpw) * n * sizeof(T)) + a16(size_t(n) * sizeof(T)) + 4 * a16(size_t(rpw) * sizeof(T)) + 16;
+}
+
+template <typename T>
+__device__ inline void jacobi_update(T& R, T off, T br, T d, T dtc, bool tiny) {
+  R = tiny ? T(0) : R + dtc * ((br - off) / d - R);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(512)
+jacobi_resident_kernel(int n, const T* __restrict__ G, int64_t ldg, const T* __restrict__ b,
+                       const uint8_t* __restrict__ sigma, T dtc, int iters, T* __restrict__ R,
+                       uint64_t* __restrict__ ll, int* __restrict__ abort_word, int* __restrict__ status,
+                       int64_t limit, int rpw) {
+  constexpr int W = LL<T>::kWords;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tid = threadIdx.x, bs = blockDim.x;
+  const int lane = tid & (kWave - 1), wv = tid / kWave, nwv = bs / kWave;
+  const int r0 = blockIdx.x * rpw;
+  const int nr = max(0, min(n, r0 + rpw) - r0);
+  const bool solo = gridDim.x == 1;
+  const size_t slot_words = size_t(n) * W;
+
+  size_t o = 0;
+  T* Gl = reinterpret_cast<T*>(smem + o); o += a16(size_t(rpw) * n * sizeof(T));
+  T* X = reinterpret_cast<T*>(smem + o);  o += a16(size_t(n) * sizeof(T));
+  T* Rs = reinterpret_cast<T*>(smem + o); o += a16(size_t(rpw) * sizeof(T));
+  T* Ds = reinterpret_cast<T*>(smem + o); o += a16(size_t(rpw) * sizeof(T));
+  T* Bs = reinterpret_cast<T*>(smem + o); o += a16(size_t(rpw) * sizeof(T));
+  T* Sg = reinterpret_cast<T*>(smem + o); o += a16(size_t(rpw) * sizeof(T));
+  int* lds_abort = reinterpret_cast<int*>(smem + o);
+
+  for (size_t i = tid; i < size_t(nr) * n; i += bs) {
+    size_t rl = i / n, j = i - rl * n;
+    Gl[i] = G[size_t(r0 + rl) * ldg + j];
+  }
+  int bits = 0;
+  for (int i = tid; i < nr; i += bs) {
+    const int r = r0 + i;
+    const T d = G[size_t(r) * ldg + r];
+    const bool tiny = !(d >= T(1e-12));
+    if (tiny) bits |= L0CIM_ST_TINY_DIAG;
+    Ds[i] = d;
+    Bs[i] = b[r];
+    Sg[i] = sigma[r] ? T(1) : T(0);
+    Rs[i] = tiny ? T(0) : R[r];
+  }
+  if (tid == 0) *lds_abort = 0;
+  __syncthreads();
+  if (!solo)
+    for (int i = tid; i < nr; i += bs) LL<T>::put(ll + size_t(r0 + i) * W, Sg[i] * Rs[i], 1u);
+
+  bool aborted = false;
+  for (int it = 0; it < iters; ++it) {
+    if (solo) {
+      for (int i = tid; i < n; i += bs) X[i] = Sg[i] * Rs[i];
+    } else {
+      bool ok = ll_gather<T>(ll + size_t(it & 1) * slot_words, n, uint32_t(it + 1), limit,
+                             abort_word, [&](int idx, T v) { X[idx] = v; });
+      if (!ok) {
+        *lds_abort = 1;
+        __hip_atomic_store(abort_word, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    __syncthreads();
+    if (*lds_abort) {
+      aborted = true;
+      break;
+    }
+    for (int rl = wv; rl < nr; rl += nwv) {
+      const int r = r0 + rl;
+      const T* gr = Gl + size_t(rl) * n;
+      T acc = T(0);
+      for (int j = lane; j < n; j += kWave)
+        if (j != r) acc += gr[j] * X[j];
+      acc = wave_sum(acc);
+      if (lane == 0) {
+        T Rv = Rs[rl];
+        jacobi_update(Rv, acc, Bs[rl], Ds[rl], dtc, !(Ds[rl] >= T(1e-12)));
+        Rs[rl] = Rv;
+        if (!solo)
+          LL<T>::put(ll + size_t((it + 1) & 1) * slot_words + size_t(r) * W, Sg[rl] * Rv,
+                     uint32_t(it + 2));
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < nr; i += bs) R[r0 + i] = Rs[i];
+  if (aborted) bits |= L0CIM_ST_TIMEOUT;
+  if (bits) raise_status(status, bits);
+}
+
+// Streamed Jacobi sweep (G too large for the resident form): one launch per
+// sweep, one wavefront per row.
+template <typename T>
+__global__ void __launch_bounds__(256)
+jacobi_sweep_kernel(int n, const T* __restrict__ G, int64_t ldg, const T* __restrict__ b,
+                    const uint8_t* __restrict__ sigma, T dtc, const T* __restrict__ sin,
+                    T* __restrict__ sout, T* __restrict__ R, int* __restrict__ status, int first) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int r = blockIdx.x * 4 + threadIdx.x / kWave;
+  if (r >= n) return;
+  const T* gr = G + size_t(r) * ldg;
+  const T d = gr[r];
+  const bool tiny = !(d >= T(1e-12));
+  T acc = T(0);
+  for (int j = lane; j < n; j += kWave)
+    if (j != r) acc += gr[j] * sin[j];
+  acc = wave_sum(acc);
+  if (lane == 0) {
+    T Rv = R[r];
+    if (first && tiny) raise_status(status, L0CIM_ST_TINY_DIAG);
+    jacobi_update(Rv, acc, b[r], d, dtc, tiny);
+    R[r] = Rv;
+    sout[r] = sigma[r] ? Rv : T(0);
+  }
+}
+
+template <typename T>
+__global__ void masked_copy_kernel(int n, const T* __restrict__ G, int64_t ldg, const uint8_t* __restrict__ sigma,
+                                   T* __restrict__ R, T* __restrict__ s) {
+  int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= n) return;
+  T d = G[size_t(r) * ldg + r];
+  if (!(d >= T(1e-12))) R[r] = T(0);
+  s[r] = sigma[r] ? R[r] : T(0);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 Cholesky refit on the support (single workgroup; the support size is
+// only known on the device).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(1024)
+chol_refit_kernel(int n, const T* __restrict__ G, int64_t ldg, const T* __restrict__ b,
+                  const uint8_t* __restrict__ sigma, T* __restrict__ R, int* __restrict__ status,
+                  int* __restrict__ idx, double* __restrict__ L, double* __restrict__ w,
+                  int* __restrict__ kcount) {
+  __shared__ int cnt[1024];
+  __shared__ double red[1024];
+  __shared__ int sh_k, sh_bad;
+  __shared__ double sh_dmax, sh_ridge, sh_piv;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  // 1. compact S in index order: contiguous chunk per thread + block scan.
+  const int chunk = (n + bs - 1) / bs;
+  const int lo = min(n, tid * chunk), hi = min(n, lo + chunk);
+  int c = 0;
+  for (int i = lo; i < hi; ++i) c += sigma[i] ? 1 : 0;
+  cnt[tid] = c;
+  __syncthreads();
+  if (tid == 0) {
+    int s = 0;
+    for (int t = 0; t < bs; ++t) {
+      int v = cnt[t];
+      cnt[t] = s;
+      s += v;
+    }
+    sh_k = s;
+  }
+  __syncthreads();
+  int pos = cnt[tid];
+  for (int i = lo; i < hi; ++i)
+    if (sigma[i]) idx[pos++] = i;
+  __syncthreads();
+  const int k = sh_k;
+  if (tid == 0) *kcount = k;
+  // 2. max diagonal of G_SS
+  double dm = 0.0;
+  for (int a = tid; a < k; a += bs) dm = fmax(dm, double(G[size_t(idx[a]) * ldg + idx[a]]));
+  red[tid] = dm;
+  __syncthreads();
+  for (int s = bs / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
+    __syncthreads();
+  }
+  if (tid == 0) {
+    sh_dmax = red[0];
+    sh_ridge = 0.0;
+  }
+  __syncthreads();
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    // 3. L <- G_SS (+ ridge I), lower triangle, FP64
+    for (size_t e = tid; e < size_t(k) * k; e += bs) {
+      int a = int(e / k), bb = int(e - size_t(a) * k);
+      if (bb <= a) {
+        double v = double(G[size_t(idx[a]) * ldg + idx[bb]]);
+        if (a == bb) v += sh_ridge;
+        L[size_t(a) * k + bb] = v;
+      }
+    }
+    if (tid == 0) sh_bad = 0;
+    __syncthreads();
+    // 4. right-looking factorisation
+    for (int j = 0; j < k; ++j) {
+      if (tid == 0) {
+        double piv = L[size_t(j) * k + j];
+        if (!(piv > 1e-12 * sh_dmax)) sh_bad = 1;
+        sh_piv = sqrt(fmax(piv, 0.0));
+        L[size_t(j) * k + j] = sh_piv;
+      }
+      __syncthreads();
+      if (sh_bad) break;
+      const double ljj = sh_piv;
+      for (int a = j + 1 + tid; a < k; a += bs) L[size_t(a) * k + j] /= ljj;
+      __syncthreads();
+      const int m = k - j - 1;
+      for (size_t e = tid; e < size_t(m) * m; e += bs) {
+        int a = j + 1 + int(e / m), bb = j + 1 + int(e % m);
+        if (bb <= a) L[size_t(a) * k + bb] -= L[size_t(a) * k + j] * L[size_t(bb) * k + j];
+      }
+      __syncthreads();
+    }
+    if (!sh_bad) break;
+    if (attempt == 0) {
+      // ridge 1e-10 * tr(G_SS) / |S|
+      double tr = 0.0;
+      for (int a = tid; a < k; a += bs) tr += double(G[size_t(idx[a]) * ldg + idx[a]]);
+      red[tid] = tr;
+      __syncthreads();
+      if (tid == 0) {
+        double s = 0.0;
+        for (int t = 0; t < bs; ++t) s += red[t];
+        sh_ridge = 1e-10 * s / double(k);
+      }
+      __syncthreads();
+      if (tid == 0) raise_status(status, L0CIM_ST_CHOL_RIDGE);
+    }
+  }
+  // 5. forward substitution L w = b_S (column oriented)
+  for (int a = tid; a < k; a += bs) w[a] = double(b[idx[a]]);
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    if (tid == 0) w[j] /= L[size_t(j) * k + j];
+    __syncthreads();
+    const double wj = w[j];
+    for (int a = j + 1 + tid; a < k; a += bs) w[a] -= L[size_t(a) * k + j] * wj;
+    __syncthreads();
+  }
+  // 6. back substitution L^T x = w
+  for (int j = k - 1; j >= 0; --j) {
+    if (tid == 0) w[j] /= L[size_t(j) * k + j];
+    __syncthreads();
+    const double xj = w[j];
+    for (int a = tid; a < j; a += bs) w[a] -= L[size_t(j) * k + a] * xj;
+    __syncthreads();
+  }
+  for (int a = tid; a < k; a += bs) R[idx[a]] = T(w[a]);
+}
+
+// Off-support rows after the refit: R_r = (b_r - G_rS R_S) / G_rr.
+template <typename T>
+__global__ void __launch_bounds__(256)
+chol_offsupport_kernel(int n, const T* __restrict__ G, int64_t ldg, const T* __restrict__ b,
+                       const uint8_t* __restrict__ sigma, const int* __restrict__ idx,
+                       const int* __restrict__ kcount, const double* __restrict__ w, T* __restrict__ R,
+                       int* __restrict__ status) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int r = blockIdx.x * 4 + threadIdx.x / kWave;
+  if (r >= n) return;
+  const T d = G[size_t(r) * ldg + r];
+  const bool tiny = !(d >= T(1e-12));
+  if (sigma[r]) return;
+  const int k = *kcount;
+  double acc = 0.0;
+  for (int a = lane; a < k; a += kWave) acc += double(G[size_t(r) * ldg + idx[a]]) * w[a];
+  acc = wave_sum(acc);
+  if (lane == 0) {
+    if (tiny) raise_status(status, L0CIM_ST_TINY_DIAG);
+    R[r] = tiny ? T(0) : T((double(b[r]) - acc) / double(d));
+  }
+}
+
+// eq. 3 residual: one wavefront per measurement row.
+template <typename T>
+__global__ void __launch_bounds__(256)
+residual_kernel(int m, int n, const T* __restrict__ A, int64_t lda, const T* __restrict__ y,
+                const uint8_t* __restrict__ sigma, const T* __restrict__ R, double* __restrict__ part) {
+  __shared__ double rs[4];
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int k = blockIdx.x * 4 + wv;
+  double acc = 0.0;
+  if (k < m) {
+    for (int j = lane; j < n; j += kWave)
+      if (sigma[j]) acc += double(A[size_t(k) * lda + j]) * double(R[j]);
+    acc = wave_sum(acc);
+  }
+  if (lane == 0) {
+    double res = (k < m) ? double(y[k]) - acc : 0.0;
+    rs[wv] = res * res;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = ((rs[0] + rs[1]) + rs[2]) + rs[3];
+}
+
+__global__ void finalize_kernel(int n, int nparts, const double* __restrict__ part,
+                                const uint8_t* __restrict__ sigma, double lam, l0cim_stats* stats,
+                                int64_t spin_steps, int n_outer) {
+  __shared__ int cnt[256];
+  int c = 0;
+  for (int i = threadIdx.x; i < n; i += 256) c += sigma[i] ? 1 : 0;
+  cnt[threadIdx.x] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int t = 0; t < 256; ++t) s += cnt[t];
+    double r2 = 0.0;
+    for (int p = 0; p < nparts; ++p) r2 += part[p];
+    stats->support_size = s;
+    stats->E = 0.5 * r2 + lam * double(s);
+    stats->spin_steps = spin_steps;
+    stats->n_outer_done = n_outer;
+  }
+}
+
+}  // namespace
+
+size_t jacobi_ws_bytes(l0cim_dtype dt, int n) {
+  size_t words = (dt == L0CIM_F64) ? 2 : 1;
+  return align_up(size_t(2) * n * words * sizeof(uint64_t)) + kAlign + 2 * align_up(size_t(n) * dtype_size(dt));
+}
+
+namespace {
+template <typename T>
+l0cim_status jacobi_typed(int n, const T* G, int64_t ldg, const T* b, const uint8_t* sigma, double dtc,
+                          int iters, T* R, int* status, void* ws, hipStream_t s, int64_t limit) {
+  DeviceInfo dev;
+  l0cim_status st = device_info(&dev);
+  if (st != L0CIM_OK) return st;
+  char* p = static_cast<char*>(ws);
+  uint64_t* ll = reinterpret_cast<uint64_t*>(p);
+  p += align_up(size_t(2) * n * LL<T>::kWords * sizeof(uint64_t));
+  int* abort_word = reinterpret_cast<int*>(p);
+  p += kAlign;
+  T* s0 = reinterpret_cast<T*>(p);
+  p += align_up(size_t(n) * sizeof(T));
+  T* s1 = reinterpret_cast<T*>(p);
+  if (iters <= 0) return L0CIM_OK;
+
+  int rpw = 0, grid = 0;
+  size_t lds = 0;
+  if (n <= 256 && jacobi_lds<T>(n, n) <= size_t(dev.max_lds)) {
+    rpw = n;
+    grid = 1;
+    lds = jacobi_lds<T>(n, n);
+  } else {
+    int r = (n + dev.cu_count - 1) / dev.cu_count;
+    if (jacobi_lds<T>(n, r) <= size_t(dev.max_lds)) {
+      rpw = r;
+      grid = (n + r - 1) / r;
+      lds = jacobi_lds<T>(n, r);
+    }
+  }
+  if (rpw) {
+    auto kern = jacobi_resident_kernel<T>;
+    if (grid > 1) {
+      hipLaunchKernelGGL(ll_clear_kernel, dim3(64), dim3(256), 0, s, ll, size_t(2) * n * LL<T>::kWords,
+                         abort_word);
+      L0_LAUNCHED("clear exchange buffer");
+    }
+    L0_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+    const int block = (rpw >= 8) ? 512 : 256;
+    T dtcT = T(dtc);
+    int nn = n, itn = iters, rp = rpw;
+    int64_t lim = limit;
+    void* kargs[] = {&nn, &G, &ldg, &b, &sigma, &dtcT, &itn, &R, &ll, &abort_word, &status, &lim, &rp};
+    if (grid > 1) {
+      L0_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(grid), dim3(block),
+                                        kargs, unsigned(lds), s));
+    } else {
+      hipLaunchKernelGGL(kern, dim3(1), dim3(block), lds, s, nn, G, ldg, b, sigma, dtcT, itn, R, ll,
+                         abort_word, status, lim, rp);
+      L0_LAUNCHED("jacobi_resident_kernel");
+    }
+    return L0CIM_OK;
+  }
+  hipLaunchKernelGGL(masked_copy_kernel<T>, dim3((n + 255) / 256), dim3(256), 0, s, n, G, ldg, sigma, R, s0);
+  L0_LAUNCHED("masked_copy_kernel");
+  T* cur = s0;
+  T* nxt = s1;
+  for (int it = 0; it < iters; ++it) {
+    hipLaunchKernelGGL(jacobi_sweep_kernel<T>, dim3((n + 3) / 4), dim3(256), 0, s, n, G, ldg, b, sigma,
+                       T(dtc), cur, nxt, R, status, it == 0 ? 1 : 0);
+    L0_LAUNCHED("jacobi_sweep_kernel");
+    T* t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  return L0CIM_OK;
+}
+}  // namespace
+
+l0cim_status launch_jacobi(l0cim_dtype dt, int n, const void* G, int64_t ldg, const void* b,
+                           const uint8_t* sigma, double dtc, int iters, void* R, int* status,
+                           void* ws, size_t ws_bytes, hipStream_t s, int64_t spin_limit) {
+  (void)ws_bytes;
+  if (dt == L0CIM_F32)
+    return jacobi_typed<float>(n, (const float*)G, ldg, (const float*)b, sigma, dtc, iters, (float*)R,
+                               status, ws, s, spin_limit);
+  if (dt == L0CIM_F64)
+    return jacobi_typed<double>(n, (const double*)G, ldg, (const double*)b, sigma, dtc, iters,
+                                (double*)R, status, ws, s, spin_limit);
+  return set_error(L0CIM_ERR_UNSUPPORTED, "update_r: dtype %d", int(dt));
+}
+
+size_t chol_ws_bytes(int n) {
+  return align_up(size_t(n) * sizeof(int)) + align_up(size_t(n) * n * sizeof(double)) +
+         align_up(size_t(n) * sizeof(double)) + kAlign;
+}
+
+l0cim_status launch_chol_refit(l0cim_dtype dt, int n, const void* G, int64_t ldg, const void* b,
+                               const uint8_t* sigma, void* R, int* status, void* ws, size_t ws_bytes,
+                               hipStream_t s) {
+  (void)ws_bytes;
+  char* p = static_cast<char*>(ws);
+  int* idx = reinterpret_cast<int*>(p);
+  p += align_up(size_t(n) * sizeof(int));
+  double* L = reinterpret_cast<double*>(p);
+  p += align_up(size_t(n) * n * sizeof(double));
+  double* w = reinterpret_cast<double*>(p);
+  p += align_up(size_t(n) * sizeof(double));
+  int* kc = reinterpret_cast<int*>(p);
+  if (dt == L0CIM_F32) {
+    hipLaunchKernelGGL(chol_refit_kernel<float>, dim3(1), dim3(1024), 0, s, n, (const float*)G, ldg,
+                       (const float*)b, sigma, (float*)R, status, idx, L, w, kc);
+    L0_LAUNCHED("chol_refit_kernel");
+    hipLaunchKernelGGL(chol_offsupport_kernel<float>, dim3((n + 3) / 4), dim3(256), 0, s, n,
+                       (const float*)G, ldg, (const float*)b, sigma, idx, kc, w, (float*)R, status);
+  } else if (dt == L0CIM_F64) {
+    hipLaunchKernelGGL(chol_refit_kernel<double>, dim3(1), dim3(1024), 0, s, n, (const double*)G, ldg,
+                       (const double*)b, sigma, (double*)R, status, idx, L, w, kc);
+    L0_LAUNCHED("chol_refit_kernel");
+    hipLaunchKernelGGL(chol_offsupport_kernel<double>, dim3((n + 3) / 4), dim3(256), 0, s, n,
+                       (const double*)G, ldg, (const double*)b, sigma, idx, kc, w, (double*)R, status);
+  } else {
+    return set_error(L0CIM_ERR_UNSUPPORTED, "chol refit: dtype %d", int(dt));
+  }
+  L0_LAUNCHED("chol_offsupport_kernel");
+  return L0CIM_OK;
+}
+
+size_t objective_ws_bytes(int m) { return align_up(size_t((m + 3) / 4) * sizeof(double)); }
+
+l0cim_status launch_objective(l0cim_dtype dt, int m, int n, const void* A, int64_t lda, const void* y,
+                              const uint8_t* sigma, const void* R, double lam, l0cim_stats* stats,
+                              int64_t spin_steps, int n_outer, void* ws, size_t ws_bytes,
+                              hipStream_t s) {
+  (void)ws_bytes;
+  double* part = static_cast<double*>(ws);
+  const int nb = (m + 3) / 4;
+  if (dt == L0CIM_F32)
+    hipLaunchKernelGGL(residual_kernel<float>, dim3(nb), dim3(256), 0, s, m, n, (const float*)A, lda,
+                       (const float*)y, sigma, (const float*)R, part);
+  else if (dt == L0CIM_F64)
+    hipLaunchKernelGGL(residual_kernel<double>, dim3(nb), dim3(256), 0, s, m, n, (const double*)A, lda,
+                       (const double*)y, sigma, (const double*)R, part);
+  else
+    return set_error(L0CIM_ERR_UNSUPPORTED, "objective: dtype %d", int(dt));
+  L0_LAUNCHED("residual_kernel");
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, n, nb, part, sigma, lam, stats,
+                     spin_steps, n_outer);
+  L0_LAUNCHED("finalize_kernel");
+  return L0CIM_OK;
+}
+
+}  // namespace l0

@@ -1,0 +1,215 @@
+// Internal declarations shared by the l0cim HIP translation units (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp8.h>
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "l0cim.h"
+
+namespace l0 {
+
+constexpr int kWave = 64;
+constexpr size_t kAlign = 256;
+constexpr int kMaxLdsBytes = 160 * 1024;   // LDS per workgroup on gfx950
+constexpr int64_t kDefaultSpinLimit = int64_t(1) << 22;
+
+inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
+
+// ---------------------------------------------------------------------------
+// Host-side error plumbing
+// ---------------------------------------------------------------------------
+l0cim_status set_error(l0cim_status s, const char* fmt, ...);
+l0cim_status hip_fail(hipError_t e, const char* what);
+#define L0_HIP(call)                                         \
+  do {                                                       \
+    hipError_t _e = (call);                                  \
+    if (_e != hipSuccess) return ::l0::hip_fail(_e, #call);  \
+  } while (0)
+#define L0_LAUNCHED(what)                                    \
+  do {                                                       \
+    hipError_t _e = hipGetLastError();                       \
+    if (_e != hipSuccess) return ::l0::hip_fail(_e, what);   \
+  } while (0)
+
+struct DeviceInfo {
+  int device;
+  int cu_count;
+  int max_lds;
+};
+l0cim_status device_info(DeviceInfo* out);
+
+// Profiling hook: brackets CIM-kernel launches with events when enabled.
+struct ProfileScope {
+  hipStream_t stream;
+  void* ev0;
+  ProfileScope(hipStream_t s);
+  ~ProfileScope();
+};
+
+inline size_t dtype_size(l0cim_dtype t) {
+  switch (t) {
+    case L0CIM_F32: return 4;
+    case L0CIM_F64: return 8;
+    case L0CIM_BF16: return 2;
+    case L0CIM_FP8E4M3: return 1;
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel argument blocks
+// ---------------------------------------------------------------------------
+struct CimArgs {
+  int n, P;
+  int n_steps, trace_steps;
+  int field, linear_j;
+  int launch;
+  double dt, p_thr, d, t_c, t_w;
+  double K, j, beta, tau;
+  double eta;
+  int64_t spin_limit;
+};
+
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
+
+// Pump rate of eq. 21 at t = k dt, evaluated in FP64.
+__device__ inline double pump_at(const CimArgs& a, int k) {
+  double t = double(k) * a.dt;
+  return (a.p_thr - a.d) + 2.0 * a.d / (1.0 + exp(-(t - a.t_c) / a.t_w));
+}
+
+template <typename T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Coupling storage decoding.  Integer-exact for bf16 and fp8 (e4m3, OCP).
+template <typename JT> struct JLoad;
+template <> struct JLoad<float> {
+  __device__ static inline float get(float v) { return v; }
+};
+template <> struct JLoad<double> {
+  __device__ static inline double get(double v) { return v; }
+};
+template <> struct JLoad<__hip_bfloat16> {
+  __device__ static inline float get(__hip_bfloat16 v) { return __bfloat162float(v); }
+};
+template <> struct JLoad<__hip_fp8_e4m3> {
+  __device__ static inline float get(__hip_fp8_e4m3 v) { return float(v); }
+};
+
+// ---------------------------------------------------------------------------
+// Low-latency exchange: each published value travels in 64-bit words whose
+// upper half is a flag (the producer's step number + 1) and whose lower half
+// is 32 bits of payload.  Stores and loads are relaxed atomics at device
+// scope, so a reader sees either the old word or the new one, never a mix,
+// and needs no separate barrier.  A float uses one word, a double two.
+// ---------------------------------------------------------------------------
+template <typename T> struct LL;
+template <> struct LL<float> {
+  static constexpr int kWords = 1;
+  __device__ static inline void put(uint64_t* p, float v, uint32_t flag) {
+    uint64_t w = (uint64_t(flag) << 32) | uint64_t(__float_as_uint(v));
+    __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+};
+template <> struct LL<double> {
+  static constexpr int kWords = 2;
+  __device__ static inline void put(uint64_t* p, double v, uint32_t flag) {
+    uint64_t bits = uint64_t(__double_as_longlong(v));
+    uint64_t w0 = (uint64_t(flag) << 32) | (bits & 0xffffffffull);
+    uint64_t w1 = (uint64_t(flag) << 32) | (bits >> 32);
+    __hip_atomic_store(p, w0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p + 1, w1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+};
+
+__device__ inline uint64_t ll_load(const uint64_t* p) {
+  return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline int abort_seen(const int* abort_word) {
+  return __hip_atomic_load(const_cast<int*>(abort_word), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline void raise_status(int* status, int bits) {
+  if (status && bits) __hip_atomic_fetch_or(status, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until word p carries `flag`; returns false after `limit` polls or once
+// another workgroup has raised the abort word.
+__device__ inline bool ll_wait(const uint64_t* p, uint32_t flag, uint64_t& w, int64_t limit,
+                               const int* abort_word) {
+  int64_t polls = 0;
+  while (uint32_t(w >> 32) != flag) {
+    if (++polls > limit) return false;
+    if ((polls & 1023) == 0 && abort_seen(abort_word)) return false;
+    w = ll_load(p);
+  }
+  return true;
+}
+
+template <typename T>
+__device__ inline T ll_decode(const uint64_t* w);
+template <>
+__device__ inline float ll_decode<float>(const uint64_t* w) {
+  return __uint_as_float(uint32_t(w[0]));
+}
+template <>
+__device__ inline double ll_decode<double>(const uint64_t* w) {
+  uint64_t bits = (w[0] & 0xffffffffull) | (w[1] << 32);
+  return __longlong_as_double(int64_t(bits));
+}
+
+// Gather `count` published values carrying `flag` from `src`, storing
+// store(idx, value).  Loads of several words are issued before any wait.
+template <typename T, typename F>
+__device__ inline bool ll_gather(const uint64_t* src, int count, uint32_t flag, int64_t limit,
+                                 const int* abort_word, F store) {
+  constexpr int W = LL<T>::kWords;
+  constexpr int E = 4;
+  bool ok = true;
+  const int bs = blockDim.x;
+  for (int base = threadIdx.x; base < count; base += bs * E) {
+    uint64_t w[E][W];
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+      int idx = base + u * bs;
+      if (idx < count) {
+#pragma unroll
+        for (int v = 0; v < W; ++v) w[u][v] = ll_load(src + size_t(idx) * W + v);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+      int idx = base + u * bs;
+      if (idx < count && ok) {
+#pragma unroll
+        for (int v = 0; v < W; ++v)
+          if (ok) ok = ll_wait(src + size_t(idx) * W + v, flag, w[u][v], limit, abort_word);
+        if (ok) store(idx, ll_decode<T>(w[u]));
+      }
+    }
+  }
+  return ok;
+}
+
+
+// Zero `count` exchange words and the abort word before a resident launch
+// (a kernel rather than a memset, so that the sequence may be graph-captured).
+__global__ static void ll_clear_kernel(uint64_t* p, size_t count, int* abort_word) {
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < count;
+       i += size_t(gridDim.x) * blockDim.x)
+    p[i] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && abort_word) *abort_word = 0;
+}
+
+}  // namespace l0

@@ -1,0 +1,47 @@
+// Host-side launchers of the l0cim kernels (internal).
+#pragma once
+
+#include "common.h"
+
+namespace l0 {
+
+// ---- Gram / Zeeman prep -------------------------------------------------
+l0cim_status launch_gram(l0cim_dtype dt, int m, int n, const void* A, int64_t lda, const void* y,
+                         void* G, int64_t ldg, void* b, hipStream_t s);
+
+// ---- couplings, initial state, R_init ------------------------------------
+l0cim_status launch_couplings(l0cim_dtype dt, int n, const void* G, int64_t ldg, const void* b,
+                              const void* R, l0cim_dtype jdt, void* J, int64_t ldj, float* rscale,
+                              void* z, hipStream_t s);
+l0cim_status launch_init_state(l0cim_dtype dt, int n, int P, uint64_t seed, int alt, double std,
+                               void* c, void* e, hipStream_t s);
+l0cim_status launch_r_init(l0cim_dtype dt, int n, const void* G, int64_t ldg, const void* b,
+                           const void* R_init, void* R, int* status, hipStream_t s);
+
+// ---- CIM run ---------------------------------------------------------------
+size_t mfcim_ws_bytes(l0cim_dtype dt, int n, int P);
+l0cim_status launch_mfcim(l0cim_dtype dt, int n, int P, l0cim_dtype jdt, const void* J, int64_t ldj,
+                          const float* rscale, const void* z, const CimArgs& a, void* c, void* e,
+                          uint8_t* sigma, double* H, void* trace, int* status, void* ws,
+                          size_t ws_bytes, hipStream_t s);
+l0cim_status launch_select(int n, int P, const double* H, const uint8_t* sigma, uint8_t* out,
+                           int32_t* q_out, double* H_out, hipStream_t s);
+
+// ---- CDP ----------------------------------------------------------------
+size_t jacobi_ws_bytes(l0cim_dtype dt, int n);
+l0cim_status launch_jacobi(l0cim_dtype dt, int n, const void* G, int64_t ldg, const void* b,
+                           const uint8_t* sigma, double dtc, int iters, void* R, int* status,
+                           void* ws, size_t ws_bytes, hipStream_t s, int64_t spin_limit);
+size_t chol_ws_bytes(int n);
+l0cim_status launch_chol_refit(l0cim_dtype dt, int n, const void* G, int64_t ldg, const void* b,
+                               const uint8_t* sigma, void* R, int* status, void* ws, size_t ws_bytes,
+                               hipStream_t s);
+
+// ---- solve epilogue ------------------------------------------------------
+size_t objective_ws_bytes(int m);
+l0cim_status launch_objective(l0cim_dtype dt, int m, int n, const void* A, int64_t lda, const void* y,
+                              const uint8_t* sigma, const void* R, double lam, l0cim_stats* stats,
+                              int64_t spin_steps, int n_outer, void* ws, size_t ws_bytes,
+                              hipStream_t s);
+
+}  // namespace l0

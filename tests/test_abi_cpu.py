@@ -1,0 +1,136 @@
+"""The C-ABI library loads, exports every declared entry point and rejects bad
+arguments on the host before touching a device (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2405_00366_amd as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "l0cim.h")
+
+FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails validation first
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(l0cim_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_built_and_exports_every_declared_symbol():
+    assert os.path.exists(L.library_path), "build with python paper_2405_00366_amd/build.py"
+    lib = L.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in l0cim.h but not exported"
+
+
+def test_version_and_status_strings():
+    lib = L.lib()
+    assert lib.l0cim_version() == 100
+    assert lib.l0cim_status_string(0) == b"ok"
+    assert lib.l0cim_status_string(3).startswith(b"workspace")
+
+
+def test_paper_default_parameters():
+    p = L.cim_params()
+    assert (p.dt, p.n_steps, p.p_thr, p.d, p.t_c, p.t_w, p.K, p.tau) == (0.02, 1000, 1.0, 0.4, 4.0, 2.0, 1.0, 1.0)
+    assert p.c0_std == 1e-2 and p.field == L.FIELD_CN
+    s = L.solve_params()
+    assert (s.eta_init, s.eta_end, s.velo, s.cdp_iters, s.dtc) == (0.8, 0.18, 51, 100, 0.1)
+
+
+def test_struct_layouts_match_header():
+    assert ctypes.sizeof(L.CimParams) == 104
+    assert ctypes.sizeof(L.SolveParams) == 64
+    assert ctypes.sizeof(L.Stats) == 40
+
+
+def test_workspace_sizes():
+    lib = L.lib()
+    cim, sp = L.cim_params(), L.solve_params()
+    ws = lib.l0cim_solve_workspace_bytes(L.F32, 1000, 2000, ctypes.byref(cim), ctypes.byref(sp))
+    # G and J dominate: 2 * 2000^2 * 4 bytes
+    assert 32_000_000 <= ws < 40_000_000
+    assert lib.l0cim_mfcim_run_workspace_bytes(L.F32, 2000, 1, L.F32) >= 2 * 2000 * 8
+    assert lib.l0cim_mfcim_run_workspace_bytes(L.F64, 2000, 1, L.F64) >= 2 * 2000 * 16
+    assert lib.l0cim_update_r_workspace_bytes(L.F64, 100, L.CDP_CHOL_F64) >= 100 * 100 * 8
+    assert lib.l0cim_solve_workspace_bytes(L.F32, 0, 10, ctypes.byref(cim), ctypes.byref(sp)) == 0
+
+
+def _err(lib):
+    return lib.l0cim_last_error().decode()
+
+
+def test_gram_rejects_bad_arguments_on_host():
+    lib = L.lib()
+    assert lib.l0cim_gram(L.F32, 4, 4, None, 4, FAKE, FAKE, 4, FAKE, None) == 1
+    assert "NULL" in _err(lib)
+    assert lib.l0cim_gram(L.F32, 4, 4, FAKE, 3, FAKE, FAKE, 4, FAKE, None) == 2
+    assert lib.l0cim_gram(L.F32, 0, 4, FAKE, 4, FAKE, FAKE, 4, FAKE, None) == 2
+    assert lib.l0cim_gram(L.BF16, 4, 4, FAKE, 4, FAKE, FAKE, 4, FAKE, None) == 5
+
+
+def test_couplings_rejects_bad_arguments_on_host():
+    lib = L.lib()
+    # FP8 storage needs row scales
+    assert lib.l0cim_build_couplings(L.F32, 8, FAKE, 8, FAKE, FAKE, L.FP8E4M3, FAKE, 8, None, FAKE, None) == 1
+    # FP64 arithmetic cannot store BF16
+    assert lib.l0cim_build_couplings(L.F64, 8, FAKE, 8, FAKE, FAKE, L.BF16, FAKE, 8, FAKE, FAKE, None) == 5
+    assert lib.l0cim_build_couplings(L.F32, 8, FAKE, 8, FAKE, FAKE, L.F32, FAKE, 7, None, FAKE, None) == 2
+
+
+def test_mfcim_run_rejects_bad_arguments_on_host():
+    lib = L.lib()
+    prm = L.cim_params()
+    args = lambda **kw: dict(dt=L.F32, n=16, P=1, jdt=L.F32, J=FAKE, ldj=16, rs=None, z=FAKE, eta=0.5,
+                             prm=ctypes.byref(prm), c=FAKE, e=FAKE, sig=FAKE, H=None, tr=None, ts=0,
+                             st=None, ws=FAKE, wsb=1 << 20, s=None) | kw
+
+    def call(a):
+        return lib.l0cim_mfcim_run(*a.values())
+
+    assert call(args(wsb=16)) == 3
+    assert call(args(ws=None)) == 3
+    assert call(args(ldj=15)) == 2
+    assert call(args(P=0)) == 2
+    assert call(args(ts=5)) == 1                    # trace_steps without a buffer
+    bad = L.cim_params(field=7)
+    assert call(args(prm=ctypes.byref(bad))) == 1
+    bad = L.cim_params(dt=0.0)
+    assert call(args(prm=ctypes.byref(bad))) == 1
+    bad = L.cim_params(launch=9)
+    assert call(args(prm=ctypes.byref(bad))) == 1
+
+
+def test_solve_rejects_bad_arguments_on_host():
+    lib = L.lib()
+    cim, sp = L.cim_params(), L.solve_params(n_outer=3, velo=3)
+    base = [L.F32, 10, 20, FAKE, 20, FAKE, None, ctypes.byref(cim), ctypes.byref(sp), FAKE, FAKE, FAKE,
+            FAKE, 1 << 30, None]
+    a = list(base)
+    a[13] = 1024
+    assert lib.l0cim_solve(*a) == 3
+    a = list(base)
+    a[4] = 19
+    assert lib.l0cim_solve(*a) == 2
+    sp0 = L.solve_params(replicas=0)
+    a = list(base)
+    a[8] = ctypes.byref(sp0)
+    assert lib.l0cim_solve(*a) == 1
+    sp1 = L.solve_params(j_dtype=L.BF16)
+    a = list(base)
+    a[0] = L.F64
+    a[8] = ctypes.byref(sp1)
+    assert lib.l0cim_solve(*a) == 5
+
+
+def test_update_r_rejects_bad_arguments_on_host():
+    lib = L.lib()
+    assert lib.l0cim_update_r(L.F32, 10, FAKE, 10, FAKE, FAKE, 7, 0.1, 100, FAKE, None, FAKE, 1 << 20, None) == 1
+    assert lib.l0cim_update_r(L.F32, 10, FAKE, 10, FAKE, FAKE, 0, 0.1, -1, FAKE, None, FAKE, 1 << 20, None) == 1
+    assert lib.l0cim_update_r(L.F32, 10, FAKE, 10, FAKE, FAKE, 1, 0.1, 0, FAKE, None, FAKE, 64, None) == 3
