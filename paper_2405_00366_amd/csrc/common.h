@@ -91,6 +91,61 @@ __device__ inline T wave_sum(T v) {
   return v;
 }
 
+// Value of `v` held by this lane's partner across lane bit OFF.  Partners
+// differ in lane bit OFF: lane ^ 32 and lane ^ 16 through the LDS crossbar,
+// the mirrored lane of the 16- or 8-lane row (i <-> 15 - i, i <-> 7 - i) and
+// lane ^ 2, lane ^ 1 through DPP.
+template <int OFF>
+__device__ inline float lane_partner(float v) {
+  const int x = __float_as_int(v);
+  if constexpr (OFF == 32) return __shfl_xor(v, 32, kWave);
+  else if constexpr (OFF == 16) return __int_as_float(__builtin_amdgcn_ds_swizzle(x, 0x401F));
+  else if constexpr (OFF == 8) return __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x140, 0xF, 0xF, false));
+  else if constexpr (OFF == 4) return __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false));
+  else if constexpr (OFF == 2) return __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false));
+  else return __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false));
+}
+
+template <int OFF>
+__device__ inline double lane_partner(double v) {
+  return __shfl_xor(v, OFF, kWave);
+}
+
+// Sum each of R values over the 64 lanes of a wavefront with a transposed
+// butterfly: at each of the first log2(R) levels a lane keeps half of its
+// values and adds its partner's copy of them, so R - 1 + (6 - log2 R)
+// exchanges replace 6 R.  Afterwards v[0] of lane l holds the full sum of
+// value number wave_row_of<R>(l); the order of additions is fixed.
+template <int R>
+__device__ inline int wave_row_of(int lane) {
+  static_assert(R >= 1 && R <= 64 && (R & (R - 1)) == 0, "R must be a power of two <= 64");
+  return R == 1 ? 0 : (lane / (64 / R)) & (R - 1);
+}
+
+template <typename T, int R, int COUNT, int OFF>
+__device__ inline void wave_sum_rows_level(T (&v)[R], int lane) {
+  if constexpr (OFF > 0) {
+    if constexpr (COUNT > 1) {
+      constexpr int H = COUNT / 2;
+      const bool hi = (lane & OFF) != 0;
+      T recv[H];
+#pragma unroll
+      for (int i = 0; i < H; ++i) recv[i] = lane_partner<OFF>(hi ? v[i] : v[i + H]);
+#pragma unroll
+      for (int i = 0; i < H; ++i) v[i] = (hi ? v[i + H] : v[i]) + recv[i];
+      wave_sum_rows_level<T, R, H, OFF / 2>(v, lane);
+    } else {
+      v[0] += lane_partner<OFF>(v[0]);
+      wave_sum_rows_level<T, R, 1, OFF / 2>(v, lane);
+    }
+  }
+}
+
+template <typename T, int R>
+__device__ inline void wave_sum_rows(T (&v)[R], int lane) {
+  wave_sum_rows_level<T, R, R, 32>(v, lane);
+}
+
 // Coupling storage decoding.  Integer-exact for bf16 and fp8 (e4m3, OCP).
 template <typename JT> struct JLoad;
 template <> struct JLoad<float> {

@@ -300,6 +300,159 @@ __global__ void select_kernel(int n, int P, const double* __restrict__ H,
   for (int i = threadIdx.x; i < n; i += blockDim.x) out[i] = src[i];
 }
 
+
+// Single-replica resident run with the couplings held in registers.  Thread t
+// of a 512-thread workgroup keeps J[r0 + rho][t + u*512] for its rows rho < R
+// and columns u < C, gathers exactly the amplitudes of those columns from the
+// exchange words, multiplies, and the row sums are reduced across the
+// workgroup through LDS.  Wavefront 0 owns the state of the workgroup's rows.
+template <typename T, typename JT, int FIELD, int R, int C>
+__global__ void __launch_bounds__(512)
+cim_regs_kernel(const JT* __restrict__ J, int64_t ldj, const float* __restrict__ rscale,
+                const T* __restrict__ z, CimArgs a, T* __restrict__ c, T* __restrict__ e,
+                uint8_t* __restrict__ sigma, double* __restrict__ Hpart, T* __restrict__ trace,
+                uint64_t* __restrict__ ll, int* __restrict__ abort_word, int* __restrict__ status,
+                int rpw) {
+  using Acc = typename AccT<T>::type;
+  constexpr int BS = 512, NW = BS / kWave;
+  constexpr int W = LL<T>::kWords;
+  __shared__ Acc part[2][NW][R];
+  __shared__ int lds_abort;
+  const int n = a.n;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  const int r0 = blockIdx.x * rpw;
+  const int nr = max(0, min(n, r0 + rpw) - r0);
+  const size_t slot_words = size_t(n) * W;
+
+  Acc Jr[R][C];
+#pragma unroll
+  for (int u = 0; u < C; ++u) {
+    const int j = tid + u * BS;
+#pragma unroll
+    for (int rho = 0; rho < R; ++rho)
+      Jr[rho][u] = (rho < nr && j < n) ? Acc(JLoad<JT>::get(J[size_t(r0 + rho) * ldj + j])) : Acc(0);
+  }
+  const bool owner = (wv == 0 && lane < nr);
+  T cv = T(0), ev = T(0), zr = T(0);
+  float scl = 1.0f;
+  if (owner) {
+    cv = c[r0 + lane];
+    ev = e[r0 + lane];
+    zr = z[r0 + lane];
+    scl = rscale ? rscale[r0 + lane] : 1.0f;
+    LL<T>::put(ll + size_t(r0 + lane) * W, cv, 1u);
+  }
+  if (tid == 0) lds_abort = 0;
+  __syncthreads();
+
+  const T st = T(sqrt(a.tau));
+  const T half_st = T(0.5 * sqrt(a.tau));
+  const T theta = T(a.eta * a.eta * sqrt(a.tau) * 0.25);
+  const T jj = T(a.j), KK = T(a.K), beta = T(a.beta), tau = T(a.tau), dt = T(a.dt);
+  const double lam = 0.5 * a.eta * a.eta;
+  bool aborted = false;
+
+  for (int k = 0; k <= a.n_steps; ++k) {
+    const bool last = (k == a.n_steps);
+    const uint64_t* src = ll + size_t(k & 1) * slot_words;
+    const uint32_t flag = uint32_t(k + 1);
+    // the pump value of this step is evaluated while the gather is in flight
+    T lin = T(0);
+    if (owner && !last) lin = T(pump_at(a, k) - 1.0 - (a.linear_j ? a.j : 0.0));
+    // 1. gather this thread's columns: issue every load, then re-poll the late ones together
+    uint64_t w[C][W];
+#pragma unroll
+    for (int u = 0; u < C; ++u) {
+      const int j = tid + u * BS;
+#pragma unroll
+      for (int v = 0; v < W; ++v) w[u][v] = (j < n) ? ll_load(src + size_t(j) * W + v) : (uint64_t(flag) << 32);
+    }
+    int64_t polls = 0;
+    bool ok = true;
+    for (;;) {
+      bool ready = true;
+#pragma unroll
+      for (int u = 0; u < C; ++u)
+#pragma unroll
+        for (int v = 0; v < W; ++v) ready = ready && (uint32_t(w[u][v] >> 32) == flag);
+      if (ready) break;
+      if (++polls > a.spin_limit || ((polls & 1023) == 0 && abort_seen(abort_word))) {
+        ok = false;
+        break;
+      }
+#pragma unroll
+      for (int u = 0; u < C; ++u) {
+        const int j = tid + u * BS;
+#pragma unroll
+        for (int v = 0; v < W; ++v)
+          if (uint32_t(w[u][v] >> 32) != flag) w[u][v] = ll_load(src + size_t(j) * W + v);
+      }
+    }
+    if (!ok) {
+      lds_abort = 1;
+      __hip_atomic_store(abort_word, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // 2. partial row sums of this thread's columns, reduced per wavefront
+    Acc acc[R];
+#pragma unroll
+    for (int rho = 0; rho < R; ++rho) acc[rho] = Acc(0);
+#pragma unroll
+    for (int u = 0; u < C; ++u) {
+      const Acc x = Acc(xform<T, FIELD>(ll_decode<T>(w[u]), st, last));
+#pragma unroll
+      for (int rho = 0; rho < R; ++rho) acc[rho] += Jr[rho][u] * x;
+    }
+    wave_sum_rows<Acc, R>(acc, lane);
+    if ((lane & (kWave / R - 1)) == 0) part[k & 1][wv][wave_row_of<R>(lane)] = acc[0];
+    __syncthreads();
+    if (lds_abort) {
+      aborted = true;
+      break;
+    }
+    // 3. owners: row sums in a fixed order, Euler update, publish
+    if (wv == 0) {
+      double hterm = 0.0;
+      if (owner) {
+        Acc yacc = Acc(0);
+        for (int q = 0; q < NW; ++q) yacc += part[k & 1][q][lane];
+        const T y = T(yacc) * T(scl);
+        if (!last) {
+          euler_update<T, FIELD>(cv, ev, y, zr, lin, theta, half_st, jj, KK, beta, tau, dt);
+          LL<T>::put(ll + size_t((k + 1) & 1) * slot_words + size_t(r0 + lane) * W, cv, uint32_t(k + 2));
+          if (k < a.trace_steps) {
+            trace[size_t(2 * k) * n + r0 + lane] = cv;
+            trace[size_t(2 * k + 1) * n + r0 + lane] = ev;
+          }
+        } else {
+          hterm = cv > T(0) ? (-0.5 * double(y) - double(zr) + lam) : 0.0;
+        }
+      }
+      if (last && Hpart) {
+        // fixed-order sum over the owned rows
+        __shared__ double hrow[kWave];
+        hrow[lane] = hterm;
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) {
+          double h = 0.0;
+          for (int q = 0; q < nr; ++q) h += hrow[q];
+          Hpart[blockIdx.x] = h;
+        }
+      }
+    }
+  }
+  if (owner) {
+    c[r0 + lane] = cv;
+    e[r0 + lane] = ev;
+    sigma[r0 + lane] = cv > T(0) ? 1 : 0;
+    int bits = 0;
+    if (!(isfinite(double(cv)) && isfinite(double(ev)))) bits |= L0CIM_ST_NONFINITE;
+    else if (fabs(double(cv)) > 1e3) bits |= L0CIM_ST_BLOWUP;
+    if (aborted) bits |= L0CIM_ST_TIMEOUT;
+    if (bits) raise_status(status, bits);
+  }
+  if (aborted && tid == 0 && Hpart) Hpart[blockIdx.x] = NAN;
+}
+
 struct RunWs {
   uint64_t* ll;
   int* abort_word;
@@ -331,21 +484,54 @@ l0cim_status run_typed(int n, int P, const JT* J, int64_t ldj, const float* rsca
   if (st != L0CIM_OK) return st;
   RunWs w = carve_run_ws<T>(ws, n, P);
 
-  // Resident launch: smallest rows-per-workgroup that fits one workgroup per CU.
+  // Launch shape.  Small problems run in one workgroup with everything in
+  // LDS; one FP32 replica keeps its couplings in registers; otherwise rows of
+  // J stay in LDS when they fit; otherwise J is streamed every step.
   int rpw = 0, grid = 0, block = 256;
   size_t lds = 0;
+  const int rpw_cu = (n + dev.cu_count - 1) / dev.cu_count;
   if (a.launch != L0CIM_LAUNCH_STREAMED) {
     const size_t whole = resident_layout<T, JT>(n, P, n).total;
     if (n <= 256 && whole <= size_t(dev.max_lds)) {
       rpw = n;
       grid = 1;
       lds = whole;
-    } else {
-      int r = (n + dev.cu_count - 1) / dev.cu_count;
-      size_t need = resident_layout<T, JT>(n, P, r).total;
+    }
+    if constexpr (sizeof(T) == 4) {
+      if (!rpw && P == 1) {
+        const int cols = (n + 511) / 512;
+        void (*rk)(const JT*, int64_t, const float*, const T*, CimArgs, T*, T*, uint8_t*, double*, T*,
+                   uint64_t*, int*, int*, int) = nullptr;
+        if (rpw_cu <= 8 && cols <= 4) rk = cim_regs_kernel<T, JT, FIELD, 8, 4>;
+        else if (rpw_cu <= 16 && cols <= 8) rk = cim_regs_kernel<T, JT, FIELD, 16, 8>;
+        if (rk) {
+          const int g = (n + rpw_cu - 1) / rpw_cu;
+          size_t words = size_t(2) * n * LL<T>::kWords;
+          hipLaunchKernelGGL(ll_clear_kernel, dim3(256), dim3(256), 0, s, w.ll, words, w.abort_word);
+          L0_LAUNCHED("clear exchange buffer");
+          CimArgs args = a;
+          const JT* Jp = J;
+          int rp = rpw_cu;
+          void* kargs[] = {&Jp, &ldj, &rscale, &z, &args, &c, &e, &sigma, &w.hpart, &trace,
+                           &w.ll, &w.abort_word, &status, &rp};
+          {
+            ProfileScope prof(s);
+            L0_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(rk), dim3(g), dim3(512),
+                                              kargs, 0u, s));
+          }
+          if (H) {
+            hipLaunchKernelGGL(reduce_h_kernel, dim3(1), dim3(64), 0, s, w.hpart, g, P, H);
+            L0_LAUNCHED("reduce_h_kernel");
+          }
+          return L0CIM_OK;
+        }
+      }
+    }
+    if (!rpw) {
+      size_t need = resident_layout<T, JT>(n, P, rpw_cu).total;
       if (need <= size_t(dev.max_lds)) {
-        rpw = r;
-        grid = (n + r - 1) / r;
+        rpw = rpw_cu;
+        grid = (n + rpw_cu - 1) / rpw_cu;
         lds = need;
       }
     }

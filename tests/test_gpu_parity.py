@@ -147,6 +147,8 @@ TRACE_CASES = [
     (250,   2, "CN", L.LAUNCH_AUTO, torch.float32),
     (2000,  1, "CN", L.LAUNCH_RESIDENT, torch.float32),
     (2000,  1, "BN", L.LAUNCH_RESIDENT, torch.float32),
+    (4000,  1, "BN", L.LAUNCH_RESIDENT, torch.float32),
+    (3001,  1, "CN", L.LAUNCH_AUTO, torch.float32),
     (777,   3, "CN", L.LAUNCH_RESIDENT, torch.float32),
     (777,   2, "CN", L.LAUNCH_STREAMED, torch.float32),
     (1500,  1, "BN", L.LAUNCH_STREAMED, torch.float32),
@@ -204,9 +206,9 @@ def test_mfcim_trace_parity(dev, n, P, field, launch, dtype):
 
 
 @pytest.mark.parametrize("fmt", ["fp8", "bf16"])
-@pytest.mark.parametrize("launch", [L.LAUNCH_AUTO, L.LAUNCH_STREAMED])
-def test_mfcim_trace_parity_quantised_couplings(dev, fmt, launch):
-    got, ref, sig, c, H, st, _ = _trace_case(dev, 1200, 2, "BN", launch, torch.float32, jfmt=fmt)
+@pytest.mark.parametrize("launch,P", [(L.LAUNCH_AUTO, 2), (L.LAUNCH_STREAMED, 2), (L.LAUNCH_AUTO, 1)])
+def test_mfcim_trace_parity_quantised_couplings(dev, fmt, launch, P):
+    got, ref, sig, c, H, st, _ = _trace_case(dev, 1200, P, "BN", launch, torch.float32, jfmt=fmt)
     assert st == 0
     worst = max(normwise(got[k, v], ref[k, v]) for k in range(got.shape[0]) for v in range(2))
     assert worst <= 1e-5
