@@ -241,6 +241,46 @@ l0cim_status l0cim_solve(l0cim_dtype dtype, int32_t m, int32_t n, const void* A,
                          l0cim_stats* stats, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Batched form: many instances of uneven size, each with P replicas, solved
+ * together by Algorithm 1 (FP32 arithmetic; couplings F32, BF16 or FP8E4M3).
+ * With several replicas the local field of every instance is the dense
+ * product J X (N x N by N x P), done on the matrix cores with the Euler
+ * update fused; one launch per Euler step covers every row tile of every
+ * instance and the launches of one CIM run are replayed from a HIP graph.
+ *
+ * Instance k reads A_k at A_pool + a_offset (m x n, leading dim lda) and
+ * y_k at y_pool + y_offset, and writes R_k (n floats) at R_pool + x_offset,
+ * sigma_k (n bytes) at sigma_pool + x_offset and stats[k].  Its initial
+ * amplitudes are keyed by `seed` exactly as l0cim_init_state, so an instance
+ * gives the same result whatever else is in the batch.
+ *
+ * A plan holds host-side tables only; its workspace is the caller's.  The
+ * first solve of a new shape class times the candidate tile shapes (it
+ * synchronises the stream once) and remembers the fastest for the process.
+ * Destroy a plan only after the work enqueued with it has completed.
+ */
+typedef struct {
+  int32_t m, n;          /* measurement rows and spins (n <= 12288) */
+  int64_t a_offset;      /* element offset of A_k in A_pool */
+  int64_t lda;           /* leading dimension of A_k (>= n) */
+  int64_t y_offset;      /* element offset of y_k in y_pool */
+  int64_t x_offset;      /* element offset of R_k and byte offset of sigma_k */
+  uint64_t seed;         /* key of the instance's initial-amplitude generator */
+} l0cim_instance;
+
+typedef struct l0cim_batch_plan_s* l0cim_batch_plan;
+
+l0cim_status l0cim_batch_plan_create(int32_t count, const l0cim_instance* inst, const l0cim_cim_params* cim,
+                                     const l0cim_solve_params* sp, l0cim_batch_plan* plan);
+size_t l0cim_batch_plan_workspace_bytes(l0cim_batch_plan plan);
+l0cim_status l0cim_batch_plan_info(l0cim_batch_plan plan, int32_t* rows_per_tile, int32_t* tiles,
+                                   int32_t* tuned);
+l0cim_status l0cim_batch_plan_destroy(l0cim_batch_plan plan);
+l0cim_status l0cim_solve_batched(l0cim_batch_plan plan, const float* A_pool, const float* y_pool,
+                                 float* R_pool, uint8_t* sigma_pool, l0cim_stats* stats, void* ws,
+                                 size_t ws_bytes, void* stream);
+
+/*
  * Kernel timing for measurement.  Between l0cim_profile_begin() and
  * l0cim_profile_end(), every launch of the CIM-run kernels made by this
  * thread is bracketed by HIP events on its own stream.  profile_end waits for

@@ -285,7 +285,7 @@ class SolveResult:
 
 
 def solve(A, y, cim: CimParams, outer: OuterParams, R_init=None, c0_list=None,
-          keep_history: bool = True) -> SolveResult:
+          keep_history: bool = True, j_format: str | None = None) -> SolveResult:
     """Alternating minimisation, Algorithm 1.
 
     For i = 0 .. n_outer-1:
@@ -295,7 +295,10 @@ def solve(A, y, cim: CimParams, outer: OuterParams, R_init=None, c0_list=None,
       sigma = H(c) at the last step (lowest-energy replica when P > 1);
       R <- Jacobi CDP on that sigma (warm start).
     c0_list, if given, supplies the (P, N) initial amplitudes of every
-    alternation; otherwise they come from the counter-based generator."""
+    alternation; otherwise they come from the counter-based generator.
+    j_format ('bf16' or 'fp8'), if given, runs the CIM on the couplings as the
+    narrow storage represents them (per-row scale times the rounded value,
+    the rounding decided in FP32 as the device decides it)."""
     A = np.asarray(A, float)
     y = np.asarray(y, float)
     G, b = gram(A, y)
@@ -315,6 +318,11 @@ def solve(A, y, cim: CimParams, outer: OuterParams, R_init=None, c0_list=None,
         eta = eta_schedule(i, outer)
         lam = lam_from_eta(eta)
         J, z = couplings(G, b, R)
+        if j_format is not None:
+            from . import quant as _quant
+            f = lambda v: np.asarray(v, float).astype(np.float32)
+            J32, _ = _quant.couplings_f32(f(G), f(b), f(R))
+            J = _quant.dequantized(*_quant.quantize_rows(J32, j_format))
         if c0_list is not None:
             c0 = np.atleast_2d(np.asarray(c0_list[i], float))
             e0 = np.ones_like(c0)

@@ -22,7 +22,8 @@ __all__ = [
     "l0cim_mfcim_run", "l0cim_select_replica", "l0cim_update_r", "l0cim_solve",
     "l0cim_mfcim_run_workspace_bytes", "l0cim_update_r_workspace_bytes",
     "l0cim_solve_workspace_bytes", "l0cim_profile_begin", "l0cim_profile_end",
-    "cim_params", "solve_params",
+    "cim_params", "solve_params", "Instance", "l0cim_batch_plan_create", "l0cim_batch_plan_workspace_bytes",
+    "l0cim_batch_plan_info", "l0cim_batch_plan_destroy", "l0cim_solve_batched", "pack_instances",
 ]
 
 F32, F64, BF16, FP8E4M3 = 0, 1, 2, 3
@@ -63,6 +64,13 @@ class Stats(ctypes.Structure):
 
 
 STATS_BYTES = ctypes.sizeof(Stats)
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [
+        ("m", c_int32), ("n", c_int32), ("a_offset", c_int64), ("lda", c_int64),
+        ("y_offset", c_int64), ("x_offset", c_int64), ("seed", c_uint64),
+    ]
 
 
 class L0cimError(RuntimeError):
@@ -118,6 +126,17 @@ def lib():
         L.l0cim_solve.argtypes = [c_int, c_int32, c_int32, vp, c_int64, vp, vp, POINTER(CimParams),
                                   POINTER(SolveParams), vp, vp, vp, vp, c_size_t, vp]
         L.l0cim_solve.restype = st
+        L.l0cim_batch_plan_create.argtypes = [c_int32, POINTER(Instance), POINTER(CimParams),
+                                              POINTER(SolveParams), POINTER(c_void_p)]
+        L.l0cim_batch_plan_create.restype = st
+        L.l0cim_batch_plan_workspace_bytes.argtypes = [c_void_p]
+        L.l0cim_batch_plan_workspace_bytes.restype = c_size_t
+        L.l0cim_batch_plan_info.argtypes = [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32)]
+        L.l0cim_batch_plan_info.restype = st
+        L.l0cim_batch_plan_destroy.argtypes = [c_void_p]
+        L.l0cim_batch_plan_destroy.restype = st
+        L.l0cim_solve_batched.argtypes = [c_void_p, vp, vp, vp, vp, vp, vp, c_size_t, vp]
+        L.l0cim_solve_batched.restype = st
         L.l0cim_profile_begin.restype = st
         L.l0cim_profile_end.argtypes = [POINTER(c_double), POINTER(c_int64)]
         L.l0cim_profile_end.restype = st
@@ -294,6 +313,66 @@ def read_stats(stats_tensor) -> Stats:
     """Copy a device stats block to the host (synchronises)."""
     raw = bytes(stats_tensor.cpu().numpy().tobytes())
     return Stats.from_buffer_copy(raw)
+
+
+# ---------------------------------------------------------------------------
+# Batched form
+# ---------------------------------------------------------------------------
+
+def l0cim_batch_plan_create(instances, cim: CimParams, sp: SolveParams):
+    """instances: sequence of Instance (or dicts with its fields).  Returns the plan handle."""
+    arr = (Instance * len(instances))()
+    for i, d in enumerate(instances):
+        arr[i] = d if isinstance(d, Instance) else Instance(**d)
+    h = c_void_p()
+    _check(lib().l0cim_batch_plan_create(len(instances), arr, ctypes.byref(cim), ctypes.byref(sp),
+                                         ctypes.byref(h)), "l0cim_batch_plan_create")
+    return h
+
+
+def l0cim_batch_plan_workspace_bytes(plan) -> int:
+    return lib().l0cim_batch_plan_workspace_bytes(plan)
+
+
+def l0cim_batch_plan_info(plan):
+    rows, tiles, tuned = c_int32(), c_int32(), c_int32()
+    _check(lib().l0cim_batch_plan_info(plan, ctypes.byref(rows), ctypes.byref(tiles), ctypes.byref(tuned)),
+           "l0cim_batch_plan_info")
+    return rows.value, tiles.value, bool(tuned.value)
+
+
+def l0cim_batch_plan_destroy(plan):
+    _check(lib().l0cim_batch_plan_destroy(plan), "l0cim_batch_plan_destroy")
+
+
+def l0cim_solve_batched(plan, A_pool, y_pool, R_pool, sigma_pool, stats, ws, stream=None):
+    _check(lib().l0cim_solve_batched(plan, _ptr(A_pool), _ptr(y_pool), _ptr(R_pool), _ptr(sigma_pool),
+                                     _ptr(stats), _ptr(ws), ws.numel(), _stream(stream)),
+           "l0cim_solve_batched")
+
+
+def pack_instances(As, ys, seeds, device="cuda"):
+    """Pack per-instance A (m x n) and y into contiguous FP32 pools and build
+    the instance descriptors.  Returns (instances, A_pool, y_pool, R_pool,
+    sigma_pool, stats, x_offsets)."""
+    insts, a_off, y_off, x_off = [], 0, 0, 0
+    for A, y, sd in zip(As, ys, seeds):
+        m, n = A.shape
+        insts.append(Instance(m=m, n=n, a_offset=a_off, lda=n, y_offset=y_off, x_offset=x_off, seed=sd))
+        a_off += m * n
+        y_off += m
+        x_off += n
+    A_pool = torch.cat([torch.as_tensor(A, dtype=torch.float32).reshape(-1) for A in As]).to(device)
+    y_pool = torch.cat([torch.as_tensor(y, dtype=torch.float32).reshape(-1) for y in ys]).to(device)
+    R_pool = torch.zeros(x_off, dtype=torch.float32, device=device)
+    sigma_pool = torch.zeros(x_off, dtype=torch.uint8, device=device)
+    stats = torch.zeros(len(insts) * STATS_BYTES, dtype=torch.uint8, device=device)
+    return insts, A_pool, y_pool, R_pool, sigma_pool, stats
+
+
+def read_stats_array(stats_tensor, count):
+    raw = bytes(stats_tensor.cpu().numpy().tobytes())
+    return [Stats.from_buffer_copy(raw, i * STATS_BYTES) for i in range(count)]
 
 
 def l0cim_profile_begin():

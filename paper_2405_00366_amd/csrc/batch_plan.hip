@@ -1,0 +1,417 @@
+// Host side of the batched engine: the plan (pool layout, row-tile table,
+// tile shape picked by timing the candidates once per shape class), the HIP
+// graph of one CIM run, and the C entry points.
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "batch.h"
+
+using namespace l0;
+
+struct l0cim_batch_plan_s {
+  int count = 0, P = 1, qb = 1;
+  l0cim_cim_params cim;
+  l0cim_solve_params sp;
+  l0cim_dtype jdt = L0CIM_F32;
+  std::vector<l0cim_instance> inst;
+  std::vector<BInst> base;               // offsets; tile fields filled per tile shape
+  std::vector<int64_t> row_prefix, st_prefix;
+  int64_t nG = 0, nV = 0, nS = 0, nSig = 0, max_tiles = 0;
+  int max_ld = 0, max_n = 0;
+  struct {
+    size_t insts, tiles, rowp, stp, eta, G, Gc, b, z, rs, J, c, c2, e, sig, hpart, chol, total;
+  } off{};
+  int rb = 0;
+  bool tuned = false;
+  std::string key;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const void* graph_ws = nullptr;
+  const void* graph_stats = nullptr;
+  int graph_rb = 0;
+  // host copies of the device tables per tile shape; they stay alive for the
+  // plan's lifetime so that asynchronous uploads never read freed memory
+  std::map<int, std::pair<std::vector<BInst>, std::vector<BTile>>> tables;
+};
+
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;   // shape class -> rows per wavefront block count
+
+int round_up_i(int x, int a) { return (x + a - 1) / a * a; }
+
+// Row tiles of every instance, largest rows-times-columns work first so that
+// the tail of a step is made of small tiles.  Results do not depend on the
+// order: every output row is computed by one wavefront in a fixed k order.
+void tile_table(const l0cim_batch_plan_s* p, int rb, std::vector<BInst>& insts, std::vector<BTile>& tiles) {
+  const int tr = 64 * rb;
+  insts = p->base;
+  std::vector<int> order(p->count);
+  for (int k = 0; k < p->count; ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return insts[x].n > insts[y].n; });
+  tiles.clear();
+  for (int k : order) {
+    insts[k].tile0 = int(tiles.size());
+    for (int r0 = 0; r0 < insts[k].n; r0 += tr) tiles.push_back(BTile{k, r0});
+    insts[k].ntiles = int(tiles.size()) - insts[k].tile0;
+  }
+}
+
+BatchDev carve(const l0cim_batch_plan_s* p, void* ws, float* R, uint8_t* sig, l0cim_stats* stats) {
+  char* b = static_cast<char*>(ws);
+  BatchDev d;
+  d.count = p->count;
+  d.insts = reinterpret_cast<const BInst*>(b + p->off.insts);
+  d.tiles = reinterpret_cast<const BTile*>(b + p->off.tiles);
+  d.row_prefix = reinterpret_cast<const int64_t*>(b + p->off.rowp);
+  d.st_prefix = reinterpret_cast<const int64_t*>(b + p->off.stp);
+  d.eta = reinterpret_cast<double*>(b + p->off.eta);
+  d.G = reinterpret_cast<float*>(b + p->off.G);
+  d.Gc = reinterpret_cast<float*>(b + p->off.Gc);
+  d.b = reinterpret_cast<float*>(b + p->off.b);
+  d.z = reinterpret_cast<float*>(b + p->off.z);
+  d.rs = reinterpret_cast<float*>(b + p->off.rs);
+  d.J = b + p->off.J;
+  d.c = reinterpret_cast<float*>(b + p->off.c);
+  d.c2 = reinterpret_cast<float*>(b + p->off.c2);
+  d.e = reinterpret_cast<float*>(b + p->off.e);
+  d.sig_all = reinterpret_cast<uint8_t*>(b + p->off.sig);
+  d.hpart = reinterpret_cast<double*>(b + p->off.hpart);
+  d.R = R;
+  d.sig_out = sig;
+  d.stats = stats;
+  return d;
+}
+
+l0cim_status upload_tables(l0cim_batch_plan_s* p, const BatchDev& d, int rb, hipStream_t s, int* ntiles) {
+  auto it = p->tables.find(rb);
+  if (it == p->tables.end()) {
+    std::pair<std::vector<BInst>, std::vector<BTile>> t;
+    tile_table(p, rb, t.first, t.second);
+    it = p->tables.emplace(rb, std::move(t)).first;
+  }
+  const auto& insts = it->second.first;
+  const auto& tiles = it->second.second;
+  L0_HIP(hipMemcpyAsync(const_cast<BInst*>(d.insts), insts.data(), insts.size() * sizeof(BInst),
+                        hipMemcpyHostToDevice, s));
+  L0_HIP(hipMemcpyAsync(const_cast<BTile*>(d.tiles), tiles.data(), tiles.size() * sizeof(BTile),
+                        hipMemcpyHostToDevice, s));
+  *ntiles = int(tiles.size());
+  return L0CIM_OK;
+}
+
+BStepArgs step_args(const l0cim_batch_plan_s* p) {
+  BStepArgs a;
+  a.P = p->P;
+  a.n_steps = p->cim.n_steps;
+  a.linear_j = p->cim.linear_j;
+  a.field = p->cim.field;
+  a.dt = p->cim.dt;
+  a.p_thr = p->cim.p_thr;
+  a.d = p->cim.d;
+  a.t_c = p->cim.t_c;
+  a.t_w = p->cim.t_w;
+  a.K = p->cim.K;
+  a.j = p->cim.j;
+  a.beta = p->cim.beta;
+  a.tau = p->cim.tau;
+  return a;
+}
+
+// Enqueue Euler steps k0..k1 (inclusive) of one CIM run.
+l0cim_status enqueue_steps(const l0cim_batch_plan_s* p, const BatchDev& d, int rb, int ntiles, int k0, int k1,
+                           hipStream_t s) {
+  const void* fn = batch_step_kernel(p->jdt, p->cim.field, p->qb, rb);
+  if (!fn) return set_error(L0CIM_ERR_UNSUPPORTED, "batched step: no kernel for this shape");
+  BStepArgs a = step_args(p);
+  int* status = &d.stats[0].status_bits;
+  for (int k = k0; k <= k1; ++k) {
+    const float* cin = (k & 1) ? d.c2 : d.c;
+    float* cout = (k & 1) ? d.c : d.c2;
+    const BTile* tiles = d.tiles;
+    const BInst* insts = d.insts;
+    const void* J = d.J;
+    const float* z = d.z;
+    const float* rs = d.rs;
+    float* e = d.e;
+    uint8_t* sig = d.sig_all;
+    double* hp = d.hpart;
+    const double* eta = d.eta;
+    int kk = k;
+    void* args[] = {&tiles, &insts, &J, &z, &rs, &cin, &cout, &e, &sig, &hp, &a, &kk, &eta, &status};
+    L0_HIP(hipLaunchKernel(fn, dim3(ntiles), dim3(256), args, 0, s));
+  }
+  return L0CIM_OK;
+}
+
+std::string shape_key(const l0cim_batch_plan_s* p) {
+  double sum_n2 = 0;
+  for (auto& i : p->inst) sum_n2 += double(i.n) * i.n;
+  int b2 = 0;
+  while ((1ull << b2) < uint64_t(sum_n2 + 1)) ++b2;
+  int bc = 0;
+  while ((1 << bc) < p->count) ++bc;
+  char buf[128];
+  snprintf(buf, sizeof(buf), "P%d/j%d/f%d/n2_%d/c%d/nmax%d", p->P, int(p->jdt), p->cim.field, b2, bc,
+           round_up_i(p->max_n, 256));
+  return buf;
+}
+
+// Time every candidate tile shape on the current problem; the state it
+// leaves behind is discarded (every alternation starts from init_state).
+l0cim_status autotune(l0cim_batch_plan_s* p, const BatchDev& d, hipStream_t s) {
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(p->key);
+    if (it != g_tune.end()) {
+      p->rb = it->second;
+      p->tuned = true;
+      return L0CIM_OK;
+    }
+  }
+  int ntiles = 0;
+  hipEvent_t e0, e1;
+  L0_HIP(hipEventCreate(&e0));
+  L0_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  int best_rb = 2;
+  const int steps = p->cim.n_steps > 0 ? (p->cim.n_steps < 8 ? p->cim.n_steps : 8) : 0;
+  for (int rb : {1, 2, 4}) {
+    l0cim_status st = upload_tables(p, d, rb, s, &ntiles);
+    if (st != L0CIM_OK) return st;
+    if (steps == 0) break;
+    st = enqueue_steps(p, d, rb, ntiles, 0, 1, s);
+    if (st != L0CIM_OK) return st;
+    L0_HIP(hipEventRecord(e0, s));
+    st = enqueue_steps(p, d, rb, ntiles, 0, steps - 1, s);
+    if (st != L0CIM_OK) return st;
+    L0_HIP(hipEventRecord(e1, s));
+    L0_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    L0_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      best_rb = rb;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  p->rb = best_rb;
+  p->tuned = true;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[p->key] = best_rb;
+  return L0CIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+l0cim_status l0cim_batch_plan_create(int32_t count, const l0cim_instance* inst, const l0cim_cim_params* cim,
+                                     const l0cim_solve_params* sp, l0cim_batch_plan* out) {
+  if (!out || !inst || !cim || !sp) return set_error(L0CIM_ERR_ARG, "batch_plan_create: NULL pointer");
+  if (count <= 0) return set_error(L0CIM_ERR_SHAPE, "batch_plan_create: count must be positive");
+  if (cim->n_steps < 0 || !(cim->dt > 0) || !(cim->tau > 0) || !(cim->t_w > 0) ||
+      (cim->field != L0CIM_FIELD_CN && cim->field != L0CIM_FIELD_BN))
+    return set_error(L0CIM_ERR_ARG, "batch_plan_create: invalid CIM parameters");
+  if (sp->replicas < 1 || sp->replicas > 64) return set_error(L0CIM_ERR_ARG, "batch_plan_create: replicas must be 1..64");
+  if (sp->n_outer <= 0 || sp->n_outer >= (1 << 24) || sp->velo <= 0 || sp->cdp_iters < 0)
+    return set_error(L0CIM_ERR_ARG, "batch_plan_create: invalid outer schedule");
+  if (sp->cdp != L0CIM_CDP_JACOBI) return set_error(L0CIM_ERR_UNSUPPORTED, "batched CDP is Jacobi");
+  const l0cim_dtype jdt = l0cim_dtype(sp->j_dtype);
+  if (jdt != L0CIM_F32 && jdt != L0CIM_BF16 && jdt != L0CIM_FP8E4M3)
+    return set_error(L0CIM_ERR_UNSUPPORTED, "batched couplings: F32, BF16 or FP8E4M3");
+  auto* p = new l0cim_batch_plan_s();
+  p->count = count;
+  p->P = sp->replicas;
+  p->qb = p->P <= 16 ? 1 : (p->P <= 32 ? 2 : 4);
+  p->cim = *cim;
+  p->sp = *sp;
+  p->jdt = jdt;
+  p->inst.assign(inst, inst + count);
+  p->base.resize(count);
+  p->row_prefix.assign(count + 1, 0);
+  p->st_prefix.assign(count + 1, 0);
+  const size_t jsz = dtype_size(jdt);
+  for (int k = 0; k < count; ++k) {
+    const l0cim_instance& I = inst[k];
+    if (I.m <= 0 || I.n <= 0 || I.lda < I.n || I.n > 12288 || I.lda > (int64_t(1) << 31) ||
+        I.a_offset < 0 || I.y_offset < 0 || I.x_offset < 0) {
+      delete p;
+      return set_error(L0CIM_ERR_SHAPE, "batch_plan_create: instance %d has a bad shape or offset", k);
+    }
+    BInst b{};
+    b.n = I.n;
+    b.m = I.m;
+    b.ld = round_up_i(I.n, 32);
+    b.lda = int(I.lda);
+    b.oG = p->nG;
+    b.oJ = p->nG;
+    b.oV = p->nV;
+    b.oS = p->nS;
+    b.oSig = p->nSig;
+    b.oX = I.x_offset;
+    b.oA = I.a_offset;
+    b.oY = I.y_offset;
+    b.seed = I.seed;
+    p->nG += int64_t(b.n) * b.ld;
+    p->nV += b.ld;
+    p->nS += int64_t(p->P) * b.ld;
+    p->nSig += int64_t(p->P) * b.n;
+    p->max_tiles += (b.n + 63) / 64;
+    p->max_ld = b.ld > p->max_ld ? b.ld : p->max_ld;
+    p->max_n = b.n > p->max_n ? b.n : p->max_n;
+    p->row_prefix[k + 1] = p->row_prefix[k] + b.n;
+    p->st_prefix[k + 1] = p->st_prefix[k] + int64_t(p->P) * b.ld;
+    p->base[k] = b;
+  }
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align_up(bytes);
+    return at;
+  };
+  p->off.insts = take(count * sizeof(BInst));
+  p->off.tiles = take(size_t(p->max_tiles) * sizeof(BTile));
+  p->off.rowp = take((count + 1) * sizeof(int64_t));
+  p->off.stp = take((count + 1) * sizeof(int64_t));
+  p->off.eta = take(sizeof(double));
+  p->off.G = take(size_t(p->nG) * 4);
+  p->off.Gc = take(size_t(p->nG) * 4);
+  p->off.b = take(size_t(p->nV) * 4);
+  p->off.z = take(size_t(p->nV) * 4);
+  p->off.rs = take(size_t(p->nV) * 4);
+  p->off.J = take(size_t(p->nG) * jsz);
+  p->off.c = take(size_t(p->nS) * 4);
+  p->off.c2 = take(size_t(p->nS) * 4);
+  p->off.e = take(size_t(p->nS) * 4);
+  p->off.sig = take(size_t(p->nSig));
+  p->off.hpart = take(size_t(p->nSig) * sizeof(double));
+  p->off.chol = take(sp->final_refit_f64 ? chol_ws_bytes(p->max_n) : 0);
+  p->off.total = o;
+  p->key = shape_key(p);
+  *out = p;
+  return L0CIM_OK;
+}
+
+size_t l0cim_batch_plan_workspace_bytes(l0cim_batch_plan plan) { return plan ? plan->off.total : 0; }
+
+l0cim_status l0cim_batch_plan_info(l0cim_batch_plan plan, int32_t* rows_per_tile, int32_t* tiles,
+                                   int32_t* tuned) {
+  if (!plan) return set_error(L0CIM_ERR_ARG, "batch_plan_info: NULL plan");
+  int rb = plan->rb ? plan->rb : 2;
+  std::vector<BInst> insts;
+  std::vector<BTile> t;
+  tile_table(plan, rb, insts, t);
+  if (rows_per_tile) *rows_per_tile = 64 * rb;
+  if (tiles) *tiles = int32_t(t.size());
+  if (tuned) *tuned = plan->tuned ? 1 : 0;
+  return L0CIM_OK;
+}
+
+l0cim_status l0cim_batch_plan_destroy(l0cim_batch_plan plan) {
+  if (!plan) return L0CIM_OK;
+  if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+  if (plan->graph) (void)hipGraphDestroy(plan->graph);
+  if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
+  delete plan;
+  return L0CIM_OK;
+}
+
+l0cim_status l0cim_solve_batched(l0cim_batch_plan p, const float* A, const float* y, float* R, uint8_t* sigma,
+                                 l0cim_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+  if (!p) return set_error(L0CIM_ERR_ARG, "solve_batched: NULL plan");
+  if (!A || !y || !R || !sigma || !stats) return set_error(L0CIM_ERR_ARG, "solve_batched: NULL pointer");
+  if (!ws || ws_bytes < p->off.total)
+    return set_error(L0CIM_ERR_WORKSPACE, "solve_batched: workspace needs %zu bytes", p->off.total);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  BatchDev d = carve(p, ws, R, sigma, stats);
+  char* base = static_cast<char*>(ws);
+#define L0_TRY(x)                  \
+  do {                             \
+    l0cim_status _s = (x);         \
+    if (_s != L0CIM_OK) return _s; \
+  } while (0)
+  L0_HIP(hipMemcpyAsync(const_cast<int64_t*>(d.row_prefix), p->row_prefix.data(), (p->count + 1) * sizeof(int64_t),
+                        hipMemcpyHostToDevice, s));
+  L0_HIP(hipMemcpyAsync(const_cast<int64_t*>(d.st_prefix), p->st_prefix.data(), (p->count + 1) * sizeof(int64_t),
+                        hipMemcpyHostToDevice, s));
+  int ntiles = 0;
+  L0_TRY(upload_tables(p, d, p->rb ? p->rb : 2, s, &ntiles));
+  L0_TRY(launch_bstats_init(stats, p->count, s));
+  for (int k = 0; k < p->count; ++k) {
+    const BInst& I = p->base[k];
+    L0_TRY(launch_gram(L0CIM_F32, I.m, I.n, A + I.oA, I.lda, y + I.oY, d.G + I.oG, I.ld, d.b + I.oV, s));
+    L0_TRY(launch_r_init(L0CIM_F32, I.n, d.G + I.oG, I.ld, d.b + I.oV, nullptr, R + I.oX,
+                         &stats[k].status_bits, s));
+  }
+  const int64_t total_rows = p->row_prefix[p->count];
+  const int64_t total_state = p->st_prefix[p->count];
+  if (!p->tuned) {
+    L0_TRY(launch_bset_scalar(d.eta, p->sp.eta_init, s));
+    L0_TRY(launch_bcouplings(d, p->jdt, total_rows, s));
+    L0_TRY(launch_binit(d, p->P, 0, p->cim.c0_std, total_state, s));
+    L0_TRY(autotune(p, d, s));
+  }
+  L0_TRY(upload_tables(p, d, p->rb, s, &ntiles));
+  // graph of one CIM run (n_steps + 1 launches), rebuilt when the workspace or tile shape changes
+  const bool use_graph = p->cim.n_steps >= 16;
+  if (use_graph && (p->graph_ws != ws || p->graph_stats != stats || p->graph_rb != p->rb || !p->exec)) {
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+    if (!p->cap_stream) L0_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    L0_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    l0cim_status st = enqueue_steps(p, d, p->rb, ntiles, 0, p->cim.n_steps, p->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t ce = hipStreamEndCapture(p->cap_stream, &g);
+    if (st != L0CIM_OK) return st;
+    if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+    p->graph = g;
+    L0_HIP(hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0));
+    p->graph_ws = ws;
+    p->graph_stats = stats;
+    p->graph_rb = p->rb;
+  }
+  double eta = p->sp.eta_init;
+  for (int i = 0; i < p->sp.n_outer; ++i) {
+    double v = p->sp.eta_init * (1.0 - double(i) / double(p->sp.velo));
+    eta = v > p->sp.eta_end ? v : p->sp.eta_end;
+    L0_TRY(launch_bset_scalar(d.eta, eta, s));
+    L0_TRY(launch_bcouplings(d, p->jdt, total_rows, s));
+    L0_TRY(launch_binit(d, p->P, i, p->cim.c0_std, total_state, s));
+    {
+      ProfileScope prof(s);
+      if (use_graph) {
+        L0_HIP(hipGraphLaunch(p->exec, s));
+      } else {
+        L0_TRY(enqueue_steps(p, d, p->rb, ntiles, 0, p->cim.n_steps, s));
+      }
+    }
+    L0_TRY(launch_bselect(d, p->P, s));
+    L0_TRY(launch_bjacobi(d, p->max_ld, p->sp.dtc, p->sp.cdp_iters, s));
+  }
+  if (p->sp.final_refit_f64) {
+    void* cws = base + p->off.chol;
+    for (int k = 0; k < p->count; ++k) {
+      const BInst& I = p->base[k];
+      L0_TRY(launch_chol_refit(L0CIM_F32, I.n, d.G + I.oG, I.ld, d.b + I.oV, sigma + I.oX, R + I.oX,
+                               &stats[k].status_bits, cws, chol_ws_bytes(p->max_n), s));
+    }
+  }
+  L0_TRY(launch_bobjective(d, A, y, 0.5 * eta * eta, int64_t(p->cim.n_steps) * p->sp.n_outer, p->sp.n_outer, p->P,
+                           s));
+#undef L0_TRY
+  return L0CIM_OK;
+}
+
+}  // extern "C"
