@@ -72,7 +72,8 @@ typedef enum {
 typedef enum {
   L0CIM_LAUNCH_AUTO = 0,
   L0CIM_LAUNCH_RESIDENT = 1,
-  L0CIM_LAUNCH_STREAMED = 2
+  L0CIM_LAUNCH_STREAMED = 2,
+  L0CIM_LAUNCH_MATRIX = 3     /* FP32 state: J X on the matrix cores, one launch per step */
 } l0cim_launch;
 
 typedef enum {
@@ -101,8 +102,9 @@ typedef struct {
   double tau;         /* CAC target amplitude (1) */
   double c0_std;      /* std of the initial amplitudes (1e-2: variance 1e-4) */
   int32_t linear_j;   /* 1: linear term (-1 + p - j - c^2) (supporting info) */
-  int32_t launch;     /* 0: automatic; 1: resident (one persistent launch, J in LDS,
-                         error if it does not fit); 2: streamed (one launch per step) */
+  int32_t launch;     /* l0cim_launch: 0 automatic; 1 resident (one persistent launch, J on
+                         chip, error if it does not fit); 2 streamed (one launch per step);
+                         3 matrix cores (FP32 state, P <= 64) */
   int64_t spin_limit; /* bound on polls of one device wait; 0 = default (2^22) */
 } l0cim_cim_params;
 

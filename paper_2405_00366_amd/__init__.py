@@ -29,7 +29,7 @@ __all__ = [
 F32, F64, BF16, FP8E4M3 = 0, 1, 2, 3
 FIELD_CN, FIELD_BN = 0, 1
 CDP_JACOBI, CDP_CHOL_F64 = 0, 1
-LAUNCH_AUTO, LAUNCH_RESIDENT, LAUNCH_STREAMED = 0, 1, 2
+LAUNCH_AUTO, LAUNCH_RESIDENT, LAUNCH_STREAMED, LAUNCH_MATRIX = 0, 1, 2, 3
 
 ST_NONFINITE, ST_BLOWUP, ST_CHOL_RIDGE, ST_TINY_DIAG, ST_TIMEOUT = 1, 2, 4, 8, 16
 

@@ -99,7 +99,7 @@ l0cim_status check_cim(const l0cim_cim_params* p) {
   if (!(p->dt > 0.0) || !(p->tau > 0.0) || !(p->t_w > 0.0))
     return set_error(L0CIM_ERR_ARG, "dt, tau and t_w must be positive");
   if (p->spin_limit < 0) return set_error(L0CIM_ERR_ARG, "spin_limit < 0");
-  if (p->launch < L0CIM_LAUNCH_AUTO || p->launch > L0CIM_LAUNCH_STREAMED)
+  if (p->launch < L0CIM_LAUNCH_AUTO || p->launch > L0CIM_LAUNCH_MATRIX)
     return set_error(L0CIM_ERR_ARG, "unknown launch shape %d", p->launch);
   return L0CIM_OK;
 }

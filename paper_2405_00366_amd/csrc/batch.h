@@ -8,6 +8,7 @@ namespace l0 {
 // Device table entry of one instance (offsets in elements of each pool).
 struct BInst {
   int n, m, ld;          // spins, measurement rows, padded row length (multiple of 32)
+  int ldj;               // row stride of J (multiple of 32)
   int tile0, ntiles;     // row tiles of this instance in the tile table
   int lda;               // leading dimension of A
   int64_t oG;            // n x ld floats in the G (and compact-G) pools
@@ -18,6 +19,9 @@ struct BInst {
   int64_t oX;            // n elements of R and sigma in the caller's pools
   int64_t oA, oY;        // A (m x lda) and y (m) in the caller's pools
   uint64_t seed;
+  int alt;               // alternation index of this instance (serving form)
+  int pad0;
+  double eta;            // its threshold eta_alt (serving form)
 };
 
 struct BTile {
@@ -27,6 +31,8 @@ struct BTile {
 struct BStepArgs {
   int P, n_steps, linear_j, field;
   double dt, p_thr, d, t_c, t_w, K, j, beta, tau;
+  float* trace;          // optional: (k, c|e, q, r) for k < trace_steps (single instance)
+  int trace_steps;
 };
 
 // Device pointers of one batched solve (carved from the workspace).

@@ -123,6 +123,8 @@ BStepArgs step_args(const l0cim_batch_plan_s* p) {
   a.j = p->cim.j;
   a.beta = p->cim.beta;
   a.tau = p->cim.tau;
+  a.trace = nullptr;
+  a.trace_steps = 0;
   return a;
 }
 
@@ -252,6 +254,7 @@ l0cim_status l0cim_batch_plan_create(int32_t count, const l0cim_instance* inst, 
     b.n = I.n;
     b.m = I.m;
     b.ld = round_up_i(I.n, 32);
+    b.ldj = b.ld;
     b.lda = int(I.lda);
     b.oG = p->nG;
     b.oJ = p->nG;

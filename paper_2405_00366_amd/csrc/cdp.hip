@@ -3,7 +3,6 @@
 //    (parameter paragraph of the numerical experiments: dtc = 0.1, 100
 //    iterations).  Resident form: rows of G stay in LDS and the vector
 //    s = sigma o R travels through flag-carrying words, as in the CIM run.
-//  * FP64 least-squares refit on the support through a Cholesky factor.
 //  * eq. 3 objective and the per-solve report.
 #include "kernels.h"
 
@@ -142,150 +141,6 @@ __global__ void masked_copy_kernel(int n, const T* __restrict__ G, int64_t ldg, 
   s[r] = sigma[r] ? R[r] : T(0);
 }
 
-// ---------------------------------------------------------------------------
-// FP64 Cholesky refit on the support (single workgroup; the support size is
-// only known on the device).
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(1024)
-chol_refit_kernel(int n, const T* __restrict__ G, int64_t ldg, const T* __restrict__ b,
-                  const uint8_t* __restrict__ sigma, T* __restrict__ R, int* __restrict__ status,
-                  int* __restrict__ idx, double* __restrict__ L, double* __restrict__ w,
-                  int* __restrict__ kcount) {
-  __shared__ int cnt[1024];
-  __shared__ double red[1024];
-  __shared__ int sh_k, sh_bad;
-  __shared__ double sh_dmax, sh_ridge, sh_piv;
-  const int tid = threadIdx.x, bs = blockDim.x;
-  // 1. compact S in index order: contiguous chunk per thread + block scan.
-  const int chunk = (n + bs - 1) / bs;
-  const int lo = min(n, tid * chunk), hi = min(n, lo + chunk);
-  int c = 0;
-  for (int i = lo; i < hi; ++i) c += sigma[i] ? 1 : 0;
-  cnt[tid] = c;
-  __syncthreads();
-  if (tid == 0) {
-    int s = 0;
-    for (int t = 0; t < bs; ++t) {
-      int v = cnt[t];
-      cnt[t] = s;
-      s += v;
-    }
-    sh_k = s;
-  }
-  __syncthreads();
-  int pos = cnt[tid];
-  for (int i = lo; i < hi; ++i)
-    if (sigma[i]) idx[pos++] = i;
-  __syncthreads();
-  const int k = sh_k;
-  if (tid == 0) *kcount = k;
-  // 2. max diagonal of G_SS
-  double dm = 0.0;
-  for (int a = tid; a < k; a += bs) dm = fmax(dm, double(G[size_t(idx[a]) * ldg + idx[a]]));
-  red[tid] = dm;
-  __syncthreads();
-  for (int s = bs / 2; s > 0; s >>= 1) {
-    if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
-    __syncthreads();
-  }
-  if (tid == 0) {
-    sh_dmax = red[0];
-    sh_ridge = 0.0;
-  }
-  __syncthreads();
-  for (int attempt = 0; attempt < 2; ++attempt) {
-    // 3. L <- G_SS (+ ridge I), lower triangle, FP64
-    for (size_t e = tid; e < size_t(k) * k; e += bs) {
-      int a = int(e / k), bb = int(e - size_t(a) * k);
-      if (bb <= a) {
-        double v = double(G[size_t(idx[a]) * ldg + idx[bb]]);
-        if (a == bb) v += sh_ridge;
-        L[size_t(a) * k + bb] = v;
-      }
-    }
-    if (tid == 0) sh_bad = 0;
-    __syncthreads();
-    // 4. right-looking factorisation
-    for (int j = 0; j < k; ++j) {
-      if (tid == 0) {
-        double piv = L[size_t(j) * k + j];
-        if (!(piv > 1e-12 * sh_dmax)) sh_bad = 1;
-        sh_piv = sqrt(fmax(piv, 0.0));
-        L[size_t(j) * k + j] = sh_piv;
-      }
-      __syncthreads();
-      if (sh_bad) break;
-      const double ljj = sh_piv;
-      for (int a = j + 1 + tid; a < k; a += bs) L[size_t(a) * k + j] /= ljj;
-      __syncthreads();
-      const int m = k - j - 1;
-      for (size_t e = tid; e < size_t(m) * m; e += bs) {
-        int a = j + 1 + int(e / m), bb = j + 1 + int(e % m);
-        if (bb <= a) L[size_t(a) * k + bb] -= L[size_t(a) * k + j] * L[size_t(bb) * k + j];
-      }
-      __syncthreads();
-    }
-    if (!sh_bad) break;
-    if (attempt == 0) {
-      // ridge 1e-10 * tr(G_SS) / |S|
-      double tr = 0.0;
-      for (int a = tid; a < k; a += bs) tr += double(G[size_t(idx[a]) * ldg + idx[a]]);
-      red[tid] = tr;
-      __syncthreads();
-      if (tid == 0) {
-        double s = 0.0;
-        for (int t = 0; t < bs; ++t) s += red[t];
-        sh_ridge = 1e-10 * s / double(k);
-      }
-      __syncthreads();
-      if (tid == 0) raise_status(status, L0CIM_ST_CHOL_RIDGE);
-    }
-  }
-  // 5. forward substitution L w = b_S (column oriented)
-  for (int a = tid; a < k; a += bs) w[a] = double(b[idx[a]]);
-  __syncthreads();
-  for (int j = 0; j < k; ++j) {
-    if (tid == 0) w[j] /= L[size_t(j) * k + j];
-    __syncthreads();
-    const double wj = w[j];
-    for (int a = j + 1 + tid; a < k; a += bs) w[a] -= L[size_t(a) * k + j] * wj;
-    __syncthreads();
-  }
-  // 6. back substitution L^T x = w
-  for (int j = k - 1; j >= 0; --j) {
-    if (tid == 0) w[j] /= L[size_t(j) * k + j];
-    __syncthreads();
-    const double xj = w[j];
-    for (int a = tid; a < j; a += bs) w[a] -= L[size_t(j) * k + a] * xj;
-    __syncthreads();
-  }
-  for (int a = tid; a < k; a += bs) R[idx[a]] = T(w[a]);
-}
-
-// Off-support rows after the refit: R_r = (b_r - G_rS R_S) / G_rr.
-template <typename T>
-__global__ void __launch_bounds__(256)
-chol_offsupport_kernel(int n, const T* __restrict__ G, int64_t ldg, const T* __restrict__ b,
-                       const uint8_t* __restrict__ sigma, const int* __restrict__ idx,
-                       const int* __restrict__ kcount, const double* __restrict__ w, T* __restrict__ R,
-                       int* __restrict__ status) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int r = blockIdx.x * 4 + threadIdx.x / kWave;
-  if (r >= n) return;
-  const T d = G[size_t(r) * ldg + r];
-  const bool tiny = !(d >= T(1e-12));
-  if (sigma[r]) return;
-  const int k = *kcount;
-  double acc = 0.0;
-  for (int a = lane; a < k; a += kWave) acc += double(G[size_t(r) * ldg + idx[a]]) * w[a];
-  acc = wave_sum(acc);
-  if (lane == 0) {
-    if (tiny) raise_status(status, L0CIM_ST_TINY_DIAG);
-    R[r] = tiny ? T(0) : T((double(b[r]) - acc) / double(d));
-  }
-}
-
 // eq. 3 residual: one wavefront per measurement row.
 template <typename T>
 __global__ void __launch_bounds__(256)
@@ -417,42 +272,6 @@ l0cim_status launch_jacobi(l0cim_dtype dt, int n, const void* G, int64_t ldg, co
     return jacobi_typed<double>(n, (const double*)G, ldg, (const double*)b, sigma, dtc, iters,
                                 (double*)R, status, ws, s, spin_limit);
   return set_error(L0CIM_ERR_UNSUPPORTED, "update_r: dtype %d", int(dt));
-}
-
-size_t chol_ws_bytes(int n) {
-  return align_up(size_t(n) * sizeof(int)) + align_up(size_t(n) * n * sizeof(double)) +
-         align_up(size_t(n) * sizeof(double)) + kAlign;
-}
-
-l0cim_status launch_chol_refit(l0cim_dtype dt, int n, const void* G, int64_t ldg, const void* b,
-                               const uint8_t* sigma, void* R, int* status, void* ws, size_t ws_bytes,
-                               hipStream_t s) {
-  (void)ws_bytes;
-  char* p = static_cast<char*>(ws);
-  int* idx = reinterpret_cast<int*>(p);
-  p += align_up(size_t(n) * sizeof(int));
-  double* L = reinterpret_cast<double*>(p);
-  p += align_up(size_t(n) * n * sizeof(double));
-  double* w = reinterpret_cast<double*>(p);
-  p += align_up(size_t(n) * sizeof(double));
-  int* kc = reinterpret_cast<int*>(p);
-  if (dt == L0CIM_F32) {
-    hipLaunchKernelGGL(chol_refit_kernel<float>, dim3(1), dim3(1024), 0, s, n, (const float*)G, ldg,
-                       (const float*)b, sigma, (float*)R, status, idx, L, w, kc);
-    L0_LAUNCHED("chol_refit_kernel");
-    hipLaunchKernelGGL(chol_offsupport_kernel<float>, dim3((n + 3) / 4), dim3(256), 0, s, n,
-                       (const float*)G, ldg, (const float*)b, sigma, idx, kc, w, (float*)R, status);
-  } else if (dt == L0CIM_F64) {
-    hipLaunchKernelGGL(chol_refit_kernel<double>, dim3(1), dim3(1024), 0, s, n, (const double*)G, ldg,
-                       (const double*)b, sigma, (double*)R, status, idx, L, w, kc);
-    L0_LAUNCHED("chol_refit_kernel");
-    hipLaunchKernelGGL(chol_offsupport_kernel<double>, dim3((n + 3) / 4), dim3(256), 0, s, n,
-                       (const double*)G, ldg, (const double*)b, sigma, idx, kc, w, (double*)R, status);
-  } else {
-    return set_error(L0CIM_ERR_UNSUPPORTED, "chol refit: dtype %d", int(dt));
-  }
-  L0_LAUNCHED("chol_offsupport_kernel");
-  return L0CIM_OK;
 }
 
 size_t objective_ws_bytes(int m) { return align_up(size_t((m + 3) / 4) * sizeof(double)); }

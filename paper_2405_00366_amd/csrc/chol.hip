@@ -1,0 +1,392 @@
+// FP64 least-squares refit of R on the support (the R-minimisation of eq. 3
+// with sigma fixed): R_S = G_SS^-1 b_S through a Cholesky factor, and
+// R_r = (b_r - G_rS R_S) / G_rr off the support.
+//
+// The support size is only known on the device, so the whole refit is one
+// cooperative launch: the support is compacted, G_SS is copied into an FP64
+// buffer padded to a multiple of 64 with identity, and a blocked
+// right-looking factorisation (64 x 64 tiles: diagonal block in one
+// workgroup, panel rows and trailing tiles spread over all workgroups) is
+// followed by blocked forward and back substitution.  Phases are separated
+// by a bounded grid barrier.  A pivot <= 1e-12 * max diag(G_SS) restarts the
+// factorisation once with a ridge of 1e-10 * tr(G_SS) / |S|.
+#include "kernels.h"
+
+namespace l0 {
+namespace {
+
+constexpr int NB = 64;
+constexpr int BS = 256;
+constexpr int64_t kBarrierLimit = int64_t(1) << 24;
+
+// control words: barrier count and generation, abort, k, and one failure
+// flag per attempt (never reset, so no workgroup can miss a flag)
+enum { C_COUNT = 0, C_GEN = 1, C_ABORT = 2, C_K = 3, C_BAD0 = 4, C_BAD1 = 5 };
+
+// Bounded grid barrier for a cooperative launch (every workgroup resident).
+__device__ bool grid_sync(int* ctl, int nblocks) {
+  __shared__ int ok_sh;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    __threadfence();
+    const int g = __hip_atomic_load(&ctl[C_GEN], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const int arrived = __hip_atomic_fetch_add(&ctl[C_COUNT], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1;
+    if (arrived == nblocks) {
+      __hip_atomic_store(&ctl[C_COUNT], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctl[C_GEN], g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      int64_t polls = 0;
+      while (__hip_atomic_load(&ctl[C_GEN], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        if (++polls > kBarrierLimit ||
+            __hip_atomic_load(&ctl[C_ABORT], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          ok = 0;
+          __hip_atomic_store(&ctl[C_ABORT], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    __threadfence();
+    ok_sh = ok;
+  }
+  __syncthreads();
+  return ok_sh != 0;
+}
+
+#define L0_GRID_SYNC()                                              \
+  do {                                                              \
+    if (!grid_sync(ctl, nwg)) {                                     \
+      if (tid == 0) raise_status(status, L0CIM_ST_TIMEOUT);         \
+      return;                                                       \
+    }                                                               \
+  } while (0)
+
+template <typename T>
+__global__ void __launch_bounds__(BS)
+chol_kernel(int n, const T* __restrict__ G, int64_t ldg, const T* __restrict__ b,
+            const uint8_t* __restrict__ sigma, T* __restrict__ R, int* __restrict__ status,
+            int* __restrict__ idx, double* __restrict__ L, double* __restrict__ w, int* __restrict__ ctl,
+            double* __restrict__ red) {
+  __shared__ double sA[NB][NB + 1];
+  __shared__ double sB[NB][NB + 1];
+  __shared__ double sv[NB];
+  __shared__ int cnt[BS];
+  __shared__ int flag;
+  const int tid = threadIdx.x, wg = blockIdx.x, nwg = gridDim.x;
+  const int lane = tid & 63, wv = tid >> 6;
+
+  // 1. compact the support (workgroup 0), max and sum of its diagonal
+  if (wg == 0) {
+    const int chunk = (n + BS - 1) / BS;
+    const int lo = min(n, tid * chunk), hi = min(n, lo + chunk);
+    int c = 0;
+    for (int i = lo; i < hi; ++i) c += sigma[i] ? 1 : 0;
+    cnt[tid] = c;
+    __syncthreads();
+    if (tid == 0) {
+      int s = 0;
+      for (int t = 0; t < BS; ++t) {
+        const int v = cnt[t];
+        cnt[t] = s;
+        s += v;
+      }
+      ctl[C_K] = s;
+    }
+    __syncthreads();
+    int pos = cnt[tid];
+    for (int i = lo; i < hi; ++i)
+      if (sigma[i]) idx[pos++] = i;
+    __syncthreads();
+    if (tid == 0) {
+      const int k = ctl[C_K];
+      double dm = 0.0, tr = 0.0;
+      for (int a = 0; a < k; ++a) {
+        const double d = double(G[size_t(idx[a]) * ldg + idx[a]]);
+        dm = fmax(dm, d);
+        tr += d;
+      }
+      red[0] = dm;
+      red[1] = tr;
+    }
+  }
+  L0_GRID_SYNC();
+  const int k = ctl[C_K];
+  const int kp = (k + NB - 1) / NB * NB;
+  const int m = kp / NB;
+  const double dmax = red[0];
+  double ridge = 0.0;
+  bool ridged = false;
+
+  for (int attempt = 0; attempt < 2 && m > 0; ++attempt) {
+    // 2. L <- G_SS (+ ridge I), padded with identity; lower triangle
+    for (size_t e = size_t(wg) * BS + tid; e < size_t(kp) * kp; e += size_t(nwg) * BS) {
+      const int i = int(e / kp), j = int(e - size_t(i) * kp);
+      if (j > i) continue;
+      double v;
+      if (i < k && j < k) v = double(G[size_t(idx[i]) * ldg + idx[j]]) + (i == j ? ridge : 0.0);
+      else v = (i == j) ? 1.0 : 0.0;
+      L[size_t(i) * kp + j] = v;
+    }
+    L0_GRID_SYNC();
+    bool bad = false;
+    for (int kb = 0; kb < m; ++kb) {
+      const int k0 = kb * NB;
+      // 3a. diagonal block, one workgroup
+      if (wg == 0) {
+        for (int e = tid; e < NB * NB; e += BS) {
+          const int i = e / NB, j = e % NB;
+          sA[i][j] = j <= i ? L[size_t(k0 + i) * kp + k0 + j] : 0.0;
+        }
+        if (tid == 0) flag = 0;
+        __syncthreads();
+        for (int j = 0; j < NB; ++j) {
+          if (tid == 0) {
+            const double piv = sA[j][j];
+            if (!(piv > 1e-12 * dmax) && k0 + j < k) flag = 1;
+            sA[j][j] = sqrt(fmax(piv, 1e-300));
+          }
+          __syncthreads();
+          if (flag) break;
+          for (int i = j + 1 + tid; i < NB; i += BS) sA[i][j] /= sA[j][j];
+          __syncthreads();
+          const int r = NB - j - 1;
+          for (int e = tid; e < r * r; e += BS) {
+            const int i = j + 1 + e / r, l = j + 1 + e % r;
+            if (l <= i) sA[i][l] -= sA[i][j] * sA[l][j];
+          }
+          __syncthreads();
+        }
+        if (flag) {
+          if (tid == 0) ctl[C_BAD0 + attempt] = 1;
+        } else {
+          for (int e = tid; e < NB * NB; e += BS) {
+            const int i = e / NB, j = e % NB;
+            if (j <= i) L[size_t(k0 + i) * kp + k0 + j] = sA[i][j];
+          }
+        }
+      }
+      L0_GRID_SYNC();
+      if (ctl[C_BAD0 + attempt]) {
+        bad = true;
+        break;
+      }
+      // 3b. panel: X L_kk^T = A_ik for every row block below
+      for (int ib = kb + 1 + wg; ib < m; ib += nwg) {
+        for (int e = tid; e < NB * NB; e += BS) {
+          const int i = e / NB, j = e % NB;
+          sA[i][j] = j <= i ? L[size_t(k0 + i) * kp + k0 + j] : 0.0;
+          sB[i][j] = L[size_t(ib * NB + i) * kp + k0 + j];
+        }
+        __syncthreads();
+        if (tid < NB) {
+          const int i = tid;
+          for (int j = 0; j < NB; ++j) {
+            double x = sB[i][j];
+            for (int l = 0; l < j; ++l) x -= sB[i][l] * sA[j][l];
+            sB[i][j] = x / sA[j][j];
+          }
+        }
+        __syncthreads();
+        for (int e = tid; e < NB * NB; e += BS) {
+          const int i = e / NB, j = e % NB;
+          L[size_t(ib * NB + i) * kp + k0 + j] = sB[i][j];
+        }
+        __syncthreads();
+      }
+      L0_GRID_SYNC();
+      // 3c. trailing update of the lower blocks (i, j), kb < j <= i < m
+      const int mt = m - kb - 1;
+      const int ntile = mt * (mt + 1) / 2;
+      for (int t = wg; t < ntile; t += nwg) {
+        int i = 0;
+        while ((i + 1) * (i + 2) / 2 <= t) ++i;
+        const int j = t - i * (i + 1) / 2;
+        const int bi = kb + 1 + i, bj = kb + 1 + j;
+        for (int e = tid; e < NB * NB; e += BS) {
+          const int r = e / NB, c = e % NB;
+          sA[r][c] = L[size_t(bi * NB + r) * kp + k0 + c];
+          sB[r][c] = L[size_t(bj * NB + r) * kp + k0 + c];
+        }
+        __syncthreads();
+        const int tr = tid / 16, tc = tid % 16;
+        double acc[4][4] = {};
+        for (int l = 0; l < NB; ++l) {
+          double a4[4], b4[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            a4[u] = sA[tr + 16 * u][l];
+            b4[u] = sB[tc + 16 * u][l];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] = fma(a4[u], b4[v], acc[u][v]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = tr + 16 * u, c = tc + 16 * v;
+            if (bi != bj || c <= r) L[size_t(bi * NB + r) * kp + bj * NB + c] -= acc[u][v];
+          }
+        __syncthreads();
+      }
+      L0_GRID_SYNC();
+    }
+    if (!bad) break;
+    // ridge and retry once
+    ridged = true;
+    ridge = 1e-10 * red[1] / double(k);
+  }
+
+  // 4. forward substitution L v = b_S, then back substitution L^T x = v
+  for (size_t a = size_t(wg) * BS + tid; a < size_t(kp); a += size_t(nwg) * BS)
+    w[a] = a < size_t(k) ? double(b[idx[a]]) : 0.0;
+  L0_GRID_SYNC();
+  for (int kb = 0; kb < m; ++kb) {
+    const int k0 = kb * NB;
+    if (wg == 0) {
+      for (int e = tid; e < NB * NB; e += BS) {
+        const int i = e / NB, j = e % NB;
+        sA[i][j] = j <= i ? L[size_t(k0 + i) * kp + k0 + j] : 0.0;
+      }
+      if (tid < NB) sv[tid] = w[k0 + tid];
+      __syncthreads();
+      for (int j = 0; j < NB; ++j) {
+        if (tid == 0) sv[j] /= sA[j][j];
+        __syncthreads();
+        for (int i = j + 1 + tid; i < NB; i += BS) sv[i] -= sA[i][j] * sv[j];
+        __syncthreads();
+      }
+      if (tid < NB) w[k0 + tid] = sv[tid];
+    }
+    L0_GRID_SYNC();
+    for (int ib = kb + 1 + wg; ib < m; ib += nwg) {
+      if (tid < NB) sv[tid] = w[k0 + tid];
+      __syncthreads();
+      if (tid < NB) {
+        double acc = 0.0;
+        const double* Lr = L + size_t(ib * NB + tid) * kp + k0;
+        for (int l = 0; l < NB; ++l) acc = fma(Lr[l], sv[l], acc);
+        w[ib * NB + tid] -= acc;
+      }
+      __syncthreads();
+    }
+    L0_GRID_SYNC();
+  }
+  for (int kb = m - 1; kb >= 0; --kb) {
+    const int k0 = kb * NB;
+    if (wg == 0) {
+      for (int e = tid; e < NB * NB; e += BS) {
+        const int i = e / NB, j = e % NB;
+        sA[i][j] = j <= i ? L[size_t(k0 + i) * kp + k0 + j] : 0.0;
+      }
+      if (tid < NB) sv[tid] = w[k0 + tid];
+      __syncthreads();
+      for (int j = NB - 1; j >= 0; --j) {
+        if (tid == 0) sv[j] /= sA[j][j];
+        __syncthreads();
+        for (int i = tid; i < j; i += BS) sv[i] -= sA[j][i] * sv[j];
+        __syncthreads();
+      }
+      if (tid < NB) w[k0 + tid] = sv[tid];
+    }
+    L0_GRID_SYNC();
+    for (int ib = wg; ib < kb; ib += nwg) {
+      if (tid < NB) sv[tid] = w[k0 + tid];
+      __syncthreads();
+      if (tid < NB) {
+        double acc = 0.0;
+        for (int l = 0; l < NB; ++l) acc = fma(L[size_t(k0 + l) * kp + ib * NB + tid], sv[l], acc);
+        w[ib * NB + tid] -= acc;
+      }
+      __syncthreads();
+    }
+    L0_GRID_SYNC();
+  }
+
+  // 5. R on the support, and the off-support rows
+  for (size_t a = size_t(wg) * BS + tid; a < size_t(k); a += size_t(nwg) * BS) R[idx[a]] = T(w[a]);
+  int bits = 0;
+  for (int r = wg * (BS / 64) + wv; r < n; r += nwg * (BS / 64)) {
+    const T d = G[size_t(r) * ldg + r];
+    const bool tiny = !(d >= T(1e-12));
+    if (tiny) bits |= L0CIM_ST_TINY_DIAG;
+    if (sigma[r]) continue;
+    double acc = 0.0;
+    for (int a = lane; a < k; a += 64) acc += double(G[size_t(r) * ldg + idx[a]]) * w[a];
+    acc = wave_sum(acc);
+    if (lane == 0) R[r] = tiny ? T(0) : T((double(b[r]) - acc) / double(d));
+  }
+  if (ridged && wg == 0 && tid == 0) bits |= L0CIM_ST_CHOL_RIDGE;
+  if (bits && lane == 0) raise_status(status, bits);
+}
+
+struct CholLayout {
+  size_t idx, L, w, ctl, red, total;
+};
+
+CholLayout chol_layout(int n) {
+  const size_t np = size_t(n + NB - 1) / NB * NB;
+  CholLayout c;
+  size_t o = 0;
+  auto take = [&](size_t bb) {
+    size_t at = o;
+    o += align_up(bb);
+    return at;
+  };
+  c.idx = take(size_t(n) * sizeof(int));
+  c.L = take(np * np * sizeof(double));
+  c.w = take(np * sizeof(double));
+  c.ctl = take(8 * sizeof(int));
+  c.red = take(4 * sizeof(double));
+  c.total = o;
+  return c;
+}
+
+__global__ void chol_ctl_clear_kernel(int* ctl) {
+  if (threadIdx.x < 8) ctl[threadIdx.x] = 0;
+}
+
+template <typename T>
+l0cim_status chol_typed(int n, const T* G, int64_t ldg, const T* b, const uint8_t* sigma, T* R, int* status,
+                        void* ws, hipStream_t s) {
+  DeviceInfo dev;
+  l0cim_status st = device_info(&dev);
+  if (st != L0CIM_OK) return st;
+  const CholLayout c = chol_layout(n);
+  char* base = static_cast<char*>(ws);
+  int* idx = reinterpret_cast<int*>(base + c.idx);
+  double* L = reinterpret_cast<double*>(base + c.L);
+  double* w = reinterpret_cast<double*>(base + c.w);
+  int* ctl = reinterpret_cast<int*>(base + c.ctl);
+  double* red = reinterpret_cast<double*>(base + c.red);
+  hipLaunchKernelGGL(chol_ctl_clear_kernel, dim3(1), dim3(64), 0, s, ctl);
+  L0_LAUNCHED("chol_ctl_clear_kernel");
+  int per_cu = 0;
+  L0_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(chol_kernel<T>), BS, 0));
+  int grid = dev.cu_count * (per_cu > 0 ? 1 : 0);
+  if (grid < 1) return set_error(L0CIM_ERR_HIP, "chol refit: kernel does not fit on a CU");
+  int nn = n;
+  void* args[] = {&nn, &G, &ldg, &b, &sigma, &R, &status, &idx, &L, &w, &ctl, &red};
+  L0_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(chol_kernel<T>), dim3(grid), dim3(BS), args, 0, s));
+  return L0CIM_OK;
+}
+
+}  // namespace
+
+size_t chol_ws_bytes(int n) { return chol_layout(n).total; }
+
+l0cim_status launch_chol_refit(l0cim_dtype dt, int n, const void* G, int64_t ldg, const void* b,
+                               const uint8_t* sigma, void* R, int* status, void* ws, size_t ws_bytes,
+                               hipStream_t s) {
+  (void)ws_bytes;
+  if (dt == L0CIM_F32)
+    return chol_typed<float>(n, (const float*)G, ldg, (const float*)b, sigma, (float*)R, status, ws, s);
+  if (dt == L0CIM_F64)
+    return chol_typed<double>(n, (const double*)G, ldg, (const double*)b, sigma, (double*)R, status, ws, s);
+  return set_error(L0CIM_ERR_UNSUPPORTED, "chol refit: dtype %d", int(dt));
+}
+
+}  // namespace l0

@@ -20,10 +20,16 @@ l0cim_status launch_r_init(l0cim_dtype dt, int n, const void* G, int64_t ldg, co
 
 // ---- CIM run ---------------------------------------------------------------
 size_t mfcim_ws_bytes(l0cim_dtype dt, int n, int P);
+size_t matrix_ws_offset(int n, int P);
 l0cim_status launch_mfcim(l0cim_dtype dt, int n, int P, l0cim_dtype jdt, const void* J, int64_t ldj,
                           const float* rscale, const void* z, const CimArgs& a, void* c, void* e,
                           uint8_t* sigma, double* H, void* trace, int* status, void* ws,
                           size_t ws_bytes, hipStream_t s);
+size_t matrix_ws_bytes(int n, int P, size_t jsize);
+bool matrix_supported(int n, int P, int64_t ldj);
+l0cim_status launch_matrix_run(int n, int P, l0cim_dtype jdt, const void* J, int64_t ldj, const float* rscale,
+                               const float* z, const CimArgs& a, float* c, float* e, uint8_t* sigma, double* H,
+                               float* trace, int* status, void* ws, hipStream_t s, int rb_hint);
 l0cim_status launch_select(int n, int P, const double* H, const uint8_t* sigma, uint8_t* out,
                            int32_t* q_out, double* H_out, hipStream_t s);
 

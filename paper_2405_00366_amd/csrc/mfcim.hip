@@ -12,6 +12,8 @@
 //    exchange stays in LDS.
 //  * cim_stream_step_kernel: one launch per Euler step, J streamed from HBM,
 //    for couplings too large to stay on chip.
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace l0 {
@@ -485,11 +487,30 @@ l0cim_status run_typed(int n, int P, const JT* J, int64_t ldj, const float* rsca
   RunWs w = carve_run_ws<T>(ws, n, P);
 
   // Launch shape.  Small problems run in one workgroup with everything in
-  // LDS; one FP32 replica keeps its couplings in registers; otherwise rows of
-  // J stay in LDS when they fit; otherwise J is streamed every step.
+  // LDS; one FP32 replica keeps its couplings in registers; a few replicas
+  // keep rows of J in LDS when they fit; many FP32 replicas stream J through
+  // the matrix cores; otherwise J is streamed every step by the vector units.
   int rpw = 0, grid = 0, block = 256;
   size_t lds = 0;
   const int rpw_cu = (n + dev.cu_count - 1) / dev.cu_count;
+  if constexpr (sizeof(T) == 4) {
+    const bool small = n <= 256 && resident_layout<T, JT>(n, P, n).total <= size_t(dev.max_lds);
+    const bool lds_fits = resident_layout<T, JT>(n, P, rpw_cu).total <= size_t(dev.max_lds);
+    const bool want = a.launch == L0CIM_LAUNCH_MATRIX ||
+                      (a.launch == L0CIM_LAUNCH_AUTO && P >= 2 && !small && !(lds_fits && P <= 4));
+    if (want) {
+      l0cim_dtype jdt = std::is_same<JT, float>::value ? L0CIM_F32
+                        : (sizeof(JT) == 2 ? L0CIM_BF16 : L0CIM_FP8E4M3);
+      if (matrix_supported(n, P, ldj))
+        return launch_matrix_run(n, P, jdt, J, ldj, rscale, z, a, c, e, sigma, H, trace, status,
+                                 static_cast<char*>(ws) + matrix_ws_offset(n, P), s, 0);
+      if (a.launch == L0CIM_LAUNCH_MATRIX)
+        return set_error(L0CIM_ERR_UNSUPPORTED, "mfcim_run: matrix launch needs P <= 64 and ldj %% 32 == 0");
+    }
+  } else {
+    if (a.launch == L0CIM_LAUNCH_MATRIX)
+      return set_error(L0CIM_ERR_UNSUPPORTED, "mfcim_run: matrix launch needs FP32 state");
+  }
   if (a.launch != L0CIM_LAUNCH_STREAMED) {
     const size_t whole = resident_layout<T, JT>(n, P, n).total;
     if (n <= 256 && whole <= size_t(dev.max_lds)) {
@@ -607,11 +628,22 @@ l0cim_status run_field(int n, int P, const void* J, int64_t ldj, const float* rs
 
 }  // namespace
 
-size_t mfcim_ws_bytes(l0cim_dtype dt, int n, int P) {
+// Workspace of a run: the exchange words, the abort word, per-workgroup
+// energies and the streamed ping-pong copy, followed (FP32 state) by the
+// matrix-core run's tables and padded state.
+static size_t base_ws_bytes(l0cim_dtype dt, int n, int P) {
   size_t ts = dtype_size(dt);
   size_t words = (dt == L0CIM_F64) ? 2 : 1;
   return align_up(size_t(2) * P * n * words * sizeof(uint64_t)) + kAlign +
          align_up(size_t(n) * P * sizeof(double)) + align_up(size_t(P) * n * ts);
+}
+
+size_t matrix_ws_offset(int n, int P) { return base_ws_bytes(L0CIM_F32, n, P); }
+
+size_t mfcim_ws_bytes(l0cim_dtype dt, int n, int P) {
+  size_t b = base_ws_bytes(dt, n, P);
+  if (dt == L0CIM_F32 && P <= 64) b += matrix_ws_bytes(n, P, 4);
+  return b;
 }
 
 l0cim_status launch_mfcim(l0cim_dtype dt, int n, int P, l0cim_dtype jdt, const void* J, int64_t ldj,

@@ -1,0 +1,227 @@
+// Single-instance CIM run on the matrix cores: the batched MFMA step kernel
+// applied to a one-instance table.  Used when several replicas make J X a
+// dense product and the couplings are streamed every step (for example the
+// MRI-shaped workload, N = 16384 with 64 replicas).  The instance and tile
+// tables and the padded copies of the state are written by a setup kernel,
+// so the whole run is a sequence of kernel launches on the caller's stream.
+#include "batch.h"
+
+namespace l0 {
+namespace {
+
+constexpr int kLd = 32;
+
+__global__ void __launch_bounds__(256)
+mat_setup_kernel(BInst I, BTile* __restrict__ tiles, int ntiles, int tr, BInst* __restrict__ inst_out,
+                 double* __restrict__ eta_out, double eta, const float* __restrict__ rscale,
+                 float* __restrict__ rs, const float* __restrict__ z_in, float* __restrict__ z,
+                 const float* __restrict__ c_in, const float* __restrict__ e_in, float* __restrict__ c,
+                 float* __restrict__ c2, float* __restrict__ e, int n, int P, int ld) {
+  const size_t gid = blockIdx.x * size_t(256) + threadIdx.x;
+  const size_t stride = size_t(gridDim.x) * 256;
+  if (gid == 0) {
+    *inst_out = I;
+    *eta_out = eta;
+  }
+  for (size_t t = gid; t < size_t(ntiles); t += stride) tiles[t] = BTile{0, int(t) * tr};
+  for (size_t i = gid; i < size_t(ld); i += stride) {
+    rs[i] = (i < size_t(n) && rscale) ? rscale[i] : 1.0f;
+    z[i] = i < size_t(n) ? z_in[i] : 0.0f;
+  }
+  for (size_t i = gid; i < size_t(P) * ld; i += stride) {
+    const size_t q = i / ld, r = i - q * ld;
+    const bool in = r < size_t(n);
+    c[i] = in ? c_in[q * n + r] : 0.0f;
+    c2[i] = 0.0f;
+    e[i] = in ? e_in[q * n + r] : 0.0f;
+  }
+}
+
+template <typename JT>
+__global__ void __launch_bounds__(256)
+mat_copyJ_kernel(const JT* __restrict__ J, int64_t ldj, JT* __restrict__ Jp, int n, int ld) {
+  const int r = blockIdx.y;
+  for (int j = blockIdx.x * 256 + threadIdx.x; j < ld; j += gridDim.x * 256)
+    Jp[size_t(r) * ld + j] = j < n ? J[size_t(r) * ldj + j] : JT(0.0f);
+}
+
+__global__ void __launch_bounds__(256)
+mat_finish_kernel(const float* __restrict__ cf, const float* __restrict__ ef, float* __restrict__ c,
+                  float* __restrict__ e, int n, int P, int ld) {
+  for (size_t i = blockIdx.x * size_t(256) + threadIdx.x; i < size_t(P) * n; i += size_t(gridDim.x) * 256) {
+    const size_t q = i / n, r = i - q * n;
+    c[i] = cf[q * ld + r];
+    e[i] = ef[q * ld + r];
+  }
+}
+
+// H_q = sum over spins (in order) of the eq. 4 terms of replica q.
+__global__ void mat_hsum_kernel(const double* __restrict__ hrow, int n, int P, double* __restrict__ H) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= P) return;
+  double h = 0.0;
+  for (int r = 0; r < n; ++r) h += hrow[size_t(q) * n + r];
+  H[q] = h;
+}
+
+struct MatLayout {
+  size_t inst, tiles, eta, rs, z, c, c2, e, hrow, J, total;
+};
+
+MatLayout mat_layout(int n, int P, size_t jsize, bool copyJ) {
+  const int ld = (n + kLd - 1) / kLd * kLd;
+  const size_t ntiles = size_t((n + 63) / 64);
+  MatLayout L;
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    size_t at = o;
+    o += align_up(b);
+    return at;
+  };
+  L.inst = take(sizeof(BInst));
+  L.tiles = take(ntiles * sizeof(BTile));
+  L.eta = take(sizeof(double));
+  L.rs = take(size_t(ld) * 4);
+  L.z = take(size_t(ld) * 4);
+  L.c = take(size_t(P) * ld * 4);
+  L.c2 = take(size_t(P) * ld * 4);
+  L.e = take(size_t(P) * ld * 4);
+  L.hrow = take(size_t(P) * n * 8);
+  L.J = take(copyJ ? size_t(n) * ld * jsize : 0);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+size_t matrix_ws_bytes(int n, int P, size_t jsize) {
+  return mat_layout(n, P, jsize, n % kLd != 0).total;
+}
+
+bool matrix_supported(int n, int P, int64_t ldj) {
+  return P >= 1 && P <= 64 && (n % kLd != 0 || ldj % kLd == 0);
+}
+
+l0cim_status launch_matrix_run(int n, int P, l0cim_dtype jdt, const void* J, int64_t ldj, const float* rscale,
+                               const float* z, const CimArgs& a, float* c, float* e, uint8_t* sigma, double* H,
+                               float* trace, int* status, void* ws, hipStream_t s, int rb_hint) {
+  DeviceInfo dev;
+  l0cim_status st = device_info(&dev);
+  if (st != L0CIM_OK) return st;
+  const int ld = (n + kLd - 1) / kLd * kLd;
+  const bool copyJ = (ldj % kLd) != 0;
+  if (copyJ && n % kLd == 0)
+    return set_error(L0CIM_ERR_UNSUPPORTED, "matrix run: leading dimension %lld of J is not a multiple of 32",
+                     (long long)ldj);
+  const size_t jsize = dtype_size(jdt);
+  const MatLayout Lw = mat_layout(n, P, jsize, copyJ);
+  char* b = static_cast<char*>(ws);
+  BInst* dinst = reinterpret_cast<BInst*>(b + Lw.inst);
+  BTile* dtiles = reinterpret_cast<BTile*>(b + Lw.tiles);
+  double* deta = reinterpret_cast<double*>(b + Lw.eta);
+  float* drs = reinterpret_cast<float*>(b + Lw.rs);
+  float* dz = reinterpret_cast<float*>(b + Lw.z);
+  float* dc = reinterpret_cast<float*>(b + Lw.c);
+  float* dc2 = reinterpret_cast<float*>(b + Lw.c2);
+  float* de = reinterpret_cast<float*>(b + Lw.e);
+  double* dh = reinterpret_cast<double*>(b + Lw.hrow);
+  const void* Jm = J;
+  int64_t ldm = ldj;
+  if (copyJ) {
+    void* Jp = b + Lw.J;
+    dim3 g((ld + 255) / 256, n);
+    if (jdt == L0CIM_F32)
+      hipLaunchKernelGGL(mat_copyJ_kernel<float>, g, dim3(256), 0, s, (const float*)J, ldj, (float*)Jp, n, ld);
+    else if (jdt == L0CIM_BF16)
+      hipLaunchKernelGGL(mat_copyJ_kernel<__hip_bfloat16>, g, dim3(256), 0, s, (const __hip_bfloat16*)J, ldj,
+                         (__hip_bfloat16*)Jp, n, ld);
+    else
+      hipLaunchKernelGGL(mat_copyJ_kernel<__hip_fp8_e4m3>, g, dim3(256), 0, s, (const __hip_fp8_e4m3*)J, ldj,
+                         (__hip_fp8_e4m3*)Jp, n, ld);
+    L0_LAUNCHED("mat_copyJ_kernel");
+    Jm = Jp;
+    ldm = ld;
+  }
+  // Tile shape: the largest row block that still gives every CU two tiles.
+  int rb = 1;
+  if (rb_hint == 1 || rb_hint == 2 || rb_hint == 4) rb = rb_hint;
+  else
+    for (int cand : {4, 2}) {
+      if ((n + 64 * cand - 1) / (64 * cand) >= 2 * dev.cu_count) {
+        rb = cand;
+        break;
+      }
+    }
+  const int qb = P <= 16 ? 1 : (P <= 32 ? 2 : 4);
+  const int tr = 64 * rb;
+  const int ntiles = (n + tr - 1) / tr;
+  BInst I{};
+  I.n = n;
+  I.ld = ld;
+  I.ldj = int(ldm);
+  I.tile0 = 0;
+  I.ntiles = ntiles;
+  {
+    size_t work = size_t(P) * ld;
+    int blocks = int((work + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(mat_setup_kernel, dim3(blocks), dim3(256), 0, s, I, dtiles, ntiles, tr, dinst, deta, a.eta,
+                       rscale, drs, z, dz, c, e, dc, dc2, de, n, P, ld);
+    L0_LAUNCHED("mat_setup_kernel");
+  }
+  const void* fn = batch_step_kernel(jdt, a.field, qb, rb);
+  if (!fn) return set_error(L0CIM_ERR_UNSUPPORTED, "matrix run: no kernel for this shape");
+  BStepArgs sa;
+  sa.P = P;
+  sa.n_steps = a.n_steps;
+  sa.linear_j = a.linear_j;
+  sa.field = a.field;
+  sa.dt = a.dt;
+  sa.p_thr = a.p_thr;
+  sa.d = a.d;
+  sa.t_c = a.t_c;
+  sa.t_w = a.t_w;
+  sa.K = a.K;
+  sa.j = a.j;
+  sa.beta = a.beta;
+  sa.tau = a.tau;
+  sa.trace = trace;
+  sa.trace_steps = a.trace_steps;
+  int dummy_status = 0;
+  (void)dummy_status;
+  {
+    ProfileScope prof(s);
+    for (int k = 0; k <= a.n_steps; ++k) {
+      const BTile* tp = dtiles;
+      const BInst* ip = dinst;
+      const float* cin = (k & 1) ? dc2 : dc;
+      float* cout = (k & 1) ? dc : dc2;
+      const float* rsp = drs;
+      const float* zp = dz;
+      float* ep = de;
+      uint8_t* sg = sigma;
+      double* hp = dh;
+      const double* etap = deta;
+      int kk = k;
+      int* stp = status;
+      void* args[] = {&tp, &ip, &Jm, &zp, &rsp, &cin, &cout, &ep, &sg, &hp, &sa, &kk, &etap, &stp};
+      L0_HIP(hipLaunchKernel(fn, dim3(ntiles), dim3(256), args, 0, s));
+    }
+  }
+  const float* cf = (a.n_steps & 1) ? dc2 : dc;
+  {
+    size_t work = size_t(P) * n;
+    int blocks = int((work + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(mat_finish_kernel, dim3(blocks), dim3(256), 0, s, cf, de, c, e, n, P, ld);
+    L0_LAUNCHED("mat_finish_kernel");
+  }
+  if (H) {
+    hipLaunchKernelGGL(mat_hsum_kernel, dim3((P + 63) / 64), dim3(64), 0, s, dh, n, P, H);
+    L0_LAUNCHED("mat_hsum_kernel");
+  }
+  return L0CIM_OK;
+}
+
+}  // namespace l0

@@ -1,12 +1,17 @@
 """Write the FP64 oracle's final supports for the seeded benchmark workloads.
 
 Calls only ``oracle`` and ``workloads``: every stored value is the oracle's.
-Usage:  python tests/golden/make_oracle_supports.py {small|plain} FIRST LAST [JOBS]
+Usage:  python tests/golden/make_oracle_supports.py {small|plain|mri} FIRST LAST [JOBS]
 
   small : N = 64,   M = 32,   fixed eta = 0.18, 1000 steps x 50 alternations,
           FP64 inputs.
   plain : N = 2000, M = 1000, eta 0.8 -> 0.18 over 30 alternations,
           2000 steps each, inputs rounded to FP32 (what the GPU receives).
+
+  mri   : 128 x 128 synthetic phantom, 3-level Haar, 30% variable-density DCT-II
+          rows (N = 16384, M = 4915), noise 1e-3, 64 replicas, K = 1, d = 0.6,
+          eta 0.8 -> 0.03 over 11 alternations of 1000 steps, binarised field,
+          FP64 couplings applied in factored form, FP64 refit.
 
 Each output line:  seed  support_size  rmse  hex(support bitmask, spin r = bit r)
 """
@@ -40,8 +45,29 @@ def bitmask_hex(sigma) -> str:
     return format(v, "x")
 
 
+MRI_CIM = O.CimParams(n_steps=1000, field=O.BN, K=1.0, d=0.6)
+MRI_OUTER = O.OuterParams(eta_init=0.8, eta_end=0.03, velo=11, n_outer=11, replicas=64)
+
+
+def one_mri(seed):
+    from oracle import mri as OM
+    from workloads import mri as WM
+    inst = WM.mri_instance(seed)
+    op = OM.MriOperator(128, inst.meta["freqs"], A=inst.A)
+    t = time.perf_counter()
+    sigma, R, hist = OM.solve(op, inst.y, MRI_CIM, O.with_params(MRI_OUTER, seed=seed),
+                              progress=lambda i, h: print(f"  seed {seed} alternation {i}: {h}", flush=True))
+    S, R_S = OM.refit(inst.A, inst.y, sigma)
+    Rf = np.zeros(op.N)
+    Rf[S] = R_S
+    dt = time.perf_counter() - t
+    return seed, int(sigma.sum()), O.rmse(sigma, Rf, inst.x, inst.xi), bitmask_hex(sigma), dt
+
+
 def one(args):
     name, seed = args
+    if name == "mri":
+        return one_mri(seed)
     w = WORKLOADS[name]
     inst = w["make"](seed)
     if w["f32"]:

@@ -152,6 +152,10 @@ TRACE_CASES = [
     (777,   3, "CN", L.LAUNCH_RESIDENT, torch.float32),
     (777,   2, "CN", L.LAUNCH_STREAMED, torch.float32),
     (1500,  1, "BN", L.LAUNCH_STREAMED, torch.float32),
+    (300,   4, "CN", L.LAUNCH_MATRIX, torch.float32),
+    (257,  16, "BN", L.LAUNCH_MATRIX, torch.float32),
+    (1000, 33, "CN", L.LAUNCH_MATRIX, torch.float32),
+    (2048, 64, "BN", L.LAUNCH_AUTO, torch.float32),
     (64,    1, "CN", L.LAUNCH_AUTO, torch.float64),
     (700,   2, "CN", L.LAUNCH_RESIDENT, torch.float64),
     (300,   1, "BN", L.LAUNCH_STREAMED, torch.float64),
@@ -206,9 +210,11 @@ def test_mfcim_trace_parity(dev, n, P, field, launch, dtype):
 
 
 @pytest.mark.parametrize("fmt", ["fp8", "bf16"])
-@pytest.mark.parametrize("launch,P", [(L.LAUNCH_AUTO, 2), (L.LAUNCH_STREAMED, 2), (L.LAUNCH_AUTO, 1)])
-def test_mfcim_trace_parity_quantised_couplings(dev, fmt, launch, P):
-    got, ref, sig, c, H, st, _ = _trace_case(dev, 1200, P, "BN", launch, torch.float32, jfmt=fmt)
+@pytest.mark.parametrize("launch,P,field", [(L.LAUNCH_AUTO, 2, "BN"), (L.LAUNCH_STREAMED, 2, "BN"),
+                                            (L.LAUNCH_AUTO, 1, "BN"), (L.LAUNCH_MATRIX, 16, "BN"),
+                                            (L.LAUNCH_MATRIX, 64, "CN"), (L.LAUNCH_MATRIX, 5, "CN")])
+def test_mfcim_trace_parity_quantised_couplings(dev, fmt, launch, P, field):
+    got, ref, sig, c, H, st, _ = _trace_case(dev, 1200, P, field, launch, torch.float32, jfmt=fmt)
     assert st == 0
     worst = max(normwise(got[k, v], ref[k, v]) for k in range(got.shape[0]) for v in range(2))
     assert worst <= 1e-5
@@ -353,6 +359,23 @@ def test_cholesky_refit_parity(dev, n, m, density):
     torch.cuda.synchronize()
     Ro32, _ = O.chol_refit(G32, b32, sigma)
     assert normwise(R32.double().cpu().numpy(), Ro32) <= 1e-6
+
+
+@pytest.mark.parametrize("n,m,density", [(3000, 2600, 0.5), (2000, 1800, 0.04)])
+def test_cholesky_refit_parity_large_support(dev, n, m, density):
+    """Supports of ~1500 and ~80 spins: several 64 x 64 blocks and a ragged
+    last block, FP64 throughout."""
+    inst = W.gaussian_instance(500 + n, n, m, density, 0.01)
+    G, b = O.gram(inst.A, inst.y)
+    sigma = inst.xi
+    R = torch.zeros(n, dtype=torch.float64, device=dev)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    L.l0cim_update_r(t(G, torch.float64, dev), t(b, torch.float64, dev), t(sigma, torch.uint8, dev), R,
+                     cdp=L.CDP_CHOL_F64, status=status)
+    torch.cuda.synchronize()
+    Ro, st = O.chol_refit(G, b, sigma)
+    assert int(status.item()) == st == 0
+    assert normwise(R.cpu().numpy(), Ro) <= 1e-9
 
 
 def test_cholesky_refit_ridge_on_singular_support(dev):
