@@ -9,10 +9,21 @@ Inputs are resident in HBM before the timed region starts.
 value = spin-steps/s counted over solves whose final support equals the FP64
 oracle's stored support for the same seed (tests/golden/oracle_supports_plain.txt).
 Prints one JSON line.
+
+--form selects the other forms of the method (one JSON line each):
+  batched    256 uneven Gaussian instances (N log-uniform in [256, 4096]),
+             16 replicas, 1000 steps x 30 alternations, FP32 couplings;
+  precision  the MRI-shaped instance (N = 16384, M = 4915), 64 replicas,
+             BF16 or FP8 couplings (--jdtype), FP64 refit, 1000 x 11;
+  serving    a stream of Gaussian requests (N log-uniform in [512, 8192]),
+             8 replicas, 1000 x 30, served by the continuous-batching server
+             at saturation and at Poisson arrival rates below it, beside the
+             single-instance path serving the same requests one at a time.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -30,6 +41,44 @@ N, M, STEPS, OUTER, P = 2000, 1000, 2000, 30, 1
 WORKLOAD = ("plain Gaussian L0RBCS: N=2000, M=1000 (alpha 0.5), Bernoulli(0.1) support, N(0,1) values, "
             "A iid N(0,1/M), noise std 0.01, 1 replica, 2000 Euler steps x 30 alternations, "
             "eta 0.8->0.18 (velo 30), Jacobi CDP 100 sweeps, FP32 couplings")
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cim_regs_kernel_plain_n2000_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2405_00366_amd", "csrc", f) for f in ("mfcim.hip", "common.h")]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the CIM kernel from the committed counter
+    summary, or None when the kernel sources changed since it was taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != kernel_source_hash() or "hbm_bytes_per_launch" not in kv:
+        return None
+    return float(kv["hbm_bytes_per_launch"])
+
+
+def traffic_probe(torch, dev):
+    """Known-size fill and copy (512 MiB each way) that calibrate the HBM
+    byte counters against the kernels of the workload in the same run."""
+    a = torch.empty(1 << 27, dtype=torch.float32, device=dev)
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
 
 
 def golden_supports():
@@ -80,12 +129,259 @@ def cpu_baseline(seconds_target: float = 15.0):
                       f"({done * STEPS} Euler steps, FP64 NumPy), {dt:.1f} s"}
 
 
+def step_bytes(n: int, P: int, jbytes: int) -> int:
+    """Algorithmic HBM bytes of one Euler step of one instance: the couplings
+    once, amplitudes and error variables read and written, z and row scale."""
+    return n * n * jbytes + 16 * P * n + 8 * n
+
+
+def percentiles(v):
+    return float(np.percentile(v, 50)), float(np.percentile(v, 99))
+
+
+def batched_bench(args, torch, L, W, dev):
+    P, steps, outer = 16, 1000, 30
+    specs = W.batch_specs(7, 256)
+    insts = [sp.build() for sp in specs]
+    descr, A, y, R, sig, stats = L.pack_instances([i.A for i in insts], [i.y for i in insts],
+                                                  [sp.seed for sp in specs], device=dev)
+    cim = L.cim_params(n_steps=steps)
+    sp = L.solve_params(eta_init=0.8, eta_end=0.18, velo=outer, n_outer=outer, replicas=P, j_dtype=L.F32)
+    plan = L.l0cim_batch_plan_create(descr, cim, sp)
+    ws = L.workspace(L.l0cim_batch_plan_workspace_bytes(plan), dev)
+    warm = L.solve_params(eta_init=0.8, eta_end=0.18, velo=outer, n_outer=1, replicas=P, j_dtype=L.F32)
+    wplan = L.l0cim_batch_plan_create(descr, L.cim_params(n_steps=steps), warm)
+    L.l0cim_solve_batched(wplan, A, y, R, sig, stats, ws)     # tunes the tile shape for this shape class
+    torch.cuda.synchronize()
+    L.l0cim_batch_plan_destroy(wplan)
+    L.l0cim_profile_begin()
+    t0 = time.perf_counter()
+    L.l0cim_solve_batched(plan, A, y, R, sig, stats, ws)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    cim_ms, launches = L.l0cim_profile_end()
+    rows, tiles, _ = L.l0cim_batch_plan_info(plan)
+    L.l0cim_batch_plan_destroy(plan)
+    st = L.read_stats_array(stats, len(descr))
+    sum_n = sum(s.N for s in specs)
+    spin_steps = sum_n * P * steps * outer
+    run_bytes = sum(step_bytes(s.N, P, 4) for s in specs) * (steps + 1)
+    achieved = run_bytes / (cim_ms / 1e3 / launches) / 1e9
+    return {
+        "metric": METRIC, "value": spin_steps / wall, "unit": "spin-steps/s", "n_gpus": 1, "steps": 1,
+        "warmup": 1, "ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batched Gaussian L0RBCS: 256 instances, N log-uniform [256, 4096], alpha U[0.3, 0.7], "
+                               "sparsity U[0.05, 0.2], noise 0.01, 16 replicas, 1000 Euler steps x 30 alternations, "
+                               "FP32 couplings, one launch per Euler step over all instances (HIP graph)",
+                   "instances": len(specs), "sum_N": sum_n, "sum_N2": sum(s.N ** 2 for s in specs),
+                   "rows_per_tile": rows, "tiles": tiles},
+        "support_match": "not gated here (the FP64 oracle of 256 instances x 16 replicas takes hours); "
+                         "parity of the batched form is covered by its GPU tests",
+        "status_nonzero": sum(1 for x in st if x.status_bits),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "bstep_kernel<float, CN, 1, rb>",
+                     "avg_launch_ms": cim_ms / launches / (steps + 1), "launches": launches * (steps + 1)},
+    }
+
+
+def precision_bench(args, torch, L, W, dev):
+    from workloads import mri as WM
+    jdt = {"bf16": L.BF16, "fp8": L.FP8E4M3}[args.jdtype]
+    jb = {"bf16": 2, "fp8": 1}[args.jdtype]
+    P, steps, outer = 64, 1000, 11
+    gold = {}
+    path = os.path.join(ROOT, "tests", "golden", "oracle_supports_mri.txt")
+    if os.path.exists(path):
+        for line in open(path):
+            if line.strip() and line[0] != "#":
+                sd, k, rm, hx = line.split()
+                gold[int(sd)] = (int(hx, 16), float(rm))
+    seeds = list(range(args.steps))
+    cim = L.cim_params(n_steps=steps, field="BN", K=1.0, d=0.6)
+    rows, total, cim_total, launches_total, match = [], 0.0, 0.0, 0, 0
+    for sd in seeds:
+        inst = WM.mri_instance(sd)
+        A = torch.tensor(inst.A, dtype=torch.float32, device=dev)
+        y = torch.tensor(inst.y, dtype=torch.float32, device=dev)
+        n = inst.N
+        sp = L.solve_params(eta_init=0.8, eta_end=0.03, velo=11, n_outer=outer, replicas=P, j_dtype=jdt,
+                            final_refit_f64=1, seed=sd)
+        ws = L.workspace(L.l0cim_solve_workspace_bytes(L.F32, inst.M, n, cim, sp), dev)
+        R = torch.empty(n, device=dev)
+        sg = torch.empty(n, dtype=torch.uint8, device=dev)
+        st = torch.zeros(L.STATS_BYTES, dtype=torch.uint8, device=dev)
+        if sd == seeds[0]:
+            warm = L.solve_params(eta_init=0.8, eta_end=0.03, velo=11, n_outer=1, replicas=P, j_dtype=jdt,
+                                  final_refit_f64=1, seed=sd)
+            L.l0cim_solve(A, y, L.cim_params(n_steps=4, field="BN", K=1.0, d=0.6), warm, R_out=R, sigma_out=sg,
+                          stats=st, ws=ws)
+            torch.cuda.synchronize()
+        L.l0cim_profile_begin()
+        t0 = time.perf_counter()
+        L.l0cim_solve(A, y, cim, sp, R_out=R, sigma_out=sg, stats=st, ws=ws)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ms, cnt = L.l0cim_profile_end()
+        total += dt
+        cim_total += ms
+        launches_total += cnt
+        sig = sg.cpu().numpy()
+        Rv = R.double().cpu().numpy()
+        rmse = float(np.sqrt(np.mean((Rv * sig - inst.x * inst.xi) ** 2)))
+        ok = sd in gold and mask_to_int(sig) == gold[sd][0]
+        match += int(ok)
+        rows.append({"seed": sd, "support": int(sig.sum()), "rmse": rmse,
+                     "oracle_rmse": gold[sd][1] if sd in gold else None, "oracle_support_match": ok,
+                     "hamming_vs_oracle": (bin(mask_to_int(sig) ^ gold[sd][0]).count("1") / n) if sd in gold
+                     else None, "status": L.read_stats(st).status_bits, "solve_s": dt})
+    spin_steps = n * P * steps * outer * len(seeds)
+    run_bytes = step_bytes(n, P, jb) * (steps + 1)
+    achieved = run_bytes / (cim_total / 1e3 / launches_total) / 1e9
+    return {
+        "metric": METRIC, "value": spin_steps / total, "unit": "spin-steps/s", "n_gpus": 1, "steps": len(seeds),
+        "warmup": 1, "ms_per_step": total * 1e3 / len(seeds), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"MRI-shaped L0RBCS stand-in: 128x128 random-ellipse phantom, 3-level Haar (N=16384), "
+                               f"30% variable-density DCT-II rows (M=4915), noise 1e-3, 64 replicas, BN field, K=1, "
+                               f"d=0.6, eta 0.8->0.03 over 11 alternations of 1000 steps, {args.jdtype} couplings "
+                               f"with per-row scales, FP64 Cholesky refit"},
+        "couplings": args.jdtype, "support_match": f"{match}/{len(seeds)}", "per_seed": rows,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": f"bstep_kernel<{args.jdtype}, BN, 4, rb>",
+                     "avg_launch_ms": cim_total / launches_total / (steps + 1)},
+    }
+
+
+def serving_bench(args, torch, L, W, dev):
+    P, steps, outer = 8, 1000, 30
+    specs = W.serving_specs(args.seed, args.requests)
+    cim = L.cim_params(n_steps=steps)
+    sp = L.solve_params(eta_init=0.8, eta_end=0.18, velo=outer, n_outer=outer, replicas=P, j_dtype=L.F32)
+    data = []
+    for k, s in enumerate(specs):
+        A, y, _x, _xi = W.gaussian_instance_device(s.seed, s.N, s.M, s.a, s.nu, dev)
+        data.append((A, y))
+    max_n = max(s.N for s in specs)
+    outs = [(torch.empty(s.N, device=dev), torch.empty(s.N, dtype=torch.uint8, device=dev),
+             torch.zeros(L.STATS_BYTES, dtype=torch.uint8, device=dev)) for s in specs]
+    free, _tot = torch.cuda.mem_get_info()
+    need = L.l0cim_server_arena_overhead(args.slots, max_n, sp) + sum(
+        L.l0cim_server_request_bytes(s.M, s.N, sp) for s in specs)
+    arena_bytes = int(min(need + (1 << 20), 0.6 * free))
+    arena = L.workspace(arena_bytes, dev)
+    torch.cuda.synchronize()
+
+    def serve(arrivals):
+        """Serve every request; arrivals are offsets (s) from the start."""
+        server = L.l0cim_server_create(cim, sp, args.slots, max_n, arena)
+        t0 = L.l0cim_server_clock(server)
+        nxt, done, lat = 0, 0, {}
+        L.l0cim_profile_begin()
+        while done < len(specs):
+            now = L.l0cim_server_clock(server) - t0
+            while nxt < len(specs) and arrivals[nxt] <= now:
+                A, y = data[nxt]
+                L.l0cim_server_submit(server, A, y, specs[nxt].seed, nxt, *outs[nxt])
+                nxt += 1
+            info = L.l0cim_server_info(server)
+            if info["active"] == 0 and info["pending"] == 0:
+                time.sleep(max(0.0, min(0.01, arrivals[nxt] - now)))
+                continue
+            done += L.l0cim_server_step(server)
+            for c in L.l0cim_server_completed(server):
+                lat[c.tag] = c.t_finish - t0 - arrivals[c.tag]
+                if len(lat) % 20 == 0:
+                    print(f"[serving] {len(lat)}/{len(specs)} done at {c.t_finish - t0:.1f} s", file=sys.stderr,
+                          flush=True)
+        end = L.l0cim_server_clock(server) - t0
+        cim_ms, launches = L.l0cim_profile_end()
+        ticks = L.l0cim_server_info(server)["ticks"]
+        L.l0cim_server_destroy(server)
+        v = [lat[k] for k in range(len(specs))]
+        return end, v, cim_ms, ticks
+
+    total_spin = sum(s.N for s in specs) * P * steps * outer
+    total_bytes = sum(step_bytes(s.N, P, 4) for s in specs) * (steps + 1) * outer
+    # saturation: every request present at t = 0
+    print(f"[serving] {len(specs)} requests, arena {arena_bytes / 1e9:.1f} GB; saturation run", file=sys.stderr,
+          flush=True)
+    makespan, lat_sat, cim_ms, ticks = serve([0.0] * len(specs))
+    thr = len(specs) / makespan
+    runs = [{"rate_frac": "saturation", "req_per_s": thr, "p50_s": percentiles(lat_sat)[0],
+             "p99_s": percentiles(lat_sat)[1], "ticks": ticks}]
+    achieved = total_bytes / (cim_ms / 1e3) / 1e9
+    for frac in args.rates:
+        print(f"[serving] Poisson arrivals at {frac} x {thr:.2f} req/s", file=sys.stderr, flush=True)
+        arr = W.poisson_arrivals(args.seed, len(specs), frac * thr)
+        span, lat, _ms, ticks = serve(list(arr))
+        p50, p99 = percentiles(lat)
+        runs.append({"rate_frac": frac, "arrival_rate": frac * thr, "req_per_s": len(specs) / span, "p50_s": p50,
+                     "p99_s": p99, "ticks": ticks})
+    # the single-instance path on the same requests, one at a time (FIFO)
+    k_plain = min(len(specs), args.plain_sample)
+    svc = []
+    ws = None
+    print(f"[serving] single-instance path on {k_plain} requests", file=sys.stderr, flush=True)
+    for k in range(k_plain):
+        A, y = data[k]
+        sps = L.solve_params(eta_init=0.8, eta_end=0.18, velo=outer, n_outer=outer, replicas=P, j_dtype=L.F32,
+                             seed=specs[k].seed)
+        nb = L.l0cim_solve_workspace_bytes(L.F32, specs[k].M, specs[k].N, cim, sps)
+        if ws is None or ws.numel() < nb:
+            ws = L.workspace(nb, dev)
+        R, sg, st = outs[k]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L.l0cim_solve(A, y, cim, sps, R_out=R, sigma_out=sg, stats=st, ws=ws)
+        torch.cuda.synchronize()
+        svc.append(time.perf_counter() - t1)
+    plain_thr = k_plain / sum(svc)
+    plain_spin = sum(specs[k].N for k in range(k_plain)) * P * steps * outer / sum(svc)
+    # FIFO replay of the measured service times under the first rate's arrivals
+    plain_p99 = None
+    if args.rates:
+        arr = W.poisson_arrivals(args.seed, len(specs), args.rates[0] * thr)[:k_plain]
+        t, lat_p = 0.0, []
+        for a_k, s_k in zip(arr, svc):
+            t = max(t, a_k) + s_k
+            lat_p.append(t - a_k)
+        plain_p99 = percentiles(lat_p)[1]
+    return {
+        "metric": METRIC, "value": total_spin / makespan, "unit": "spin-steps/s", "n_gpus": 1,
+        "steps": len(specs), "warmup": 0, "ms_per_step": makespan * 1e3 / len(specs), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "serving: Gaussian L0RBCS requests, N log-uniform [512, 8192], alpha U[0.2, 0.6], "
+                               "sparsity U[0.05, 0.2], noise 0.01, 8 replicas, 1000 Euler steps x 30 alternations, "
+                               "FP32 couplings, continuous batching (one alternation per tick)",
+                   "requests": len(specs), "max_slots": args.slots, "arena_GB": arena_bytes / 1e9},
+        "requests_per_s": thr, "runs": runs,
+        "single_instance_path": {"requests_measured": k_plain, "req_per_s": plain_thr, "spin_steps_per_s": plain_spin,
+                                 "p99_s_at_first_rate_fifo": plain_p99,
+                                 "service_s_p50": percentiles(svc)[0]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "bstep_kernel<float, CN, 1, rb>",
+                     "note": "algorithmic bytes of every Euler step served / CIM kernel time, saturation run"},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="run a 512 MiB fill and copy first (HBM counter calibration)")
+    ap.add_argument("--form", choices=["plain", "batched", "precision", "serving"], default="plain")
+    ap.add_argument("--jdtype", choices=["bf16", "fp8"], default="bf16", help="precision form couplings")
+    ap.add_argument("--requests", type=int, default=200, help="serving form: number of requests")
+    ap.add_argument("--slots", type=int, default=48, help="serving form: resident requests at most")
+    ap.add_argument("--rates", type=float, nargs="*", default=[0.5, 0.9],
+                    help="serving form: Poisson arrival rates as fractions of the saturation throughput")
+    ap.add_argument("--plain-sample", type=int, default=24,
+                    help="serving form: requests timed on the single-instance path")
+    ap.add_argument("--seed", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
@@ -100,6 +396,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.traffic_probe:
+        traffic_probe(torch, dev)
+    if args.form != "plain":
+        fn = {"batched": batched_bench, "precision": precision_bench, "serving": serving_bench}[args.form]
+        print(json.dumps(fn(args, torch, L, W, dev)), flush=True)
+        return
     gold = golden_supports()
     seeds = sorted(gold)[: args.warmup + args.steps] if len(gold) >= args.warmup + args.steps else \
         list(range(args.warmup + args.steps))
@@ -176,8 +478,10 @@ def main():
         "p99_ms": float(np.percentile(lat, 99)),
         "status_nonzero": status_bad,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "cim_resident_kernel", "regime": "couplings resident in LDS",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "kernel": "cim_regs_kernel",
+                     "regime": "couplings held in registers across the run; achieved counts the "
+                               "algorithmic N^2*4 B of couplings per Euler step, traffic is what HBM served",
                      "avg_launch_ms": avg_launch_s * 1e3, "launches": cim_launches},
     }
     if not args.no_cpu:

@@ -283,6 +283,66 @@ l0cim_status l0cim_solve_batched(l0cim_batch_plan plan, const float* A_pool, con
                                  size_t ws_bytes, void* stream);
 
 /*
+ * Serving form: continuous batching of solves over one device arena.
+ *
+ * A server runs Algorithm 1 (the batched form's kernels, one CIM
+ * configuration and outer schedule for every request) on requests that
+ * arrive over time.  Requests wait in arrival order until a slot is free and
+ * their footprint fits in the arena (first fit); each l0cim_server_step then
+ * advances every resident request by one alternation in shared launches,
+ * each request with its own alternation index, eta_i (eq. 22) and seed, and
+ * reports the requests that have completed n_outer alternations.  A
+ * request's arithmetic does not depend on the other requests, so its result
+ * is bitwise the same alone and in any mix.
+ *
+ * Memory: the arena (device, 256-byte aligned, caller-owned, untouched by
+ * anyone else while the server lives) holds a head of
+ * l0cim_server_arena_overhead() bytes and the requests' blocks of
+ * l0cim_server_request_bytes() each: G, its support-compacted copy, J, A, y,
+ * the per-spin vectors and the P x n state.  No call allocates device memory.
+ *
+ * submit: A (m x n, leading dim lda) and y (m) are device memory that must
+ * stay valid until the request is reported; they are copied into the arena
+ * when the request is admitted.  On completion R (n floats), sigma (n bytes)
+ * and the stats are copied to R_out, sigma_out and stats_out.  Returns
+ * L0CIM_ERR_WORKSPACE for a request larger than the whole arena heap, and
+ * L0CIM_ERR_SHAPE for n above max_n.
+ *
+ * step: admission, one alternation, reports; enqueued on the server's stream
+ * and waited for before it returns (the tick boundary is where requests join
+ * and leave).  `completed` receives the number of requests reported.
+ * After a device error the server refuses further work.
+ *
+ * completed: copies up to `max` completion records (oldest first) and drops
+ * them from the server.  Times are seconds on the server's steady clock
+ * (l0cim_server_clock, zero at creation).
+ */
+typedef struct l0cim_server_s* l0cim_server;
+
+typedef struct {
+  int64_t tag;           /* caller's request id */
+  int32_t n, m;
+  double t_submit;       /* when submit was called */
+  double t_admit;        /* start of the tick that admitted it */
+  double t_finish;       /* end of the tick that reported it */
+} l0cim_completion;
+
+size_t l0cim_server_request_bytes(int32_t m, int32_t n, const l0cim_solve_params* sp);
+size_t l0cim_server_arena_overhead(int32_t max_slots, int32_t max_n, const l0cim_solve_params* sp);
+l0cim_status l0cim_server_create(const l0cim_cim_params* cim, const l0cim_solve_params* sp, int32_t max_slots,
+                                 int32_t max_n, void* arena, size_t arena_bytes, void* stream,
+                                 l0cim_server* server);
+double l0cim_server_clock(l0cim_server server);
+l0cim_status l0cim_server_submit(l0cim_server server, int32_t m, int32_t n, const float* A, int64_t lda,
+                                 const float* y, uint64_t seed, int64_t tag, float* R_out,
+                                 uint8_t* sigma_out, l0cim_stats* stats_out);
+l0cim_status l0cim_server_step(l0cim_server server, int32_t* completed);
+int32_t l0cim_server_completed(l0cim_server server, l0cim_completion* out, int32_t max);
+l0cim_status l0cim_server_info(l0cim_server server, int32_t* active, int32_t* pending, size_t* bytes_in_use,
+                               size_t* heap_bytes, int64_t* ticks);
+l0cim_status l0cim_server_destroy(l0cim_server server);
+
+/*
  * Kernel timing for measurement.  Between l0cim_profile_begin() and
  * l0cim_profile_end(), every launch of the CIM-run kernels made by this
  * thread is bracketed by HIP events on its own stream.  profile_end waits for

@@ -24,6 +24,9 @@ __all__ = [
     "l0cim_solve_workspace_bytes", "l0cim_profile_begin", "l0cim_profile_end",
     "cim_params", "solve_params", "Instance", "l0cim_batch_plan_create", "l0cim_batch_plan_workspace_bytes",
     "l0cim_batch_plan_info", "l0cim_batch_plan_destroy", "l0cim_solve_batched", "pack_instances",
+    "Completion", "l0cim_server_request_bytes", "l0cim_server_arena_overhead", "l0cim_server_create",
+    "l0cim_server_clock", "l0cim_server_submit", "l0cim_server_step", "l0cim_server_completed",
+    "l0cim_server_info", "l0cim_server_destroy",
 ]
 
 F32, F64, BF16, FP8E4M3 = 0, 1, 2, 3
@@ -71,6 +74,11 @@ class Instance(ctypes.Structure):
         ("m", c_int32), ("n", c_int32), ("a_offset", c_int64), ("lda", c_int64),
         ("y_offset", c_int64), ("x_offset", c_int64), ("seed", c_uint64),
     ]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("tag", c_int64), ("n", c_int32), ("m", c_int32), ("t_submit", c_double),
+                ("t_admit", c_double), ("t_finish", c_double)]
 
 
 class L0cimError(RuntimeError):
@@ -137,6 +145,27 @@ def lib():
         L.l0cim_batch_plan_destroy.restype = st
         L.l0cim_solve_batched.argtypes = [c_void_p, vp, vp, vp, vp, vp, vp, c_size_t, vp]
         L.l0cim_solve_batched.restype = st
+        L.l0cim_server_request_bytes.argtypes = [c_int32, c_int32, POINTER(SolveParams)]
+        L.l0cim_server_request_bytes.restype = c_size_t
+        L.l0cim_server_arena_overhead.argtypes = [c_int32, c_int32, POINTER(SolveParams)]
+        L.l0cim_server_arena_overhead.restype = c_size_t
+        L.l0cim_server_create.argtypes = [POINTER(CimParams), POINTER(SolveParams), c_int32, c_int32, vp,
+                                          c_size_t, vp, POINTER(c_void_p)]
+        L.l0cim_server_create.restype = st
+        L.l0cim_server_clock.argtypes = [c_void_p]
+        L.l0cim_server_clock.restype = c_double
+        L.l0cim_server_submit.argtypes = [c_void_p, c_int32, c_int32, vp, c_int64, vp, c_uint64, c_int64, vp, vp,
+                                          vp]
+        L.l0cim_server_submit.restype = st
+        L.l0cim_server_step.argtypes = [c_void_p, POINTER(c_int32)]
+        L.l0cim_server_step.restype = st
+        L.l0cim_server_completed.argtypes = [c_void_p, POINTER(Completion), c_int32]
+        L.l0cim_server_completed.restype = c_int32
+        L.l0cim_server_info.argtypes = [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_size_t),
+                                        POINTER(c_size_t), POINTER(c_int64)]
+        L.l0cim_server_info.restype = st
+        L.l0cim_server_destroy.argtypes = [c_void_p]
+        L.l0cim_server_destroy.restype = st
         L.l0cim_profile_begin.restype = st
         L.l0cim_profile_end.argtypes = [POINTER(c_double), POINTER(c_int64)]
         L.l0cim_profile_end.restype = st
@@ -373,6 +402,56 @@ def pack_instances(As, ys, seeds, device="cuda"):
 def read_stats_array(stats_tensor, count):
     raw = bytes(stats_tensor.cpu().numpy().tobytes())
     return [Stats.from_buffer_copy(raw, i * STATS_BYTES) for i in range(count)]
+
+
+def l0cim_server_request_bytes(m: int, n: int, sp: SolveParams) -> int:
+    return lib().l0cim_server_request_bytes(m, n, ctypes.byref(sp))
+
+
+def l0cim_server_arena_overhead(max_slots: int, max_n: int, sp: SolveParams) -> int:
+    return lib().l0cim_server_arena_overhead(max_slots, max_n, ctypes.byref(sp))
+
+
+def l0cim_server_create(cim: CimParams, sp: SolveParams, max_slots: int, max_n: int, arena, stream=None):
+    """arena: a uint8 CUDA tensor (256-byte aligned) that the server uses until destroyed."""
+    h = c_void_p()
+    _check(lib().l0cim_server_create(ctypes.byref(cim), ctypes.byref(sp), max_slots, max_n, _ptr(arena),
+                                     arena.numel() * arena.element_size(), _stream(stream), ctypes.byref(h)),
+           "l0cim_server_create")
+    return h
+
+
+def l0cim_server_clock(server) -> float:
+    return lib().l0cim_server_clock(server)
+
+
+def l0cim_server_submit(server, A, y, seed: int, tag: int, R_out, sigma_out, stats_out):
+    m, n = A.shape
+    _check(lib().l0cim_server_submit(server, m, n, _ptr(A), _ld(A), _ptr(y), seed, tag, _ptr(R_out),
+                                     _ptr(sigma_out), _ptr(stats_out)), "l0cim_server_submit")
+
+
+def l0cim_server_step(server) -> int:
+    done = c_int32()
+    _check(lib().l0cim_server_step(server, ctypes.byref(done)), "l0cim_server_step")
+    return done.value
+
+
+def l0cim_server_completed(server, max_records: int = 4096):
+    buf = (Completion * max_records)()
+    k = lib().l0cim_server_completed(server, buf, max_records)
+    return [buf[i] for i in range(k)]
+
+
+def l0cim_server_info(server):
+    a, p, u, h, t = c_int32(), c_int32(), c_size_t(), c_size_t(), c_int64()
+    _check(lib().l0cim_server_info(server, ctypes.byref(a), ctypes.byref(p), ctypes.byref(u), ctypes.byref(h),
+                                   ctypes.byref(t)), "l0cim_server_info")
+    return dict(active=a.value, pending=p.value, bytes_in_use=u.value, heap_bytes=h.value, ticks=t.value)
+
+
+def l0cim_server_destroy(server):
+    _check(lib().l0cim_server_destroy(server), "l0cim_server_destroy")
 
 
 def l0cim_profile_begin():

@@ -5,23 +5,30 @@
 
 namespace l0 {
 
-// Device table entry of one instance (offsets in elements of each pool).
+// Device table entry of one instance: its sizes and the device addresses of
+// everything it reads and writes, so that instances may live anywhere (the
+// pools of a batch plan, a serving arena, a caller's single-instance buffers).
 struct BInst {
   int n, m, ld;          // spins, measurement rows, padded row length (multiple of 32)
   int ldj;               // row stride of J (multiple of 32)
   int tile0, ntiles;     // row tiles of this instance in the tile table
   int lda;               // leading dimension of A
-  int64_t oG;            // n x ld floats in the G (and compact-G) pools
-  int64_t oJ;            // n x ld coupling elements in the J pool
-  int64_t oV;            // ld floats in the b, z and row-scale pools
-  int64_t oS;            // P x ld floats in the c, c2 and e pools
-  int64_t oSig;          // P x n bytes in the all-replica support pool
-  int64_t oX;            // n elements of R and sigma in the caller's pools
-  int64_t oA, oY;        // A (m x lda) and y (m) in the caller's pools
+  int alt;               // alternation index (used when the launch passes alt < 0)
   uint64_t seed;
-  int alt;               // alternation index of this instance (serving form)
-  int pad0;
-  double eta;            // its threshold eta_alt (serving form)
+  double eta;            // threshold eta of the alternation (used when no global eta is passed)
+  const float* A;        // m x lda
+  const float* y;        // m
+  float* G;              // n x ld Gram rows
+  float* Gc;             // n x ld scratch: G restricted to the support's columns
+  void* J;               // n x ldj couplings (FP32, BF16 or FP8 e4m3)
+  float *b, *z, *rs;     // ld: A^T y, Zeeman term R o b, per-row coupling scale
+  float* R;              // n amplitudes (in/out)
+  uint8_t* sig;          // n chosen support (out)
+  float *c, *c2, *e;     // P x ld: amplitudes (double-buffered) and error variables
+  uint8_t* sig_all;      // P x n supports of every replica
+  double* hpart;         // P x n per-spin eq. 4 terms
+  int* status;           // status word (first field of the instance's stats)
+  l0cim_stats* st;       // report of the instance
 };
 
 struct BTile {
@@ -35,21 +42,14 @@ struct BStepArgs {
   int trace_steps;
 };
 
-// Device pointers of one batched solve (carved from the workspace).
+// Device tables of one batched launch sequence.
 struct BatchDev {
   int count;
   const BInst* insts;
   const BTile* tiles;
   const int64_t* row_prefix;   // count + 1: prefix sums of n
   const int64_t* st_prefix;    // count + 1: prefix sums of P * ld
-  double* eta;
-  float *G, *Gc, *b, *z, *rs, *c, *c2, *e;
-  void* J;
-  uint8_t* sig_all;
-  double* hpart;
-  float* R;          // caller pool
-  uint8_t* sig_out;  // caller pool
-  l0cim_stats* stats;
+  const double* eta;           // one eta for every instance, or NULL: each instance's own
 };
 
 const void* batch_step_kernel(l0cim_dtype jdt, int field, int qb, int rb);
@@ -57,9 +57,13 @@ l0cim_status launch_bcouplings(const BatchDev& d, l0cim_dtype jdt, int64_t total
 l0cim_status launch_binit(const BatchDev& d, int P, int alt, double std, int64_t total_state, hipStream_t s);
 l0cim_status launch_bselect(const BatchDev& d, int P, hipStream_t s);
 l0cim_status launch_bjacobi(const BatchDev& d, int max_ld, double dtc, int iters, hipStream_t s);
-l0cim_status launch_bobjective(const BatchDev& d, const float* A, const float* y, double lam,
-                               int64_t steps_per_spin, int n_outer, int P, hipStream_t s);
-l0cim_status launch_bstats_init(l0cim_stats* st, int count, hipStream_t s);
+// lam < 0: each instance's own 0.5 eta^2, alternation count alt + 1 and
+// spin-steps n P steps_per_alt (alt + 1); otherwise the given values.
+l0cim_status launch_bobjective(const BatchDev& d, double lam, int64_t steps_per_alt, int n_outer, int P,
+                               hipStream_t s);
+l0cim_status launch_bstats_init(const BatchDev& d, hipStream_t s);
+l0cim_status enqueue_bsteps(const BatchDev& d, const void* fn, const BStepArgs& a, int ntiles, int k0, int k1,
+                            hipStream_t s);
 l0cim_status launch_bfill(float* p, int64_t count, hipStream_t s);
 l0cim_status launch_bset_scalar(double* p, double v, hipStream_t s);
 

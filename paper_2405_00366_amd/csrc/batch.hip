@@ -69,24 +69,22 @@ __device__ inline int find_inst(const int64_t* prefix, int count, int64_t g) {
 // and for narrow storage the row scale amax / Q_max and RNE(J / scale).
 template <typename JT>
 __global__ void __launch_bounds__(256)
-bcouplings_kernel(const BInst* __restrict__ insts, const int64_t* __restrict__ row_prefix, int count,
-                  const float* __restrict__ Gp, const float* __restrict__ bp, const float* __restrict__ Rp,
-                  JT* __restrict__ Jp, float* __restrict__ zp, float* __restrict__ rsp) {
+bcouplings_kernel(const BInst* __restrict__ insts, const int64_t* __restrict__ row_prefix, int count) {
   __shared__ float red[256];
   const int k = find_inst(row_prefix, count, blockIdx.x);
   const BInst I = insts[k];
   const int r = int(blockIdx.x - row_prefix[k]);
   const int n = I.n, ld = I.ld;
-  const float* G = Gp + I.oG + size_t(r) * ld;
-  const float* R = Rp + I.oX;
+  const float* G = I.G + size_t(r) * ld;
+  const float* R = I.R;
   const float Rr = R[r];
-  JT* J = Jp + I.oJ + size_t(r) * I.ldj;
+  JT* J = static_cast<JT*>(I.J) + size_t(r) * I.ldj;
   if constexpr (sizeof(JT) == 4) {
     for (int j = threadIdx.x; j < ld; j += 256)
       J[j] = (j < n && j != r) ? -(G[j] * (Rr * R[j])) : 0.0f;
     if (threadIdx.x == 0) {
-      zp[I.oV + r] = Rr * bp[I.oV + r];
-      rsp[I.oV + r] = 1.0f;
+      I.z[r] = Rr * I.b[r];
+      I.rs[r] = 1.0f;
     }
   } else {
     constexpr float qmax = sizeof(JT) == 2 ? 1.0f : 448.0f;
@@ -108,8 +106,8 @@ bcouplings_kernel(const BInst* __restrict__ insts, const int64_t* __restrict__ r
       else J[j] = __hip_fp8_e4m3(fminf(fmaxf(v, -448.0f), 448.0f));
     }
     if (threadIdx.x == 0) {
-      zp[I.oV + r] = Rr * bp[I.oV + r];
-      rsp[I.oV + r] = scale;
+      I.z[r] = Rr * I.b[r];
+      I.rs[r] = scale;
     }
   }
 }
@@ -125,7 +123,7 @@ __device__ inline uint64_t bmix64(uint64_t x) {
 // keyed by the instance's seed.
 __global__ void __launch_bounds__(256)
 binit_kernel(const BInst* __restrict__ insts, const int64_t* __restrict__ st_prefix, int count, int P,
-             int alt, double std, float* __restrict__ cp, float* __restrict__ c2p, float* __restrict__ ep) {
+             int alt, double std) {
   const int64_t total = st_prefix[count];
   for (int64_t g = blockIdx.x * int64_t(256) + threadIdx.x; g < total; g += int64_t(gridDim.x) * 256) {
     const int k = find_inst(st_prefix, count, g);
@@ -144,9 +142,9 @@ binit_kernel(const BInst* __restrict__ insts, const int64_t* __restrict__ st_pre
       cv = float(std * (sqrt(-2.0 * log(1.0 - u1)) * cos(6.283185307179586 * u2)));
       ev = 1.0f;
     }
-    cp[I.oS + li] = cv;
-    c2p[I.oS + li] = 0.0f;
-    ep[I.oS + li] = ev;
+    I.c[li] = cv;
+    I.c2[li] = 0.0f;
+    I.e[li] = ev;
   }
 }
 
@@ -160,19 +158,16 @@ binit_kernel(const BInst* __restrict__ insts, const int64_t* __restrict__ st_pre
 // sums every column of the chunk exactly once.
 template <typename JT, int FIELD, int QB, int RB>
 __global__ void __launch_bounds__(256)
-bstep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, const JT* __restrict__ Jp,
-             const float* __restrict__ zp, const float* __restrict__ rsp, const float* __restrict__ cin_p,
-             float* __restrict__ cout_p, float* __restrict__ ep, uint8_t* __restrict__ sigp,
-             double* __restrict__ Hpart, BStepArgs a, int k, const double* __restrict__ etap,
-             int* __restrict__ status_p) {
+bstep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, BStepArgs a, int k,
+             const double* __restrict__ etap) {
   const BTile tl = tiles[blockIdx.x];
   const BInst I = insts[tl.inst];
   const int n = I.n, ld = I.ld, P = a.P;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int rbase = tl.row0 + wv * 16 * RB;
-  const JT* J = Jp + I.oJ;
-  const float* cin = cin_p + I.oS;
+  const JT* J = static_cast<const JT*>(I.J);
+  const float* cin = (k & 1) ? I.c2 : I.c;
   const bool last = (k == a.n_steps);
   const float st = float(sqrt(a.tau));
 
@@ -323,10 +318,10 @@ bstep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, c
   const float lin = float((a.p_thr - a.d) + 2.0 * a.d / (1.0 + exp(-(double(k) * a.dt - a.t_c) / a.t_w)) -
                           1.0 - (a.linear_j ? a.j : 0.0));
   const float jj = float(a.j), KK = float(a.K), beta = float(a.beta), tau = float(a.tau), dt = float(a.dt);
-  const float* z = zp + I.oV;
-  const float* rs = rsp + I.oV;
-  float* e = ep + I.oS;
-  float* cout = cout_p + I.oS;
+  const float* z = I.z;
+  const float* rs = I.rs;
+  float* e = I.e;
+  float* cout = (k & 1) ? I.c : I.c2;
   int bits = 0;
 #pragma unroll
   for (int qb = 0; qb < QB; ++qb) {
@@ -360,8 +355,8 @@ bstep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, c
             }
           } else {
             const bool s = cv > 0.0f;
-            Hpart[I.oSig + size_t(q) * n + r] = s ? (-0.5 * double(y) - double(z[r]) + lam) : 0.0;
-            sigp[I.oSig + size_t(q) * n + r] = s ? 1 : 0;
+            I.hpart[size_t(q) * n + r] = s ? (-0.5 * double(y) - double(z[r]) + lam) : 0.0;
+            I.sig_all[size_t(q) * n + r] = s ? 1 : 0;
             if (!(isfinite(cv) && isfinite(ev))) bits |= L0CIM_ST_NONFINITE;
             else if (fabsf(cv) > 1e3f) bits |= L0CIM_ST_BLOWUP;
           }
@@ -373,20 +368,19 @@ bstep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, c
       }
     }
   }
-  if (last && bits) raise_status(status_p + tl.inst * (sizeof(l0cim_stats) / sizeof(int)), bits);
+  if (last && bits) raise_status(I.status, bits);
 }
 
 // Per instance: H_q = sum of the per-spin eq. 4 terms in spin order (so the
 // result does not depend on the tile shape or on the rest of the batch),
 // lowest-energy replica (first on ties, NaN last), copy of its support.
 __global__ void __launch_bounds__(256)
-bselect_kernel(const BInst* __restrict__ insts, int P, const double* __restrict__ hrow,
-               const uint8_t* __restrict__ sigp, uint8_t* __restrict__ sig_out, l0cim_stats* __restrict__ stats) {
+bselect_kernel(const BInst* __restrict__ insts, int P) {
   __shared__ int qs;
   __shared__ double hq[64];
   const BInst I = insts[blockIdx.x];
   if (threadIdx.x < P) {
-    const double* hr = hrow + I.oSig + size_t(threadIdx.x) * I.n;
+    const double* hr = I.hpart + size_t(threadIdx.x) * I.n;
     double h = 0.0;
     for (int r = 0; r < I.n; ++r) h += hr[r];
     hq[threadIdx.x] = h;
@@ -403,12 +397,12 @@ bselect_kernel(const BInst* __restrict__ insts, int P, const double* __restrict_
       }
     }
     qs = best;
-    stats[blockIdx.x].selected_replica = best;
-    stats[blockIdx.x].H = hb;
+    I.st->selected_replica = best;
+    I.st->H = hb;
   }
   __syncthreads();
-  const uint8_t* src = sigp + I.oSig + size_t(qs) * I.n;
-  for (int i = threadIdx.x; i < I.n; i += 256) sig_out[I.oX + i] = src[i];
+  const uint8_t* src = I.sig_all + size_t(qs) * I.n;
+  for (int i = threadIdx.x; i < I.n; i += 256) I.sig[i] = src[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -417,9 +411,7 @@ bselect_kernel(const BInst* __restrict__ insts, int P, const double* __restrict_
 // Jacobi sweeps update every r (same update as the single-instance path).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(1024)
-bjacobi_kernel(const BInst* __restrict__ insts, const float* __restrict__ Gp, const float* __restrict__ bp,
-               const uint8_t* __restrict__ sig_out, float* __restrict__ Rp, float* __restrict__ Gc_p,
-               float dtc, int iters, l0cim_stats* __restrict__ stats) {
+bjacobi_kernel(const BInst* __restrict__ insts, float dtc, int iters) {
   extern __shared__ __align__(16) unsigned char smem[];
   const BInst I = insts[blockIdx.x];
   const int n = I.n, ld = I.ld;
@@ -430,11 +422,11 @@ bjacobi_kernel(const BInst* __restrict__ insts, const float* __restrict__ Gp, co
   float* sR = Rl + ld;                                     // |S|
   __shared__ int cnt[1024];
   __shared__ int sh_k;
-  const uint8_t* sg = sig_out + I.oX;
-  const float* G = Gp + I.oG;
-  const float* b = bp + I.oV;
-  float* R = Rp + I.oX;
-  float* Gc = Gc_p + I.oG;
+  const uint8_t* sg = I.sig;
+  const float* G = I.G;
+  const float* b = I.b;
+  float* R = I.R;
+  float* Gc = I.Gc;
   // support list in index order
   const int chunk = (n + bs - 1) / bs;
   const int lo = min(n, tid * chunk), hi = min(n, lo + chunk);
@@ -490,23 +482,21 @@ bjacobi_kernel(const BInst* __restrict__ insts, const float* __restrict__ Gp, co
     __syncthreads();
   }
   for (int i = tid; i < n; i += bs) R[i] = Rl[i];
-  if (bits && tid == 0) raise_status(&stats[blockIdx.x].status_bits, bits);
+  if (bits && tid == 0) raise_status(I.status, bits);
   (void)cnt;
 }
 
 // eq. 3 objective and the per-instance report: one workgroup per instance.
 __global__ void __launch_bounds__(256)
-bobjective_kernel(const BInst* __restrict__ insts, const float* __restrict__ Ap, const float* __restrict__ yp,
-                  const uint8_t* __restrict__ sig_out, const float* __restrict__ Rp, double lam,
-                  int64_t steps_per_spin, int n_outer, int P, l0cim_stats* __restrict__ stats) {
+bobjective_kernel(const BInst* __restrict__ insts, double lam, int64_t steps_per_alt, int n_outer, int P) {
   __shared__ double part[4];
   __shared__ int cnt[256];
   const BInst I = insts[blockIdx.x];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const float* A = Ap + I.oA;
-  const float* y = yp + I.oY;
-  const uint8_t* sg = sig_out + I.oX;
-  const float* R = Rp + I.oX;
+  const float* A = I.A;
+  const float* y = I.y;
+  const uint8_t* sg = I.sig;
+  const float* R = I.R;
   double r2 = 0.0;
   for (int row = wv; row < I.m; row += 4) {
     double acc = 0.0;
@@ -525,16 +515,20 @@ bobjective_kernel(const BInst* __restrict__ insts, const float* __restrict__ Ap,
     int s = 0;
     for (int t = 0; t < 256; ++t) s += cnt[t];
     const double rr = ((part[0] + part[1]) + part[2]) + part[3];
-    stats[blockIdx.x].support_size = s;
-    stats[blockIdx.x].E = 0.5 * rr + lam * double(s);
-    stats[blockIdx.x].spin_steps = int64_t(I.n) * P * steps_per_spin;
-    stats[blockIdx.x].n_outer_done = n_outer;
+    const bool own = lam < 0.0;
+    const double lm = own ? 0.5 * I.eta * I.eta : lam;
+    const int no = own ? I.alt + 1 : n_outer;
+    I.st->support_size = s;
+    I.st->E = 0.5 * rr + lm * double(s);
+    I.st->spin_steps = int64_t(I.n) * P * steps_per_alt * no;
+    I.st->n_outer_done = no;
   }
 }
 
-__global__ void bstats_init_kernel(l0cim_stats* st, int count) {
+__global__ void bstats_init_kernel(const BInst* __restrict__ insts, int count) {
   int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= count) return;
+  l0cim_stats* st = insts[i].st - i;
   st[i].status_bits = 0;
   st[i].selected_replica = 0;
   st[i].support_size = 0;
@@ -591,18 +585,30 @@ const void* batch_step_kernel(l0cim_dtype jdt, int field, int qb, int rb) {
   return nullptr;
 }
 
+l0cim_status enqueue_bsteps(const BatchDev& d, const void* fn, const BStepArgs& a, int ntiles, int k0, int k1,
+                            hipStream_t s) {
+  for (int k = k0; k <= k1; ++k) {
+    const BTile* tiles = d.tiles;
+    const BInst* insts = d.insts;
+    BStepArgs aa = a;
+    int kk = k;
+    const double* eta = d.eta;
+    void* args[] = {&tiles, &insts, &aa, &kk, &eta};
+    L0_HIP(hipLaunchKernel(fn, dim3(ntiles), dim3(256), args, 0, s));
+  }
+  return L0CIM_OK;
+}
+
 l0cim_status launch_bcouplings(const BatchDev& d, l0cim_dtype jdt, int64_t total_rows, hipStream_t s) {
   if (jdt == L0CIM_F32)
     hipLaunchKernelGGL(bcouplings_kernel<float>, dim3(unsigned(total_rows)), dim3(256), 0, s, d.insts,
-                       d.row_prefix, d.count, d.G, d.b, d.R, static_cast<float*>(d.J), d.z, d.rs);
+                       d.row_prefix, d.count);
   else if (jdt == L0CIM_BF16)
     hipLaunchKernelGGL(bcouplings_kernel<__hip_bfloat16>, dim3(unsigned(total_rows)), dim3(256), 0, s,
-                       d.insts, d.row_prefix, d.count, d.G, d.b, d.R, static_cast<__hip_bfloat16*>(d.J),
-                       d.z, d.rs);
+                       d.insts, d.row_prefix, d.count);
   else
     hipLaunchKernelGGL(bcouplings_kernel<__hip_fp8_e4m3>, dim3(unsigned(total_rows)), dim3(256), 0, s,
-                       d.insts, d.row_prefix, d.count, d.G, d.b, d.R, static_cast<__hip_fp8_e4m3*>(d.J),
-                       d.z, d.rs);
+                       d.insts, d.row_prefix, d.count);
   L0_LAUNCHED("bcouplings_kernel");
   return L0CIM_OK;
 }
@@ -610,15 +616,13 @@ l0cim_status launch_bcouplings(const BatchDev& d, l0cim_dtype jdt, int64_t total
 l0cim_status launch_binit(const BatchDev& d, int P, int alt, double std, int64_t total_state, hipStream_t s) {
   int blocks = int((total_state + 255) / 256);
   if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(binit_kernel, dim3(blocks), dim3(256), 0, s, d.insts, d.st_prefix, d.count, P, alt, std,
-                     d.c, d.c2, d.e);
+  hipLaunchKernelGGL(binit_kernel, dim3(blocks), dim3(256), 0, s, d.insts, d.st_prefix, d.count, P, alt, std);
   L0_LAUNCHED("binit_kernel");
   return L0CIM_OK;
 }
 
 l0cim_status launch_bselect(const BatchDev& d, int P, hipStream_t s) {
-  hipLaunchKernelGGL(bselect_kernel, dim3(d.count), dim3(256), 0, s, d.insts, P, d.hpart, d.sig_all,
-                     d.sig_out, d.stats);
+  hipLaunchKernelGGL(bselect_kernel, dim3(d.count), dim3(256), 0, s, d.insts, P);
   L0_LAUNCHED("bselect_kernel");
   return L0CIM_OK;
 }
@@ -627,22 +631,20 @@ l0cim_status launch_bjacobi(const BatchDev& d, int max_ld, double dtc, int iters
   const size_t lds = size_t(max_ld) * 4 * 3;
   L0_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(bjacobi_kernel),
                              hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-  hipLaunchKernelGGL(bjacobi_kernel, dim3(d.count), dim3(1024), lds, s, d.insts, d.G, d.b, d.sig_out, d.R,
-                     d.Gc, float(dtc), iters, d.stats);
+  hipLaunchKernelGGL(bjacobi_kernel, dim3(d.count), dim3(1024), lds, s, d.insts, float(dtc), iters);
   L0_LAUNCHED("bjacobi_kernel");
   return L0CIM_OK;
 }
 
-l0cim_status launch_bobjective(const BatchDev& d, const float* A, const float* y, double lam,
-                               int64_t steps_per_spin, int n_outer, int P, hipStream_t s) {
-  hipLaunchKernelGGL(bobjective_kernel, dim3(d.count), dim3(256), 0, s, d.insts, A, y, d.sig_out, d.R, lam,
-                     steps_per_spin, n_outer, P, d.stats);
+l0cim_status launch_bobjective(const BatchDev& d, double lam, int64_t steps_per_alt, int n_outer, int P,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(bobjective_kernel, dim3(d.count), dim3(256), 0, s, d.insts, lam, steps_per_alt, n_outer, P);
   L0_LAUNCHED("bobjective_kernel");
   return L0CIM_OK;
 }
 
-l0cim_status launch_bstats_init(l0cim_stats* st, int count, hipStream_t s) {
-  hipLaunchKernelGGL(bstats_init_kernel, dim3((count + 255) / 256), dim3(256), 0, s, st, count);
+l0cim_status launch_bstats_init(const BatchDev& d, hipStream_t s) {
+  hipLaunchKernelGGL(bstats_init_kernel, dim3((d.count + 255) / 256), dim3(256), 0, s, d.insts, d.count);
   L0_LAUNCHED("bstats_init_kernel");
   return L0CIM_OK;
 }

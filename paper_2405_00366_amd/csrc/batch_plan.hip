@@ -14,13 +14,21 @@
 
 using namespace l0;
 
+// Where one instance lives: element offsets into the plan's pools (G, J,
+// per-spin vectors, state, supports) and into the caller's pools (A, y, R, sigma).
+struct PoolSlot {
+  int n, m, ld, lda;
+  int64_t oG, oV, oS, oSig, oX, oA, oY;
+  uint64_t seed;
+};
+
 struct l0cim_batch_plan_s {
   int count = 0, P = 1, qb = 1;
   l0cim_cim_params cim;
   l0cim_solve_params sp;
   l0cim_dtype jdt = L0CIM_F32;
   std::vector<l0cim_instance> inst;
-  std::vector<BInst> base;               // offsets; tile fields filled per tile shape
+  std::vector<PoolSlot> base;
   std::vector<int64_t> row_prefix, st_prefix;
   int64_t nG = 0, nV = 0, nS = 0, nSig = 0, max_tiles = 0;
   int max_ld = 0, max_n = 0;
@@ -34,11 +42,12 @@ struct l0cim_batch_plan_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   const void* graph_ws = nullptr;
-  const void* graph_stats = nullptr;
   int graph_rb = 0;
-  // host copies of the device tables per tile shape; they stay alive for the
-  // plan's lifetime so that asynchronous uploads never read freed memory
-  std::map<int, std::pair<std::vector<BInst>, std::vector<BTile>>> tables;
+  // pinned staging buffer of the device tables; an upload waits for the
+  // previous one to have left it before writing it again
+  void* staging = nullptr;
+  size_t staging_bytes = 0;
+  hipEvent_t staged = nullptr;
 };
 
 namespace {
@@ -51,59 +60,95 @@ int round_up_i(int x, int a) { return (x + a - 1) / a * a; }
 // Row tiles of every instance, largest rows-times-columns work first so that
 // the tail of a step is made of small tiles.  Results do not depend on the
 // order: every output row is computed by one wavefront in a fixed k order.
-void tile_table(const l0cim_batch_plan_s* p, int rb, std::vector<BInst>& insts, std::vector<BTile>& tiles) {
+void tile_table(const l0cim_batch_plan_s* p, int rb, std::vector<BTile>& tiles) {
   const int tr = 64 * rb;
-  insts = p->base;
   std::vector<int> order(p->count);
   for (int k = 0; k < p->count; ++k) order[k] = k;
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return insts[x].n > insts[y].n; });
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return p->base[x].n > p->base[y].n; });
   tiles.clear();
-  for (int k : order) {
-    insts[k].tile0 = int(tiles.size());
-    for (int r0 = 0; r0 < insts[k].n; r0 += tr) tiles.push_back(BTile{k, r0});
-    insts[k].ntiles = int(tiles.size()) - insts[k].tile0;
-  }
+  for (int k : order)
+    for (int r0 = 0; r0 < p->base[k].n; r0 += tr) tiles.push_back(BTile{k, r0});
 }
 
-BatchDev carve(const l0cim_batch_plan_s* p, void* ws, float* R, uint8_t* sig, l0cim_stats* stats) {
-  char* b = static_cast<char*>(ws);
+struct Pools {
+  char* ws;
+  const float *A, *y;
+  float* R;
+  uint8_t* sig;
+  l0cim_stats* stats;
+};
+
+BInst make_inst(const l0cim_batch_plan_s* p, int k, const Pools& pl) {
+  const PoolSlot& q = p->base[k];
+  char* b = pl.ws;
+  BInst I{};
+  I.n = q.n;
+  I.m = q.m;
+  I.ld = q.ld;
+  I.ldj = q.ld;
+  I.lda = q.lda;
+  I.seed = q.seed;
+  I.A = pl.A + q.oA;
+  I.y = pl.y + q.oY;
+  I.G = reinterpret_cast<float*>(b + p->off.G) + q.oG;
+  I.Gc = reinterpret_cast<float*>(b + p->off.Gc) + q.oG;
+  I.J = b + p->off.J + size_t(q.oG) * dtype_size(p->jdt);
+  I.b = reinterpret_cast<float*>(b + p->off.b) + q.oV;
+  I.z = reinterpret_cast<float*>(b + p->off.z) + q.oV;
+  I.rs = reinterpret_cast<float*>(b + p->off.rs) + q.oV;
+  I.R = pl.R + q.oX;
+  I.sig = pl.sig + q.oX;
+  I.c = reinterpret_cast<float*>(b + p->off.c) + q.oS;
+  I.c2 = reinterpret_cast<float*>(b + p->off.c2) + q.oS;
+  I.e = reinterpret_cast<float*>(b + p->off.e) + q.oS;
+  I.sig_all = reinterpret_cast<uint8_t*>(b + p->off.sig) + q.oSig;
+  I.hpart = reinterpret_cast<double*>(b + p->off.hpart) + q.oSig;
+  I.st = pl.stats + k;
+  I.status = &pl.stats[k].status_bits;
+  return I;
+}
+
+BatchDev carve(const l0cim_batch_plan_s* p, char* ws) {
   BatchDev d;
   d.count = p->count;
-  d.insts = reinterpret_cast<const BInst*>(b + p->off.insts);
-  d.tiles = reinterpret_cast<const BTile*>(b + p->off.tiles);
-  d.row_prefix = reinterpret_cast<const int64_t*>(b + p->off.rowp);
-  d.st_prefix = reinterpret_cast<const int64_t*>(b + p->off.stp);
-  d.eta = reinterpret_cast<double*>(b + p->off.eta);
-  d.G = reinterpret_cast<float*>(b + p->off.G);
-  d.Gc = reinterpret_cast<float*>(b + p->off.Gc);
-  d.b = reinterpret_cast<float*>(b + p->off.b);
-  d.z = reinterpret_cast<float*>(b + p->off.z);
-  d.rs = reinterpret_cast<float*>(b + p->off.rs);
-  d.J = b + p->off.J;
-  d.c = reinterpret_cast<float*>(b + p->off.c);
-  d.c2 = reinterpret_cast<float*>(b + p->off.c2);
-  d.e = reinterpret_cast<float*>(b + p->off.e);
-  d.sig_all = reinterpret_cast<uint8_t*>(b + p->off.sig);
-  d.hpart = reinterpret_cast<double*>(b + p->off.hpart);
-  d.R = R;
-  d.sig_out = sig;
-  d.stats = stats;
+  d.insts = reinterpret_cast<const BInst*>(ws + p->off.insts);
+  d.tiles = reinterpret_cast<const BTile*>(ws + p->off.tiles);
+  d.row_prefix = reinterpret_cast<const int64_t*>(ws + p->off.rowp);
+  d.st_prefix = reinterpret_cast<const int64_t*>(ws + p->off.stp);
+  d.eta = reinterpret_cast<const double*>(ws + p->off.eta);
   return d;
 }
 
-l0cim_status upload_tables(l0cim_batch_plan_s* p, const BatchDev& d, int rb, hipStream_t s, int* ntiles) {
-  auto it = p->tables.find(rb);
-  if (it == p->tables.end()) {
-    std::pair<std::vector<BInst>, std::vector<BTile>> t;
-    tile_table(p, rb, t.first, t.second);
-    it = p->tables.emplace(rb, std::move(t)).first;
+// Upload the instance table (with tile ranges for rows-per-block `rb`), the
+// tile table and the prefix tables through the pinned staging buffer.
+l0cim_status upload_tables(l0cim_batch_plan_s* p, const BatchDev& d, const Pools& pl, int rb, hipStream_t s,
+                           int* ntiles) {
+  std::vector<BTile> tiles;
+  tile_table(p, rb, tiles);
+  const size_t bi = size_t(p->count) * sizeof(BInst), bt = tiles.size() * sizeof(BTile);
+  const size_t bp = size_t(p->count + 1) * sizeof(int64_t);
+  L0_HIP(hipEventSynchronize(p->staged));
+  char* h = static_cast<char*>(p->staging);
+  BInst* hi = reinterpret_cast<BInst*>(h);
+  for (int k = 0; k < p->count; ++k) hi[k] = make_inst(p, k, pl);
+  for (size_t t = 0; t < tiles.size(); ++t) {
+    BInst& I = hi[tiles[t].inst];
+    if (tiles[t].row0 == 0) {
+      I.tile0 = int(t);
+      I.ntiles = 0;
+    }
+    ++I.ntiles;
   }
-  const auto& insts = it->second.first;
-  const auto& tiles = it->second.second;
-  L0_HIP(hipMemcpyAsync(const_cast<BInst*>(d.insts), insts.data(), insts.size() * sizeof(BInst),
+  memcpy(h + align_up(bi), tiles.data(), bt);
+  memcpy(h + align_up(bi) + align_up(bt), p->row_prefix.data(), bp);
+  memcpy(h + align_up(bi) + align_up(bt) + align_up(bp), p->st_prefix.data(), bp);
+  L0_HIP(hipMemcpyAsync(const_cast<BInst*>(d.insts), h, bi, hipMemcpyHostToDevice, s));
+  L0_HIP(hipMemcpyAsync(const_cast<BTile*>(d.tiles), h + align_up(bi), bt, hipMemcpyHostToDevice, s));
+  L0_HIP(hipMemcpyAsync(const_cast<int64_t*>(d.row_prefix), h + align_up(bi) + align_up(bt), bp,
                         hipMemcpyHostToDevice, s));
-  L0_HIP(hipMemcpyAsync(const_cast<BTile*>(d.tiles), tiles.data(), tiles.size() * sizeof(BTile),
+  L0_HIP(hipMemcpyAsync(const_cast<int64_t*>(d.st_prefix), h + align_up(bi) + align_up(bt) + align_up(bp), bp,
                         hipMemcpyHostToDevice, s));
+  L0_HIP(hipEventRecord(p->staged, s));
   *ntiles = int(tiles.size());
   return L0CIM_OK;
 }
@@ -133,25 +178,7 @@ l0cim_status enqueue_steps(const l0cim_batch_plan_s* p, const BatchDev& d, int r
                            hipStream_t s) {
   const void* fn = batch_step_kernel(p->jdt, p->cim.field, p->qb, rb);
   if (!fn) return set_error(L0CIM_ERR_UNSUPPORTED, "batched step: no kernel for this shape");
-  BStepArgs a = step_args(p);
-  int* status = &d.stats[0].status_bits;
-  for (int k = k0; k <= k1; ++k) {
-    const float* cin = (k & 1) ? d.c2 : d.c;
-    float* cout = (k & 1) ? d.c : d.c2;
-    const BTile* tiles = d.tiles;
-    const BInst* insts = d.insts;
-    const void* J = d.J;
-    const float* z = d.z;
-    const float* rs = d.rs;
-    float* e = d.e;
-    uint8_t* sig = d.sig_all;
-    double* hp = d.hpart;
-    const double* eta = d.eta;
-    int kk = k;
-    void* args[] = {&tiles, &insts, &J, &z, &rs, &cin, &cout, &e, &sig, &hp, &a, &kk, &eta, &status};
-    L0_HIP(hipLaunchKernel(fn, dim3(ntiles), dim3(256), args, 0, s));
-  }
-  return L0CIM_OK;
+  return enqueue_bsteps(d, fn, step_args(p), ntiles, k0, k1, s);
 }
 
 std::string shape_key(const l0cim_batch_plan_s* p) {
@@ -169,7 +196,7 @@ std::string shape_key(const l0cim_batch_plan_s* p) {
 
 // Time every candidate tile shape on the current problem; the state it
 // leaves behind is discarded (every alternation starts from init_state).
-l0cim_status autotune(l0cim_batch_plan_s* p, const BatchDev& d, hipStream_t s) {
+l0cim_status autotune(l0cim_batch_plan_s* p, const BatchDev& d, const Pools& pl, hipStream_t s) {
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(p->key);
@@ -187,7 +214,7 @@ l0cim_status autotune(l0cim_batch_plan_s* p, const BatchDev& d, hipStream_t s) {
   int best_rb = 2;
   const int steps = p->cim.n_steps > 0 ? (p->cim.n_steps < 8 ? p->cim.n_steps : 8) : 0;
   for (int rb : {1, 2, 4}) {
-    l0cim_status st = upload_tables(p, d, rb, s, &ntiles);
+    l0cim_status st = upload_tables(p, d, pl, rb, s, &ntiles);
     if (st != L0CIM_OK) return st;
     if (steps == 0) break;
     st = enqueue_steps(p, d, rb, ntiles, 0, 1, s);
@@ -250,14 +277,12 @@ l0cim_status l0cim_batch_plan_create(int32_t count, const l0cim_instance* inst, 
       delete p;
       return set_error(L0CIM_ERR_SHAPE, "batch_plan_create: instance %d has a bad shape or offset", k);
     }
-    BInst b{};
+    PoolSlot b{};
     b.n = I.n;
     b.m = I.m;
     b.ld = round_up_i(I.n, 32);
-    b.ldj = b.ld;
     b.lda = int(I.lda);
     b.oG = p->nG;
-    b.oJ = p->nG;
     b.oV = p->nV;
     b.oS = p->nS;
     b.oSig = p->nSig;
@@ -301,6 +326,15 @@ l0cim_status l0cim_batch_plan_create(int32_t count, const l0cim_instance* inst, 
   p->off.chol = take(sp->final_refit_f64 ? chol_ws_bytes(p->max_n) : 0);
   p->off.total = o;
   p->key = shape_key(p);
+  p->staging_bytes = align_up(count * sizeof(BInst)) + align_up(size_t(p->max_tiles) * sizeof(BTile)) +
+                     2 * align_up((count + 1) * sizeof(int64_t));
+  hipError_t he = hipHostMalloc(&p->staging, p->staging_bytes, hipHostMallocDefault);
+  if (he == hipSuccess) he = hipEventCreateWithFlags(&p->staged, hipEventDisableTiming);
+  if (he != hipSuccess) {
+    if (p->staging) (void)hipHostFree(p->staging);
+    delete p;
+    return hip_fail(he, "batch_plan_create: staging buffer");
+  }
   *out = p;
   return L0CIM_OK;
 }
@@ -311,9 +345,8 @@ l0cim_status l0cim_batch_plan_info(l0cim_batch_plan plan, int32_t* rows_per_tile
                                    int32_t* tuned) {
   if (!plan) return set_error(L0CIM_ERR_ARG, "batch_plan_info: NULL plan");
   int rb = plan->rb ? plan->rb : 2;
-  std::vector<BInst> insts;
   std::vector<BTile> t;
-  tile_table(plan, rb, insts, t);
+  tile_table(plan, rb, t);
   if (rows_per_tile) *rows_per_tile = 64 * rb;
   if (tiles) *tiles = int32_t(t.size());
   if (tuned) *tuned = plan->tuned ? 1 : 0;
@@ -325,6 +358,11 @@ l0cim_status l0cim_batch_plan_destroy(l0cim_batch_plan plan) {
   if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
   if (plan->graph) (void)hipGraphDestroy(plan->graph);
   if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
+  if (plan->staged) {
+    (void)hipEventSynchronize(plan->staged);
+    (void)hipEventDestroy(plan->staged);
+  }
+  if (plan->staging) (void)hipHostFree(plan->staging);
   delete plan;
   return L0CIM_OK;
 }
@@ -336,38 +374,34 @@ l0cim_status l0cim_solve_batched(l0cim_batch_plan p, const float* A, const float
   if (!ws || ws_bytes < p->off.total)
     return set_error(L0CIM_ERR_WORKSPACE, "solve_batched: workspace needs %zu bytes", p->off.total);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  BatchDev d = carve(p, ws, R, sigma, stats);
   char* base = static_cast<char*>(ws);
+  BatchDev d = carve(p, base);
+  const Pools pl{base, A, y, R, sigma, stats};
 #define L0_TRY(x)                  \
   do {                             \
     l0cim_status _s = (x);         \
     if (_s != L0CIM_OK) return _s; \
   } while (0)
-  L0_HIP(hipMemcpyAsync(const_cast<int64_t*>(d.row_prefix), p->row_prefix.data(), (p->count + 1) * sizeof(int64_t),
-                        hipMemcpyHostToDevice, s));
-  L0_HIP(hipMemcpyAsync(const_cast<int64_t*>(d.st_prefix), p->st_prefix.data(), (p->count + 1) * sizeof(int64_t),
-                        hipMemcpyHostToDevice, s));
   int ntiles = 0;
-  L0_TRY(upload_tables(p, d, p->rb ? p->rb : 2, s, &ntiles));
-  L0_TRY(launch_bstats_init(stats, p->count, s));
+  L0_TRY(upload_tables(p, d, pl, p->rb ? p->rb : 2, s, &ntiles));
+  L0_TRY(launch_bstats_init(d, s));
   for (int k = 0; k < p->count; ++k) {
-    const BInst& I = p->base[k];
-    L0_TRY(launch_gram(L0CIM_F32, I.m, I.n, A + I.oA, I.lda, y + I.oY, d.G + I.oG, I.ld, d.b + I.oV, s));
-    L0_TRY(launch_r_init(L0CIM_F32, I.n, d.G + I.oG, I.ld, d.b + I.oV, nullptr, R + I.oX,
-                         &stats[k].status_bits, s));
+    const BInst I = make_inst(p, k, pl);
+    L0_TRY(launch_gram(L0CIM_F32, I.m, I.n, I.A, I.lda, I.y, I.G, I.ld, I.b, s));
+    L0_TRY(launch_r_init(L0CIM_F32, I.n, I.G, I.ld, I.b, nullptr, I.R, I.status, s));
   }
   const int64_t total_rows = p->row_prefix[p->count];
   const int64_t total_state = p->st_prefix[p->count];
   if (!p->tuned) {
-    L0_TRY(launch_bset_scalar(d.eta, p->sp.eta_init, s));
+    L0_TRY(launch_bset_scalar(const_cast<double*>(d.eta), p->sp.eta_init, s));
     L0_TRY(launch_bcouplings(d, p->jdt, total_rows, s));
     L0_TRY(launch_binit(d, p->P, 0, p->cim.c0_std, total_state, s));
-    L0_TRY(autotune(p, d, s));
+    L0_TRY(autotune(p, d, pl, s));
   }
-  L0_TRY(upload_tables(p, d, p->rb, s, &ntiles));
+  L0_TRY(upload_tables(p, d, pl, p->rb, s, &ntiles));
   // graph of one CIM run (n_steps + 1 launches), rebuilt when the workspace or tile shape changes
   const bool use_graph = p->cim.n_steps >= 16;
-  if (use_graph && (p->graph_ws != ws || p->graph_stats != stats || p->graph_rb != p->rb || !p->exec)) {
+  if (use_graph && (p->graph_ws != ws || p->graph_rb != p->rb || !p->exec)) {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     p->exec = nullptr;
@@ -382,14 +416,13 @@ l0cim_status l0cim_solve_batched(l0cim_batch_plan p, const float* A, const float
     p->graph = g;
     L0_HIP(hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0));
     p->graph_ws = ws;
-    p->graph_stats = stats;
     p->graph_rb = p->rb;
   }
   double eta = p->sp.eta_init;
   for (int i = 0; i < p->sp.n_outer; ++i) {
     double v = p->sp.eta_init * (1.0 - double(i) / double(p->sp.velo));
     eta = v > p->sp.eta_end ? v : p->sp.eta_end;
-    L0_TRY(launch_bset_scalar(d.eta, eta, s));
+    L0_TRY(launch_bset_scalar(const_cast<double*>(d.eta), eta, s));
     L0_TRY(launch_bcouplings(d, p->jdt, total_rows, s));
     L0_TRY(launch_binit(d, p->P, i, p->cim.c0_std, total_state, s));
     {
@@ -406,13 +439,12 @@ l0cim_status l0cim_solve_batched(l0cim_batch_plan p, const float* A, const float
   if (p->sp.final_refit_f64) {
     void* cws = base + p->off.chol;
     for (int k = 0; k < p->count; ++k) {
-      const BInst& I = p->base[k];
-      L0_TRY(launch_chol_refit(L0CIM_F32, I.n, d.G + I.oG, I.ld, d.b + I.oV, sigma + I.oX, R + I.oX,
-                               &stats[k].status_bits, cws, chol_ws_bytes(p->max_n), s));
+      const BInst I = make_inst(p, k, pl);
+      L0_TRY(launch_chol_refit(L0CIM_F32, I.n, I.G, I.ld, I.b, I.sig, I.R, I.status, cws, chol_ws_bytes(p->max_n),
+                               s));
     }
   }
-  L0_TRY(launch_bobjective(d, A, y, 0.5 * eta * eta, int64_t(p->cim.n_steps) * p->sp.n_outer, p->sp.n_outer, p->P,
-                           s));
+  L0_TRY(launch_bobjective(d, 0.5 * eta * eta, p->cim.n_steps, p->sp.n_outer, p->P, s));
 #undef L0_TRY
   return L0CIM_OK;
 }

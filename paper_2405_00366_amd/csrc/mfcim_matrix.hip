@@ -161,6 +161,15 @@ l0cim_status launch_matrix_run(int n, int P, l0cim_dtype jdt, const void* J, int
   I.ldj = int(ldm);
   I.tile0 = 0;
   I.ntiles = ntiles;
+  I.J = const_cast<void*>(Jm);
+  I.z = dz;
+  I.rs = drs;
+  I.c = dc;
+  I.c2 = dc2;
+  I.e = de;
+  I.sig_all = sigma;
+  I.hpart = dh;
+  I.status = status;
   {
     size_t work = size_t(P) * ld;
     int blocks = int((work + 255) / 256);
@@ -188,26 +197,15 @@ l0cim_status launch_matrix_run(int n, int P, l0cim_dtype jdt, const void* J, int
   sa.tau = a.tau;
   sa.trace = trace;
   sa.trace_steps = a.trace_steps;
-  int dummy_status = 0;
-  (void)dummy_status;
+  BatchDev d{};
+  d.count = 1;
+  d.insts = dinst;
+  d.tiles = dtiles;
+  d.eta = deta;
   {
     ProfileScope prof(s);
-    for (int k = 0; k <= a.n_steps; ++k) {
-      const BTile* tp = dtiles;
-      const BInst* ip = dinst;
-      const float* cin = (k & 1) ? dc2 : dc;
-      float* cout = (k & 1) ? dc : dc2;
-      const float* rsp = drs;
-      const float* zp = dz;
-      float* ep = de;
-      uint8_t* sg = sigma;
-      double* hp = dh;
-      const double* etap = deta;
-      int kk = k;
-      int* stp = status;
-      void* args[] = {&tp, &ip, &Jm, &zp, &rsp, &cin, &cout, &ep, &sg, &hp, &sa, &kk, &etap, &stp};
-      L0_HIP(hipLaunchKernel(fn, dim3(ntiles), dim3(256), args, 0, s));
-    }
+    st = enqueue_bsteps(d, fn, sa, ntiles, 0, a.n_steps, s);
+    if (st != L0CIM_OK) return st;
   }
   const float* cf = (a.n_steps & 1) ? dc2 : dc;
   {

@@ -135,3 +135,47 @@ def test_update_r_rejects_bad_arguments_on_host():
     assert lib.l0cim_update_r(L.F32, 10, FAKE, 10, FAKE, FAKE, 7, 0.1, 100, FAKE, None, FAKE, 1 << 20, None) == 1
     assert lib.l0cim_update_r(L.F32, 10, FAKE, 10, FAKE, FAKE, 0, 0.1, -1, FAKE, None, FAKE, 1 << 20, None) == 1
     assert lib.l0cim_update_r(L.F32, 10, FAKE, 10, FAKE, FAKE, 1, 0.1, 0, FAKE, None, FAKE, 64, None) == 3
+
+
+def _al(x):
+    return (x + 255) // 256 * 256
+
+
+def test_server_footprint_formula():
+    """Per-request arena bytes: G, compacted G and J (n x ld), four per-spin
+    vectors and sigma (ld), three P x ld state arrays, P x n supports and
+    energy terms, and the copies of A and y; every array 256-byte aligned."""
+    lib = L.lib()
+    for (m, n, P, jdt, jb) in [(50, 96, 8, L.F32, 4), (4915, 8192, 8, L.BF16, 2), (7, 33, 64, L.FP8E4M3, 1)]:
+        sp = L.solve_params(replicas=P, j_dtype=jdt)
+        ld = (n + 31) // 32 * 32
+        want = (2 * _al(n * ld * 4) + _al(n * ld * jb) + 4 * _al(ld * 4) + _al(ld) + 3 * _al(P * ld * 4)
+                + _al(P * n) + _al(P * n * 8) + _al(m * n * 4) + _al(m * 4))
+        assert lib.l0cim_server_request_bytes(m, n, ctypes.byref(sp)) == want
+    sp = L.solve_params()
+    assert lib.l0cim_server_request_bytes(0, 10, ctypes.byref(sp)) == 0
+    assert lib.l0cim_server_arena_overhead(16, 8192, ctypes.byref(sp)) > 16 * ctypes.sizeof(L.Stats)
+
+
+def test_server_create_rejects_bad_arguments_on_host():
+    lib = L.lib()
+    cim, sp = L.cim_params(), L.solve_params(replicas=8)
+    h = ctypes.c_void_p()
+    big = 1 << 30
+
+    def create(c=cim, s=sp, slots=4, max_n=1000, arena=FAKE, nbytes=big):
+        return lib.l0cim_server_create(ctypes.byref(c), ctypes.byref(s), slots, max_n, arena, nbytes, None,
+                                       ctypes.byref(h))
+
+    assert create(arena=None) == 1
+    assert create(slots=0) == 1
+    assert create(max_n=20000) == 2
+    assert create(s=L.solve_params(replicas=65)) == 1
+    assert create(s=L.solve_params(cdp=L.CDP_CHOL_F64)) == 5
+    assert create(s=L.solve_params(j_dtype=L.F64)) == 5
+    assert create(c=L.cim_params(dt=0.0)) == 1
+    assert create(arena=ctypes.c_void_p(0x1004)) == 1          # not 256-byte aligned
+    assert create(nbytes=1024) == 3
+    assert "arena" in _err(lib)
+    assert lib.l0cim_server_step(None, None) == 1
+    assert lib.l0cim_server_submit(None, 1, 1, FAKE, 1, FAKE, 0, 0, FAKE, FAKE, FAKE) == 1

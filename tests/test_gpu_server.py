@@ -1,0 +1,187 @@
+"""GPU checks of the serving form (continuous batching over one arena)."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2405_00366_amd as L
+import workloads as W
+from oracle import mfcim as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    return torch.device("cuda:0")
+
+
+# (seed, N, M, sparsity): uneven sizes, one above the 64-row tile multiple
+SPECS = [(401, 96, 50, 0.1), (402, 333, 170, 0.12), (403, 64, 40, 0.2), (404, 517, 260, 0.08),
+         (405, 200, 90, 0.15), (406, 129, 70, 0.1)]
+
+
+def _params(P=8, n_steps=300, n_outer=4, jdt=L.F32, field="CN"):
+    cim = L.cim_params(n_steps=n_steps, field=field)
+    sp = L.solve_params(eta_init=0.8, eta_end=0.4, velo=n_outer, n_outer=n_outer, replicas=P, j_dtype=jdt)
+    return cim, sp
+
+
+class Requests:
+    """Device copies of the requests' inputs and their output buffers."""
+
+    def __init__(self, specs, dev):
+        self.specs = specs
+        self.insts = [W.gaussian_instance(s, N, M, a, 0.01).rounded_f32() for (s, N, M, a) in specs]
+        self.A = [torch.tensor(i.A, dtype=torch.float32, device=dev) for i in self.insts]
+        self.y = [torch.tensor(i.y, dtype=torch.float32, device=dev) for i in self.insts]
+        self.R = [torch.full((i.N,), float("nan"), dtype=torch.float32, device=dev) for i in self.insts]
+        self.sig = [torch.full((i.N,), 7, dtype=torch.uint8, device=dev) for i in self.insts]
+        self.st = [torch.zeros(L.STATS_BYTES, dtype=torch.uint8, device=dev) for _ in self.insts]
+
+    def submit(self, server, k):
+        L.l0cim_server_submit(server, self.A[k], self.y[k], self.specs[k][0], k, self.R[k], self.sig[k], self.st[k])
+
+    def result(self, k):
+        return (self.sig[k].cpu().numpy(), self.R[k].cpu().numpy(), L.read_stats(self.st[k]))
+
+
+def _serve(reqs, cim, sp, schedule, dev, max_slots=16, arena_bytes=None):
+    """schedule: list of lists; before tick t, submit the request indices schedule[t]."""
+    max_n = max(i.N for i in reqs.insts)
+    if arena_bytes is None:
+        arena_bytes = L.l0cim_server_arena_overhead(max_slots, max_n, sp) + sum(
+            L.l0cim_server_request_bytes(i.M, i.N, sp) for i in reqs.insts) + 4096
+    arena = L.workspace(arena_bytes, dev)
+    server = L.l0cim_server_create(cim, sp, max_slots, max_n, arena)
+    done, infos, t = [], [], 0
+    try:
+        while True:
+            for k in (schedule[t] if t < len(schedule) else []):
+                reqs.submit(server, k)
+            L.l0cim_server_step(server)
+            infos.append(L.l0cim_server_info(server))
+            done += L.l0cim_server_completed(server)
+            t += 1
+            if t >= len(schedule) and infos[-1]["active"] == 0 and infos[-1]["pending"] == 0:
+                break
+            assert t < 1000
+    finally:
+        L.l0cim_server_destroy(server)
+    return done, infos
+
+
+def _same(a, b):
+    (sa, Ra, ta), (sb, Rb, tb) = a, b
+    return (np.array_equal(sa, sb) and np.array_equal(Ra.view(np.uint32), Rb.view(np.uint32))
+            and ta.E == tb.E and ta.H == tb.H and ta.selected_replica == tb.selected_replica
+            and ta.support_size == tb.support_size and ta.status_bits == tb.status_bits)
+
+
+def test_server_result_same_alone_and_in_the_mix(dev):
+    """Each request gives bitwise the same R, sigma and report when it is
+    served alone and when it joins, mid-run, a stream of other requests."""
+    cim, sp = _params()
+    reqs = Requests(SPECS, dev)
+    alone = []
+    for k in range(len(SPECS)):
+        _serve(reqs, cim, sp, [[k]], dev)
+        alone.append(reqs.result(k))
+    reqs2 = Requests(SPECS, dev)
+    # staggered arrivals: 2 at tick 0, 1 at tick 1, 2 at tick 2, 1 at tick 5
+    done, infos = _serve(reqs2, cim, sp, [[0, 1], [2], [3, 4], [], [], [5]], dev)
+    assert sorted(c.tag for c in done) == list(range(len(SPECS)))
+    assert max(i["active"] for i in infos) >= 4          # requests really shared the launches
+    for k in range(len(SPECS)):
+        assert _same(alone[k], reqs2.result(k)), f"request {k}"
+        st = alone[k][2]
+        assert st.n_outer_done == sp.n_outer
+        assert st.spin_steps == SPECS[k][1] * sp.replicas * cim.n_steps * sp.n_outer
+
+
+def test_server_matches_batched_plan(dev):
+    """The server and a batch plan over the same requests give the same bits."""
+    cim, sp = _params(P=16, n_steps=200, n_outer=3)
+    reqs = Requests(SPECS[:4], dev)
+    _serve(reqs, cim, sp, [[0, 1, 2, 3]], dev)
+    descr, A, y, R, sig, stats = L.pack_instances([i.A for i in reqs.insts], [i.y for i in reqs.insts],
+                                                  [s for (s, *_r) in SPECS[:4]], device=dev)
+    plan = L.l0cim_batch_plan_create(descr, cim, sp)
+    ws = L.workspace(L.l0cim_batch_plan_workspace_bytes(plan), dev)
+    L.l0cim_solve_batched(plan, A, y, R, sig, stats, ws)
+    torch.cuda.synchronize()
+    st = L.read_stats_array(stats, len(descr))
+    L.l0cim_batch_plan_destroy(plan)
+    for k, d in enumerate(descr):
+        o, n = d.x_offset, d.n
+        ref = (sig[o:o + n].cpu().numpy(), R[o:o + n].cpu().numpy(), st[k])
+        assert _same(ref, reqs.result(k)), f"request {k}"
+
+
+def test_server_admits_by_footprint(dev):
+    """An arena that holds two of the requests at a time: the others wait in
+    arrival order, memory is returned as requests finish, all complete."""
+    cim, sp = _params(n_steps=100, n_outer=2)
+    specs = [(501, 300, 150, 0.1), (502, 300, 150, 0.1), (503, 300, 150, 0.1), (504, 300, 150, 0.1)]
+    reqs = Requests(specs, dev)
+    fp = L.l0cim_server_request_bytes(150, 300, sp)
+    arena_bytes = L.l0cim_server_arena_overhead(8, 300, sp) + 2 * fp + fp // 2
+    done, infos = _serve(reqs, cim, sp, [[0, 1, 2, 3]], dev, max_slots=8, arena_bytes=arena_bytes)
+    assert infos[0]["active"] == 2 and infos[0]["pending"] == 2
+    assert infos[0]["bytes_in_use"] == 2 * fp
+    assert [c.tag for c in done] == [0, 1, 2, 3]
+    assert done[2].t_admit >= done[0].t_finish
+    assert infos[-1]["bytes_in_use"] == 0
+    for k in range(4):
+        sg, R, st = reqs.result(k)
+        assert st.n_outer_done == 2 and st.status_bits == 0
+        assert set(np.unique(sg)) <= {0, 1}
+        assert np.all(np.isfinite(R))
+
+
+def test_server_slot_limit(dev):
+    """max_slots bounds the resident set whatever the memory."""
+    cim, sp = _params(n_steps=50, n_outer=2)
+    specs = [(600 + k, 70, 40, 0.1) for k in range(5)]
+    reqs = Requests(specs, dev)
+    done, infos = _serve(reqs, cim, sp, [[0, 1, 2, 3, 4]], dev, max_slots=2)
+    assert max(i["active"] for i in infos) <= 2
+    assert sorted(c.tag for c in done) == list(range(5))
+
+
+def test_server_rejects_requests_it_can_never_hold(dev):
+    cim, sp = _params()
+    arena = L.workspace(L.l0cim_server_arena_overhead(4, 256, sp) + L.l0cim_server_request_bytes(64, 128, sp), dev)
+    server = L.l0cim_server_create(cim, sp, 4, 256, arena)
+    try:
+        big = torch.zeros(200, 256, device=dev)
+        with pytest.raises(L.L0cimError) as e:
+            L.l0cim_server_submit(server, big, torch.zeros(200, device=dev), 1, 1,
+                                  torch.zeros(256, device=dev), torch.zeros(256, dtype=torch.uint8, device=dev),
+                                  torch.zeros(L.STATS_BYTES, dtype=torch.uint8, device=dev))
+        assert e.value.status == 3
+        wide = torch.zeros(8, 300, device=dev)
+        with pytest.raises(L.L0cimError) as e:
+            L.l0cim_server_submit(server, wide, torch.zeros(8, device=dev), 1, 2,
+                                  torch.zeros(300, device=dev), torch.zeros(300, dtype=torch.uint8, device=dev),
+                                  torch.zeros(L.STATS_BYTES, dtype=torch.uint8, device=dev))
+        assert e.value.status == 2
+        assert L.l0cim_server_info(server)["pending"] == 0
+    finally:
+        L.l0cim_server_destroy(server)
+
+
+def test_server_supports_agree_with_oracle(dev):
+    """Full 1000-step runs with 8 replicas and 4 alternations served as a
+    stream: after the bifurcation trajectories are chaotic, so the gate is
+    on the final supports, as for the batched form."""
+    cim, sp = _params(P=8, n_steps=1000, n_outer=4)
+    specs = [(701, 120, 60, 0.1), (702, 90, 50, 0.15), (703, 150, 80, 0.1)]
+    reqs = Requests(specs, dev)
+    _serve(reqs, cim, sp, [[0], [1], [2]], dev)
+    same = 0
+    for k, ((s, N, M, a), inst) in enumerate(zip(specs, reqs.insts)):
+        ref = O.solve(inst.A, inst.y, O.CimParams(n_steps=1000),
+                      O.OuterParams(eta_init=0.8, eta_end=0.4, velo=4, n_outer=4, replicas=8, seed=s))
+        same += int(np.array_equal(reqs.result(k)[0], ref.sigma))
+    assert same >= 2

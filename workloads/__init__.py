@@ -161,3 +161,20 @@ def poisson_arrivals(seed: int, count: int, rate: float) -> np.ndarray:
     """Arrival times (seconds) of a Poisson process with the given rate."""
     rng = np.random.default_rng(np.random.SeedSequence([seed, 0xA771]))
     return np.cumsum(rng.exponential(1.0 / rate, size=count))
+
+
+def gaussian_instance_device(seed: int, N: int, M: int, a: float, nu: float, device):
+    """The same law as gaussian_instance (A iid N(0, 1/M), Bernoulli(a)
+    support, N(0, 1) values, noise std nu), drawn with torch's counter-based
+    generator on `device` so that thousands of requests can be made quickly.
+    Returns FP32 tensors (A, y, x, xi); the draws differ from the NumPy ones."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    A = torch.randn(M, N, generator=g, device=device, dtype=torch.float32) / math.sqrt(M)
+    xi = (torch.rand(N, generator=g, device=device) < a).to(torch.uint8)
+    x = torch.randn(N, generator=g, device=device, dtype=torch.float32)
+    w = torch.randn(M, generator=g, device=device, dtype=torch.float32) * nu
+    y = torch.mv(A, x * xi) + w
+    return A, y, x, xi
