@@ -20,16 +20,38 @@ struct BInst {
   const float* y;        // m
   float* G;              // n x ld Gram rows
   float* Gc;             // n x ld scratch: G restricted to the support's columns
-  void* J;               // n x ldj couplings (FP32, BF16 or FP8 e4m3)
+  void* J;               // couplings (FP32, BF16 or FP8 e4m3) in the panel layout, n16 x ld
   float *b, *z, *rs;     // ld: A^T y, Zeeman term R o b, per-row coupling scale
   float* R;              // n amplitudes (in/out)
   uint8_t* sig;          // n chosen support (out)
   float *c, *c2, *e;     // P x ld: amplitudes (double-buffered) and error variables
+  uint32_t *xb, *xb2;    // P x ld / 32: support bits of c and c2 (binarised field)
+  float* jw;             // CDP and report scratch: 5 ld + 192 words
   uint8_t* sig_all;      // P x n supports of every replica
   double* hpart;         // P x n per-spin eq. 4 terms
   int* status;           // status word (first field of the instance's stats)
   l0cim_stats* st;       // report of the instance
 };
+
+// Panel layout of the couplings: rows in panels of 16 (the row count padded
+// to n16, a multiple of 16), columns in chunks of 32 (ld); block (p, c)
+// holds J[16 p, 16 p + 16) x [32 c, 32 c + 32) as 512 consecutive elements
+// in the order the matrix-core operands are loaded, so that each wavefront
+// load reads one contiguous run:
+//   4-byte elements: (li, 8 lk + 4 h + u) at ((16 h + li) * 4 + lk) * 4 + u
+//   1- and 2-byte:   (li, 8 lk + t)       at (4 li + lk) * 8 + t
+__host__ __device__ inline size_t jpanel_offset(int r, int j, int ld, int esize) {
+  const int li = r & 15, jj = j & 31, lk = jj >> 3, t = jj & 7;
+  const size_t blk = (size_t(r >> 4) * size_t(ld >> 5) + size_t(j >> 5)) * 512;
+  if (esize == 4) return blk + size_t(((16 * (t >> 2) + li) * 4 + lk) * 4 + (t & 3));
+  return blk + size_t((4 * li + lk) * 8 + t);
+}
+inline int round_up16(int n) { return (n + 15) / 16 * 16; }
+// Tile shapes with RB panels per workgroup and 16 QB replicas.
+inline bool step_shape_ok(int qb, int rb) {
+  return (qb == 1 && (rb == 1 || rb == 2 || rb == 4 || rb == 8)) || (qb == 2 && (rb == 1 || rb == 2 || rb == 4)) ||
+         (qb == 4 && (rb == 1 || rb == 2));
+}
 
 struct BTile {
   int inst, row0;
@@ -47,7 +69,7 @@ struct BatchDev {
   int count;
   const BInst* insts;
   const BTile* tiles;
-  const int64_t* row_prefix;   // count + 1: prefix sums of n
+  const int64_t* row_prefix;   // count + 1: prefix sums of n16 (rows padded to 16)
   const int64_t* st_prefix;    // count + 1: prefix sums of P * ld
   const double* eta;           // one eta for every instance, or NULL: each instance's own
 };
@@ -55,8 +77,13 @@ struct BatchDev {
 const void* batch_step_kernel(l0cim_dtype jdt, int field, int qb, int rb);
 l0cim_status launch_bcouplings(const BatchDev& d, l0cim_dtype jdt, int64_t total_rows, hipStream_t s);
 l0cim_status launch_binit(const BatchDev& d, int P, int alt, double std, int64_t total_state, hipStream_t s);
+l0cim_status launch_bbits(const BatchDev& d, int64_t total_words, hipStream_t s);
 l0cim_status launch_bselect(const BatchDev& d, int P, hipStream_t s);
-l0cim_status launch_bjacobi(const BatchDev& d, int max_ld, double dtc, int iters, hipStream_t s);
+// Words of per-instance CDP scratch for padded row length ld.
+inline size_t bjac_words(int ld) { return size_t(5) * ld + 192; }
+// Row tiles of `rows_per_tile` rows (the same tile table as the step launches).
+l0cim_status launch_bjacobi(const BatchDev& d, int ntiles, int rows_per_tile, double dtc, int iters,
+                            hipStream_t s);
 // lam < 0: each instance's own 0.5 eta^2, alternation count alt + 1 and
 // spin-steps n P steps_per_alt (alt + 1); otherwise the given values.
 l0cim_status launch_bobjective(const BatchDev& d, double lam, int64_t steps_per_alt, int n_outer, int P,

@@ -24,14 +24,11 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 constexpr int kCN = 0;
 constexpr int kBN = 1;
 
-// FP8 couplings are widened to bf16 in registers (every e4m3 value is exact
-// in bf16) and multiplied on the bf16 matrix cores, so the products and their
-// FP32 sums are the ones the dequantised definition gives; the bytes read from
-// HBM are still one per coupling.  The direct fp8 x fp8 instruction path below
-// is kept switched off: its trajectories drifted from the dequantised
-// definition by about 5e-3 after a full run, while a single-instruction check
-// on normal e4m3 values summed exactly, so the cause is not pinned down.
-constexpr bool kFp8Matrix = false;
+// FP8 couplings are widened to bf16 in registers with the hardware e4m3 ->
+// f32 conversion (exact for every e4m3 code, subnormals included, and every
+// e4m3 value is exact in bf16) and multiplied on the bf16 matrix cores, so
+// products and FP32 sums are those of the dequantised definition; HBM still
+// serves one byte per coupling.
 
 __device__ inline v4f mfma_f32(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -65,8 +62,10 @@ __device__ inline int find_inst(const int64_t* prefix, int count, int64_t g) {
 // Per-alternation preparation over all instances
 // ---------------------------------------------------------------------------
 
-// One workgroup per (instance, row): J row (zero diagonal, zero padding), z,
-// and for narrow storage the row scale amax / Q_max and RNE(J / scale).
+// One workgroup per (instance, row of the 16-padded row range): J row (zero
+// diagonal, zero padding) written into the panel layout, z, and for narrow
+// storage the row scale amax / Q_max and RNE(J / scale).  Padding rows are
+// written as zeros.
 template <typename JT>
 __global__ void __launch_bounds__(256)
 bcouplings_kernel(const BInst* __restrict__ insts, const int64_t* __restrict__ row_prefix, int count) {
@@ -75,13 +74,17 @@ bcouplings_kernel(const BInst* __restrict__ insts, const int64_t* __restrict__ r
   const BInst I = insts[k];
   const int r = int(blockIdx.x - row_prefix[k]);
   const int n = I.n, ld = I.ld;
+  JT* J = static_cast<JT*>(I.J);
+  if (r >= n) {
+    for (int j = threadIdx.x; j < ld; j += 256) J[jpanel_offset(r, j, ld, int(sizeof(JT)))] = JT(0.0f);
+    return;
+  }
   const float* G = I.G + size_t(r) * ld;
   const float* R = I.R;
   const float Rr = R[r];
-  JT* J = static_cast<JT*>(I.J) + size_t(r) * I.ldj;
   if constexpr (sizeof(JT) == 4) {
     for (int j = threadIdx.x; j < ld; j += 256)
-      J[j] = (j < n && j != r) ? -(G[j] * (Rr * R[j])) : 0.0f;
+      J[jpanel_offset(r, j, ld, 4)] = (j < n && j != r) ? -(G[j] * (Rr * R[j])) : 0.0f;
     if (threadIdx.x == 0) {
       I.z[r] = Rr * I.b[r];
       I.rs[r] = 1.0f;
@@ -102,8 +105,9 @@ bcouplings_kernel(const BInst* __restrict__ insts, const int64_t* __restrict__ r
     const float scale = red[0] > 0.0f ? red[0] / qmax : 1.0f;
     for (int j = threadIdx.x; j < ld; j += 256) {
       float v = (j < n && j != r) ? -(G[j] * (Rr * R[j])) / scale : 0.0f;
-      if constexpr (sizeof(JT) == 2) J[j] = __float2bfloat16(v);
-      else J[j] = __hip_fp8_e4m3(fminf(fmaxf(v, -448.0f), 448.0f));
+      const size_t o = jpanel_offset(r, j, ld, int(sizeof(JT)));
+      if constexpr (sizeof(JT) == 2) J[o] = __float2bfloat16(v);
+      else J[o] = __hip_fp8_e4m3(fminf(fmaxf(v, -448.0f), 448.0f));
     }
     if (threadIdx.x == 0) {
       I.z[r] = Rr * I.b[r];
@@ -151,25 +155,109 @@ binit_kernel(const BInst* __restrict__ insts, const int64_t* __restrict__ st_pre
 // ---------------------------------------------------------------------------
 // The Euler step over all row tiles of all instances
 // ---------------------------------------------------------------------------
+//
+// A workgroup owns 16 * RB rows (RB panels) of one instance for all its
+// replicas (16 * QB columns of X) and its four wavefronts split the columns
+// of J into four contiguous ranges of 32-column chunks (boundaries fixed by
+// the instance's ld).  Each wavefront keeps D chunks of operands in flight,
+// sums its range on the matrix cores, and the four partial sums are added in
+// LDS in wavefront order before the fused Euler epilogue.  Every output
+// row's arithmetic is therefore a function of its instance only.
+//
+// Operands of one chunk for lane (li = lane % 16, lk = lane / 16):
+//   A: J[16 p + li][32 c + 8 lk + t], t < 8, from the panel block (p, c);
+//   B: X[q = 16 qb + li][32 c + 8 lk + t]: amplitudes (continuous field) or
+//      bits 8 lk + t of the support word (binarised field).
 
-// Operand loaders: lane (li = lane % 16, lk = lane / 16).  A: row li of the
-// 16-row block, columns [j0 + KW*lk, +KW).  B: replica li, the same columns.
-// Both sides map the lane's KW values to the same k indices, so the product
-// sums every column of the chunk exactly once.
+template <typename JT> struct ARaw;
+template <> struct ARaw<float> { float4 v0, v1; };
+template <> struct ARaw<__hip_bfloat16> { uint4 v; };
+template <> struct ARaw<__hip_fp8_e4m3> { uint2 v; };
+
+template <int FIELD> struct BRaw { float4 v0, v1; };
+template <> struct BRaw<kBN> { uint32_t v; };
+
+template <typename JT, int FIELD, int RB, int QB>
+struct Stage {
+  ARaw<JT> a[RB];
+  BRaw<FIELD> b[QB];
+};
+
+// Chunks in flight per wavefront: about 96 registers of operands.
+constexpr int pipe_depth(int jsize, int field, int RB, int QB) {
+  const int v = RB * (jsize == 4 ? 8 : (jsize == 2 ? 4 : 2)) + QB * (field == kBN ? 1 : 8);
+  const int d = 96 / v;
+  return d < 2 ? 2 : (d > 8 ? 8 : d);
+}
+
+// 8 bits (bit t = column 8 lk + t) -> 8 bf16 values 0 / 1.
+__device__ inline v8bf bits_to_bf16(uint32_t byte) {
+  uint4 w;
+  w.x = ((byte & 1u) ? 0x3F80u : 0u) | ((byte & 2u) ? 0x3F800000u : 0u);
+  w.y = ((byte & 4u) ? 0x3F80u : 0u) | ((byte & 8u) ? 0x3F800000u : 0u);
+  w.z = ((byte & 16u) ? 0x3F80u : 0u) | ((byte & 32u) ? 0x3F800000u : 0u);
+  w.w = ((byte & 64u) ? 0x3F80u : 0u) | ((byte & 128u) ? 0x3F800000u : 0u);
+  return __builtin_bit_cast(v8bf, w);
+}
+
+// 8 e4m3 codes -> 8 bf16 (exact: f32 from the hardware conversion, then its
+// upper half, which carries every e4m3 value without rounding).
+__device__ inline v8bf fp8_to_bf16(uint2 v) {
+  typedef float v2f __attribute__((ext_vector_type(2)));
+  const v2f f0 = __builtin_amdgcn_cvt_pk_f32_fp8(int(v.x), false);
+  const v2f f1 = __builtin_amdgcn_cvt_pk_f32_fp8(int(v.x), true);
+  const v2f f2 = __builtin_amdgcn_cvt_pk_f32_fp8(int(v.y), false);
+  const v2f f3 = __builtin_amdgcn_cvt_pk_f32_fp8(int(v.y), true);
+  auto pack = [](v2f f) {
+    return (__float_as_uint(f[0]) >> 16) | (__float_as_uint(f[1]) & 0xFFFF0000u);
+  };
+  uint4 w;
+  w.x = pack(f0);
+  w.y = pack(f1);
+  w.z = pack(f2);
+  w.w = pack(f3);
+  return __builtin_bit_cast(v8bf, w);
+}
+
 template <typename JT, int FIELD, int QB, int RB>
 __global__ void __launch_bounds__(256)
 bstep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, BStepArgs a, int k,
              const double* __restrict__ etap) {
+  constexpr bool kF32 = sizeof(JT) == 4;
+  constexpr int D = pipe_depth(int(sizeof(JT)), FIELD, RB, QB);
+  static_assert(RB * QB <= 8, "partial sums must fit in 32 KB of LDS");
+  __shared__ v4f red[4][RB * QB][64];
   const BTile tl = tiles[blockIdx.x];
   const BInst I = insts[tl.inst];
-  const int n = I.n, ld = I.ld, P = a.P;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int n = I.n, ld = I.ld, P = a.P, nch = ld >> 5;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int rbase = tl.row0 + wv * 16 * RB;
-  const JT* J = static_cast<const JT*>(I.J);
-  const float* cin = (k & 1) ? I.c2 : I.c;
+  const int p0 = tl.row0 >> 4;
   const bool last = (k == a.n_steps);
   const float st = float(sqrt(a.tau));
+  const float* cin = (k & 1) ? I.c2 : I.c;
+  const uint32_t* xin = (k & 1) ? I.xb2 : I.xb;
+  const JT* J = static_cast<const JT*>(I.J);
+  const int c0 = (w * nch) >> 2, c1 = ((w + 1) * nch) >> 2;
+  const int lane_off = kF32 ? (li * 4 + lk) * 4 : (li * 4 + lk) * 8;
+
+  bool pv[RB];
+  const JT* pbase[RB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    pv[rb] = (p0 + rb) * 16 < n;
+    pbase[rb] = J + size_t(p0 + rb) * nch * 512 + lane_off;
+  }
+  bool qon[QB];
+  const float* cbase[QB];
+  const uint32_t* xbase[QB];
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) {
+    const int q = qb * 16 + li;
+    qon[qb] = q < P;
+    cbase[qb] = cin + size_t(q) * ld + 8 * lk;
+    xbase[qb] = xin + size_t(q) * nch;
+  }
 
   v4f acc[RB][QB];
 #pragma unroll
@@ -177,140 +265,115 @@ bstep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, B
 #pragma unroll
     for (int qb = 0; qb < QB; ++qb) acc[rb][qb] = v4f{0.f, 0.f, 0.f, 0.f};
 
-  if constexpr (sizeof(JT) == 4) {
-    // FP32: per 32-column chunk each lane loads two float4 of A (per row
-    // block) and of B (per replica block), feeding 8 MFMA steps of k = 4.
-    // The next chunk's loads are issued before this chunk's MFMAs.
-    auto loadA = [&](int j0, float4 (&av)[RB][2]) {
+  using St = Stage<JT, FIELD, RB, QB>;
+  auto load = [&](int c, St& S) {
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb) {
-        const int row = rbase + rb * 16 + li;
-        const float* src = J + size_t(row) * I.ldj + j0 + 8 * lk;
-        av[rb][0] = row < n ? *reinterpret_cast<const float4*>(src) : make_float4(0.f, 0.f, 0.f, 0.f);
-        av[rb][1] = row < n ? *reinterpret_cast<const float4*>(src + 4) : make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int rb = 0; rb < RB; ++rb) {
+      const JT* src = pbase[rb] + size_t(c) * 512;
+      if constexpr (kF32) {
+        S.a[rb].v0 = pv[rb] ? *reinterpret_cast<const float4*>(src) : make_float4(0.f, 0.f, 0.f, 0.f);
+        S.a[rb].v1 = pv[rb] ? *reinterpret_cast<const float4*>(src + 256) : make_float4(0.f, 0.f, 0.f, 0.f);
+      } else if constexpr (sizeof(JT) == 2) {
+        S.a[rb].v = pv[rb] ? *reinterpret_cast<const uint4*>(src) : make_uint4(0u, 0u, 0u, 0u);
+      } else {
+        S.a[rb].v = pv[rb] ? *reinterpret_cast<const uint2*>(src) : make_uint2(0u, 0u);
       }
-    };
-    auto loadB = [&](int j0, float4 (&bv)[QB][2]) {
+    }
+#pragma unroll
+    for (int qb = 0; qb < QB; ++qb) {
+      if constexpr (FIELD == kBN) {
+        S.b[qb].v = qon[qb] ? xbase[qb][c] : 0u;
+      } else {
+        const float* cs = cbase[qb] + c * 32;
+        S.b[qb].v0 = qon[qb] ? *reinterpret_cast<const float4*>(cs) : make_float4(0.f, 0.f, 0.f, 0.f);
+        S.b[qb].v1 = qon[qb] ? *reinterpret_cast<const float4*>(cs + 4) : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
+  };
+  auto compute = [&](const St& S) {
+    if constexpr (kF32) {
 #pragma unroll
       for (int qb = 0; qb < QB; ++qb) {
-        const int q = qb * 16 + li;
-        const float* src = cin + size_t(q) * ld + j0 + 8 * lk;
-        bv[qb][0] = q < P ? *reinterpret_cast<const float4*>(src) : make_float4(0.f, 0.f, 0.f, 0.f);
-        bv[qb][1] = q < P ? *reinterpret_cast<const float4*>(src + 4) : make_float4(0.f, 0.f, 0.f, 0.f);
-      }
-    };
-    float4 a0[RB][2], b0[QB][2], a1[RB][2], b1[QB][2];
-    loadA(0, a0);
-    loadB(0, b0);
-    auto compute = [&](float4 (&av)[RB][2], float4 (&bv)[QB][2]) {
-#pragma unroll
-      for (int qb = 0; qb < QB; ++qb) {
-        const bool on = (qb * 16 + li) < P;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          const float4 c4 = bv[qb][h];
-          const float x0 = on ? xf<FIELD>(c4.x, st, last) : 0.f, x1 = on ? xf<FIELD>(c4.y, st, last) : 0.f;
-          const float x2 = on ? xf<FIELD>(c4.z, st, last) : 0.f, x3 = on ? xf<FIELD>(c4.w, st, last) : 0.f;
+          float x[4];
+          if constexpr (FIELD == kBN) {
+            const uint32_t byte = (S.b[qb].v >> (8 * lk)) & 0xFFu;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) x[u] = float((byte >> (4 * h + u)) & 1u);
+          } else {
+            const float4 c4 = h ? S.b[qb].v1 : S.b[qb].v0;
+            const bool on = qon[qb];
+            x[0] = on ? xf<FIELD>(c4.x, st, last) : 0.f;
+            x[1] = on ? xf<FIELD>(c4.y, st, last) : 0.f;
+            x[2] = on ? xf<FIELD>(c4.z, st, last) : 0.f;
+            x[3] = on ? xf<FIELD>(c4.w, st, last) : 0.f;
+          }
 #pragma unroll
           for (int rb = 0; rb < RB; ++rb) {
-            acc[rb][qb] = mfma_f32(av[rb][h].x, x0, acc[rb][qb]);
-            acc[rb][qb] = mfma_f32(av[rb][h].y, x1, acc[rb][qb]);
-            acc[rb][qb] = mfma_f32(av[rb][h].z, x2, acc[rb][qb]);
-            acc[rb][qb] = mfma_f32(av[rb][h].w, x3, acc[rb][qb]);
+            const float4 a4 = h ? S.a[rb].v1 : S.a[rb].v0;
+            acc[rb][qb] = mfma_f32(a4.x, x[0], acc[rb][qb]);
+            acc[rb][qb] = mfma_f32(a4.y, x[1], acc[rb][qb]);
+            acc[rb][qb] = mfma_f32(a4.z, x[2], acc[rb][qb]);
+            acc[rb][qb] = mfma_f32(a4.w, x[3], acc[rb][qb]);
           }
         }
       }
-    };
-    int j0 = 0;
-    for (; j0 + 32 < ld; j0 += 64) {
-      loadA(j0 + 32, a1);
-      loadB(j0 + 32, b1);
-      compute(a0, b0);
-      if (j0 + 64 < ld) {
-        loadA(j0 + 64, a0);
-        loadB(j0 + 64, b0);
-      }
-      compute(a1, b1);
-    }
-    if (j0 < ld) compute(a0, b0);
-  } else if constexpr (kFp8Matrix && sizeof(JT) == 1 && FIELD == kBN) {
-    // FP8 couplings, binarised operand: 8 e4m3 values per lane, k = 32.
-    for (int j0 = 0; j0 < ld; j0 += 32) {
-      long av[RB], bv[QB];
+    } else {
+      v8bf av[RB];
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb) {
-        const int row = rbase + rb * 16 + li;
-        av[rb] = row < n ? *reinterpret_cast<const long*>(J + size_t(row) * I.ldj + j0 + 8 * lk) : 0l;
+        if constexpr (sizeof(JT) == 2) av[rb] = __builtin_bit_cast(v8bf, S.a[rb].v);
+        else av[rb] = fp8_to_bf16(S.a[rb].v);
       }
 #pragma unroll
       for (int qb = 0; qb < QB; ++qb) {
-        const int q = qb * 16 + li;
-        uint64_t bits = 0;
-        if (q < P) {
-          const float4 c0 = *reinterpret_cast<const float4*>(cin + size_t(q) * ld + j0 + 8 * lk);
-          const float4 c1 = *reinterpret_cast<const float4*>(cin + size_t(q) * ld + j0 + 8 * lk + 4);
-          const float cc[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+        if constexpr (FIELD == kBN) {
+          const v8bf bx = bits_to_bf16((S.b[qb].v >> (8 * lk)) & 0xFFu);
 #pragma unroll
-          for (int t = 0; t < 8; ++t) bits |= (cc[t] > 0.0f ? uint64_t(0x38) : uint64_t(0)) << (8 * t);
-        }
-        bv[qb] = long(bits);   // 0x38 is 1.0 in OCP e4m3
-      }
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-        for (int qb = 0; qb < QB; ++qb) acc[rb][qb] = mfma_fp8(av[rb], bv[qb], acc[rb][qb]);
-    }
-  } else {
-    // BF16 couplings (or FP8 widened to bf16 exactly): 8 values per lane,
-    // k = 32; the continuous operand is split into bf16 hi + lo.
-    for (int j0 = 0; j0 < ld; j0 += 32) {
-      v8bf av[RB], bh[QB], bl[QB];
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb) {
-        const int row = rbase + rb * 16 + li;
-        if constexpr (sizeof(JT) == 2) {
-          if (row < n) {
-            av[rb] = *reinterpret_cast<const v8bf*>(J + size_t(row) * I.ldj + j0 + 8 * lk);
-          } else {
-#pragma unroll
-            for (int t = 0; t < 8; ++t) av[rb][t] = __bf16(0.0f);
-          }
+          for (int rb = 0; rb < RB; ++rb) acc[rb][qb] = mfma_bf16(av[rb], bx, acc[rb][qb]);
         } else {
-          const JT* src = J + size_t(row) * I.ldj + j0 + 8 * lk;
+          const float cc[8] = {S.b[qb].v0.x, S.b[qb].v0.y, S.b[qb].v0.z, S.b[qb].v0.w,
+                               S.b[qb].v1.x, S.b[qb].v1.y, S.b[qb].v1.z, S.b[qb].v1.w};
+          v8bf bh, bl;
 #pragma unroll
-          for (int t = 0; t < 8; ++t) av[rb][t] = __bf16(row < n ? float(src[t]) : 0.0f);
+          for (int t = 0; t < 8; ++t) {
+            const float xv = qon[qb] ? xf<FIELD>(cc[t], st, last) : 0.f;
+            const __bf16 hv = __bf16(xv);
+            bh[t] = hv;
+            bl[t] = __bf16(xv - float(hv));
+          }
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) {
+            acc[rb][qb] = mfma_bf16(av[rb], bh, acc[rb][qb]);
+            if (!last) acc[rb][qb] = mfma_bf16(av[rb], bl, acc[rb][qb]);
+          }
         }
       }
+    }
+  };
+
+  St buf[D];
 #pragma unroll
-      for (int qb = 0; qb < QB; ++qb) {
-        const int q = qb * 16 + li;
-        float cc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        if (q < P) {
-          const float4 c0 = *reinterpret_cast<const float4*>(cin + size_t(q) * ld + j0 + 8 * lk);
-          const float4 c1 = *reinterpret_cast<const float4*>(cin + size_t(q) * ld + j0 + 8 * lk + 4);
-          cc[0] = xf<FIELD>(c0.x, st, last); cc[1] = xf<FIELD>(c0.y, st, last);
-          cc[2] = xf<FIELD>(c0.z, st, last); cc[3] = xf<FIELD>(c0.w, st, last);
-          cc[4] = xf<FIELD>(c1.x, st, last); cc[5] = xf<FIELD>(c1.y, st, last);
-          cc[6] = xf<FIELD>(c1.z, st, last); cc[7] = xf<FIELD>(c1.w, st, last);
-        }
+  for (int s = 0; s < D; ++s)
+    if (c0 + s < c1) load(c0 + s, buf[s]);
+  for (int c = c0; c < c1; c += D) {
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const __bf16 h = __bf16(cc[t]);
-          bh[qb][t] = h;
-          bl[qb][t] = __bf16(cc[t] - float(h));
-        }
+    for (int s = 0; s < D; ++s) {
+      if (c + s < c1) {
+        compute(buf[s]);
+        if (c + s + D < c1) load(c + s + D, buf[s]);
       }
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-        for (int qb = 0; qb < QB; ++qb) {
-          acc[rb][qb] = mfma_bf16(av[rb], bh[qb], acc[rb][qb]);
-          if (FIELD == kCN && !last) acc[rb][qb] = mfma_bf16(av[rb], bl[qb], acc[rb][qb]);
-        }
     }
   }
 
-  // Epilogue: lane holds rows rbase + rb*16 + 4*lk + v (v < 4) of replica qb*16 + li.
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int qb = 0; qb < QB; ++qb) red[w][rb * QB + qb][lane] = acc[rb][qb];
+  __syncthreads();
+
+  // Epilogue: lane holds rows 16 (p0 + rb) + 4 lk + v (v < 4) of replica 16 qb + li.
   const double eta = etap ? *etap : I.eta;
   const float theta = float(eta * eta * sqrt(a.tau) * 0.25);
   const float half_st = float(0.5 * sqrt(a.tau));
@@ -322,53 +385,85 @@ bstep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, B
   const float* rs = I.rs;
   float* e = I.e;
   float* cout = (k & 1) ? I.c : I.c2;
+  uint16_t* xout = reinterpret_cast<uint16_t*>((k & 1) ? I.xb : I.xb2);
   int bits = 0;
-#pragma unroll
-  for (int qb = 0; qb < QB; ++qb) {
+  for (int b = w; b < RB * QB; b += 4) {
+    const int rb = b / QB, qb = b - (b / QB) * QB;
+    v4f sacc = red[0][b][lane];
+    sacc += red[1][b][lane];
+    sacc += red[2][b][lane];
+    sacc += red[3][b][lane];
     const int q = qb * 16 + li;
+    const int r0 = (p0 + rb) * 16 + 4 * lk;
+    uint32_t nib = 0;
+    if (q < P && r0 < n) {
+      const size_t off = size_t(q) * ld + r0;
+      float4 c4 = *reinterpret_cast<const float4*>(cin + off);
+      float4 e4 = *reinterpret_cast<const float4*>(e + off);
+      float cvs[4] = {c4.x, c4.y, c4.z, c4.w};
+      float evs[4] = {e4.x, e4.y, e4.z, e4.w};
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-      const int r0 = rbase + rb * 16 + 4 * lk;
-      if (q < P && r0 < n) {
-        const size_t off = size_t(q) * ld + r0;
-        float4 c4 = *reinterpret_cast<const float4*>(cin + off);
-        float4 e4 = *reinterpret_cast<const float4*>(e + off);
-        float cvs[4] = {c4.x, c4.y, c4.z, c4.w};
-        float evs[4] = {e4.x, e4.y, e4.z, e4.w};
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int r = r0 + v;
-          if (r >= n) continue;
-          const float y = acc[rb][qb][v] * rs[r];
-          float cv = cvs[v], ev = evs[v];
-          if (!last) {
-            const float phi = (FIELD == kCN) ? (y + half_st * z[r]) : (half_st * (y + z[r]));
-            const float inj = jj * ev * (phi - theta);
-            const float c2 = cv * cv;
-            const float dc = (lin - c2) * cv + KK * inj;
-            const float de = -beta * (c2 - tau) * ev;
-            cvs[v] = cv + dt * dc;
-            evs[v] = ev + dt * de;
-            if (k < a.trace_steps) {
-              a.trace[(size_t(2 * k) * P + q) * n + r] = cvs[v];
-              a.trace[(size_t(2 * k + 1) * P + q) * n + r] = evs[v];
-            }
-          } else {
-            const bool s = cv > 0.0f;
-            I.hpart[size_t(q) * n + r] = s ? (-0.5 * double(y) - double(z[r]) + lam) : 0.0;
-            I.sig_all[size_t(q) * n + r] = s ? 1 : 0;
-            if (!(isfinite(cv) && isfinite(ev))) bits |= L0CIM_ST_NONFINITE;
-            else if (fabsf(cv) > 1e3f) bits |= L0CIM_ST_BLOWUP;
-          }
-        }
+      for (int v = 0; v < 4; ++v) {
+        const int r = r0 + v;
+        if (r >= n) continue;
+        const float y = sacc[v] * rs[r];
+        float cv = cvs[v], ev = evs[v];
         if (!last) {
-          *reinterpret_cast<float4*>(cout + off) = make_float4(cvs[0], cvs[1], cvs[2], cvs[3]);
-          *reinterpret_cast<float4*>(e + off) = make_float4(evs[0], evs[1], evs[2], evs[3]);
+          const float phi = (FIELD == kCN) ? (y + half_st * z[r]) : (half_st * (y + z[r]));
+          const float inj = jj * ev * (phi - theta);
+          const float c2 = cv * cv;
+          const float dc = (lin - c2) * cv + KK * inj;
+          const float de = -beta * (c2 - tau) * ev;
+          cvs[v] = cv + dt * dc;
+          evs[v] = ev + dt * de;
+          nib |= (cvs[v] > 0.0f ? 1u : 0u) << v;
+          if (k < a.trace_steps) {
+            a.trace[(size_t(2 * k) * P + q) * n + r] = cvs[v];
+            a.trace[(size_t(2 * k + 1) * P + q) * n + r] = evs[v];
+          }
+        } else {
+          const bool sg = cv > 0.0f;
+          I.hpart[size_t(q) * n + r] = sg ? (-0.5 * double(y) - double(z[r]) + lam) : 0.0;
+          I.sig_all[size_t(q) * n + r] = sg ? 1 : 0;
+          if (!(isfinite(cv) && isfinite(ev))) bits |= L0CIM_ST_NONFINITE;
+          else if (fabsf(cv) > 1e3f) bits |= L0CIM_ST_BLOWUP;
         }
       }
+      if (!last) {
+        *reinterpret_cast<float4*>(cout + off) = make_float4(cvs[0], cvs[1], cvs[2], cvs[3]);
+        *reinterpret_cast<float4*>(e + off) = make_float4(evs[0], evs[1], evs[2], evs[3]);
+      }
+    }
+    if constexpr (FIELD == kBN) {
+      // support bits of the panel for the next step: 4 rows per lane, 16 per replica
+      uint32_t word = nib << (4 * lk);
+      word |= uint32_t(__shfl_xor(int(word), 16, kWave));
+      word |= uint32_t(__shfl_xor(int(word), 32, kWave));
+      if (!last && lk == 0 && q < P && (p0 + rb) * 16 < n) xout[size_t(q) * (ld >> 4) + p0 + rb] = uint16_t(word);
     }
   }
   if (last && bits) raise_status(I.status, bits);
+}
+
+// Support bits of the initial amplitudes (binarised field): word (q, c)
+// holds c_q[32 c + t] > 0 in bit t; the other buffer starts at zero.  With
+// no prefix table the launch covers instance 0 alone.
+__global__ void __launch_bounds__(256)
+bbits_kernel(const BInst* __restrict__ insts, const int64_t* __restrict__ st_prefix, int count,
+             int64_t total_words) {
+  for (int64_t g = blockIdx.x * int64_t(256) + threadIdx.x; g < total_words; g += int64_t(gridDim.x) * 256) {
+    const int64_t e0 = g * 32;
+    const int k = st_prefix ? find_inst(st_prefix, count, e0) : 0;
+    const BInst I = insts[k];
+    const int64_t li = e0 - (st_prefix ? st_prefix[k] : 0);
+    const int64_t q = li / I.ld, r0 = li - q * I.ld;
+    const float* c = I.c + q * I.ld + r0;
+    uint32_t wv = 0;
+    for (int t = 0; t < 32; ++t) wv |= (c[t] > 0.0f ? 1u : 0u) << t;
+    const int64_t wi = q * (I.ld >> 5) + (r0 >> 5);
+    I.xb[wi] = wv;
+    I.xb2[wi] = 0u;
+  }
 }
 
 // Per instance: H_q = sum of the per-spin eq. 4 terms in spin order (so the
@@ -406,115 +501,159 @@ bselect_kernel(const BInst* __restrict__ insts, int P) {
 }
 
 // ---------------------------------------------------------------------------
-// CDP for every instance: one workgroup per instance.  The support's columns
-// of G are gathered once into a compact block, then `iters` synchronous
-// Jacobi sweeps update every r (same update as the single-instance path).
+// CDP for every instance (synchronous damped Jacobi over all r, the same
+// update as the single-instance path).  Per alternation: a preparation
+// kernel per instance (support list, its inverse, R on the support), one
+// pass that gathers the support's columns of G into a compact block, then
+// one launch per sweep over the row tiles of every instance.  Each row's sum
+// runs over the support in index order split by lane, so the result depends
+// only on the instance.
+// Per-instance scratch (words of 4 bytes, ld = padded row length):
+//   [0, ld) R of the other parity   [ld, 3 ld) R on the support, two parities
+//   [3 ld, 4 ld) support list       [4 ld, 5 ld) position in the list or -1
+//   [5 ld, 5 ld + 64) counters      [5 ld + 64, 5 ld + 192) 64 FP64 partial sums
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024)
-bjacobi_kernel(const BInst* __restrict__ insts, float dtc, int iters) {
-  extern __shared__ __align__(16) unsigned char smem[];
+constexpr int kObjChunks = 64;
+
+__global__ void __launch_bounds__(256)
+bjac_prep_kernel(const BInst* __restrict__ insts) {
+  __shared__ int cnt[256];
   const BInst I = insts[blockIdx.x];
-  const int n = I.n, ld = I.ld;
-  const int tid = threadIdx.x, bs = blockDim.x;
-  const int lane = tid & 63, wv = tid >> 6, nwv = bs >> 6;
-  int* S = reinterpret_cast<int*>(smem);                  // n
-  float* Rl = reinterpret_cast<float*>(smem + 4 * size_t(ld));   // n
-  float* sR = Rl + ld;                                     // |S|
-  __shared__ int cnt[1024];
-  __shared__ int sh_k;
-  const uint8_t* sg = I.sig;
-  const float* G = I.G;
-  const float* b = I.b;
-  float* R = I.R;
-  float* Gc = I.Gc;
-  // support list in index order
-  const int chunk = (n + bs - 1) / bs;
+  const int n = I.n, ld = I.ld, tid = threadIdx.x;
+  float* Rn = I.jw;
+  float* sR0 = I.jw + ld;
+  int* S = reinterpret_cast<int*>(I.jw + 3 * ld);
+  int* pos = reinterpret_cast<int*>(I.jw + 4 * ld);
+  int* misc = reinterpret_cast<int*>(I.jw + 5 * ld);
+  const int chunk = (n + 255) / 256;
   const int lo = min(n, tid * chunk), hi = min(n, lo + chunk);
   int c = 0;
-  for (int i = lo; i < hi; ++i) c += sg[i] ? 1 : 0;
+  for (int i = lo; i < hi; ++i) c += I.sig[i] ? 1 : 0;
   cnt[tid] = c;
   __syncthreads();
   if (tid == 0) {
-    int s = 0;
-    for (int t = 0; t < bs; ++t) {
-      int v = cnt[t];
-      cnt[t] = s;
-      s += v;
+    int t = 0;
+    for (int u = 0; u < 256; ++u) {
+      const int v = cnt[u];
+      cnt[u] = t;
+      t += v;
     }
-    sh_k = s;
+    misc[0] = t;
   }
   __syncthreads();
-  int pos = cnt[tid];
-  for (int i = lo; i < hi; ++i)
-    if (sg[i]) S[pos++] = i;
+  int at = cnt[tid];
   int bits = 0;
-  for (int i = tid; i < n; i += bs) {
-    const float d = G[size_t(i) * ld + i];
+  for (int i = lo; i < hi; ++i) {
+    const float d = I.G[size_t(i) * ld + i];
     const bool tiny = !(d >= 1e-12f);
     if (tiny) bits |= L0CIM_ST_TINY_DIAG;
-    Rl[i] = tiny ? 0.0f : R[i];
-  }
-  __syncthreads();
-  const int ks = sh_k;
-  // compact columns: Gc[r][s] = G[r][S[s]]
-  for (size_t e = tid; e < size_t(n) * ks; e += bs) {
-    const int r = int(e / ks), s = int(e - size_t(r) * ks);
-    Gc[size_t(r) * ks + s] = G[size_t(r) * ld + S[s]];
-  }
-  for (int s = tid; s < ks; s += bs) sR[s] = Rl[S[s]];
-  __syncthreads();
-  for (int it = 0; it < iters; ++it) {
-    for (int r = wv; r < n; r += nwv) {
-      const float* gr = Gc + size_t(r) * ks;
-      float acc = 0.0f;
-      for (int s = lane; s < ks; s += kWave)
-        if (S[s] != r) acc += gr[s] * sR[s];
-      acc = wave_sum(acc);
-      if (lane == 0) {
-        const float d = G[size_t(r) * ld + r];
-        const bool tiny = !(d >= 1e-12f);
-        const float Rv = Rl[r];
-        Rl[r] = tiny ? 0.0f : Rv + dtc * ((b[r] - acc) / d - Rv);
-      }
+    const float r = tiny ? 0.0f : I.R[i];
+    I.R[i] = r;
+    Rn[i] = r;
+    if (I.sig[i]) {
+      S[at] = i;
+      sR0[at] = r;
+      pos[i] = at++;
+    } else {
+      pos[i] = -1;
     }
-    __syncthreads();
-    for (int s = tid; s < ks; s += bs) sR[s] = Rl[S[s]];
-    __syncthreads();
   }
-  for (int i = tid; i < n; i += bs) R[i] = Rl[i];
-  if (bits && tid == 0) raise_status(I.status, bits);
-  (void)cnt;
+  if (bits) raise_status(I.status, bits);
 }
 
-// eq. 3 objective and the per-instance report: one workgroup per instance.
+// Gc[r][s] = G[r][S[s]] for the rows of one tile (a wavefront per row).
 __global__ void __launch_bounds__(256)
-bobjective_kernel(const BInst* __restrict__ insts, double lam, int64_t steps_per_alt, int n_outer, int P) {
-  __shared__ double part[4];
-  __shared__ int cnt[256];
-  const BInst I = insts[blockIdx.x];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const float* A = I.A;
-  const float* y = I.y;
-  const uint8_t* sg = I.sig;
-  const float* R = I.R;
-  double r2 = 0.0;
-  for (int row = wv; row < I.m; row += 4) {
-    double acc = 0.0;
-    for (int j = lane; j < I.n; j += kWave)
-      if (sg[j]) acc += double(A[size_t(row) * I.lda + j]) * double(R[j]);
+bjac_compact_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, int rows_per_tile) {
+  const BTile tl = tiles[blockIdx.x];
+  const BInst I = insts[tl.inst];
+  const int ld = I.ld;
+  const int* S = reinterpret_cast<const int*>(I.jw + 3 * ld);
+  const int ks = reinterpret_cast<const int*>(I.jw + 5 * ld)[0];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r1 = min(I.n, tl.row0 + rows_per_tile);
+  for (int r = tl.row0 + w; r < r1; r += 4) {
+    const float* g = I.G + size_t(r) * ld;
+    float* gc = I.Gc + size_t(r) * ks;
+    for (int s = lane; s < ks; s += kWave) gc[s] = g[S[s]];
+  }
+}
+
+// One synchronous sweep; `flip` selects which R buffers are read and written
+// so that the last sweep writes the instance's own R.
+__global__ void __launch_bounds__(256)
+bjac_sweep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, int rows_per_tile, float dtc,
+                  int it, int flip) {
+  const BTile tl = tiles[blockIdx.x];
+  const BInst I = insts[tl.inst];
+  const int ld = I.ld;
+  const float* sRi = I.jw + ld + (it & 1) * ld;
+  float* sRo = I.jw + ld + ((it + 1) & 1) * ld;
+  const float* Ri = flip ? I.jw : I.R;
+  float* Ro = flip ? I.R : I.jw;
+  const int* S = reinterpret_cast<const int*>(I.jw + 3 * ld);
+  const int* pos = reinterpret_cast<const int*>(I.jw + 4 * ld);
+  const int ks = reinterpret_cast<const int*>(I.jw + 5 * ld)[0];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r1 = min(I.n, tl.row0 + rows_per_tile);
+  for (int r = tl.row0 + w; r < r1; r += 4) {
+    const float* gc = I.Gc + size_t(r) * ks;
+    const int pr = pos[r];
+    float acc = 0.0f;
+    for (int s = lane; s < ks; s += kWave)
+      if (s != pr) acc += gc[s] * sRi[s];
     acc = wave_sum(acc);
-    const double res = double(y[row]) - acc;
+    if (lane == 0) {
+      const float d = I.G[size_t(r) * ld + r];
+      const bool tiny = !(d >= 1e-12f);
+      const float Rv = Ri[r];
+      const float Rnew = tiny ? 0.0f : Rv + dtc * ((I.b[r] - acc) / d - Rv);
+      Ro[r] = Rnew;
+      if (pr >= 0) sRo[pr] = Rnew;
+    }
+  }
+  (void)S;
+}
+
+// eq. 3 objective and the per-instance report.  Phase 1: FP64 partial sums
+// of squared residuals over fixed row chunks of A; phase 2: their ordered sum.
+__global__ void __launch_bounds__(256)
+bobj_partial_kernel(const BInst* __restrict__ insts) {
+  __shared__ double wpart[4];
+  const int k = blockIdx.x / kObjChunks, ch = blockIdx.x % kObjChunks;
+  const BInst I = insts[k];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double r2 = 0.0;
+  for (int row = ch * 4 + w; row < I.m; row += kObjChunks * 4) {
+    double acc = 0.0;
+    const float* a = I.A + size_t(row) * I.lda;
+    for (int j = lane; j < I.n; j += kWave)
+      if (I.sig[j]) acc += double(a[j]) * double(I.R[j]);
+    acc = wave_sum(acc);
+    const double res = double(I.y[row]) - acc;
     r2 += res * res;
   }
-  if (lane == 0) part[wv] = r2;
+  if (lane == 0) wpart[w] = r2;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double* part = reinterpret_cast<double*>(I.jw + 5 * I.ld + 64);
+    part[ch] = ((wpart[0] + wpart[1]) + wpart[2]) + wpart[3];
+  }
+}
+
+__global__ void __launch_bounds__(256)
+bobj_final_kernel(const BInst* __restrict__ insts, double lam, int64_t steps_per_alt, int n_outer, int P) {
+  __shared__ int cnt[256];
+  const BInst I = insts[blockIdx.x];
   int c = 0;
-  for (int j = threadIdx.x; j < I.n; j += 256) c += sg[j] ? 1 : 0;
+  for (int j = threadIdx.x; j < I.n; j += 256) c += I.sig[j] ? 1 : 0;
   cnt[threadIdx.x] = c;
   __syncthreads();
   if (threadIdx.x == 0) {
     int s = 0;
     for (int t = 0; t < 256; ++t) s += cnt[t];
-    const double rr = ((part[0] + part[1]) + part[2]) + part[3];
+    const double* part = reinterpret_cast<const double*>(I.jw + 5 * I.ld + 64);
+    double rr = 0.0;
+    for (int ch = 0; ch < kObjChunks; ++ch) rr += part[ch];
     const bool own = lam < 0.0;
     const double lm = own ? 0.5 * I.eta * I.eta : lam;
     const int no = own ? I.alt + 1 : n_outer;
@@ -557,19 +696,19 @@ static const void* step_kernel_ptr() {
 
 template <typename JT, int FIELD>
 static const void* step_kernel_q(int qb, int rb) {
-#define L0_RB(Q)                                               \
-  switch (rb) {                                                \
-    case 1: return step_kernel_ptr<JT, FIELD, Q, 1>();         \
-    case 2: return step_kernel_ptr<JT, FIELD, Q, 2>();         \
-    case 4: return step_kernel_ptr<JT, FIELD, Q, 4>();         \
-  }                                                            \
-  return nullptr;
-  switch (qb) {
-    case 1: { L0_RB(1) }
-    case 2: { L0_RB(2) }
-    case 4: { L0_RB(4) }
+  if (qb == 1) {
+    if (rb == 1) return step_kernel_ptr<JT, FIELD, 1, 1>();
+    if (rb == 2) return step_kernel_ptr<JT, FIELD, 1, 2>();
+    if (rb == 4) return step_kernel_ptr<JT, FIELD, 1, 4>();
+    if (rb == 8) return step_kernel_ptr<JT, FIELD, 1, 8>();
+  } else if (qb == 2) {
+    if (rb == 1) return step_kernel_ptr<JT, FIELD, 2, 1>();
+    if (rb == 2) return step_kernel_ptr<JT, FIELD, 2, 2>();
+    if (rb == 4) return step_kernel_ptr<JT, FIELD, 2, 4>();
+  } else if (qb == 4) {
+    if (rb == 1) return step_kernel_ptr<JT, FIELD, 4, 1>();
+    if (rb == 2) return step_kernel_ptr<JT, FIELD, 4, 2>();
   }
-#undef L0_RB
   return nullptr;
 }
 
@@ -621,25 +760,43 @@ l0cim_status launch_binit(const BatchDev& d, int P, int alt, double std, int64_t
   return L0CIM_OK;
 }
 
+l0cim_status launch_bbits(const BatchDev& d, int64_t total_words, hipStream_t s) {
+  int blocks = int((total_words + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(bbits_kernel, dim3(blocks), dim3(256), 0, s, d.insts, d.st_prefix, d.count, total_words);
+  L0_LAUNCHED("bbits_kernel");
+  return L0CIM_OK;
+}
+
 l0cim_status launch_bselect(const BatchDev& d, int P, hipStream_t s) {
   hipLaunchKernelGGL(bselect_kernel, dim3(d.count), dim3(256), 0, s, d.insts, P);
   L0_LAUNCHED("bselect_kernel");
   return L0CIM_OK;
 }
 
-l0cim_status launch_bjacobi(const BatchDev& d, int max_ld, double dtc, int iters, hipStream_t s) {
-  const size_t lds = size_t(max_ld) * 4 * 3;
-  L0_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(bjacobi_kernel),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-  hipLaunchKernelGGL(bjacobi_kernel, dim3(d.count), dim3(1024), lds, s, d.insts, float(dtc), iters);
-  L0_LAUNCHED("bjacobi_kernel");
+l0cim_status launch_bjacobi(const BatchDev& d, int ntiles, int rows_per_tile, double dtc, int iters,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(bjac_prep_kernel, dim3(d.count), dim3(256), 0, s, d.insts);
+  L0_LAUNCHED("bjac_prep_kernel");
+  if (iters <= 0) return L0CIM_OK;
+  hipLaunchKernelGGL(bjac_compact_kernel, dim3(ntiles), dim3(256), 0, s, d.tiles, d.insts, rows_per_tile);
+  L0_LAUNCHED("bjac_compact_kernel");
+  for (int it = 0; it < iters; ++it) {
+    const int flip = ((iters - it) & 1) ? 1 : 0;
+    hipLaunchKernelGGL(bjac_sweep_kernel, dim3(ntiles), dim3(256), 0, s, d.tiles, d.insts, rows_per_tile,
+                       float(dtc), it, flip);
+    L0_LAUNCHED("bjac_sweep_kernel");
+  }
   return L0CIM_OK;
 }
 
 l0cim_status launch_bobjective(const BatchDev& d, double lam, int64_t steps_per_alt, int n_outer, int P,
                                hipStream_t s) {
-  hipLaunchKernelGGL(bobjective_kernel, dim3(d.count), dim3(256), 0, s, d.insts, lam, steps_per_alt, n_outer, P);
-  L0_LAUNCHED("bobjective_kernel");
+  hipLaunchKernelGGL(bobj_partial_kernel, dim3(d.count * kObjChunks), dim3(256), 0, s, d.insts);
+  L0_LAUNCHED("bobj_partial_kernel");
+  hipLaunchKernelGGL(bobj_final_kernel, dim3(d.count), dim3(256), 0, s, d.insts, lam, steps_per_alt, n_outer, P);
+  L0_LAUNCHED("bobj_final_kernel");
   return L0CIM_OK;
 }
 

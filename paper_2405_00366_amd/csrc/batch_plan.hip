@@ -18,7 +18,7 @@ using namespace l0;
 // per-spin vectors, state, supports) and into the caller's pools (A, y, R, sigma).
 struct PoolSlot {
   int n, m, ld, lda;
-  int64_t oG, oV, oS, oSig, oX, oA, oY;
+  int64_t oG, oJ, oV, oS, oSig, oX, oA, oY, oW;
   uint64_t seed;
 };
 
@@ -30,10 +30,10 @@ struct l0cim_batch_plan_s {
   std::vector<l0cim_instance> inst;
   std::vector<PoolSlot> base;
   std::vector<int64_t> row_prefix, st_prefix;
-  int64_t nG = 0, nV = 0, nS = 0, nSig = 0, max_tiles = 0;
+  int64_t nG = 0, nJ = 0, nV = 0, nS = 0, nSig = 0, nW = 0, max_tiles = 0;
   int max_ld = 0, max_n = 0;
   struct {
-    size_t insts, tiles, rowp, stp, eta, G, Gc, b, z, rs, J, c, c2, e, sig, hpart, chol, total;
+    size_t insts, tiles, rowp, stp, eta, G, Gc, b, z, rs, J, c, c2, e, xb, xb2, sig, hpart, jw, chol, total;
   } off{};
   int rb = 0;
   bool tuned = false;
@@ -61,7 +61,7 @@ int round_up_i(int x, int a) { return (x + a - 1) / a * a; }
 // the tail of a step is made of small tiles.  Results do not depend on the
 // order: every output row is computed by one wavefront in a fixed k order.
 void tile_table(const l0cim_batch_plan_s* p, int rb, std::vector<BTile>& tiles) {
-  const int tr = 64 * rb;
+  const int tr = 16 * rb;
   std::vector<int> order(p->count);
   for (int k = 0; k < p->count; ++k) order[k] = k;
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return p->base[x].n > p->base[y].n; });
@@ -92,7 +92,7 @@ BInst make_inst(const l0cim_batch_plan_s* p, int k, const Pools& pl) {
   I.y = pl.y + q.oY;
   I.G = reinterpret_cast<float*>(b + p->off.G) + q.oG;
   I.Gc = reinterpret_cast<float*>(b + p->off.Gc) + q.oG;
-  I.J = b + p->off.J + size_t(q.oG) * dtype_size(p->jdt);
+  I.J = b + p->off.J + size_t(q.oJ) * dtype_size(p->jdt);
   I.b = reinterpret_cast<float*>(b + p->off.b) + q.oV;
   I.z = reinterpret_cast<float*>(b + p->off.z) + q.oV;
   I.rs = reinterpret_cast<float*>(b + p->off.rs) + q.oV;
@@ -101,7 +101,10 @@ BInst make_inst(const l0cim_batch_plan_s* p, int k, const Pools& pl) {
   I.c = reinterpret_cast<float*>(b + p->off.c) + q.oS;
   I.c2 = reinterpret_cast<float*>(b + p->off.c2) + q.oS;
   I.e = reinterpret_cast<float*>(b + p->off.e) + q.oS;
+  I.xb = reinterpret_cast<uint32_t*>(b + p->off.xb) + q.oS / 32;
+  I.xb2 = reinterpret_cast<uint32_t*>(b + p->off.xb2) + q.oS / 32;
   I.sig_all = reinterpret_cast<uint8_t*>(b + p->off.sig) + q.oSig;
+  I.jw = reinterpret_cast<float*>(b + p->off.jw) + q.oW;
   I.hpart = reinterpret_cast<double*>(b + p->off.hpart) + q.oSig;
   I.st = pl.stats + k;
   I.status = &pl.stats[k].status_bits;
@@ -213,7 +216,8 @@ l0cim_status autotune(l0cim_batch_plan_s* p, const BatchDev& d, const Pools& pl,
   float best = 1e30f;
   int best_rb = 2;
   const int steps = p->cim.n_steps > 0 ? (p->cim.n_steps < 8 ? p->cim.n_steps : 8) : 0;
-  for (int rb : {1, 2, 4}) {
+  for (int rb : {1, 2, 4, 8}) {
+    if (!step_shape_ok(p->qb, rb)) continue;
     l0cim_status st = upload_tables(p, d, pl, rb, s, &ntiles);
     if (st != L0CIM_OK) return st;
     if (steps == 0) break;
@@ -283,21 +287,25 @@ l0cim_status l0cim_batch_plan_create(int32_t count, const l0cim_instance* inst, 
     b.ld = round_up_i(I.n, 32);
     b.lda = int(I.lda);
     b.oG = p->nG;
+    b.oJ = p->nJ;
     b.oV = p->nV;
     b.oS = p->nS;
     b.oSig = p->nSig;
+    b.oW = p->nW;
     b.oX = I.x_offset;
     b.oA = I.a_offset;
     b.oY = I.y_offset;
     b.seed = I.seed;
     p->nG += int64_t(b.n) * b.ld;
+    p->nJ += int64_t(round_up16(b.n)) * b.ld;
     p->nV += b.ld;
     p->nS += int64_t(p->P) * b.ld;
     p->nSig += int64_t(p->P) * b.n;
-    p->max_tiles += (b.n + 63) / 64;
+    p->nW += int64_t(bjac_words(b.ld));
+    p->max_tiles += (b.n + 15) / 16;
     p->max_ld = b.ld > p->max_ld ? b.ld : p->max_ld;
     p->max_n = b.n > p->max_n ? b.n : p->max_n;
-    p->row_prefix[k + 1] = p->row_prefix[k] + b.n;
+    p->row_prefix[k + 1] = p->row_prefix[k] + round_up16(b.n);
     p->st_prefix[k + 1] = p->st_prefix[k] + int64_t(p->P) * b.ld;
     p->base[k] = b;
   }
@@ -317,12 +325,15 @@ l0cim_status l0cim_batch_plan_create(int32_t count, const l0cim_instance* inst, 
   p->off.b = take(size_t(p->nV) * 4);
   p->off.z = take(size_t(p->nV) * 4);
   p->off.rs = take(size_t(p->nV) * 4);
-  p->off.J = take(size_t(p->nG) * jsz);
+  p->off.J = take(size_t(p->nJ) * jsz);
   p->off.c = take(size_t(p->nS) * 4);
   p->off.c2 = take(size_t(p->nS) * 4);
   p->off.e = take(size_t(p->nS) * 4);
+  p->off.xb = take(size_t(p->nS) / 8);
+  p->off.xb2 = take(size_t(p->nS) / 8);
   p->off.sig = take(size_t(p->nSig));
   p->off.hpart = take(size_t(p->nSig) * sizeof(double));
+  p->off.jw = take(size_t(p->nW) * 4);
   p->off.chol = take(sp->final_refit_f64 ? chol_ws_bytes(p->max_n) : 0);
   p->off.total = o;
   p->key = shape_key(p);
@@ -347,7 +358,7 @@ l0cim_status l0cim_batch_plan_info(l0cim_batch_plan plan, int32_t* rows_per_tile
   int rb = plan->rb ? plan->rb : 2;
   std::vector<BTile> t;
   tile_table(plan, rb, t);
-  if (rows_per_tile) *rows_per_tile = 64 * rb;
+  if (rows_per_tile) *rows_per_tile = 16 * rb;
   if (tiles) *tiles = int32_t(t.size());
   if (tuned) *tuned = plan->tuned ? 1 : 0;
   return L0CIM_OK;
@@ -396,6 +407,7 @@ l0cim_status l0cim_solve_batched(l0cim_batch_plan p, const float* A, const float
     L0_TRY(launch_bset_scalar(const_cast<double*>(d.eta), p->sp.eta_init, s));
     L0_TRY(launch_bcouplings(d, p->jdt, total_rows, s));
     L0_TRY(launch_binit(d, p->P, 0, p->cim.c0_std, total_state, s));
+    if (p->cim.field == L0CIM_FIELD_BN) L0_TRY(launch_bbits(d, total_state / 32, s));
     L0_TRY(autotune(p, d, pl, s));
   }
   L0_TRY(upload_tables(p, d, pl, p->rb, s, &ntiles));
@@ -425,6 +437,7 @@ l0cim_status l0cim_solve_batched(l0cim_batch_plan p, const float* A, const float
     L0_TRY(launch_bset_scalar(const_cast<double*>(d.eta), eta, s));
     L0_TRY(launch_bcouplings(d, p->jdt, total_rows, s));
     L0_TRY(launch_binit(d, p->P, i, p->cim.c0_std, total_state, s));
+    if (p->cim.field == L0CIM_FIELD_BN) L0_TRY(launch_bbits(d, total_state / 32, s));
     {
       ProfileScope prof(s);
       if (use_graph) {
@@ -434,7 +447,7 @@ l0cim_status l0cim_solve_batched(l0cim_batch_plan p, const float* A, const float
       }
     }
     L0_TRY(launch_bselect(d, p->P, s));
-    L0_TRY(launch_bjacobi(d, p->max_ld, p->sp.dtc, p->sp.cdp_iters, s));
+    L0_TRY(launch_bjacobi(d, ntiles, 16 * p->rb, p->sp.dtc, p->sp.cdp_iters, s));
   }
   if (p->sp.final_refit_f64) {
     void* cws = base + p->off.chol;

@@ -1,7 +1,8 @@
 // Single-instance CIM run on the matrix cores: the batched MFMA step kernel
 // applied to a one-instance table.  Used when several replicas make J X a
 // dense product and the couplings are streamed every step (for example the
-// MRI-shaped workload, N = 16384 with 64 replicas).  The instance and tile
+// MRI-shaped workload, N = 16384 with 64 replicas).  The caller's row-major
+// couplings are copied once into the panel layout; the instance and tile
 // tables and the padded copies of the state are written by a setup kernel,
 // so the whole run is a sequence of kernel launches on the caller's stream.
 #include "batch.h"
@@ -37,12 +38,13 @@ mat_setup_kernel(BInst I, BTile* __restrict__ tiles, int ntiles, int tr, BInst* 
   }
 }
 
+// Row r (< n16) of the caller's couplings into the panel layout, zero padded.
 template <typename JT>
 __global__ void __launch_bounds__(256)
 mat_copyJ_kernel(const JT* __restrict__ J, int64_t ldj, JT* __restrict__ Jp, int n, int ld) {
   const int r = blockIdx.y;
   for (int j = blockIdx.x * 256 + threadIdx.x; j < ld; j += gridDim.x * 256)
-    Jp[size_t(r) * ld + j] = j < n ? J[size_t(r) * ldj + j] : JT(0.0f);
+    Jp[jpanel_offset(r, j, ld, int(sizeof(JT)))] = (r < n && j < n) ? J[size_t(r) * ldj + j] : JT(0.0f);
 }
 
 __global__ void __launch_bounds__(256)
@@ -65,12 +67,12 @@ __global__ void mat_hsum_kernel(const double* __restrict__ hrow, int n, int P, d
 }
 
 struct MatLayout {
-  size_t inst, tiles, eta, rs, z, c, c2, e, hrow, J, total;
+  size_t inst, tiles, eta, rs, z, c, c2, e, xb, xb2, hrow, J, total;
 };
 
-MatLayout mat_layout(int n, int P, size_t jsize, bool copyJ) {
+MatLayout mat_layout(int n, int P, size_t jsize) {
   const int ld = (n + kLd - 1) / kLd * kLd;
-  const size_t ntiles = size_t((n + 63) / 64);
+  const size_t ntiles = size_t((n + 15) / 16);
   MatLayout L;
   size_t o = 0;
   auto take = [&](size_t b) {
@@ -86,21 +88,19 @@ MatLayout mat_layout(int n, int P, size_t jsize, bool copyJ) {
   L.c = take(size_t(P) * ld * 4);
   L.c2 = take(size_t(P) * ld * 4);
   L.e = take(size_t(P) * ld * 4);
+  L.xb = take(size_t(P) * ld / 8);
+  L.xb2 = take(size_t(P) * ld / 8);
   L.hrow = take(size_t(P) * n * 8);
-  L.J = take(copyJ ? size_t(n) * ld * jsize : 0);
+  L.J = take(size_t(round_up16(n)) * ld * jsize);
   L.total = o;
   return L;
 }
 
 }  // namespace
 
-size_t matrix_ws_bytes(int n, int P, size_t jsize) {
-  return mat_layout(n, P, jsize, n % kLd != 0).total;
-}
+size_t matrix_ws_bytes(int n, int P, size_t jsize) { return mat_layout(n, P, jsize).total; }
 
-bool matrix_supported(int n, int P, int64_t ldj) {
-  return P >= 1 && P <= 64 && (n % kLd != 0 || ldj % kLd == 0);
-}
+bool matrix_supported(int n, int P, int64_t ldj) { return P >= 1 && P <= 64 && n >= 1 && ldj >= n; }
 
 l0cim_status launch_matrix_run(int n, int P, l0cim_dtype jdt, const void* J, int64_t ldj, const float* rscale,
                                const float* z, const CimArgs& a, float* c, float* e, uint8_t* sigma, double* H,
@@ -109,12 +109,8 @@ l0cim_status launch_matrix_run(int n, int P, l0cim_dtype jdt, const void* J, int
   l0cim_status st = device_info(&dev);
   if (st != L0CIM_OK) return st;
   const int ld = (n + kLd - 1) / kLd * kLd;
-  const bool copyJ = (ldj % kLd) != 0;
-  if (copyJ && n % kLd == 0)
-    return set_error(L0CIM_ERR_UNSUPPORTED, "matrix run: leading dimension %lld of J is not a multiple of 32",
-                     (long long)ldj);
   const size_t jsize = dtype_size(jdt);
-  const MatLayout Lw = mat_layout(n, P, jsize, copyJ);
+  const MatLayout Lw = mat_layout(n, P, jsize);
   char* b = static_cast<char*>(ws);
   BInst* dinst = reinterpret_cast<BInst*>(b + Lw.inst);
   BTile* dtiles = reinterpret_cast<BTile*>(b + Lw.tiles);
@@ -125,11 +121,11 @@ l0cim_status launch_matrix_run(int n, int P, l0cim_dtype jdt, const void* J, int
   float* dc2 = reinterpret_cast<float*>(b + Lw.c2);
   float* de = reinterpret_cast<float*>(b + Lw.e);
   double* dh = reinterpret_cast<double*>(b + Lw.hrow);
-  const void* Jm = J;
-  int64_t ldm = ldj;
-  if (copyJ) {
-    void* Jp = b + Lw.J;
-    dim3 g((ld + 255) / 256, n);
+  uint32_t* dxb = reinterpret_cast<uint32_t*>(b + Lw.xb);
+  uint32_t* dxb2 = reinterpret_cast<uint32_t*>(b + Lw.xb2);
+  void* Jp = b + Lw.J;
+  {
+    dim3 g((ld + 255) / 256, round_up16(n));
     if (jdt == L0CIM_F32)
       hipLaunchKernelGGL(mat_copyJ_kernel<float>, g, dim3(256), 0, s, (const float*)J, ldj, (float*)Jp, n, ld);
     else if (jdt == L0CIM_BF16)
@@ -139,29 +135,29 @@ l0cim_status launch_matrix_run(int n, int P, l0cim_dtype jdt, const void* J, int
       hipLaunchKernelGGL(mat_copyJ_kernel<__hip_fp8_e4m3>, g, dim3(256), 0, s, (const __hip_fp8_e4m3*)J, ldj,
                          (__hip_fp8_e4m3*)Jp, n, ld);
     L0_LAUNCHED("mat_copyJ_kernel");
-    Jm = Jp;
-    ldm = ld;
   }
-  // Tile shape: the largest row block that still gives every CU two tiles.
+  // Tile shape: the largest row block that still gives every CU four tiles.
+  const int qb = P <= 16 ? 1 : (P <= 32 ? 2 : 4);
   int rb = 1;
-  if (rb_hint == 1 || rb_hint == 2 || rb_hint == 4) rb = rb_hint;
+  if (step_shape_ok(qb, rb_hint)) rb = rb_hint;
   else
-    for (int cand : {4, 2}) {
-      if ((n + 64 * cand - 1) / (64 * cand) >= 2 * dev.cu_count) {
+    for (int cand : {8, 4, 2}) {
+      if (step_shape_ok(qb, cand) && (n + 16 * cand - 1) / (16 * cand) >= 4 * dev.cu_count) {
         rb = cand;
         break;
       }
     }
-  const int qb = P <= 16 ? 1 : (P <= 32 ? 2 : 4);
-  const int tr = 64 * rb;
+  const int tr = 16 * rb;
   const int ntiles = (n + tr - 1) / tr;
   BInst I{};
   I.n = n;
   I.ld = ld;
-  I.ldj = int(ldm);
+  I.ldj = ld;
   I.tile0 = 0;
   I.ntiles = ntiles;
-  I.J = const_cast<void*>(Jm);
+  I.J = Jp;
+  I.xb = dxb;
+  I.xb2 = dxb2;
   I.z = dz;
   I.rs = drs;
   I.c = dc;
@@ -202,6 +198,10 @@ l0cim_status launch_matrix_run(int n, int P, l0cim_dtype jdt, const void* J, int
   d.insts = dinst;
   d.tiles = dtiles;
   d.eta = deta;
+  if (a.field == L0CIM_FIELD_BN) {
+    st = launch_bbits(d, int64_t(P) * ld / 32, s);
+    if (st != L0CIM_OK) return st;
+  }
   {
     ProfileScope prof(s);
     st = enqueue_bsteps(d, fn, sa, ntiles, 0, a.n_steps, s);

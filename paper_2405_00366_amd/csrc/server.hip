@@ -31,7 +31,7 @@ int round_up32(int x) { return (x + 31) / 32 * 32; }
 
 // Byte offsets of one request's arrays inside its arena block.
 struct ReqLayout {
-  size_t G, Gc, J, b, z, rs, R, sig, c, c2, e, sig_all, hpart, A, y, total;
+  size_t G, Gc, J, b, z, rs, R, sig, c, c2, e, xb, xb2, sig_all, hpart, jw, A, y, total;
 };
 
 ReqLayout req_layout(int m, int n, int P, size_t jsz) {
@@ -45,7 +45,7 @@ ReqLayout req_layout(int m, int n, int P, size_t jsz) {
   };
   L.G = take(size_t(n) * ld * 4);
   L.Gc = take(size_t(n) * ld * 4);
-  L.J = take(size_t(n) * ld * jsz);
+  L.J = take(size_t(round_up16(n)) * ld * jsz);
   L.b = take(ld * 4);
   L.z = take(ld * 4);
   L.rs = take(ld * 4);
@@ -54,8 +54,11 @@ ReqLayout req_layout(int m, int n, int P, size_t jsz) {
   L.c = take(size_t(P) * ld * 4);
   L.c2 = take(size_t(P) * ld * 4);
   L.e = take(size_t(P) * ld * 4);
+  L.xb = take(size_t(P) * ld / 8);
+  L.xb2 = take(size_t(P) * ld / 8);
   L.sig_all = take(size_t(P) * n);
   L.hpart = take(size_t(P) * n * 8);
+  L.jw = take(bjac_words(int(ld)) * 4);
   L.A = take(size_t(m) * n * 4);
   L.y = take(size_t(m) * 4);
   L.total = o;
@@ -70,7 +73,7 @@ struct HeadLayout {
 
 HeadLayout head_layout(int max_slots, int max_n, bool chol) {
   HeadLayout H;
-  H.max_tiles = max_slots * ((max_n + 63) / 64);
+  H.max_tiles = max_slots * ((max_n + 15) / 16);
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t at = o;
@@ -197,8 +200,11 @@ struct l0cim_server_s {
     I.c = reinterpret_cast<float*>(b + L.c);
     I.c2 = reinterpret_cast<float*>(b + L.c2);
     I.e = reinterpret_cast<float*>(b + L.e);
+    I.xb = reinterpret_cast<uint32_t*>(b + L.xb);
+    I.xb2 = reinterpret_cast<uint32_t*>(b + L.xb2);
     I.sig_all = reinterpret_cast<uint8_t*>(b + L.sig_all);
     I.hpart = reinterpret_cast<double*>(b + L.hpart);
+    I.jw = reinterpret_cast<float*>(b + L.jw);
     I.st = slot_stats(r.slot);
     I.status = &I.st->status_bits;
     return I;
@@ -252,16 +258,16 @@ l0cim_status tick(l0cim_server_s* sv, int* n_done) {
   // tile shape: the largest row block that still gives every CU two tiles
   auto tiles_for = [&](int rb) {
     int64_t t = 0;
-    for (const Req& r : sv->active) t += (r.n + 64 * rb - 1) / (64 * rb);
+    for (const Req& r : sv->active) t += (r.n + 16 * rb - 1) / (16 * rb);
     return t;
   };
   int rb = 1;
-  for (int cand : {4, 2})
-    if (tiles_for(cand) >= 2 * sv->cu_count) {
+  for (int cand : {8, 4, 2})
+    if (step_shape_ok(sv->qb, cand) && tiles_for(cand) >= 4 * sv->cu_count) {
       rb = cand;
       break;
     }
-  const int tr = 64 * rb;
+  const int tr = 16 * rb;
   // host tables in the pinned staging buffer (the previous tick has finished)
   char* h = static_cast<char*>(sv->staging);
   BInst* hi = reinterpret_cast<BInst*>(h);
@@ -275,13 +281,11 @@ l0cim_status tick(l0cim_server_s* sv, int* n_done) {
   int nt = 0;
   hrow[0] = 0;
   hst[0] = 0;
-  int max_ld = 0;
   for (int k = 0; k < count; ++k) {
     const Req& r = sv->active[k];
     hi[k] = sv->make_inst(r);
-    hrow[k + 1] = hrow[k] + r.n;
+    hrow[k + 1] = hrow[k] + round_up16(r.n);
     hst[k + 1] = hst[k] + int64_t(sv->P) * hi[k].ld;
-    max_ld = std::max(max_ld, hi[k].ld);
   }
   for (int k : order) {
     hi[k].tile0 = nt;
@@ -303,6 +307,7 @@ l0cim_status tick(l0cim_server_s* sv, int* n_done) {
   // one alternation
   L0_TRY(launch_bcouplings(d, sv->jdt, hrow[count], s));
   L0_TRY(launch_binit(d, sv->P, -1, sv->cim.c0_std, hst[count], s));
+  if (sv->cim.field == L0CIM_FIELD_BN) L0_TRY(launch_bbits(d, hst[count] / 32, s));
   const void* fn = batch_step_kernel(sv->jdt, sv->cim.field, sv->qb, rb);
   if (!fn) return set_error(L0CIM_ERR_UNSUPPORTED, "server: no step kernel for this shape");
   BStepArgs a{};
@@ -324,7 +329,7 @@ l0cim_status tick(l0cim_server_s* sv, int* n_done) {
     L0_TRY(enqueue_bsteps(d, fn, a, nt, 0, sv->cim.n_steps, s));
   }
   L0_TRY(launch_bselect(d, sv->P, s));
-  L0_TRY(launch_bjacobi(d, max_ld, sv->sp.dtc, sv->sp.cdp_iters, s));
+  L0_TRY(launch_bjacobi(d, nt, tr, sv->sp.dtc, sv->sp.cdp_iters, s));
   // report the requests that are done
   if (nret) {
     BatchDev dr{};

@@ -54,9 +54,10 @@ def test_workspace_sizes():
     lib = L.lib()
     cim, sp = L.cim_params(), L.solve_params()
     ws = lib.l0cim_solve_workspace_bytes(L.F32, 1000, 2000, ctypes.byref(cim), ctypes.byref(sp))
-    # G and J take 2 * 2000^2 * 4 bytes; the FP64 Cholesky refit's padded
-    # factor adds at most 2048^2 * 8 bytes on top
-    assert 32_000_000 <= ws < 32_000_000 + 2048 * 2048 * 8 + 4_000_000
+    # G and J take 2 * 2000^2 * 4 bytes; the matrix-core run's panel copy of
+    # J (2000 x 2016 x 4) and the FP64 Cholesky refit's padded factor
+    # (2048^2 x 8) come on top
+    assert 32_000_000 <= ws < 32_000_000 + 2000 * 2016 * 4 + 2048 * 2048 * 8 + 4_000_000
     assert lib.l0cim_mfcim_run_workspace_bytes(L.F32, 2000, 1, L.F32) >= 2 * 2000 * 8
     assert lib.l0cim_mfcim_run_workspace_bytes(L.F64, 2000, 1, L.F64) >= 2 * 2000 * 16
     assert lib.l0cim_update_r_workspace_bytes(L.F64, 100, L.CDP_CHOL_F64) >= 100 * 100 * 8
@@ -142,15 +143,18 @@ def _al(x):
 
 
 def test_server_footprint_formula():
-    """Per-request arena bytes: G, compacted G and J (n x ld), four per-spin
-    vectors and sigma (ld), three P x ld state arrays, P x n supports and
-    energy terms, and the copies of A and y; every array 256-byte aligned."""
+    """Per-request arena bytes: G and compacted G (n x ld), J (n padded to 16
+    x ld), four per-spin vectors and sigma (ld), three P x ld state arrays,
+    two P x ld support-bit arrays, P x n supports and energy terms, the CDP
+    scratch, and the copies of A and y; every array 256-byte aligned."""
     lib = L.lib()
     for (m, n, P, jdt, jb) in [(50, 96, 8, L.F32, 4), (4915, 8192, 8, L.BF16, 2), (7, 33, 64, L.FP8E4M3, 1)]:
         sp = L.solve_params(replicas=P, j_dtype=jdt)
         ld = (n + 31) // 32 * 32
-        want = (2 * _al(n * ld * 4) + _al(n * ld * jb) + 4 * _al(ld * 4) + _al(ld) + 3 * _al(P * ld * 4)
-                + _al(P * n) + _al(P * n * 8) + _al(m * n * 4) + _al(m * 4))
+        n16 = (n + 15) // 16 * 16
+        want = (2 * _al(n * ld * 4) + _al(n16 * ld * jb) + 4 * _al(ld * 4) + _al(ld) + 3 * _al(P * ld * 4)
+                + 2 * _al(P * ld // 8)
+                + _al(P * n) + _al(P * n * 8) + _al((5 * ld + 192) * 4) + _al(m * n * 4) + _al(m * 4))
         assert lib.l0cim_server_request_bytes(m, n, ctypes.byref(sp)) == want
     sp = L.solve_params()
     assert lib.l0cim_server_request_bytes(0, 10, ctypes.byref(sp)) == 0
