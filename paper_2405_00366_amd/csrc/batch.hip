@@ -169,12 +169,23 @@ binit_kernel(const BInst* __restrict__ insts, const int64_t* __restrict__ st_pre
 //   B: X[q = 16 qb + li][32 c + 8 lk + t]: amplitudes (continuous field) or
 //      bits 8 lk + t of the support word (binarised field).
 
-template <typename JT> struct ARaw;
-template <> struct ARaw<float> { float4 v0, v1; };
-template <> struct ARaw<__hip_bfloat16> { uint4 v; };
-template <> struct ARaw<__hip_fp8_e4m3> { uint2 v; };
+// Loads through the global address space: pointers read from the instance
+// table are generic, and generic (flat) loads would also hold the LDS/scalar
+// counter, so a wait for one chunk would drain every chunk in flight.
+template <typename T>
+__device__ inline T gload(const void* p) {
+  return *(const __attribute__((address_space(1))) T*)(p);
+}
 
-template <int FIELD> struct BRaw { float4 v0, v1; };
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+typedef unsigned v2u __attribute__((ext_vector_type(2)));
+
+template <typename JT> struct ARaw;
+template <> struct ARaw<float> { v4f v0, v1; };
+template <> struct ARaw<__hip_bfloat16> { v4u v; };
+template <> struct ARaw<__hip_fp8_e4m3> { v2u v; };
+
+template <int FIELD> struct BRaw { v4f v0, v1; };
 template <> struct BRaw<kBN> { uint32_t v; };
 
 template <typename JT, int FIELD, int RB, int QB>
@@ -192,7 +203,7 @@ constexpr int pipe_depth(int jsize, int field, int RB, int QB) {
 
 // 8 bits (bit t = column 8 lk + t) -> 8 bf16 values 0 / 1.
 __device__ inline v8bf bits_to_bf16(uint32_t byte) {
-  uint4 w;
+  v4u w;
   w.x = ((byte & 1u) ? 0x3F80u : 0u) | ((byte & 2u) ? 0x3F800000u : 0u);
   w.y = ((byte & 4u) ? 0x3F80u : 0u) | ((byte & 8u) ? 0x3F800000u : 0u);
   w.z = ((byte & 16u) ? 0x3F80u : 0u) | ((byte & 32u) ? 0x3F800000u : 0u);
@@ -202,7 +213,7 @@ __device__ inline v8bf bits_to_bf16(uint32_t byte) {
 
 // 8 e4m3 codes -> 8 bf16 (exact: f32 from the hardware conversion, then its
 // upper half, which carries every e4m3 value without rounding).
-__device__ inline v8bf fp8_to_bf16(uint2 v) {
+__device__ inline v8bf fp8_to_bf16(v2u v) {
   typedef float v2f __attribute__((ext_vector_type(2)));
   const v2f f0 = __builtin_amdgcn_cvt_pk_f32_fp8(int(v.x), false);
   const v2f f1 = __builtin_amdgcn_cvt_pk_f32_fp8(int(v.x), true);
@@ -211,7 +222,7 @@ __device__ inline v8bf fp8_to_bf16(uint2 v) {
   auto pack = [](v2f f) {
     return (__float_as_uint(f[0]) >> 16) | (__float_as_uint(f[1]) & 0xFFFF0000u);
   };
-  uint4 w;
+  v4u w;
   w.x = pack(f0);
   w.y = pack(f1);
   w.z = pack(f2);
@@ -241,12 +252,13 @@ bstep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, B
   const int c0 = (w * nch) >> 2, c1 = ((w + 1) * nch) >> 2;
   const int lane_off = kF32 ? (li * 4 + lk) * 4 : (li * 4 + lk) * 8;
 
-  bool pv[RB];
+  // Rows of panels past the instance and replicas past P read valid
+  // addresses of panel p0 / replica 0 instead; their sums are never used.
   const JT* pbase[RB];
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
-    pv[rb] = (p0 + rb) * 16 < n;
-    pbase[rb] = J + size_t(p0 + rb) * nch * 512 + lane_off;
+    const int pp = (p0 + rb) * 16 < n ? p0 + rb : p0;
+    pbase[rb] = J + size_t(pp) * nch * 512 + lane_off;
   }
   bool qon[QB];
   const float* cbase[QB];
@@ -255,8 +267,8 @@ bstep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, B
   for (int qb = 0; qb < QB; ++qb) {
     const int q = qb * 16 + li;
     qon[qb] = q < P;
-    cbase[qb] = cin + size_t(q) * ld + 8 * lk;
-    xbase[qb] = xin + size_t(q) * nch;
+    cbase[qb] = cin + size_t(q < P ? q : 0) * ld + 8 * lk;
+    xbase[qb] = xin + size_t(q < P ? q : 0) * nch;
   }
 
   v4f acc[RB][QB];
@@ -271,22 +283,22 @@ bstep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, B
     for (int rb = 0; rb < RB; ++rb) {
       const JT* src = pbase[rb] + size_t(c) * 512;
       if constexpr (kF32) {
-        S.a[rb].v0 = pv[rb] ? *reinterpret_cast<const float4*>(src) : make_float4(0.f, 0.f, 0.f, 0.f);
-        S.a[rb].v1 = pv[rb] ? *reinterpret_cast<const float4*>(src + 256) : make_float4(0.f, 0.f, 0.f, 0.f);
+        S.a[rb].v0 = gload<v4f>(src);
+        S.a[rb].v1 = gload<v4f>(src + 256);
       } else if constexpr (sizeof(JT) == 2) {
-        S.a[rb].v = pv[rb] ? *reinterpret_cast<const uint4*>(src) : make_uint4(0u, 0u, 0u, 0u);
+        S.a[rb].v = gload<v4u>(src);
       } else {
-        S.a[rb].v = pv[rb] ? *reinterpret_cast<const uint2*>(src) : make_uint2(0u, 0u);
+        S.a[rb].v = gload<v2u>(src);
       }
     }
 #pragma unroll
     for (int qb = 0; qb < QB; ++qb) {
       if constexpr (FIELD == kBN) {
-        S.b[qb].v = qon[qb] ? xbase[qb][c] : 0u;
+        S.b[qb].v = gload<uint32_t>(xbase[qb] + c);
       } else {
         const float* cs = cbase[qb] + c * 32;
-        S.b[qb].v0 = qon[qb] ? *reinterpret_cast<const float4*>(cs) : make_float4(0.f, 0.f, 0.f, 0.f);
-        S.b[qb].v1 = qon[qb] ? *reinterpret_cast<const float4*>(cs + 4) : make_float4(0.f, 0.f, 0.f, 0.f);
+        S.b[qb].v0 = gload<v4f>(cs);
+        S.b[qb].v1 = gload<v4f>(cs + 4);
       }
     }
   };
@@ -302,7 +314,7 @@ bstep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, B
 #pragma unroll
             for (int u = 0; u < 4; ++u) x[u] = float((byte >> (4 * h + u)) & 1u);
           } else {
-            const float4 c4 = h ? S.b[qb].v1 : S.b[qb].v0;
+            const v4f c4 = h ? S.b[qb].v1 : S.b[qb].v0;
             const bool on = qon[qb];
             x[0] = on ? xf<FIELD>(c4.x, st, last) : 0.f;
             x[1] = on ? xf<FIELD>(c4.y, st, last) : 0.f;
@@ -311,7 +323,7 @@ bstep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, B
           }
 #pragma unroll
           for (int rb = 0; rb < RB; ++rb) {
-            const float4 a4 = h ? S.a[rb].v1 : S.a[rb].v0;
+            const v4f a4 = h ? S.a[rb].v1 : S.a[rb].v0;
             acc[rb][qb] = mfma_f32(a4.x, x[0], acc[rb][qb]);
             acc[rb][qb] = mfma_f32(a4.y, x[1], acc[rb][qb]);
             acc[rb][qb] = mfma_f32(a4.z, x[2], acc[rb][qb]);
@@ -353,17 +365,32 @@ bstep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, B
     }
   };
 
+  // D chunks in flight: a branch-free steady state, then the last 2 D - 1 at most
   St buf[D];
+  if (c1 - c0 >= D) {
 #pragma unroll
-  for (int s = 0; s < D; ++s)
-    if (c0 + s < c1) load(c0 + s, buf[s]);
-  for (int c = c0; c < c1; c += D) {
+    for (int s = 0; s < D; ++s) load(c0 + s, buf[s]);
+    int c = c0;
+    for (; c + 2 * D <= c1; c += D) {
+#pragma unroll
+      for (int s = 0; s < D; ++s) {
+        compute(buf[s]);
+        load(c + D + s, buf[s]);
+      }
+    }
+    const int rem = c1 - c - D;
 #pragma unroll
     for (int s = 0; s < D; ++s) {
-      if (c + s < c1) {
-        compute(buf[s]);
-        if (c + s + D < c1) load(c + s + D, buf[s]);
-      }
+      compute(buf[s]);
+      if (s < rem) load(c + D + s, buf[s]);
+    }
+#pragma unroll
+    for (int s = 0; s < D; ++s)
+      if (s < rem) compute(buf[s]);
+  } else {
+    for (int c = c0; c < c1; ++c) {
+      load(c, buf[0]);
+      compute(buf[0]);
     }
   }
 
