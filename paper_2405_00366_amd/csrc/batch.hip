@@ -194,11 +194,11 @@ struct Stage {
   BRaw<FIELD> b[QB];
 };
 
-// Chunks in flight per wavefront: about 96 registers of operands.
+// Chunks in flight per wavefront: about 96 registers of operands, 2 to 12.
 constexpr int pipe_depth(int jsize, int field, int RB, int QB) {
   const int v = RB * (jsize == 4 ? 8 : (jsize == 2 ? 4 : 2)) + QB * (field == kBN ? 1 : 8);
   const int d = 96 / v;
-  return d < 2 ? 2 : (d > 8 ? 8 : d);
+  return d < 2 ? 2 : (d > 12 ? 12 : d);
 }
 
 // 8 bits (bit t = column 8 lk + t) -> 8 bf16 values 0 / 1.
@@ -493,22 +493,33 @@ bbits_kernel(const BInst* __restrict__ insts, const int64_t* __restrict__ st_pre
   }
 }
 
-// Per instance: H_q = sum of the per-spin eq. 4 terms in spin order (so the
-// result does not depend on the tile shape or on the rest of the batch),
-// lowest-energy replica (first on ties, NaN last), copy of its support.
+// Per instance: H_q = sum of the per-spin eq. 4 terms (256 contiguous runs
+// of spins summed in order, then a fixed tree, so the result depends only on
+// the instance), lowest-energy replica (first on ties, NaN last), copy of its
+// support.
 __global__ void __launch_bounds__(256)
 bselect_kernel(const BInst* __restrict__ insts, int P) {
-  __shared__ int qs;
+  __shared__ double part[256];
   __shared__ double hq[64];
+  __shared__ int qs;
   const BInst I = insts[blockIdx.x];
-  if (threadIdx.x < P) {
-    const double* hr = I.hpart + size_t(threadIdx.x) * I.n;
+  const int t = threadIdx.x, n = I.n;
+  const int chunk = (n + 255) / 256;
+  const int lo = min(n, t * chunk), hi = min(n, lo + chunk);
+  for (int q = 0; q < P; ++q) {
+    const double* hr = I.hpart + size_t(q) * n;
     double h = 0.0;
-    for (int r = 0; r < I.n; ++r) h += hr[r];
-    hq[threadIdx.x] = h;
+    for (int r = lo; r < hi; ++r) h += hr[r];
+    part[t] = h;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (t < w) part[t] += part[t + w];
+      __syncthreads();
+    }
+    if (t == 0) hq[q] = part[0];
+    __syncthreads();
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
+  if (t == 0) {
     int best = 0;
     double hb = hq[0];
     for (int q = 1; q < P; ++q) {
@@ -523,8 +534,8 @@ bselect_kernel(const BInst* __restrict__ insts, int P) {
     I.st->H = hb;
   }
   __syncthreads();
-  const uint8_t* src = I.sig_all + size_t(qs) * I.n;
-  for (int i = threadIdx.x; i < I.n; i += 256) I.sig[i] = src[i];
+  const uint8_t* src = I.sig_all + size_t(qs) * n;
+  for (int i = t; i < n; i += 256) I.sig[i] = src[i];
 }
 
 // ---------------------------------------------------------------------------

@@ -5,6 +5,9 @@
 // couplings are copied once into the panel layout; the instance and tile
 // tables and the padded copies of the state are written by a setup kernel,
 // so the whole run is a sequence of kernel launches on the caller's stream.
+#include <map>
+#include <mutex>
+
 #include "batch.h"
 
 namespace l0 {
@@ -57,13 +60,23 @@ mat_finish_kernel(const float* __restrict__ cf, const float* __restrict__ ef, fl
   }
 }
 
-// H_q = sum over spins (in order) of the eq. 4 terms of replica q.
-__global__ void mat_hsum_kernel(const double* __restrict__ hrow, int n, int P, double* __restrict__ H) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= P) return;
+// H_q = sum over spins of the eq. 4 terms of replica q: one workgroup per
+// replica, 256 contiguous runs of spins summed in order, then a fixed tree.
+__global__ void __launch_bounds__(256)
+mat_hsum_kernel(const double* __restrict__ hrow, int n, double* __restrict__ H) {
+  __shared__ double part[256];
+  const int q = blockIdx.x, t = threadIdx.x;
+  const int chunk = (n + 255) / 256;
+  const int lo = min(n, t * chunk), hi = min(n, lo + chunk);
   double h = 0.0;
-  for (int r = 0; r < n; ++r) h += hrow[size_t(q) * n + r];
-  H[q] = h;
+  for (int r = lo; r < hi; ++r) h += hrow[size_t(q) * n + r];
+  part[t] = h;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) part[t] += part[t + w];
+    __syncthreads();
+  }
+  if (t == 0) H[q] = part[0];
 }
 
 struct MatLayout {
@@ -94,6 +107,27 @@ MatLayout mat_layout(int n, int P, size_t jsize) {
   L.J = take(size_t(round_up16(n)) * ld * jsize);
   L.total = o;
   return L;
+}
+
+struct MatKey {
+  int n, P, jdt, field;
+  bool operator<(const MatKey& o) const {
+    return n != o.n ? n < o.n : (P != o.P ? P < o.P : (jdt != o.jdt ? jdt < o.jdt : field < o.field));
+  }
+};
+
+std::mutex g_shape_mu;
+std::map<MatKey, int> g_shape;
+
+int tuned_shape(const MatKey& k) {
+  std::lock_guard<std::mutex> lk(g_shape_mu);
+  auto it = g_shape.find(k);
+  return it == g_shape.end() ? 0 : it->second;
+}
+
+void remember_shape(const MatKey& k, int rb) {
+  std::lock_guard<std::mutex> lk(g_shape_mu);
+  g_shape[k] = rb;
 }
 
 }  // namespace
@@ -136,47 +170,7 @@ l0cim_status launch_matrix_run(int n, int P, l0cim_dtype jdt, const void* J, int
                          (__hip_fp8_e4m3*)Jp, n, ld);
     L0_LAUNCHED("mat_copyJ_kernel");
   }
-  // Tile shape: the largest row block that still gives every CU four tiles.
   const int qb = P <= 16 ? 1 : (P <= 32 ? 2 : 4);
-  int rb = 1;
-  if (step_shape_ok(qb, rb_hint)) rb = rb_hint;
-  else
-    for (int cand : {8, 4, 2}) {
-      if (step_shape_ok(qb, cand) && (n + 16 * cand - 1) / (16 * cand) >= 4 * dev.cu_count) {
-        rb = cand;
-        break;
-      }
-    }
-  const int tr = 16 * rb;
-  const int ntiles = (n + tr - 1) / tr;
-  BInst I{};
-  I.n = n;
-  I.ld = ld;
-  I.ldj = ld;
-  I.tile0 = 0;
-  I.ntiles = ntiles;
-  I.J = Jp;
-  I.xb = dxb;
-  I.xb2 = dxb2;
-  I.z = dz;
-  I.rs = drs;
-  I.c = dc;
-  I.c2 = dc2;
-  I.e = de;
-  I.sig_all = sigma;
-  I.hpart = dh;
-  I.status = status;
-  {
-    size_t work = size_t(P) * ld;
-    int blocks = int((work + 255) / 256);
-    if (blocks > 4096) blocks = 4096;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(mat_setup_kernel, dim3(blocks), dim3(256), 0, s, I, dtiles, ntiles, tr, dinst, deta, a.eta,
-                       rscale, drs, z, dz, c, e, dc, dc2, de, n, P, ld);
-    L0_LAUNCHED("mat_setup_kernel");
-  }
-  const void* fn = batch_step_kernel(jdt, a.field, qb, rb);
-  if (!fn) return set_error(L0CIM_ERR_UNSUPPORTED, "matrix run: no kernel for this shape");
   BStepArgs sa;
   sa.P = P;
   sa.n_steps = a.n_steps;
@@ -198,10 +192,99 @@ l0cim_status launch_matrix_run(int n, int P, l0cim_dtype jdt, const void* J, int
   d.insts = dinst;
   d.tiles = dtiles;
   d.eta = deta;
-  if (a.field == L0CIM_FIELD_BN) {
-    st = launch_bbits(d, int64_t(P) * ld / 32, s);
-    if (st != L0CIM_OK) return st;
+  // Tables and padded state for tile shape rb (RB panels per workgroup).
+  auto setup = [&](int rb, int* ntiles_out) -> l0cim_status {
+    const int tr = 16 * rb;
+    const int ntiles = (n + tr - 1) / tr;
+    BInst I{};
+    I.n = n;
+    I.ld = ld;
+    I.ldj = ld;
+    I.tile0 = 0;
+    I.ntiles = ntiles;
+    I.J = Jp;
+    I.xb = dxb;
+    I.xb2 = dxb2;
+    I.z = dz;
+    I.rs = drs;
+    I.c = dc;
+    I.c2 = dc2;
+    I.e = de;
+    I.sig_all = sigma;
+    I.hpart = dh;
+    I.status = status;
+    size_t work = size_t(P) * ld;
+    int blocks = int((work + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(mat_setup_kernel, dim3(blocks), dim3(256), 0, s, I, dtiles, ntiles, tr, dinst, deta, a.eta,
+                       rscale, drs, z, dz, c, e, dc, dc2, de, n, P, ld);
+    L0_LAUNCHED("mat_setup_kernel");
+    if (a.field == L0CIM_FIELD_BN) {
+      l0cim_status r = launch_bbits(d, int64_t(P) * ld / 32, s);
+      if (r != L0CIM_OK) return r;
+    }
+    *ntiles_out = ntiles;
+    return L0CIM_OK;
+  };
+  // Tile shape: the caller's, else the fastest of the candidates timed once
+  // per (n, P, coupling type, field) in this process, else the largest row
+  // block that still gives every CU four tiles.  Trial steps touch only the
+  // padded copies of the state, which the final setup rewrites.
+  int rb = 0;
+  if (step_shape_ok(qb, rb_hint)) rb = rb_hint;
+  const MatKey key{n, P, int(jdt), a.field};
+  if (!rb) rb = tuned_shape(key);
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  L0_HIP(hipStreamIsCapturing(s, &cap));
+  if (!rb && a.n_steps >= 16 && cap == hipStreamCaptureStatusNone) {
+    BStepArgs ta = sa;
+    ta.trace = nullptr;
+    ta.trace_steps = 0;
+    hipEvent_t e0, e1;
+    L0_HIP(hipEventCreate(&e0));
+    L0_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_rb = 1;
+    for (int cand : {1, 2, 4, 8}) {
+      if (!step_shape_ok(qb, cand)) continue;
+      int nt = 0;
+      st = setup(cand, &nt);
+      if (st != L0CIM_OK) return st;
+      const void* fc = batch_step_kernel(jdt, a.field, qb, cand);
+      st = enqueue_bsteps(d, fc, ta, nt, 0, 1, s);
+      if (st != L0CIM_OK) return st;
+      L0_HIP(hipEventRecord(e0, s));
+      st = enqueue_bsteps(d, fc, ta, nt, 2, 9, s);
+      if (st != L0CIM_OK) return st;
+      L0_HIP(hipEventRecord(e1, s));
+      L0_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      L0_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        best_rb = cand;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    rb = best_rb;
+    remember_shape(key, rb);
   }
+  if (!rb) {
+    rb = 1;
+    for (int cand : {8, 4, 2}) {
+      if (step_shape_ok(qb, cand) && (n + 16 * cand - 1) / (16 * cand) >= 4 * dev.cu_count) {
+        rb = cand;
+        break;
+      }
+    }
+  }
+  int ntiles = 0;
+  st = setup(rb, &ntiles);
+  if (st != L0CIM_OK) return st;
+  const void* fn = batch_step_kernel(jdt, a.field, qb, rb);
+  if (!fn) return set_error(L0CIM_ERR_UNSUPPORTED, "matrix run: no kernel for this shape");
   {
     ProfileScope prof(s);
     st = enqueue_bsteps(d, fn, sa, ntiles, 0, a.n_steps, s);
@@ -216,7 +299,7 @@ l0cim_status launch_matrix_run(int n, int P, l0cim_dtype jdt, const void* J, int
     L0_LAUNCHED("mat_finish_kernel");
   }
   if (H) {
-    hipLaunchKernelGGL(mat_hsum_kernel, dim3((P + 63) / 64), dim3(64), 0, s, dh, n, P, H);
+    hipLaunchKernelGGL(mat_hsum_kernel, dim3(P), dim3(256), 0, s, dh, n, H);
     L0_LAUNCHED("mat_hsum_kernel");
   }
   return L0CIM_OK;
