@@ -3,6 +3,12 @@
 //    (parameter paragraph of the numerical experiments: dtc = 0.1, 100
 //    iterations).  Resident form: rows of G stay in LDS and the vector
 //    s = sigma o R travels through flag-carrying words, as in the CIM run.
+//  * Support form (FP32, support of at most 256 spins): only the support's
+//    R enter the sums, so its sweeps run in one workgroup with G_SS in
+//    registers; an off-support R is an affine function of the support's R
+//    history, R_r(K) = f R_r(0) + (1 - f) b_r / G_rr - (dtc / G_rr) G_rS V
+//    with f = (1 - dtc)^K and V = sum_k (1 - dtc)^(K-1-k) R_S(k), which is
+//    the same K synchronous sweeps unrolled.
 //  * eq. 3 objective and the per-solve report.
 #include "kernels.h"
 
@@ -21,12 +27,138 @@ __device__ inline void jacobi_update(T& R, T off, T br, T d, T dtc, bool tiny) {
   R = tiny ? T(0) : R + dtc * ((br - off) / d - R);
 }
 
+constexpr int kSupportMax = 256;
+
+// Control block of the support form: [0] = 1 when it has done the update,
+// [1] = support size; then the support list and V.
+struct SupportCtl {
+  int* flag;
+  int* list;
+  float* V;
+};
+
+// flag words at 0, the support list at 256, V at 256 + 4 kSupportMax
+constexpr size_t kCtlList = 256, kCtlV = kCtlList + 4 * kSupportMax;
+
+inline size_t support_ctl_bytes() { return kCtlV + 4 * kSupportMax; }
+
+__device__ inline SupportCtl support_ctl(void* p) {
+  char* c = static_cast<char*>(p);
+  return SupportCtl{reinterpret_cast<int*>(c), reinterpret_cast<int*>(c + kCtlList),
+                    reinterpret_cast<float*>(c + kCtlV)};
+}
+
+// One workgroup: thread t owns row t / 4 of G_SS and its columns
+// [64 (t % 4), 64 (t % 4) + 64) in registers; R_S double-buffered in LDS.
+__global__ void __launch_bounds__(1024)
+jacobi_support_kernel(int n, const float* __restrict__ G, int64_t ldg, const float* __restrict__ b,
+                      const uint8_t* __restrict__ sigma, float dtc, int iters, float* __restrict__ R,
+                      int* __restrict__ status, void* ctl_p) {
+  __shared__ int cnt[1024];
+  __shared__ int S[kSupportMax];
+  __shared__ float Rb[2][kSupportMax];
+  __shared__ int sh_k;
+  const SupportCtl ctl = support_ctl(ctl_p);
+  const int t = threadIdx.x;
+  const int chunk = (n + 1023) / 1024;
+  const int lo = min(n, t * chunk), hi = min(n, lo + chunk);
+  int c = 0;
+  for (int i = lo; i < hi; ++i) c += sigma[i] ? 1 : 0;
+  cnt[t] = c;
+  __syncthreads();
+  if (t == 0) {
+    int a = 0;
+    for (int u = 0; u < 1024; ++u) {
+      const int v = cnt[u];
+      cnt[u] = a;
+      a += v;
+    }
+    sh_k = a;
+    ctl.flag[0] = a <= kSupportMax ? 1 : 0;
+    ctl.flag[1] = a;
+  }
+  __syncthreads();
+  const int ks = sh_k;
+  if (ks > kSupportMax || ks == 0) return;   // too large: the resident form runs; empty: nothing here
+  int at = cnt[t];
+  for (int i = lo; i < hi; ++i)
+    if (sigma[i]) {
+      S[at] = i;
+      ctl.list[at] = i;
+      ++at;
+    }
+  __syncthreads();
+  const int row = t >> 2, q = t & 3;
+  const bool own = row < ks;
+  const int r = own ? S[row] : 0;
+  float g[64];
+#pragma unroll
+  for (int u = 0; u < 64; ++u) {
+    const int j = q * 64 + u;
+    g[u] = (own && j < ks && j != row) ? G[size_t(r) * ldg + S[j < ks ? j : 0]] : 0.0f;
+  }
+  const float d = own ? G[size_t(r) * ldg + r] : 1.0f;
+  const bool tiny = !(d >= 1e-12f);
+  const float br = own ? b[r] : 0.0f;
+  if (own && q == 0) Rb[0][row] = tiny ? 0.0f : R[r];
+  for (int j = ks + t; j < kSupportMax; j += 1024) {
+    Rb[0][j] = 0.0f;
+    Rb[1][j] = 0.0f;
+  }
+  float V = 0.0f;
+  __syncthreads();
+  for (int it = 0; it < iters; ++it) {
+    const float* x = Rb[it & 1] + q * 64;
+    float acc = 0.0f;
+#pragma unroll
+    for (int u = 0; u < 64; ++u) acc += g[u] * x[u];
+    acc += __shfl_xor(acc, 1, kWave);
+    acc += __shfl_xor(acc, 2, kWave);
+    if (own && q == 0) {
+      const float Rv = Rb[it & 1][row];
+      V = (1.0f - dtc) * V + Rv;
+      Rb[(it + 1) & 1][row] = tiny ? 0.0f : Rv + dtc * ((br - acc) / d - Rv);
+    }
+    __syncthreads();
+  }
+  if (own && q == 0) {
+    R[r] = Rb[iters & 1][row];
+    ctl.V[row] = V;
+    if (tiny) raise_status(status, L0CIM_ST_TINY_DIAG);
+  }
+}
+
+// Off-support rows after the support form: one wavefront per row.
+__global__ void __launch_bounds__(256)
+jacobi_offsupport_kernel(int n, const float* __restrict__ G, int64_t ldg, const float* __restrict__ b,
+                         const uint8_t* __restrict__ sigma, float dtc, int iters, float* __restrict__ R,
+                         int* __restrict__ status, void* ctl_p) {
+  const SupportCtl ctl = support_ctl(ctl_p);
+  if (ctl.flag[0] == 0) return;
+  const int ks = ctl.flag[1];
+  const int lane = threadIdx.x & 63;
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= n || sigma[r]) return;
+  float acc = 0.0f;
+  for (int s = lane; s < ks; s += kWave) acc += G[size_t(r) * ldg + ctl.list[s]] * ctl.V[s];
+  acc = wave_sum(acc);
+  if (lane == 0) {
+    const float d = G[size_t(r) * ldg + r];
+    const bool tiny = !(d >= 1e-12f);
+    float f = 1.0f;
+    for (int k = 0; k < iters; ++k) f *= (1.0f - dtc);
+    R[r] = tiny ? 0.0f : f * R[r] + (1.0f - f) * (b[r] / d) - (dtc / d) * acc;
+    if (tiny) raise_status(status, L0CIM_ST_TINY_DIAG);
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(512)
 jacobi_resident_kernel(int n, const T* __restrict__ G, int64_t ldg, const T* __restrict__ b,
                        const uint8_t* __restrict__ sigma, T dtc, int iters, T* __restrict__ R,
                        uint64_t* __restrict__ ll, int* __restrict__ abort_word, int* __restrict__ status,
-                       int64_t limit, int rpw) {
+                       int64_t limit, int rpw, const int* __restrict__ done) {
+  if (done && done[0]) return;   // the support form has already updated R
   constexpr int W = LL<T>::kWords;
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, bs = blockDim.x;
@@ -187,7 +319,8 @@ __global__ void finalize_kernel(int n, int nparts, const double* __restrict__ pa
 
 size_t jacobi_ws_bytes(l0cim_dtype dt, int n) {
   size_t words = (dt == L0CIM_F64) ? 2 : 1;
-  return align_up(size_t(2) * n * words * sizeof(uint64_t)) + kAlign + 2 * align_up(size_t(n) * dtype_size(dt));
+  return align_up(size_t(2) * n * words * sizeof(uint64_t)) + kAlign + 2 * align_up(size_t(n) * dtype_size(dt)) +
+         support_ctl_bytes();
 }
 
 namespace {
@@ -205,6 +338,8 @@ l0cim_status jacobi_typed(int n, const T* G, int64_t ldg, const T* b, const uint
   T* s0 = reinterpret_cast<T*>(p);
   p += align_up(size_t(n) * sizeof(T));
   T* s1 = reinterpret_cast<T*>(p);
+  p += align_up(size_t(n) * sizeof(T));
+  void* ctl = p;
   if (iters <= 0) return L0CIM_OK;
 
   int rpw = 0, grid = 0;
@@ -223,6 +358,17 @@ l0cim_status jacobi_typed(int n, const T* G, int64_t ldg, const T* b, const uint
   }
   if (rpw) {
     auto kern = jacobi_resident_kernel<T>;
+    const int* done = nullptr;
+    if constexpr (sizeof(T) == 4) {
+      // support form first; the resident kernel returns at once when it succeeded
+      hipLaunchKernelGGL(jacobi_support_kernel, dim3(1), dim3(1024), 0, s, n, G, ldg, b, sigma, float(dtc), iters,
+                         R, status, ctl);
+      L0_LAUNCHED("jacobi_support_kernel");
+      hipLaunchKernelGGL(jacobi_offsupport_kernel, dim3((n + 3) / 4), dim3(256), 0, s, n, G, ldg, b, sigma,
+                         float(dtc), iters, R, status, ctl);
+      L0_LAUNCHED("jacobi_offsupport_kernel");
+      done = static_cast<const int*>(ctl);
+    }
     if (grid > 1) {
       hipLaunchKernelGGL(ll_clear_kernel, dim3(64), dim3(256), 0, s, ll, size_t(2) * n * LL<T>::kWords,
                          abort_word);
@@ -234,13 +380,13 @@ l0cim_status jacobi_typed(int n, const T* G, int64_t ldg, const T* b, const uint
     T dtcT = T(dtc);
     int nn = n, itn = iters, rp = rpw;
     int64_t lim = limit;
-    void* kargs[] = {&nn, &G, &ldg, &b, &sigma, &dtcT, &itn, &R, &ll, &abort_word, &status, &lim, &rp};
+    void* kargs[] = {&nn, &G, &ldg, &b, &sigma, &dtcT, &itn, &R, &ll, &abort_word, &status, &lim, &rp, &done};
     if (grid > 1) {
       L0_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(grid), dim3(block),
                                         kargs, unsigned(lds), s));
     } else {
       hipLaunchKernelGGL(kern, dim3(1), dim3(block), lds, s, nn, G, ldg, b, sigma, dtcT, itn, R, ll,
-                         abort_word, status, lim, rp);
+                         abort_word, status, lim, rp, done);
       L0_LAUNCHED("jacobi_resident_kernel");
     }
     return L0CIM_OK;

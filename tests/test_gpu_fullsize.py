@@ -1,0 +1,163 @@
+"""GPU parity at the full sizes of the measured workloads, in the launch
+configurations the benchmark times, on outputs the oracle can afford.
+
+  * MRI-shaped precision form (N = 16384, M = 4915, 64 replicas, BN field):
+    BF16 / FP8 couplings with row scales bit-exact on sampled rows, then the
+    first 10 Euler steps of the matrix-core run against the oracle on the same
+    rounded couplings (normwise 1e-5 per step, every spin and replica).
+  * Batched form (the 256-instance batch, 16 replicas): one alternation of
+    150 steps; for the smallest, a middle and the largest instance the chosen
+    replica carries the oracle's support for that replica with the oracle's
+    minimum energy, and the CDP result agrees to 1e-4.
+  * Serving form (requests of N = 8192, 4096 and 600, 8 replicas): the same
+    checks through the server.
+Inputs are rounded to FP32 before either side sees them.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2405_00366_amd as L
+import workloads as W
+from oracle import mfcim as O, quant as Q, rng as ORNG
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    return torch.device("cuda:0")
+
+
+def f32(x):
+    return np.asarray(x, np.float64).astype(np.float32)
+
+
+def normwise(got, ref):
+    den = np.max(np.abs(ref))
+    return float(np.max(np.abs(got - ref)) / (den if den > 0 else 1.0))
+
+
+@pytest.fixture(scope="module")
+def mri(dev):
+    """The seed-0 MRI-shaped instance with FP32 G, b and R = b / diag(G)."""
+    from workloads import mri as WM
+    inst = WM.mri_instance(0)
+    A = f32(inst.A)
+    y = f32(inst.y)
+    G = (A.astype(np.float64).T @ A.astype(np.float64)).astype(np.float32)
+    b = (A.astype(np.float64).T @ y.astype(np.float64)).astype(np.float32)
+    R = (b / np.diag(G)).astype(np.float32)
+    Gd = torch.from_numpy(G).to(dev)
+    return dict(G=G, b=b, R=R, Gd=Gd, bd=torch.from_numpy(b).to(dev), Rd=torch.from_numpy(R).to(dev))
+
+
+@pytest.mark.parametrize("fmt,code", [("bf16", L.BF16), ("fp8", L.FP8E4M3)])
+def test_mri_precision_couplings_and_first_steps(dev, mri, fmt, code):
+    n, P, steps, eta = mri["G"].shape[0], 64, 10, 0.8
+    J, rs, z = L.l0cim_build_couplings(mri["Gd"], mri["bd"], mri["Rd"], j_dtype=code)
+    torch.cuda.synchronize()
+    # every row's scale and 256 sampled rows' codes, bit-exact
+    J32, z32 = Q.couplings_f32(mri["G"], mri["b"], mri["R"])
+    q, s = Q.quantize_rows(J32, fmt)
+    del J32
+    assert np.array_equal(rs.cpu().numpy(), s)
+    rows = np.random.default_rng(0).choice(n, 256, replace=False)
+    rows_t = torch.from_numpy(rows).to(dev)
+    assert np.array_equal(J.index_select(0, rows_t).float().cpu().numpy(), q[rows])
+    assert np.array_equal(z.cpu().numpy(), z32)
+    # the first Euler steps of the run the benchmark launches (matrix cores, autotuned tile)
+    c0 = f32(W.initial_amplitudes(3, P, n))
+    c = torch.from_numpy(c0).to(dev)
+    e = torch.ones_like(c)
+    tr = torch.empty((steps, 2, P, n), dtype=torch.float32, device=dev)
+    prm = L.cim_params(n_steps=steps, field="BN", K=1.0, d=0.6)
+    L.l0cim_mfcim_run(J, z, eta, prm, c, e, trace=tr, trace_steps=steps, row_scale=rs)
+    torch.cuda.synchronize()
+    Jo = Q.dequantized(q, s)
+    del q
+    _, _, tro = O.mfcim_run(Jo, z32.astype(np.float64), eta, c0.astype(np.float64), np.ones((P, n)),
+                            O.CimParams(n_steps=steps, field=O.BN, K=1.0, d=0.6), trace_steps=steps)
+    got = tr.double().cpu().numpy()
+    for k in range(steps):
+        assert normwise(got[k, 0], tro[k, 0]) <= 1e-5, f"c, step {k}"
+        assert normwise(got[k, 1], tro[k, 1]) <= 1e-5, f"e, step {k}"
+
+
+def _one_alternation(inst, seed, P, steps, eta):
+    """Oracle replicas of alternation 0 from R = b / diag(G): supports,
+    eq. 4 energies, and the Jacobi CDP result for each replica's support."""
+    G, b = O.gram(inst.A, inst.y)
+    R0 = b / np.diag(G)
+    J, z = O.couplings(G, b, R0)
+    c0, e0 = ORNG.initial_state(seed, 0, P, inst.N, 1e-2)
+    c, e, _ = O.mfcim_run(J, z, eta, c0, e0, O.CimParams(n_steps=steps))
+    sig = O.threshold(c)
+    H = O.ising_energy(J, z, sig, O.lam_from_eta(eta))
+    return G, b, R0, sig, H
+
+
+def _check_choice(inst, seed, P, steps, eta, sg, R, stt, what):
+    G, b, R0, sig, H = _one_alternation(inst, seed, P, steps, eta)
+    q = stt.selected_replica
+    assert 0 <= q < P, what
+    assert np.array_equal(sg, sig[q]), f"{what}: replica {q}"
+    assert H[q] <= H.min() + 1e-6 * max(1.0, abs(H.min())), what
+    Ro, _ = O.cdp_jacobi(G, b, sig[q], R0, 0.1, 100)
+    assert np.max(np.abs(R - Ro)) / np.max(np.abs(Ro)) <= 1e-4, what
+
+
+def test_batched_full_batch_one_alternation(dev):
+    P, steps, eta = 16, 150, 0.8
+    specs = W.batch_specs(7, 256)
+    insts = [sp.build().rounded_f32() for sp in specs]
+    descr, A, y, R, sig, stats = L.pack_instances([i.A for i in insts], [i.y for i in insts],
+                                                  [sp.seed for sp in specs], device=dev)
+    cim = L.cim_params(n_steps=steps)
+    sp = L.solve_params(eta_init=eta, eta_end=0.18, velo=30, n_outer=1, replicas=P, j_dtype=L.F32)
+    plan = L.l0cim_batch_plan_create(descr, cim, sp)
+    ws = L.workspace(L.l0cim_batch_plan_workspace_bytes(plan), dev)
+    L.l0cim_solve_batched(plan, A, y, R, sig, stats, ws)
+    torch.cuda.synchronize()
+    st = L.read_stats_array(stats, len(descr))
+    L.l0cim_batch_plan_destroy(plan)
+    assert all(s.status_bits == 0 for s in st)
+    order = np.argsort([s.N for s in specs])
+    for k in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
+        d = descr[k]
+        o, n = d.x_offset, d.n
+        _check_choice(insts[k], specs[k].seed, P, steps, eta, sig[o:o + n].cpu().numpy(),
+                      R[o:o + n].double().cpu().numpy(), st[k], f"instance {k} (N = {n})")
+
+
+def test_serving_full_size_requests(dev):
+    P, steps, eta = 8, 150, 0.8
+    shapes = [(8192, 4915, 0.1, 901), (4096, 1638, 0.15, 902), (600, 300, 0.1, 903)]
+    insts = [W.gaussian_instance(sd, N, M, a, 0.01).rounded_f32() for (N, M, a, sd) in shapes]
+    cim = L.cim_params(n_steps=steps)
+    sp = L.solve_params(eta_init=eta, eta_end=0.18, velo=30, n_outer=1, replicas=P, j_dtype=L.F32)
+    max_n = max(i.N for i in insts)
+    arena = L.workspace(L.l0cim_server_arena_overhead(48, max_n, sp) +
+                        sum(L.l0cim_server_request_bytes(i.M, i.N, sp) for i in insts) + 4096, dev)
+    server = L.l0cim_server_create(cim, sp, 48, max_n, arena)
+    outs = []
+    try:
+        for k, (inst, (N, M, a, sd)) in enumerate(zip(insts, shapes)):
+            A = torch.tensor(inst.A, dtype=torch.float32, device=dev)
+            y = torch.tensor(inst.y, dtype=torch.float32, device=dev)
+            o = (torch.empty(N, device=dev), torch.empty(N, dtype=torch.uint8, device=dev),
+                 torch.zeros(L.STATS_BYTES, dtype=torch.uint8, device=dev), A, y)
+            outs.append(o)
+            L.l0cim_server_submit(server, A, y, sd, k, o[0], o[1], o[2])
+        done = 0
+        while done < len(insts):
+            done += L.l0cim_server_step(server)
+    finally:
+        L.l0cim_server_destroy(server)
+    for k, (inst, (N, M, a, sd)) in enumerate(zip(insts, shapes)):
+        R, sg, st, _, _ = outs[k]
+        stt = L.read_stats(st)
+        assert stt.status_bits == 0
+        _check_choice(inst, sd, P, steps, eta, sg.cpu().numpy(), R.double().cpu().numpy(), stt,
+                      f"request N = {N}")

@@ -320,22 +320,48 @@ def test_jacobi_parity(dev, n, dtype):
     assert normwise(Rg.double().cpu().numpy(), Ro) <= tol
 
 
-def test_jacobi_tiny_diagonal(dev):
+@pytest.mark.parametrize("k", [0, 1, 255, 256, 257])
+def test_jacobi_support_sizes_fp32(dev, k):
+    """Supports around the one-workgroup limit (256 spins): both the support
+    form and the resident form it hands over to agree with the sweeps."""
+    n = 1200
+    _, G32, b32, _ = problem(77, n)
+    sigma = np.zeros(n, np.uint8)
+    sigma[np.random.default_rng(k).choice(n, k, replace=False)] = 1
+    R0 = f32(W.random_r(8, n))
+    Rg = t(R0, torch.float32, dev)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    L.l0cim_update_r(t(G32, torch.float32, dev), t(b32, torch.float32, dev), t(sigma, torch.uint8, dev), Rg,
+                     iters=100, status=status)
+    torch.cuda.synchronize()
+    Ro, st = O.cdp_jacobi(G32, b32, sigma, R0, 0.1, 100)
+    assert int(status.item()) == st == 0
+    assert normwise(Rg.double().cpu().numpy(), Ro) <= 1e-5
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_jacobi_tiny_diagonal(dev, dtype):
     n = 64
     inst = W.gaussian_instance(8, n, 40, 0.2, 0.01)
     A = inst.A.copy()
     A[:, 5] = 0.0
     G, b = O.gram(A, inst.y)
+    if dtype == torch.float32:
+        G, b = f32(G), f32(b)
     sigma = np.ones(n, np.uint8)
-    R = t(np.ones(n), torch.float64, dev)
+    sigma[::3] = 0
+    R = t(np.ones(n), dtype, dev)
     status = torch.zeros(1, dtype=torch.int32, device=dev)
-    L.l0cim_update_r(t(G, torch.float64, dev), t(b, torch.float64, dev), t(sigma, torch.uint8, dev), R,
+    L.l0cim_update_r(t(G, dtype, dev), t(b, dtype, dev), t(sigma, torch.uint8, dev), R,
                      iters=10, status=status)
     torch.cuda.synchronize()
     Ro, st = O.cdp_jacobi(G, b, sigma, np.ones(n), 0.1, 10)
     assert int(status.item()) == st == L.ST_TINY_DIAG
     assert R[5].item() == 0.0
-    np.testing.assert_allclose(R.cpu().numpy(), Ro, rtol=1e-12, atol=1e-14)
+    if dtype == torch.float64:
+        np.testing.assert_allclose(R.cpu().numpy(), Ro, rtol=1e-12, atol=1e-14)
+    else:
+        assert normwise(R.double().cpu().numpy(), Ro) <= 1e-5
 
 
 @pytest.mark.parametrize("n,m,density", [(300, 200, 0.1), (64, 32, 0.1), (500, 400, 0.3)])
