@@ -343,6 +343,18 @@ l0cim_status l0cim_server_info(l0cim_server server, int32_t* active, int32_t* pe
 l0cim_status l0cim_server_destroy(l0cim_server server);
 
 /*
+ * Tile shape of the single-instance matrix-core run (several replicas): rows
+ * of J per workgroup, 16 * RB with RB in {1, 2, 4, 8} (RB * ceil(P / 16) <= 8).
+ * The first run of a new (n, P, coupling type, field) in a process times the
+ * candidates on a few Euler steps (it synchronises the stream once, and is
+ * skipped under stream capture) and remembers the fastest.  get returns the
+ * remembered shape (0: none yet); set pins one for this process (0 forgets
+ * it).  Invalid shapes return L0CIM_ERR_ARG.
+ */
+l0cim_status l0cim_matrix_tile_get(int32_t n, int32_t P, l0cim_dtype j_dtype, int32_t field, int32_t* rows);
+l0cim_status l0cim_matrix_tile_set(int32_t n, int32_t P, l0cim_dtype j_dtype, int32_t field, int32_t rows);
+
+/*
  * Kernel timing for measurement.  Between l0cim_profile_begin() and
  * l0cim_profile_end(), every launch of the CIM-run kernels made by this
  * thread is bracketed by HIP events on its own stream.  profile_end waits for

@@ -166,6 +166,10 @@ def lib():
         L.l0cim_server_info.restype = st
         L.l0cim_server_destroy.argtypes = [c_void_p]
         L.l0cim_server_destroy.restype = st
+        L.l0cim_matrix_tile_get.argtypes = [c_int32, c_int32, c_int32, c_int32, POINTER(c_int32)]
+        L.l0cim_matrix_tile_get.restype = st
+        L.l0cim_matrix_tile_set.argtypes = [c_int32, c_int32, c_int32, c_int32, c_int32]
+        L.l0cim_matrix_tile_set.restype = st
         L.l0cim_profile_begin.restype = st
         L.l0cim_profile_end.argtypes = [POINTER(c_double), POINTER(c_int64)]
         L.l0cim_profile_end.restype = st
@@ -452,6 +456,21 @@ def l0cim_server_info(server):
 
 def l0cim_server_destroy(server):
     _check(lib().l0cim_server_destroy(server), "l0cim_server_destroy")
+
+
+def _field_code(field) -> int:
+    return {"CN": FIELD_CN, "BN": FIELD_BN}.get(field, field)
+
+
+def l0cim_matrix_tile_get(n: int, P: int, j_dtype: int, field) -> int:
+    rows = c_int32()
+    _check(lib().l0cim_matrix_tile_get(n, P, j_dtype, _field_code(field), ctypes.byref(rows)),
+           "l0cim_matrix_tile_get")
+    return rows.value
+
+
+def l0cim_matrix_tile_set(n: int, P: int, j_dtype: int, field, rows: int):
+    _check(lib().l0cim_matrix_tile_set(n, P, j_dtype, _field_code(field), rows), "l0cim_matrix_tile_set")
 
 
 def l0cim_profile_begin():

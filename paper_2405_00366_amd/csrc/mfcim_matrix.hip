@@ -127,7 +127,8 @@ int tuned_shape(const MatKey& k) {
 
 void remember_shape(const MatKey& k, int rb) {
   std::lock_guard<std::mutex> lk(g_shape_mu);
-  g_shape[k] = rb;
+  if (rb) g_shape[k] = rb;
+  else g_shape.erase(k);
 }
 
 }  // namespace
@@ -306,3 +307,22 @@ l0cim_status launch_matrix_run(int n, int P, l0cim_dtype jdt, const void* J, int
 }
 
 }  // namespace l0
+
+extern "C" {
+
+l0cim_status l0cim_matrix_tile_get(int32_t n, int32_t P, l0cim_dtype j_dtype, int32_t field, int32_t* rows) {
+  if (!rows) return l0::set_error(L0CIM_ERR_ARG, "matrix_tile_get: NULL pointer");
+  *rows = 16 * l0::tuned_shape(l0::MatKey{n, P, int(j_dtype), field});
+  return L0CIM_OK;
+}
+
+l0cim_status l0cim_matrix_tile_set(int32_t n, int32_t P, l0cim_dtype j_dtype, int32_t field, int32_t rows) {
+  const int qb = P <= 16 ? 1 : (P <= 32 ? 2 : 4);
+  if (rows != 0 && (rows % 16 != 0 || !l0::step_shape_ok(qb, rows / 16)))
+    return l0::set_error(L0CIM_ERR_ARG, "matrix_tile_set: %d rows per workgroup is not a shape for %d replicas",
+                         rows, P);
+  l0::remember_shape(l0::MatKey{n, P, int(j_dtype), field}, rows / 16);
+  return L0CIM_OK;
+}
+
+}  // extern "C"
