@@ -25,7 +25,7 @@ struct BInst {
   float* R;              // n amplitudes (in/out)
   uint8_t* sig;          // n chosen support (out)
   float *c, *c2, *e;     // P x ld: amplitudes (double-buffered) and error variables
-  uint32_t *xb, *xb2;    // P x ld / 32: support bits of c and c2 (binarised field)
+  uint32_t *xb, *xb2;    // support bits of c and c2 (binarised field), xbits_words(ld, P) each
   float* jw;             // CDP and report scratch: 5 ld + 192 words
   uint8_t* sig_all;      // P x n supports of every replica
   double* hpart;         // P x n per-spin eq. 4 terms
@@ -47,6 +47,12 @@ __host__ __device__ inline size_t jpanel_offset(int r, int j, int ld, int esize)
   return blk + size_t((4 * li + lk) * 8 + t);
 }
 inline int round_up16(int n) { return (n + 15) / 16 * 16; }
+// Support bits: for each 32-column chunk c a block of 16 QB words (QB =
+// ceil(P / 16)); bit t of word c * 16 QB + li * QB + qb holds
+// H(c_q) of column 32 c + t for replica q = 16 qb + li, so the QB words a
+// lane needs for one chunk are adjacent.
+inline int xbits_qb(int P) { return P <= 16 ? 1 : (P <= 32 ? 2 : 4); }
+inline size_t xbits_words(int ld, int P) { return size_t(ld / 32) * 16 * xbits_qb(P); }
 // Tile shapes with RB panels per workgroup and 16 QB replicas.
 inline bool step_shape_ok(int qb, int rb) {
   return (qb == 1 && (rb == 1 || rb == 2 || rb == 4 || rb == 8)) || (qb == 2 && (rb == 1 || rb == 2 || rb == 4)) ||
@@ -77,7 +83,7 @@ struct BatchDev {
 const void* batch_step_kernel(l0cim_dtype jdt, int field, int qb, int rb);
 l0cim_status launch_bcouplings(const BatchDev& d, l0cim_dtype jdt, int64_t total_rows, hipStream_t s);
 l0cim_status launch_binit(const BatchDev& d, int P, int alt, double std, int64_t total_state, hipStream_t s);
-l0cim_status launch_bbits(const BatchDev& d, int64_t total_words, hipStream_t s);
+l0cim_status launch_bbits(const BatchDev& d, int QB, int64_t total_words, hipStream_t s);
 l0cim_status launch_bselect(const BatchDev& d, int P, hipStream_t s);
 // Words of per-instance CDP scratch for padded row length ld.
 inline size_t bjac_words(int ld) { return size_t(5) * ld + 192; }

@@ -262,14 +262,14 @@ bstep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, B
   }
   bool qon[QB];
   const float* cbase[QB];
-  const uint32_t* xbase[QB];
 #pragma unroll
   for (int qb = 0; qb < QB; ++qb) {
     const int q = qb * 16 + li;
     qon[qb] = q < P;
     cbase[qb] = cin + size_t(q < P ? q : 0) * ld + 8 * lk;
-    xbase[qb] = xin + size_t(q < P ? q : 0) * nch;
   }
+  // support words of this lane's 16 QB-replica block row: adjacent, one load per chunk
+  const uint32_t* xbase = xin + size_t(li) * QB;
 
   v4f acc[RB][QB];
 #pragma unroll
@@ -291,10 +291,25 @@ bstep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, B
         S.a[rb].v = gload<v2u>(src);
       }
     }
+    if constexpr (FIELD == kBN) {
+      const uint32_t* xw = xbase + size_t(c) * (16 * QB);
+      if constexpr (QB == 1) {
+        S.b[0].v = gload<uint32_t>(xw);
+      } else if constexpr (QB == 2) {
+        const v2u w2 = gload<v2u>(xw);
+        S.b[0].v = w2.x;
+        S.b[1].v = w2.y;
+      } else {
+        const v4u w4 = gload<v4u>(xw);
+        S.b[0].v = w4.x;
+        S.b[1].v = w4.y;
+        S.b[2].v = w4.z;
+        S.b[3].v = w4.w;
+      }
+    }
 #pragma unroll
     for (int qb = 0; qb < QB; ++qb) {
       if constexpr (FIELD == kBN) {
-        S.b[qb].v = gload<uint32_t>(xbase[qb] + c);
       } else {
         const float* cs = cbase[qb] + c * 32;
         S.b[qb].v0 = gload<v4f>(cs);
@@ -466,17 +481,20 @@ bstep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, B
       uint32_t word = nib << (4 * lk);
       word |= uint32_t(__shfl_xor(int(word), 16, kWave));
       word |= uint32_t(__shfl_xor(int(word), 32, kWave));
-      if (!last && lk == 0 && q < P && (p0 + rb) * 16 < n) xout[size_t(q) * (ld >> 4) + p0 + rb] = uint16_t(word);
+      const int pp = p0 + rb;
+      if (!last && lk == 0 && q < P && pp * 16 < n)
+        xout[2 * ((size_t(pp >> 1) * 16 + li) * QB + qb) + (pp & 1)] = uint16_t(word);
     }
   }
   if (last && bits) raise_status(I.status, bits);
 }
 
-// Support bits of the initial amplitudes (binarised field): word (q, c)
-// holds c_q[32 c + t] > 0 in bit t; the other buffer starts at zero.  With
-// no prefix table the launch covers instance 0 alone.
+// Support bits of the initial amplitudes (binarised field), in the chunk
+// block layout: the word of (replica q, chunk c) holds c_q[32 c + t] > 0 in
+// bit t; the other buffer starts at zero.  With no prefix table the launch
+// covers instance 0 alone.
 __global__ void __launch_bounds__(256)
-bbits_kernel(const BInst* __restrict__ insts, const int64_t* __restrict__ st_prefix, int count,
+bbits_kernel(const BInst* __restrict__ insts, const int64_t* __restrict__ st_prefix, int count, int QB,
              int64_t total_words) {
   for (int64_t g = blockIdx.x * int64_t(256) + threadIdx.x; g < total_words; g += int64_t(gridDim.x) * 256) {
     const int64_t e0 = g * 32;
@@ -487,7 +505,7 @@ bbits_kernel(const BInst* __restrict__ insts, const int64_t* __restrict__ st_pre
     const float* c = I.c + q * I.ld + r0;
     uint32_t wv = 0;
     for (int t = 0; t < 32; ++t) wv |= (c[t] > 0.0f ? 1u : 0u) << t;
-    const int64_t wi = q * (I.ld >> 5) + (r0 >> 5);
+    const int64_t wi = ((r0 >> 5) * 16 + (q & 15)) * QB + (q >> 4);
     I.xb[wi] = wv;
     I.xb2[wi] = 0u;
   }
@@ -798,11 +816,11 @@ l0cim_status launch_binit(const BatchDev& d, int P, int alt, double std, int64_t
   return L0CIM_OK;
 }
 
-l0cim_status launch_bbits(const BatchDev& d, int64_t total_words, hipStream_t s) {
+l0cim_status launch_bbits(const BatchDev& d, int QB, int64_t total_words, hipStream_t s) {
   int blocks = int((total_words + 255) / 256);
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(bbits_kernel, dim3(blocks), dim3(256), 0, s, d.insts, d.st_prefix, d.count, total_words);
+  hipLaunchKernelGGL(bbits_kernel, dim3(blocks), dim3(256), 0, s, d.insts, d.st_prefix, d.count, QB, total_words);
   L0_LAUNCHED("bbits_kernel");
   return L0CIM_OK;
 }

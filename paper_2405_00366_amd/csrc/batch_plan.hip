@@ -18,7 +18,7 @@ using namespace l0;
 // per-spin vectors, state, supports) and into the caller's pools (A, y, R, sigma).
 struct PoolSlot {
   int n, m, ld, lda;
-  int64_t oG, oJ, oV, oS, oSig, oX, oA, oY, oW;
+  int64_t oG, oJ, oV, oS, oSig, oX, oA, oY, oW, oB;
   uint64_t seed;
 };
 
@@ -30,7 +30,7 @@ struct l0cim_batch_plan_s {
   std::vector<l0cim_instance> inst;
   std::vector<PoolSlot> base;
   std::vector<int64_t> row_prefix, st_prefix;
-  int64_t nG = 0, nJ = 0, nV = 0, nS = 0, nSig = 0, nW = 0, max_tiles = 0;
+  int64_t nG = 0, nJ = 0, nV = 0, nS = 0, nSig = 0, nW = 0, nB = 0, max_tiles = 0;
   int max_ld = 0, max_n = 0;
   struct {
     size_t insts, tiles, rowp, stp, eta, G, Gc, b, z, rs, J, c, c2, e, xb, xb2, sig, hpart, jw, chol, total;
@@ -101,8 +101,8 @@ BInst make_inst(const l0cim_batch_plan_s* p, int k, const Pools& pl) {
   I.c = reinterpret_cast<float*>(b + p->off.c) + q.oS;
   I.c2 = reinterpret_cast<float*>(b + p->off.c2) + q.oS;
   I.e = reinterpret_cast<float*>(b + p->off.e) + q.oS;
-  I.xb = reinterpret_cast<uint32_t*>(b + p->off.xb) + q.oS / 32;
-  I.xb2 = reinterpret_cast<uint32_t*>(b + p->off.xb2) + q.oS / 32;
+  I.xb = reinterpret_cast<uint32_t*>(b + p->off.xb) + q.oB;
+  I.xb2 = reinterpret_cast<uint32_t*>(b + p->off.xb2) + q.oB;
   I.sig_all = reinterpret_cast<uint8_t*>(b + p->off.sig) + q.oSig;
   I.jw = reinterpret_cast<float*>(b + p->off.jw) + q.oW;
   I.hpart = reinterpret_cast<double*>(b + p->off.hpart) + q.oSig;
@@ -292,6 +292,7 @@ l0cim_status l0cim_batch_plan_create(int32_t count, const l0cim_instance* inst, 
     b.oS = p->nS;
     b.oSig = p->nSig;
     b.oW = p->nW;
+    b.oB = p->nB;
     b.oX = I.x_offset;
     b.oA = I.a_offset;
     b.oY = I.y_offset;
@@ -302,6 +303,7 @@ l0cim_status l0cim_batch_plan_create(int32_t count, const l0cim_instance* inst, 
     p->nS += int64_t(p->P) * b.ld;
     p->nSig += int64_t(p->P) * b.n;
     p->nW += int64_t(bjac_words(b.ld));
+    p->nB += int64_t(xbits_words(b.ld, p->P));
     p->max_tiles += (b.n + 15) / 16;
     p->max_ld = b.ld > p->max_ld ? b.ld : p->max_ld;
     p->max_n = b.n > p->max_n ? b.n : p->max_n;
@@ -329,8 +331,8 @@ l0cim_status l0cim_batch_plan_create(int32_t count, const l0cim_instance* inst, 
   p->off.c = take(size_t(p->nS) * 4);
   p->off.c2 = take(size_t(p->nS) * 4);
   p->off.e = take(size_t(p->nS) * 4);
-  p->off.xb = take(size_t(p->nS) / 8);
-  p->off.xb2 = take(size_t(p->nS) / 8);
+  p->off.xb = take(size_t(p->nB) * 4);
+  p->off.xb2 = take(size_t(p->nB) * 4);
   p->off.sig = take(size_t(p->nSig));
   p->off.hpart = take(size_t(p->nSig) * sizeof(double));
   p->off.jw = take(size_t(p->nW) * 4);
@@ -407,7 +409,7 @@ l0cim_status l0cim_solve_batched(l0cim_batch_plan p, const float* A, const float
     L0_TRY(launch_bset_scalar(const_cast<double*>(d.eta), p->sp.eta_init, s));
     L0_TRY(launch_bcouplings(d, p->jdt, total_rows, s));
     L0_TRY(launch_binit(d, p->P, 0, p->cim.c0_std, total_state, s));
-    if (p->cim.field == L0CIM_FIELD_BN) L0_TRY(launch_bbits(d, total_state / 32, s));
+    if (p->cim.field == L0CIM_FIELD_BN) L0_TRY(launch_bbits(d, p->qb, total_state / 32, s));
     L0_TRY(autotune(p, d, pl, s));
   }
   L0_TRY(upload_tables(p, d, pl, p->rb, s, &ntiles));
@@ -437,7 +439,7 @@ l0cim_status l0cim_solve_batched(l0cim_batch_plan p, const float* A, const float
     L0_TRY(launch_bset_scalar(const_cast<double*>(d.eta), eta, s));
     L0_TRY(launch_bcouplings(d, p->jdt, total_rows, s));
     L0_TRY(launch_binit(d, p->P, i, p->cim.c0_std, total_state, s));
-    if (p->cim.field == L0CIM_FIELD_BN) L0_TRY(launch_bbits(d, total_state / 32, s));
+    if (p->cim.field == L0CIM_FIELD_BN) L0_TRY(launch_bbits(d, p->qb, total_state / 32, s));
     {
       ProfileScope prof(s);
       if (use_graph) {

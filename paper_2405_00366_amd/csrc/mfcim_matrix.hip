@@ -101,8 +101,8 @@ MatLayout mat_layout(int n, int P, size_t jsize) {
   L.c = take(size_t(P) * ld * 4);
   L.c2 = take(size_t(P) * ld * 4);
   L.e = take(size_t(P) * ld * 4);
-  L.xb = take(size_t(P) * ld / 8);
-  L.xb2 = take(size_t(P) * ld / 8);
+  L.xb = take(xbits_words(ld, P) * 4);
+  L.xb2 = take(xbits_words(ld, P) * 4);
   L.hrow = take(size_t(P) * n * 8);
   L.J = take(size_t(round_up16(n)) * ld * jsize);
   L.total = o;
@@ -222,7 +222,7 @@ l0cim_status launch_matrix_run(int n, int P, l0cim_dtype jdt, const void* J, int
                        rscale, drs, z, dz, c, e, dc, dc2, de, n, P, ld);
     L0_LAUNCHED("mat_setup_kernel");
     if (a.field == L0CIM_FIELD_BN) {
-      l0cim_status r = launch_bbits(d, int64_t(P) * ld / 32, s);
+      l0cim_status r = launch_bbits(d, qb, int64_t(P) * ld / 32, s);
       if (r != L0CIM_OK) return r;
     }
     *ntiles_out = ntiles;

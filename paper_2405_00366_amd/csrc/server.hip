@@ -54,8 +54,8 @@ ReqLayout req_layout(int m, int n, int P, size_t jsz) {
   L.c = take(size_t(P) * ld * 4);
   L.c2 = take(size_t(P) * ld * 4);
   L.e = take(size_t(P) * ld * 4);
-  L.xb = take(size_t(P) * ld / 8);
-  L.xb2 = take(size_t(P) * ld / 8);
+  L.xb = take(xbits_words(int(ld), P) * 4);
+  L.xb2 = take(xbits_words(int(ld), P) * 4);
   L.sig_all = take(size_t(P) * n);
   L.hpart = take(size_t(P) * n * 8);
   L.jw = take(bjac_words(int(ld)) * 4);
@@ -307,7 +307,7 @@ l0cim_status tick(l0cim_server_s* sv, int* n_done) {
   // one alternation
   L0_TRY(launch_bcouplings(d, sv->jdt, hrow[count], s));
   L0_TRY(launch_binit(d, sv->P, -1, sv->cim.c0_std, hst[count], s));
-  if (sv->cim.field == L0CIM_FIELD_BN) L0_TRY(launch_bbits(d, hst[count] / 32, s));
+  if (sv->cim.field == L0CIM_FIELD_BN) L0_TRY(launch_bbits(d, sv->qb, hst[count] / 32, s));
   const void* fn = batch_step_kernel(sv->jdt, sv->cim.field, sv->qb, rb);
   if (!fn) return set_error(L0CIM_ERR_UNSUPPORTED, "server: no step kernel for this shape");
   BStepArgs a{};

@@ -153,7 +153,7 @@ def test_server_footprint_formula():
         ld = (n + 31) // 32 * 32
         n16 = (n + 15) // 16 * 16
         want = (2 * _al(n * ld * 4) + _al(n16 * ld * jb) + 4 * _al(ld * 4) + _al(ld) + 3 * _al(P * ld * 4)
-                + 2 * _al(P * ld // 8)
+                + 2 * _al((ld // 32) * 16 * (1 if P <= 16 else 2 if P <= 32 else 4) * 4)
                 + _al(P * n) + _al(P * n * 8) + _al((5 * ld + 192) * 4) + _al(m * n * 4) + _al(m * 4))
         assert lib.l0cim_server_request_bytes(m, n, ctypes.byref(sp)) == want
     sp = L.solve_params()
