@@ -1,6 +1,8 @@
 // Internal declarations shared by the l0cim HIP translation units (gfx950).
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp8.h>
@@ -122,10 +124,28 @@ __device__ inline int wave_row_of(int lane) {
   return R == 1 ? 0 : (lane / (64 / R)) & (R - 1);
 }
 
+// a' + b' after swapping a's upper half-rows with b's lower ones gives, in
+// every lane, own + partner of a (lower lanes) or of b (upper lanes).
+template <int OFF>
+__device__ inline float swap_pair_sum(float a, float b) {
+  if constexpr (OFF == 32) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  } else {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+}
+
 template <typename T, int R, int COUNT, int OFF>
 __device__ inline void wave_sum_rows_level(T (&v)[R], int lane) {
   if constexpr (OFF > 0) {
-    if constexpr (COUNT > 1) {
+    if constexpr (std::is_same<T, float>::value && (OFF == 32 || OFF == 16)) {
+      constexpr int H = COUNT > 1 ? COUNT / 2 : 1;
+#pragma unroll
+      for (int i = 0; i < H; ++i) v[i] = swap_pair_sum<OFF>(v[i], COUNT > 1 ? v[i + H] : v[i]);
+      wave_sum_rows_level<T, R, (COUNT > 1 ? COUNT / 2 : 1), OFF / 2>(v, lane);
+    } else if constexpr (COUNT > 1) {
       constexpr int H = COUNT / 2;
       const bool hi = (lane & OFF) != 0;
       T recv[H];
