@@ -573,7 +573,7 @@ constexpr int kObjChunks = 64;
 
 __global__ void __launch_bounds__(256)
 bjac_prep_kernel(const BInst* __restrict__ insts) {
-  __shared__ int cnt[256];
+  __shared__ int scan_sh[256 / kWave + 1];
   const BInst I = insts[blockIdx.x];
   const int n = I.n, ld = I.ld, tid = threadIdx.x;
   float* Rn = I.jw;
@@ -585,19 +585,9 @@ bjac_prep_kernel(const BInst* __restrict__ insts) {
   const int lo = min(n, tid * chunk), hi = min(n, lo + chunk);
   int c = 0;
   for (int i = lo; i < hi; ++i) c += I.sig[i] ? 1 : 0;
-  cnt[tid] = c;
-  __syncthreads();
-  if (tid == 0) {
-    int t = 0;
-    for (int u = 0; u < 256; ++u) {
-      const int v = cnt[u];
-      cnt[u] = t;
-      t += v;
-    }
-    misc[0] = t;
-  }
-  __syncthreads();
-  int at = cnt[tid];
+  int ks = 0;
+  int at = block_exclusive_scan<256>(c, scan_sh, &ks);
+  if (tid == 0) misc[0] = ks;
   int bits = 0;
   for (int i = lo; i < hi; ++i) {
     const float d = I.G[size_t(i) * ld + i];
@@ -698,15 +688,13 @@ bobj_partial_kernel(const BInst* __restrict__ insts) {
 
 __global__ void __launch_bounds__(256)
 bobj_final_kernel(const BInst* __restrict__ insts, double lam, int64_t steps_per_alt, int n_outer, int P) {
-  __shared__ int cnt[256];
+  __shared__ int scan_sh[256 / kWave + 1];
   const BInst I = insts[blockIdx.x];
   int c = 0;
   for (int j = threadIdx.x; j < I.n; j += 256) c += I.sig[j] ? 1 : 0;
-  cnt[threadIdx.x] = c;
-  __syncthreads();
+  int s = 0;
+  (void)block_exclusive_scan<256>(c, scan_sh, &s);
   if (threadIdx.x == 0) {
-    int s = 0;
-    for (int t = 0; t < 256; ++t) s += cnt[t];
     const double* part = reinterpret_cast<const double*>(I.jw + 5 * I.ld + 64);
     double rr = 0.0;
     for (int ch = 0; ch < kObjChunks; ++ch) rr += part[ch];

@@ -48,82 +48,93 @@ __device__ inline SupportCtl support_ctl(void* p) {
                     reinterpret_cast<float*>(c + kCtlV)};
 }
 
-// One workgroup: thread t owns row t / 4 of G_SS and its columns
-// [64 (t % 4), 64 (t % 4) + 64) in registers; R_S double-buffered in LDS.
+// One workgroup of 1024 threads: thread t holds the 4 x 16 block of G_SS at
+// rows 4 (t / 16) + i, columns 16 (t % 16) + u in registers (diagonal
+// zeroed).  Per sweep each thread reads its 16 amplitudes from LDS, the 16
+// lanes of a row group reduce their 4 row sums with a transposed butterfly,
+// and lane 4 i of the group owns row i.  R_S is double-buffered in LDS.
 __global__ void __launch_bounds__(1024)
 jacobi_support_kernel(int n, const float* __restrict__ G, int64_t ldg, const float* __restrict__ b,
                       const uint8_t* __restrict__ sigma, float dtc, int iters, float* __restrict__ R,
                       int* __restrict__ status, void* ctl_p) {
-  __shared__ int cnt[1024];
+  __shared__ int scan_sh[1024 / kWave + 1];
   __shared__ int S[kSupportMax];
-  __shared__ float Rb[2][kSupportMax];
-  __shared__ int sh_k;
+  __shared__ __align__(16) float Rb[2][kSupportMax];
   const SupportCtl ctl = support_ctl(ctl_p);
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & (kWave - 1);
   const int chunk = (n + 1023) / 1024;
   const int lo = min(n, t * chunk), hi = min(n, lo + chunk);
   int c = 0;
   for (int i = lo; i < hi; ++i) c += sigma[i] ? 1 : 0;
-  cnt[t] = c;
-  __syncthreads();
+  int ks = 0;
+  int at = block_exclusive_scan<1024>(c, scan_sh, &ks);
   if (t == 0) {
-    int a = 0;
-    for (int u = 0; u < 1024; ++u) {
-      const int v = cnt[u];
-      cnt[u] = a;
-      a += v;
-    }
-    sh_k = a;
-    ctl.flag[0] = a <= kSupportMax ? 1 : 0;
-    ctl.flag[1] = a;
+    ctl.flag[0] = ks <= kSupportMax ? 1 : 0;
+    ctl.flag[1] = ks;
   }
-  __syncthreads();
-  const int ks = sh_k;
   if (ks > kSupportMax || ks == 0) return;   // too large: the resident form runs; empty: nothing here
-  int at = cnt[t];
   for (int i = lo; i < hi; ++i)
     if (sigma[i]) {
       S[at] = i;
       ctl.list[at] = i;
       ++at;
     }
-  __syncthreads();
-  const int row = t >> 2, q = t & 3;
-  const bool own = row < ks;
-  const int r = own ? S[row] : 0;
-  float g[64];
-#pragma unroll
-  for (int u = 0; u < 64; ++u) {
-    const int j = q * 64 + u;
-    g[u] = (own && j < ks && j != row) ? G[size_t(r) * ldg + S[j < ks ? j : 0]] : 0.0f;
-  }
-  const float d = own ? G[size_t(r) * ldg + r] : 1.0f;
-  const bool tiny = !(d >= 1e-12f);
-  const float br = own ? b[r] : 0.0f;
-  if (own && q == 0) Rb[0][row] = tiny ? 0.0f : R[r];
   for (int j = ks + t; j < kSupportMax; j += 1024) {
     Rb[0][j] = 0.0f;
     Rb[1][j] = 0.0f;
   }
+  __syncthreads();
+  const int rg = t >> 4, cg = t & 15;
+  float g[4][16];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int row = 4 * rg + i;
+    const int r = row < ks ? S[row] : 0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int col = 16 * cg + u;
+      g[i][u] = (row < ks && col < ks && col != row) ? G[size_t(r) * ldg + S[col < ks ? col : 0]] : 0.0f;
+    }
+  }
+  // row owned by this lane (lanes 4 i of each 16-lane group), see wave_sum_rows_level
+  const int orow = 4 * rg + ((lane >> 2) & 3);
+  const bool own = (lane & 3) == 0 && orow < ks;
+  const int r = own ? S[orow] : 0;
+  const float d = own ? G[size_t(r) * ldg + r] : 1.0f;
+  const bool tiny = !(d >= 1e-12f);
+  const float br = own ? b[r] : 0.0f;
+  if (own) Rb[0][orow] = tiny ? 0.0f : R[r];
   float V = 0.0f;
   __syncthreads();
   for (int it = 0; it < iters; ++it) {
-    const float* x = Rb[it & 1] + q * 64;
-    float acc = 0.0f;
+    const float4* x4 = reinterpret_cast<const float4*>(Rb[it & 1] + 16 * cg);
+    float x[16];
 #pragma unroll
-    for (int u = 0; u < 64; ++u) acc += g[u] * x[u];
-    acc += __shfl_xor(acc, 1, kWave);
-    acc += __shfl_xor(acc, 2, kWave);
-    if (own && q == 0) {
-      const float Rv = Rb[it & 1][row];
+    for (int q = 0; q < 4; ++q) {
+      const float4 v = x4[q];
+      x[4 * q] = v.x;
+      x[4 * q + 1] = v.y;
+      x[4 * q + 2] = v.z;
+      x[4 * q + 3] = v.w;
+    }
+    float acc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      acc[i] = 0.0f;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc[i] += g[i][u] * x[u];
+    }
+    wave_sum_rows_level<float, 4, 4, 8>(acc, lane);
+    if (own) {
+      const float Rv = Rb[it & 1][orow];
       V = (1.0f - dtc) * V + Rv;
-      Rb[(it + 1) & 1][row] = tiny ? 0.0f : Rv + dtc * ((br - acc) / d - Rv);
+      Rb[(it + 1) & 1][orow] = tiny ? 0.0f : Rv + dtc * ((br - acc[0]) / d - Rv);
     }
     __syncthreads();
   }
-  if (own && q == 0) {
-    R[r] = Rb[iters & 1][row];
-    ctl.V[row] = V;
+  if (own) {
+    R[r] = Rb[iters & 1][orow];
+    ctl.V[orow] = V;
     if (tiny) raise_status(status, L0CIM_ST_TINY_DIAG);
   }
 }

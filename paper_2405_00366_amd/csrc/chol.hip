@@ -82,19 +82,9 @@ chol_kernel(int n, const T* __restrict__ G, int64_t ldg, const T* __restrict__ b
     const int lo = min(n, tid * chunk), hi = min(n, lo + chunk);
     int c = 0;
     for (int i = lo; i < hi; ++i) c += sigma[i] ? 1 : 0;
-    cnt[tid] = c;
-    __syncthreads();
-    if (tid == 0) {
-      int s = 0;
-      for (int t = 0; t < BS; ++t) {
-        const int v = cnt[t];
-        cnt[t] = s;
-        s += v;
-      }
-      ctl[C_K] = s;
-    }
-    __syncthreads();
-    int pos = cnt[tid];
+    int ks = 0;
+    int pos = block_exclusive_scan<BS>(c, cnt, &ks);
+    if (tid == 0) ctl[C_K] = ks;
     for (int i = lo; i < hi; ++i)
       if (sigma[i]) idx[pos++] = i;
     __syncthreads();

@@ -166,6 +166,37 @@ __device__ inline void wave_sum_rows(T (&v)[R], int lane) {
   wave_sum_rows_level<T, R, R, 32>(v, lane);
 }
 
+// Exclusive prefix sum of one int per thread over a workgroup of BS threads
+// (a multiple of 64, at most 1024): wavefront scans, then the wavefront
+// totals in order.  `sh` is LDS scratch of BS / 64 + 1 ints; every thread
+// gets its exclusive prefix and the total.  Ends with a barrier.
+template <int BS>
+__device__ inline int block_exclusive_scan(int v, int* sh, int* total) {
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int y = __shfl_up(x, o, kWave);
+    if (lane >= o) x += y;
+  }
+  if (lane == kWave - 1) sh[wv] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int w = 0; w < BS / kWave; ++w) {
+      const int t = sh[w];
+      sh[w] = acc;
+      acc += t;
+    }
+    sh[BS / kWave] = acc;
+  }
+  __syncthreads();
+  *total = sh[BS / kWave];
+  const int r = sh[wv] + x - v;
+  __syncthreads();
+  return r;
+}
+
 // Coupling storage decoding.  Integer-exact for bf16 and fp8 (e4m3, OCP).
 template <typename JT> struct JLoad;
 template <> struct JLoad<float> {

@@ -270,12 +270,23 @@ cim_stream_step_kernel(const JT* __restrict__ J, int64_t ldj, const float* __res
   }
 }
 
-__global__ void reduce_h_kernel(const double* __restrict__ Hpart, int G, int P, double* __restrict__ H) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= P) return;
+// One workgroup per replica: 256 contiguous runs of the G partials summed in
+// order, then a fixed tree.
+__global__ void __launch_bounds__(256)
+reduce_h_kernel(const double* __restrict__ Hpart, int G, int P, double* __restrict__ H) {
+  __shared__ double part[256];
+  const int q = blockIdx.x, t = threadIdx.x;
+  const int chunk = (G + 255) / 256;
+  const int lo = min(G, t * chunk), hi = min(G, lo + chunk);
   double h = 0.0;
-  for (int w = 0; w < G; ++w) h += Hpart[size_t(w) * P + q];
-  H[q] = h;
+  for (int w = lo; w < hi; ++w) h += Hpart[size_t(w) * P + q];
+  part[t] = h;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) part[t] += part[t + s];
+    __syncthreads();
+  }
+  if (t == 0) H[q] = part[0];
 }
 
 // argmin over replicas (first on ties), then copy that replica's sigma.
@@ -541,7 +552,7 @@ l0cim_status run_typed(int n, int P, const JT* J, int64_t ldj, const float* rsca
                                               kargs, 0u, s));
           }
           if (H) {
-            hipLaunchKernelGGL(reduce_h_kernel, dim3(1), dim3(64), 0, s, w.hpart, g, P, H);
+            hipLaunchKernelGGL(reduce_h_kernel, dim3(P), dim3(256), 0, s, w.hpart, g, P, H);
             L0_LAUNCHED("reduce_h_kernel");
           }
           return L0CIM_OK;
@@ -606,7 +617,7 @@ l0cim_status run_typed(int n, int P, const JT* J, int64_t ldj, const float* rsca
     }
   }
   if (H) {
-    hipLaunchKernelGGL(reduce_h_kernel, dim3((P + 63) / 64), dim3(64), 0, s, w.hpart, grid, P, H);
+    hipLaunchKernelGGL(reduce_h_kernel, dim3(P), dim3(256), 0, s, w.hpart, grid, P, H);
     L0_LAUNCHED("reduce_h_kernel");
   }
   return L0CIM_OK;
