@@ -558,14 +558,18 @@ bselect_kernel(const BInst* __restrict__ insts, int P) {
 
 // ---------------------------------------------------------------------------
 // CDP for every instance (synchronous damped Jacobi over all r, the same
-// update as the single-instance path).  Per alternation: a preparation
-// kernel per instance (support list, its inverse, R on the support), one
-// pass that gathers the support's columns of G into a compact block, then
-// one launch per sweep over the row tiles of every instance.  Each row's sum
-// runs over the support in index order split by lane, so the result depends
-// only on the instance.
+// update as the single-instance path).  Only the support's R enter the sums,
+// so the sweeps run over the support rows and every other R follows at the
+// end from the affine form R_r(K) = f R_r(0) + (1 - f) b_r / G_rr -
+// (dtc / G_rr) G_rS V, f = (1 - dtc)^K, V = sum_k (1 - dtc)^(K-1-k) R_S(k)
+// (the K sweeps unrolled).  Per alternation: a preparation kernel per
+// instance (support list, its inverse, R on the support), one pass that
+// gathers G's support columns into a compact block, one launch per sweep, one
+// final pass; all over the row tiles of every instance (a tile's rows double
+// as support indices in the sweeps).  Each sum runs over the support in index
+// order split by lane, so the result depends only on the instance.
 // Per-instance scratch (words of 4 bytes, ld = padded row length):
-//   [0, ld) R of the other parity   [ld, 3 ld) R on the support, two parities
+//   [0, ld) V                       [ld, 3 ld) R on the support, two parities
 //   [3 ld, 4 ld) support list       [4 ld, 5 ld) position in the list or -1
 //   [5 ld, 5 ld + 64) counters      [5 ld + 64, 5 ld + 192) 64 FP64 partial sums
 // ---------------------------------------------------------------------------
@@ -576,7 +580,7 @@ bjac_prep_kernel(const BInst* __restrict__ insts) {
   __shared__ int scan_sh[256 / kWave + 1];
   const BInst I = insts[blockIdx.x];
   const int n = I.n, ld = I.ld, tid = threadIdx.x;
-  float* Rn = I.jw;
+  float* V = I.jw;
   float* sR0 = I.jw + ld;
   int* S = reinterpret_cast<int*>(I.jw + 3 * ld);
   int* pos = reinterpret_cast<int*>(I.jw + 4 * ld);
@@ -595,10 +599,10 @@ bjac_prep_kernel(const BInst* __restrict__ insts) {
     if (tiny) bits |= L0CIM_ST_TINY_DIAG;
     const float r = tiny ? 0.0f : I.R[i];
     I.R[i] = r;
-    Rn[i] = r;
     if (I.sig[i]) {
       S[at] = i;
       sR0[at] = r;
+      V[at] = 0.0f;
       pos[i] = at++;
     } else {
       pos[i] = -1;
@@ -624,40 +628,70 @@ bjac_compact_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ i
   }
 }
 
-// One synchronous sweep; `flip` selects which R buffers are read and written
-// so that the last sweep writes the instance's own R.
+// One synchronous sweep over the support rows (support indices of the tile).
 __global__ void __launch_bounds__(256)
 bjac_sweep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, int rows_per_tile, float dtc,
-                  int it, int flip) {
+                  int it) {
   const BTile tl = tiles[blockIdx.x];
   const BInst I = insts[tl.inst];
   const int ld = I.ld;
+  const int ks = reinterpret_cast<const int*>(I.jw + 5 * ld)[0];
+  if (tl.row0 >= ks) return;
+  float* V = I.jw;
   const float* sRi = I.jw + ld + (it & 1) * ld;
   float* sRo = I.jw + ld + ((it + 1) & 1) * ld;
-  const float* Ri = flip ? I.jw : I.R;
-  float* Ro = flip ? I.R : I.jw;
   const int* S = reinterpret_cast<const int*>(I.jw + 3 * ld);
-  const int* pos = reinterpret_cast<const int*>(I.jw + 4 * ld);
-  const int ks = reinterpret_cast<const int*>(I.jw + 5 * ld)[0];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int r1 = min(I.n, tl.row0 + rows_per_tile);
-  for (int r = tl.row0 + w; r < r1; r += 4) {
+  const int i1 = min(ks, tl.row0 + rows_per_tile);
+  for (int i = tl.row0 + w; i < i1; i += 4) {
+    const int r = S[i];
     const float* gc = I.Gc + size_t(r) * ks;
-    const int pr = pos[r];
     float acc = 0.0f;
     for (int s = lane; s < ks; s += kWave)
-      if (s != pr) acc += gc[s] * sRi[s];
+      if (s != i) acc += gc[s] * sRi[s];
     acc = wave_sum(acc);
     if (lane == 0) {
       const float d = I.G[size_t(r) * ld + r];
       const bool tiny = !(d >= 1e-12f);
-      const float Rv = Ri[r];
-      const float Rnew = tiny ? 0.0f : Rv + dtc * ((I.b[r] - acc) / d - Rv);
-      Ro[r] = Rnew;
-      if (pr >= 0) sRo[pr] = Rnew;
+      const float Rv = sRi[i];
+      V[i] = (1.0f - dtc) * V[i] + Rv;
+      sRo[i] = tiny ? 0.0f : Rv + dtc * ((I.b[r] - acc) / d - Rv);
     }
   }
-  (void)S;
+}
+
+// Every R after K sweeps: the support's from the last sweep, the others from
+// the affine form.
+__global__ void __launch_bounds__(256)
+bjac_final_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, int rows_per_tile, float dtc,
+                  int iters) {
+  const BTile tl = tiles[blockIdx.x];
+  const BInst I = insts[tl.inst];
+  const int ld = I.ld;
+  const int ks = reinterpret_cast<const int*>(I.jw + 5 * ld)[0];
+  const float* V = I.jw;
+  const float* sRK = I.jw + ld + (iters & 1) * ld;
+  const int* pos = reinterpret_cast<const int*>(I.jw + 4 * ld);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r1 = min(I.n, tl.row0 + rows_per_tile);
+  float f = 1.0f;
+  for (int k = 0; k < iters; ++k) f *= (1.0f - dtc);
+  for (int r = tl.row0 + w; r < r1; r += 4) {
+    const int pr = pos[r];
+    if (pr >= 0) {
+      if (lane == 0) I.R[r] = sRK[pr];
+      continue;
+    }
+    const float* gc = I.Gc + size_t(r) * ks;
+    float acc = 0.0f;
+    for (int s = lane; s < ks; s += kWave) acc += gc[s] * V[s];
+    acc = wave_sum(acc);
+    if (lane == 0) {
+      const float d = I.G[size_t(r) * ld + r];
+      const bool tiny = !(d >= 1e-12f);
+      I.R[r] = tiny ? 0.0f : f * I.R[r] + (1.0f - f) * (I.b[r] / d) - (dtc / d) * acc;
+    }
+  }
 }
 
 // eq. 3 objective and the per-instance report.  Phase 1: FP64 partial sums
@@ -827,11 +861,13 @@ l0cim_status launch_bjacobi(const BatchDev& d, int ntiles, int rows_per_tile, do
   hipLaunchKernelGGL(bjac_compact_kernel, dim3(ntiles), dim3(256), 0, s, d.tiles, d.insts, rows_per_tile);
   L0_LAUNCHED("bjac_compact_kernel");
   for (int it = 0; it < iters; ++it) {
-    const int flip = ((iters - it) & 1) ? 1 : 0;
     hipLaunchKernelGGL(bjac_sweep_kernel, dim3(ntiles), dim3(256), 0, s, d.tiles, d.insts, rows_per_tile,
-                       float(dtc), it, flip);
+                       float(dtc), it);
     L0_LAUNCHED("bjac_sweep_kernel");
   }
+  hipLaunchKernelGGL(bjac_final_kernel, dim3(ntiles), dim3(256), 0, s, d.tiles, d.insts, rows_per_tile, float(dtc),
+                     iters);
+  L0_LAUNCHED("bjac_final_kernel");
   return L0CIM_OK;
 }
 

@@ -254,7 +254,9 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 jacobi_sweep_kernel(int n, const T* __restrict__ G, int64_t ldg, const T* __restrict__ b,
                     const uint8_t* __restrict__ sigma, T dtc, const T* __restrict__ sin,
-                    T* __restrict__ sout, T* __restrict__ R, int* __restrict__ status, int first) {
+                    T* __restrict__ sout, T* __restrict__ R, int* __restrict__ status, int first,
+                    const int* __restrict__ done) {
+  if (done[0]) return;   // the support form has updated R
   const int lane = threadIdx.x & (kWave - 1);
   const int r = blockIdx.x * 4 + threadIdx.x / kWave;
   if (r >= n) return;
@@ -276,12 +278,171 @@ jacobi_sweep_kernel(int n, const T* __restrict__ G, int64_t ldg, const T* __rest
 
 template <typename T>
 __global__ void masked_copy_kernel(int n, const T* __restrict__ G, int64_t ldg, const uint8_t* __restrict__ sigma,
-                                   T* __restrict__ R, T* __restrict__ s) {
+                                   T* __restrict__ R, T* __restrict__ s, const int* __restrict__ done) {
+  if (done[0]) return;
   int r = blockIdx.x * 256 + threadIdx.x;
   if (r >= n) return;
   T d = G[size_t(r) * ldg + r];
   if (!(d >= T(1e-12))) R[r] = T(0);
   s[r] = sigma[r] ? R[r] : T(0);
+}
+
+// ---------------------------------------------------------------------------
+// Support form for large N (G too large for the resident kernel): the
+// support's block G_SS is compacted once, the sweeps run over the support
+// rows only (one launch each), and one pass sets every R with the affine form
+// above.  Used while |S| <= sup_kmax<T>(n); otherwise the streamed sweeps run
+// (they check the flag and return at once when this form has run).
+// ---------------------------------------------------------------------------
+template <typename T>
+__host__ __device__ inline int sup_kmax(int n) {
+  const int cap = sizeof(T) == 4 ? 8192 : 4096;
+  return n < cap ? n : cap;
+}
+
+template <typename T>
+struct SupWs {
+  int* ctl;      // [0] 1 when the support form runs, [1] |S|
+  int* S;        // support list (n)
+  int* pos;      // position in the list or -1 (n)
+  T* sR;         // R on the support, two parities (2 kmax)
+  T* V;          // sum_k (1 - dtc)^(K-1-k) R_S(k) (kmax)
+  T* Gss;        // |S| x |S| (kmax^2)
+};
+
+template <typename T>
+__host__ __device__ inline size_t sup_ws_bytes(int n) {
+  const size_t k = size_t(sup_kmax<T>(n));
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  return al(2 * sizeof(int)) + 2 * al(size_t(n) * sizeof(int)) + al(2 * k * sizeof(T)) + al(k * sizeof(T)) +
+         al(k * k * sizeof(T));
+}
+
+template <typename T>
+__host__ __device__ inline SupWs<T> sup_ws(void* p, int n) {
+  const size_t k = size_t(sup_kmax<T>(n));
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  char* c = static_cast<char*>(p);
+  SupWs<T> w;
+  w.ctl = reinterpret_cast<int*>(c);
+  c += al(2 * sizeof(int));
+  w.S = reinterpret_cast<int*>(c);
+  c += al(size_t(n) * sizeof(int));
+  w.pos = reinterpret_cast<int*>(c);
+  c += al(size_t(n) * sizeof(int));
+  w.sR = reinterpret_cast<T*>(c);
+  c += al(2 * k * sizeof(T));
+  w.V = reinterpret_cast<T*>(c);
+  c += al(k * sizeof(T));
+  w.Gss = reinterpret_cast<T*>(c);
+  return w;
+}
+
+// One workgroup: support list, its inverse, R on the support, V = 0.
+template <typename T>
+__global__ void __launch_bounds__(1024)
+sup_prep_kernel(int n, const T* __restrict__ G, int64_t ldg, const uint8_t* __restrict__ sigma,
+                T* __restrict__ R, int* __restrict__ status, SupWs<T> w) {
+  __shared__ int scan_sh[1024 / kWave + 1];
+  const int t = threadIdx.x;
+  const int chunk = (n + 1023) / 1024;
+  const int lo = min(n, t * chunk), hi = min(n, lo + chunk);
+  int c = 0;
+  for (int i = lo; i < hi; ++i) c += sigma[i] ? 1 : 0;
+  int ks = 0;
+  int at = block_exclusive_scan<1024>(c, scan_sh, &ks);
+  const bool run = ks <= sup_kmax<T>(n);
+  if (t == 0) {
+    w.ctl[0] = run ? 1 : 0;
+    w.ctl[1] = ks;
+  }
+  if (!run) return;
+  int bits = 0;
+  for (int i = lo; i < hi; ++i) {
+    const T d = G[size_t(i) * ldg + i];
+    const bool tiny = !(d >= T(1e-12));
+    if (tiny) bits |= L0CIM_ST_TINY_DIAG;
+    const T r = tiny ? T(0) : R[i];
+    R[i] = r;
+    if (sigma[i]) {
+      w.S[at] = i;
+      w.pos[i] = at;
+      w.sR[at] = r;
+      w.V[at] = T(0);
+      ++at;
+    } else {
+      w.pos[i] = -1;
+    }
+  }
+  if (bits) raise_status(status, bits);
+}
+
+// G_SS[i][j] = G[S_i][S_j], one wavefront per row, rows strided over the grid.
+template <typename T>
+__global__ void __launch_bounds__(256)
+sup_compact_kernel(const T* __restrict__ G, int64_t ldg, SupWs<T> w) {
+  if (!w.ctl[0]) return;
+  const int ks = w.ctl[1];
+  const int lane = threadIdx.x & (kWave - 1);
+  for (int i = blockIdx.x * 4 + threadIdx.x / kWave; i < ks; i += gridDim.x * 4) {
+    const T* g = G + size_t(w.S[i]) * ldg;
+    T* o = w.Gss + size_t(i) * ks;
+    for (int j = lane; j < ks; j += kWave) o[j] = g[w.S[j]];
+  }
+}
+
+// One synchronous sweep over the support rows; V accumulates the input.
+template <typename T>
+__global__ void __launch_bounds__(256)
+sup_sweep_kernel(const T* __restrict__ b, T dtc, int it, SupWs<T> w) {
+  if (!w.ctl[0]) return;
+  const int ks = w.ctl[1];
+  const T* sin = w.sR + size_t(it & 1) * ks;
+  T* sout = w.sR + size_t((it + 1) & 1) * ks;
+  const int lane = threadIdx.x & (kWave - 1);
+  for (int i = blockIdx.x * 4 + threadIdx.x / kWave; i < ks; i += gridDim.x * 4) {
+    const T* g = w.Gss + size_t(i) * ks;
+    T acc = T(0);
+    for (int j = lane; j < ks; j += kWave)
+      if (j != i) acc += g[j] * sin[j];
+    acc = wave_sum(acc);
+    if (lane == 0) {
+      const T d = g[i];
+      T Rv = sin[i];
+      w.V[i] = (T(1) - dtc) * w.V[i] + Rv;
+      jacobi_update(Rv, acc, b[w.S[i]], d, dtc, !(d >= T(1e-12)));
+      sout[i] = Rv;
+    }
+  }
+}
+
+// Every R after K sweeps: the support's from the last sweep, the others from
+// the affine form (one wavefront per row).
+template <typename T>
+__global__ void __launch_bounds__(256)
+sup_final_kernel(int n, const T* __restrict__ G, int64_t ldg, const T* __restrict__ b, T dtc, int iters,
+                 T* __restrict__ R, SupWs<T> w) {
+  if (!w.ctl[0]) return;
+  const int ks = w.ctl[1];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int r = blockIdx.x * 4 + threadIdx.x / kWave;
+  if (r >= n) return;
+  const int pr = w.pos[r];
+  if (pr >= 0) {
+    if (lane == 0) R[r] = w.sR[size_t(iters & 1) * ks + pr];
+    return;
+  }
+  const T* g = G + size_t(r) * ldg;
+  T acc = T(0);
+  for (int s = lane; s < ks; s += kWave) acc += g[w.S[s]] * w.V[s];
+  acc = wave_sum(acc);
+  if (lane == 0) {
+    const T d = g[r];
+    const bool tiny = !(d >= T(1e-12));
+    T f = T(1);
+    for (int k = 0; k < iters; ++k) f *= (T(1) - dtc);
+    R[r] = tiny ? T(0) : f * R[r] + (T(1) - f) * (b[r] / d) - (dtc / d) * acc;
+  }
 }
 
 // eq. 3 residual: one wavefront per measurement row.
@@ -331,7 +492,7 @@ __global__ void finalize_kernel(int n, int nparts, const double* __restrict__ pa
 size_t jacobi_ws_bytes(l0cim_dtype dt, int n) {
   size_t words = (dt == L0CIM_F64) ? 2 : 1;
   return align_up(size_t(2) * n * words * sizeof(uint64_t)) + kAlign + 2 * align_up(size_t(n) * dtype_size(dt)) +
-         support_ctl_bytes();
+         support_ctl_bytes() + (dt == L0CIM_F64 ? sup_ws_bytes<double>(n) : sup_ws_bytes<float>(n));
 }
 
 namespace {
@@ -351,6 +512,8 @@ l0cim_status jacobi_typed(int n, const T* G, int64_t ldg, const T* b, const uint
   T* s1 = reinterpret_cast<T*>(p);
   p += align_up(size_t(n) * sizeof(T));
   void* ctl = p;
+  p += align_up(support_ctl_bytes());
+  const SupWs<T> sw = sup_ws<T>(p, n);
   if (iters <= 0) return L0CIM_OK;
 
   int rpw = 0, grid = 0;
@@ -402,13 +565,30 @@ l0cim_status jacobi_typed(int n, const T* G, int64_t ldg, const T* b, const uint
     }
     return L0CIM_OK;
   }
-  hipLaunchKernelGGL(masked_copy_kernel<T>, dim3((n + 255) / 256), dim3(256), 0, s, n, G, ldg, sigma, R, s0);
+  // support form first; the streamed sweeps return at once when it ran
+  {
+    const int kmax = sup_kmax<T>(n);
+    int grid = (kmax + 3) / 4;
+    if (grid > 4 * dev.cu_count) grid = 4 * dev.cu_count;
+    hipLaunchKernelGGL(sup_prep_kernel<T>, dim3(1), dim3(1024), 0, s, n, G, ldg, sigma, R, status, sw);
+    L0_LAUNCHED("sup_prep_kernel");
+    hipLaunchKernelGGL(sup_compact_kernel<T>, dim3(grid), dim3(256), 0, s, G, ldg, sw);
+    L0_LAUNCHED("sup_compact_kernel");
+    for (int it = 0; it < iters; ++it) {
+      hipLaunchKernelGGL(sup_sweep_kernel<T>, dim3(grid), dim3(256), 0, s, b, T(dtc), it, sw);
+      L0_LAUNCHED("sup_sweep_kernel");
+    }
+    hipLaunchKernelGGL(sup_final_kernel<T>, dim3((n + 3) / 4), dim3(256), 0, s, n, G, ldg, b, T(dtc), iters, R, sw);
+    L0_LAUNCHED("sup_final_kernel");
+  }
+  const int* done = sw.ctl;
+  hipLaunchKernelGGL(masked_copy_kernel<T>, dim3((n + 255) / 256), dim3(256), 0, s, n, G, ldg, sigma, R, s0, done);
   L0_LAUNCHED("masked_copy_kernel");
   T* cur = s0;
   T* nxt = s1;
   for (int it = 0; it < iters; ++it) {
     hipLaunchKernelGGL(jacobi_sweep_kernel<T>, dim3((n + 3) / 4), dim3(256), 0, s, n, G, ldg, b, sigma,
-                       T(dtc), cur, nxt, R, status, it == 0 ? 1 : 0);
+                       T(dtc), cur, nxt, R, status, it == 0 ? 1 : 0, done);
     L0_LAUNCHED("jacobi_sweep_kernel");
     T* t = cur;
     cur = nxt;

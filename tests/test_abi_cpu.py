@@ -55,9 +55,9 @@ def test_workspace_sizes():
     cim, sp = L.cim_params(), L.solve_params()
     ws = lib.l0cim_solve_workspace_bytes(L.F32, 1000, 2000, ctypes.byref(cim), ctypes.byref(sp))
     # G and J take 2 * 2000^2 * 4 bytes; the matrix-core run's panel copy of
-    # J (2000 x 2016 x 4) and the FP64 Cholesky refit's padded factor
-    # (2048^2 x 8) come on top
-    assert 32_000_000 <= ws < 32_000_000 + 2000 * 2016 * 4 + 2048 * 2048 * 8 + 4_000_000
+    # J (2000 x 2016 x 4), the FP64 Cholesky refit's padded factor (2048^2 x 8)
+    # and the CDP's compacted support block (at most 2000^2 x 4) come on top
+    assert 32_000_000 <= ws < 32_000_000 + 2000 * 2016 * 4 + 2048 * 2048 * 8 + 2000 * 2000 * 4 + 4_000_000
     assert lib.l0cim_mfcim_run_workspace_bytes(L.F32, 2000, 1, L.F32) >= 2 * 2000 * 8
     assert lib.l0cim_mfcim_run_workspace_bytes(L.F64, 2000, 1, L.F64) >= 2 * 2000 * 16
     assert lib.l0cim_update_r_workspace_bytes(L.F64, 100, L.CDP_CHOL_F64) >= 100 * 100 * 8

@@ -339,6 +339,25 @@ def test_jacobi_support_sizes_fp32(dev, k):
     assert normwise(Rg.double().cpu().numpy(), Ro) <= 1e-5
 
 
+@pytest.mark.parametrize("density", [0.1, 1.0])
+def test_jacobi_large_n_fp64(dev, density):
+    """N = 4500 in FP64 (G too large for the resident form): a 10% support
+    runs the large-N support form, a full support (above its 4096 limit)
+    the streamed sweeps it hands over to."""
+    n = 4500
+    _, G32, b32, _ = problem(91, n)
+    sigma = (np.random.default_rng(5).random(n) < density).astype(np.uint8)
+    R0 = f32(W.random_r(9, n))
+    Rg = t(R0, torch.float64, dev)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    L.l0cim_update_r(t(G32, torch.float64, dev), t(b32, torch.float64, dev), t(sigma, torch.uint8, dev), Rg,
+                     iters=100, status=status)
+    torch.cuda.synchronize()
+    Ro, st = O.cdp_jacobi(G32, b32, sigma, R0, 0.1, 100)
+    assert int(status.item()) == st == 0
+    assert normwise(Rg.cpu().numpy(), Ro) <= 1e-12
+
+
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_jacobi_tiny_diagonal(dev, dtype):
     n = 64
