@@ -19,44 +19,67 @@ constexpr int NB = 64;
 constexpr int BS = 256;
 constexpr int64_t kBarrierLimit = int64_t(1) << 24;
 
-// control words: barrier count and generation, abort, k, and one failure
-// flag per attempt (never reset, so no workgroup can miss a flag)
-enum { C_COUNT = 0, C_GEN = 1, C_ABORT = 2, C_K = 3, C_BAD0 = 4, C_BAD1 = 5 };
+// control words: barrier generation, abort, k, and one failure flag per
+// attempt (never reset, so no workgroup can miss a flag)
+enum { C_GEN = 1, C_ABORT = 2, C_K = 3, C_BAD0 = 4, C_BAD1 = 5 };
 
 // Bounded grid barrier for a cooperative launch (every workgroup resident).
-__device__ bool grid_sync(int* ctl, int nblocks) {
+// Each workgroup publishes its arrival in a slot of its own (no contended
+// atomic), workgroup 0 waits for every slot and then publishes the new
+// generation, which the others wait for.  `gen` counts the barriers passed
+// and is the same in every workgroup.  A wait that exceeds the poll bound, or
+// sees the abort word, fails the barrier and raises the abort word.
+constexpr int kSlot = 16;   // ints between arrival slots (64 bytes)
+
+__device__ bool grid_sync(int* ctl, int* arrive, int nblocks, int& gen) {
   __shared__ int ok_sh;
+  ++gen;
+  if (threadIdx.x == 0) ok_sh = 1;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int ok = 1;
+  const int tid = threadIdx.x, wg = blockIdx.x;
+  if (tid == 0) {
     __threadfence();
-    const int g = __hip_atomic_load(&ctl[C_GEN], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    const int arrived = __hip_atomic_fetch_add(&ctl[C_COUNT], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1;
-    if (arrived == nblocks) {
-      __hip_atomic_store(&ctl[C_COUNT], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&ctl[C_GEN], g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
+    __hip_atomic_store(&arrive[wg * kSlot], gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  auto give_up = [&]() {
+    ok_sh = 0;
+    __hip_atomic_store(&ctl[C_ABORT], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
+  if (wg == 0) {
+    for (int w = tid; w < nblocks; w += BS) {
       int64_t polls = 0;
-      while (__hip_atomic_load(&ctl[C_GEN], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-        if (++polls > kBarrierLimit ||
-            __hip_atomic_load(&ctl[C_ABORT], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-          ok = 0;
-          __hip_atomic_store(&ctl[C_ABORT], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      while (__hip_atomic_load(&arrive[w * kSlot], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < gen) {
+        if (++polls > kBarrierLimit || ((polls & 255) == 0 &&
+                                        __hip_atomic_load(&ctl[C_ABORT], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+          give_up();
           break;
         }
-        __builtin_amdgcn_s_sleep(2);
+        __builtin_amdgcn_s_sleep(1);
       }
     }
-    __threadfence();
-    ok_sh = ok;
+    __syncthreads();
+    if (tid == 0 && ok_sh) {
+      __threadfence();
+      __hip_atomic_store(&ctl[C_GEN], gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  } else if (tid == 0) {
+    int64_t polls = 0;
+    while (__hip_atomic_load(&ctl[C_GEN], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < gen) {
+      if (++polls > kBarrierLimit || __hip_atomic_load(&ctl[C_ABORT], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        give_up();
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
   }
+  if (tid == 0) __threadfence();
   __syncthreads();
   return ok_sh != 0;
 }
 
 #define L0_GRID_SYNC()                                              \
   do {                                                              \
-    if (!grid_sync(ctl, nwg)) {                                     \
+    if (!grid_sync(ctl, arrive, nwg, gen)) {                        \
       if (tid == 0) raise_status(status, L0CIM_ST_TIMEOUT);         \
       return;                                                       \
     }                                                               \
@@ -67,7 +90,8 @@ __global__ void __launch_bounds__(BS)
 chol_kernel(int n, const T* __restrict__ G, int64_t ldg, const T* __restrict__ b,
             const uint8_t* __restrict__ sigma, T* __restrict__ R, int* __restrict__ status,
             int* __restrict__ idx, double* __restrict__ L, double* __restrict__ w, int* __restrict__ ctl,
-            double* __restrict__ red) {
+            double* __restrict__ red, int* __restrict__ arrive) {
+  int gen = 0;
   __shared__ double sA[NB][NB + 1];
   __shared__ double sB[NB][NB + 1];
   __shared__ double sv[NB];
@@ -314,8 +338,9 @@ chol_kernel(int n, const T* __restrict__ G, int64_t ldg, const T* __restrict__ b
 }
 
 struct CholLayout {
-  size_t idx, L, w, ctl, red, total;
+  size_t idx, L, w, ctl, red, arrive, total;
 };
+constexpr int kMaxGrid = 1024;
 
 CholLayout chol_layout(int n) {
   const size_t np = size_t(n + NB - 1) / NB * NB;
@@ -331,12 +356,14 @@ CholLayout chol_layout(int n) {
   c.w = take(np * sizeof(double));
   c.ctl = take(8 * sizeof(int));
   c.red = take(4 * sizeof(double));
+  c.arrive = take(size_t(kMaxGrid) * kSlot * sizeof(int));
   c.total = o;
   return c;
 }
 
-__global__ void chol_ctl_clear_kernel(int* ctl) {
+__global__ void chol_ctl_clear_kernel(int* ctl, int* arrive) {
   if (threadIdx.x < 8) ctl[threadIdx.x] = 0;
+  for (int i = threadIdx.x; i < kMaxGrid; i += blockDim.x) arrive[i * kSlot] = 0;
 }
 
 template <typename T>
@@ -352,14 +379,16 @@ l0cim_status chol_typed(int n, const T* G, int64_t ldg, const T* b, const uint8_
   double* w = reinterpret_cast<double*>(base + c.w);
   int* ctl = reinterpret_cast<int*>(base + c.ctl);
   double* red = reinterpret_cast<double*>(base + c.red);
-  hipLaunchKernelGGL(chol_ctl_clear_kernel, dim3(1), dim3(64), 0, s, ctl);
+  int* arrive = reinterpret_cast<int*>(base + c.arrive);
+  hipLaunchKernelGGL(chol_ctl_clear_kernel, dim3(1), dim3(256), 0, s, ctl, arrive);
   L0_LAUNCHED("chol_ctl_clear_kernel");
   int per_cu = 0;
   L0_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(chol_kernel<T>), BS, 0));
   int grid = dev.cu_count * (per_cu > 0 ? 1 : 0);
+  if (grid > kMaxGrid) grid = kMaxGrid;
   if (grid < 1) return set_error(L0CIM_ERR_HIP, "chol refit: kernel does not fit on a CU");
   int nn = n;
-  void* args[] = {&nn, &G, &ldg, &b, &sigma, &R, &status, &idx, &L, &w, &ctl, &red};
+  void* args[] = {&nn, &G, &ldg, &b, &sigma, &R, &status, &idx, &L, &w, &ctl, &red, &arrive};
   L0_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(chol_kernel<T>), dim3(grid), dim3(BS), args, 0, s));
   return L0CIM_OK;
 }
