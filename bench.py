@@ -152,10 +152,12 @@ def batched_bench(args, torch, L, W, dev):
     descr, A, y, R, sig, stats = L.pack_instances([i.A for i in insts], [i.y for i in insts],
                                                   [sp.seed for sp in specs], device=dev)
     cim = L.cim_params(n_steps=steps)
-    sp = L.solve_params(eta_init=0.8, eta_end=0.18, velo=outer, n_outer=outer, replicas=P, j_dtype=L.F32)
+    flags = L.SOLVE_NO_GRAPH if args.no_graph else 0
+    sp = L.solve_params(eta_init=0.8, eta_end=0.18, velo=outer, n_outer=outer, replicas=P, j_dtype=L.F32,
+                        flags=flags)
     plan = L.l0cim_batch_plan_create(descr, cim, sp)
     ws = L.workspace(L.l0cim_batch_plan_workspace_bytes(plan), dev)
-    warm = L.solve_params(eta_init=0.8, eta_end=0.18, velo=outer, n_outer=1, replicas=P, j_dtype=L.F32)
+    warm = L.solve_params(eta_init=0.8, eta_end=0.18, velo=outer, n_outer=1, replicas=P, j_dtype=L.F32, flags=flags)
     wplan = L.l0cim_batch_plan_create(descr, L.cim_params(n_steps=steps), warm)
     L.l0cim_solve_batched(wplan, A, y, R, sig, stats, ws)     # tunes the tile shape for this shape class
     torch.cuda.synchronize()
@@ -389,6 +391,8 @@ def main():
     ap.add_argument("--plain-sample", type=int, default=24,
                     help="serving form: requests timed on the single-instance path")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-graph", action="store_true",
+                    help="batched form: launch the Euler steps one by one (no HIP graph replay)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "

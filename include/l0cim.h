@@ -120,8 +120,11 @@ typedef struct {
   int32_t replicas;          /* P >= 1 independent CIM trajectories */
   uint64_t seed;             /* key of the initial-amplitude generator */
   int32_t j_dtype;           /* coupling storage: F32 | F64 | BF16 | FP8E4M3 */
-  int32_t reserved0;
+  int32_t flags;             /* OR of L0CIM_SOLVE_*: NO_GRAPH launches the batched form's Euler
+                                steps one by one instead of replaying a HIP graph */
 } l0cim_solve_params;
+
+#define L0CIM_SOLVE_NO_GRAPH 1
 
 /* Per-solve report, written by the device into caller memory. */
 typedef struct {

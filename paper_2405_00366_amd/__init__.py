@@ -35,6 +35,7 @@ CDP_JACOBI, CDP_CHOL_F64 = 0, 1
 LAUNCH_AUTO, LAUNCH_RESIDENT, LAUNCH_STREAMED, LAUNCH_MATRIX = 0, 1, 2, 3
 
 ST_NONFINITE, ST_BLOWUP, ST_CHOL_RIDGE, ST_TINY_DIAG, ST_TIMEOUT = 1, 2, 4, 8, 16
+SOLVE_NO_GRAPH = 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libl0cim.so")
@@ -55,7 +56,7 @@ class SolveParams(ctypes.Structure):
         ("eta_init", c_double), ("eta_end", c_double), ("velo", c_int32), ("n_outer", c_int32),
         ("cdp", c_int32), ("cdp_iters", c_int32), ("dtc", c_double),
         ("final_refit_f64", c_int32), ("replicas", c_int32), ("seed", c_uint64),
-        ("j_dtype", c_int32), ("reserved0", c_int32),
+        ("j_dtype", c_int32), ("flags", c_int32),
     ]
 
 

@@ -414,7 +414,7 @@ l0cim_status l0cim_solve_batched(l0cim_batch_plan p, const float* A, const float
   }
   L0_TRY(upload_tables(p, d, pl, p->rb, s, &ntiles));
   // graph of one CIM run (n_steps + 1 launches), rebuilt when the workspace or tile shape changes
-  const bool use_graph = p->cim.n_steps >= 16;
+  const bool use_graph = p->cim.n_steps >= 16 && !(p->sp.flags & L0CIM_SOLVE_NO_GRAPH);
   if (use_graph && (p->graph_ws != ws || p->graph_rb != p->rb || !p->exec)) {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
