@@ -44,30 +44,32 @@ WORKLOAD = ("plain Gaussian L0RBCS: N=2000, M=1000 (alpha 0.5), Bernoulli(0.1) s
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cim_regs_kernel_plain_n2000_traffic.txt")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2405_00366_amd", "csrc", f) for f in ("mfcim.hip", "common.h")]
+KERNEL_SOURCES = ("mfcim.hip", "common.h")
+PRECISION_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bstep_kernel_mri_bf16_traffic.txt")
+PRECISION_SOURCES = ("batch.hip", "batch.h", "mfcim_matrix.hip")
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(sources=KERNEL_SOURCES) -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
+    for f in sources:
+        with open(os.path.join(ROOT, "paper_2405_00366_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per launch of the CIM kernel from the committed counter
-    summary, or None when the kernel sources changed since it was taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(path=TRAFFIC_FILE, sources=KERNEL_SOURCES, key="hbm_bytes_per_launch"):
+    """HBM bytes per launch of a kernel from its committed counter summary, or
+    None when the kernel sources changed since the counters were taken."""
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("source_sha256") != kernel_source_hash() or "hbm_bytes_per_launch" not in kv:
+    if kv.get("source_sha256") != kernel_source_hash(sources) or key not in kv:
         return None
-    return float(kv["hbm_bytes_per_launch"])
+    return float(kv[key])
 
 
 def traffic_probe(torch, dev):
@@ -197,7 +199,7 @@ def precision_bench(args, torch, L, W, dev):
     from workloads import mri as WM
     jdt = {"bf16": L.BF16, "fp8": L.FP8E4M3}[args.jdtype]
     jb = {"bf16": 2, "fp8": 1}[args.jdtype]
-    P, steps, outer = 64, 1000, 11
+    P, steps, outer = 64, args.euler_steps or 1000, args.alternations or 11
     gold = {}
     path = os.path.join(ROOT, "tests", "golden", "oracle_supports_mri.txt")
     if os.path.exists(path):
@@ -209,7 +211,9 @@ def precision_bench(args, torch, L, W, dev):
     cim = L.cim_params(n_steps=steps, field="BN", K=1.0, d=0.6)
     rows, total, cim_total, launches_total, match = [], 0.0, 0.0, 0, 0
     for sd in seeds:
+        print(f"[precision] building the MRI-shaped instance of seed {sd}", file=sys.stderr, flush=True)
         inst = WM.mri_instance(sd)
+        print(f"[precision] solving ({args.jdtype}, {outer} x {steps} steps)", file=sys.stderr, flush=True)
         A = torch.tensor(inst.A, dtype=torch.float32, device=dev)
         y = torch.tensor(inst.y, dtype=torch.float32, device=dev)
         n = inst.N
@@ -237,7 +241,7 @@ def precision_bench(args, torch, L, W, dev):
         sig = sg.cpu().numpy()
         Rv = R.double().cpu().numpy()
         rmse = float(np.sqrt(np.mean((Rv * sig - inst.x * inst.xi) ** 2)))
-        ok = sd in gold and mask_to_int(sig) == gold[sd][0]
+        ok = sd in gold and mask_to_int(sig) == gold[sd][0] and (steps, outer) == (1000, 11)
         match += int(ok)
         rows.append({"seed": sd, "support": int(sig.sum()), "rmse": rmse,
                      "oracle_rmse": gold[sd][1] if sd in gold else None, "oracle_support_match": ok,
@@ -256,7 +260,10 @@ def precision_bench(args, torch, L, W, dev):
                                f"with per-row scales, FP64 Cholesky refit"},
         "couplings": args.jdtype, "support_match": f"{match}/{len(seeds)}", "per_seed": rows,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": f"bstep_kernel<{args.jdtype}, BN, 4, rb>",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(PRECISION_TRAFFIC_FILE, PRECISION_SOURCES, "hbm_bytes_per_step")
+                     if args.jdtype == "bf16" else None,
+                     "kernel": f"bstep_kernel<{args.jdtype}, BN, 4, rb>",
                      "avg_launch_ms": cim_total / launches_total / (steps + 1)},
     }
 
@@ -391,6 +398,10 @@ def main():
     ap.add_argument("--plain-sample", type=int, default=24,
                     help="serving form: requests timed on the single-instance path")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--euler-steps", type=int, default=0,
+                    help="precision form: Euler steps per alternation instead of 1000 (profiling runs)")
+    ap.add_argument("--alternations", type=int, default=0,
+                    help="precision form: alternations instead of 11 (profiling runs)")
     ap.add_argument("--no-graph", action="store_true",
                     help="batched form: launch the Euler steps one by one (no HIP graph replay)")
     args = ap.parse_args()
