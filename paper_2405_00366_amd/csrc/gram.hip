@@ -1,9 +1,11 @@
 // Gram and Zeeman preparation: G = A^T A, b = A^T y (the negated couplings
 // and the Zeeman term over sqrt(tau), stated after eq. 11 and eq. 15).
 //
-// G is computed with an LDS-tiled outer-product kernel; every output element
-// accumulates over k in the same order with explicit FMAs, so G_ij and G_ji
-// are bitwise equal.
+// FP32: the matrix cores compute the 128 x 128 tiles on and above the
+// diagonal and each value is written to G_ij and G_ji, so G is bitwise
+// symmetric and half the products are formed.  FP64: an LDS-tiled
+// outer-product kernel in which every element accumulates over k in the same
+// order with explicit FMAs (again G_ij and G_ji bitwise equal).
 #include "kernels.h"
 
 namespace l0 {
@@ -70,6 +72,98 @@ gram_kernel(int m, int n, const T* __restrict__ A, int64_t lda, T* __restrict__ 
   }
 }
 
+typedef float v4f __attribute__((ext_vector_type(4)));
+constexpr int kMT = 128;   // output tile
+constexpr int kMK = 16;    // rows of A per chunk
+
+// One workgroup per tile (I, J), I <= J, of the upper triangle; 4 wavefronts
+// of 64 x 64 (4 x 4 blocks of 16 x 16).  A chunk of 16 rows of A is staged
+// in LDS column-major (16 values of a column contiguous); the matrix-core
+// step s of lane group g uses row 4 g + s of the chunk on both operands, so
+// each lane reads its 4 values of a column with one 16-byte load.
+__global__ void __launch_bounds__(256)
+gram_mfma_kernel(int m, int n, const float* __restrict__ A, int64_t lda, float* __restrict__ G, int64_t ldg,
+                 int tiles) {
+  __shared__ __align__(16) float As[kMT][kMK];
+  __shared__ __align__(16) float Bs[kMT][kMK];
+  // tile (I, J) of the upper triangle, row by row
+  int I = 0, rem = blockIdx.x;
+  while (rem >= tiles - I) {
+    rem -= tiles - I;
+    ++I;
+  }
+  const int J = I + rem;
+  const bool diag = I == J;
+  const int i0 = I * kMT, j0 = J * kMT;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  const int c = lane & 15, g = lane >> 4;
+  v4f acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+  // loader: thread t moves rows (t / 32) and (t / 32) + 8 of the chunk, columns 4 (t % 32) .. + 3
+  const int lr = t >> 5, lc = 4 * (t & 31);
+  auto fetch = [&](int k0, int col0, float (&v)[2][4]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int k = k0 + lr + 8 * h;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int col = col0 + lc + u;
+        v[h][u] = (k < m && col < n) ? A[size_t(k) * lda + col] : 0.0f;
+      }
+    }
+  };
+  float va[2][4], vb[2][4];
+  fetch(0, i0, va);
+  if (!diag) fetch(0, j0, vb);
+  for (int k0 = 0; k0 < m; k0 += kMK) {
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        As[lc + u][lr + 8 * h] = va[h][u];
+        if (!diag) Bs[lc + u][lr + 8 * h] = vb[h][u];
+      }
+    __syncthreads();
+    if (k0 + kMK < m) {
+      fetch(k0 + kMK, i0, va);
+      if (!diag) fetch(k0 + kMK, j0, vb);
+    }
+    const float(*Bp)[kMK] = diag ? As : Bs;
+    v4f ra[4], rb[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) ra[a] = *reinterpret_cast<const v4f*>(&As[wr * 64 + a * 16 + c][4 * g]);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) rb[b] = *reinterpret_cast<const v4f*>(&Bp[wc * 64 + b * 16 + c][4 * g]);
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra[a][st], rb[b][st], acc[a][b], 0, 0, 0);
+  }
+  // lane holds D[4 g + v][c] of block (a, b): row i0 + 64 wr + 16 a + 4 g + v, column j0 + 64 wc + 16 b + c
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int j = j0 + wc * 64 + b * 16 + c;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + wr * 64 + a * 16 + 4 * g + v;
+        if (i < n && j < n && (!diag || i <= j)) {
+          G[size_t(i) * ldg + j] = acc[a][b][v];
+          G[size_t(j) * ldg + i] = acc[a][b][v];
+        }
+      }
+    }
+}
+
 // b_j = sum_k A_kj y_k: 64 columns per workgroup, four k-phases summed in a
 // fixed order.
 template <typename T>
@@ -89,9 +183,16 @@ aty_kernel(int m, int n, const T* __restrict__ A, int64_t lda, const T* __restri
 template <typename T>
 l0cim_status gram_typed(int m, int n, const T* A, int64_t lda, const T* y, T* G, int64_t ldg, T* b,
                         hipStream_t s) {
-  dim3 grid((n + kTile - 1) / kTile, (n + kTile - 1) / kTile);
-  hipLaunchKernelGGL(gram_kernel<T>, grid, dim3(256), 0, s, m, n, A, lda, G, ldg);
-  L0_LAUNCHED("gram_kernel");
+  if constexpr (sizeof(T) == 4) {
+    const int tiles = (n + kMT - 1) / kMT;
+    hipLaunchKernelGGL(gram_mfma_kernel, dim3(unsigned(int64_t(tiles) * (tiles + 1) / 2)), dim3(256), 0, s, m, n,
+                       A, lda, G, ldg, tiles);
+    L0_LAUNCHED("gram_mfma_kernel");
+  } else {
+    dim3 grid((n + kTile - 1) / kTile, (n + kTile - 1) / kTile);
+    hipLaunchKernelGGL(gram_kernel<T>, grid, dim3(256), 0, s, m, n, A, lda, G, ldg);
+    L0_LAUNCHED("gram_kernel");
+  }
   hipLaunchKernelGGL(aty_kernel<T>, dim3((n + 63) / 64), dim3(256), 0, s, m, n, A, lda, y, b);
   L0_LAUNCHED("aty_kernel");
   return L0CIM_OK;
