@@ -347,7 +347,7 @@ l0cim_status l0cim_server_destroy(l0cim_server server);
 
 /*
  * Tile shape of the single-instance matrix-core run (several replicas): rows
- * of J per workgroup, 16 * RB with RB in {1, 2, 4, 8} (RB * ceil(P / 16) <= 8).
+ * of J per workgroup, 16 * RB with RB in {1, 2, 4, 8} (RB * ceil(P / 16) <= 16).
  * The first run of a new (n, P, coupling type, field) in a process times the
  * candidates on a few Euler steps (it synchronises the stream once, and is
  * skipped under stream capture) and remembers the fastest.  get returns the

@@ -55,8 +55,8 @@ inline int xbits_qb(int P) { return P <= 16 ? 1 : (P <= 32 ? 2 : 4); }
 inline size_t xbits_words(int ld, int P) { return size_t(ld / 32) * 16 * xbits_qb(P); }
 // Tile shapes with RB panels per workgroup and 16 QB replicas.
 inline bool step_shape_ok(int qb, int rb) {
-  return (qb == 1 && (rb == 1 || rb == 2 || rb == 4 || rb == 8)) || (qb == 2 && (rb == 1 || rb == 2 || rb == 4)) ||
-         (qb == 4 && (rb == 1 || rb == 2));
+  return (qb == 1 && (rb == 1 || rb == 2 || rb == 4 || rb == 8)) ||
+         (qb == 2 && (rb == 1 || rb == 2 || rb == 4 || rb == 8)) || (qb == 4 && (rb == 1 || rb == 2 || rb == 4));
 }
 
 struct BTile {

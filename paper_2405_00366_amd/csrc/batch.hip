@@ -243,7 +243,7 @@ bstep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, B
              const double* __restrict__ etap) {
   constexpr bool kF32 = sizeof(JT) == 4;
   constexpr int D = pipe_depth(int(sizeof(JT)), FIELD, RB, QB);
-  static_assert(RB * QB <= 8, "partial sums must fit in 32 KB of LDS");
+  static_assert(RB * QB <= 16, "partial sums must fit in 64 KB of LDS");
   __shared__ v4f red[4][RB * QB][64];
   const BTile tl = tiles[blockIdx.x];
   const BInst I = insts[tl.inst];
@@ -790,9 +790,11 @@ static const void* step_kernel_q(int qb, int rb) {
     if (rb == 1) return step_kernel_ptr<JT, FIELD, 2, 1>();
     if (rb == 2) return step_kernel_ptr<JT, FIELD, 2, 2>();
     if (rb == 4) return step_kernel_ptr<JT, FIELD, 2, 4>();
+    if (rb == 8) return step_kernel_ptr<JT, FIELD, 2, 8>();
   } else if (qb == 4) {
     if (rb == 1) return step_kernel_ptr<JT, FIELD, 4, 1>();
     if (rb == 2) return step_kernel_ptr<JT, FIELD, 4, 2>();
+    if (rb == 4) return step_kernel_ptr<JT, FIELD, 4, 4>();
   }
   return nullptr;
 }

@@ -191,7 +191,7 @@ def test_matrix_tile_pin_roundtrip_on_host():
     assert L.l0cim_matrix_tile_get(3000, 64, L.BF16, "BN") == 32
     assert L.l0cim_matrix_tile_get(3000, 64, L.FP8E4M3, "BN") == 0
     with pytest.raises(L.L0cimError):
-        L.l0cim_matrix_tile_set(3000, 64, L.BF16, "BN", 64)     # 4 x 4 blocks exceed the LDS sums
+        L.l0cim_matrix_tile_set(3000, 64, L.BF16, "BN", 128)    # 8 x 4 blocks exceed the LDS sums
     with pytest.raises(L.L0cimError):
         L.l0cim_matrix_tile_set(3000, 8, L.F32, "CN", 24)
     L.l0cim_matrix_tile_set(3000, 64, L.BF16, "BN", 0)
