@@ -25,10 +25,12 @@ constexpr int kCN = 0;
 constexpr int kBN = 1;
 
 // FP8 couplings are widened to bf16 in registers with the hardware e4m3 ->
-// f32 conversion (exact for every e4m3 code, subnormals included, and every
-// e4m3 value is exact in bf16) and multiplied on the bf16 matrix cores, so
-// products and FP32 sums are those of the dequantised definition; HBM still
-// serves one byte per coupling.
+// bf16 pair conversion (exact for every e4m3 code, subnormals included) and
+// multiplied on the bf16 matrix cores, so products and FP32 sums are those of
+// the dequantised definition; HBM still serves one byte per coupling.  (The
+// FP8 matrix cores themselves are not used: their results on these codes
+// differ from the exact products' FP32 sums by more than the FP32 state
+// tolerance.)
 
 __device__ inline v4f mfma_f32(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -208,32 +210,31 @@ constexpr int pipe_depth(int jsize, int field, int RB, int QB) {
   return d < 2 ? 2 : (d > 12 ? 12 : d);
 }
 
-// 8 bits (bit t = column 8 lk + t) -> 8 bf16 values 0 / 1.
-__device__ inline v8bf bits_to_bf16(uint32_t byte) {
+// 8 support bits (bits pos .. pos + 7 of the word; bit pos + t is column
+// 8 lk + t) -> 8 bf16 values 0 / 1.  Each nibble is spread to the low bit of
+// four bytes by one multiply (the four shifted copies occupy disjoint bit
+// ranges, so nothing carries), which makes e4m3 codes 0 / 0x01 (2^-9); the
+// hardware pair conversion scales them by 2^9 to bf16 0 / 1, exactly.
+__device__ inline v8bf bits_to_bf16(uint32_t word, int pos) {
+  const uint32_t lo = (((word >> pos) & 0xFu) * 0x00204081u) & 0x01010101u;
+  const uint32_t hi = (((word >> (pos + 4)) & 0xFu) * 0x00204081u) & 0x01010101u;
   v4u w;
-  w.x = ((byte & 1u) ? 0x3F80u : 0u) | ((byte & 2u) ? 0x3F800000u : 0u);
-  w.y = ((byte & 4u) ? 0x3F80u : 0u) | ((byte & 8u) ? 0x3F800000u : 0u);
-  w.z = ((byte & 16u) ? 0x3F80u : 0u) | ((byte & 32u) ? 0x3F800000u : 0u);
-  w.w = ((byte & 64u) ? 0x3F80u : 0u) | ((byte & 128u) ? 0x3F800000u : 0u);
+  w.x = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(int(lo), 512.0f, false));
+  w.y = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(int(lo), 512.0f, true));
+  w.z = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(int(hi), 512.0f, false));
+  w.w = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(int(hi), 512.0f, true));
   return __builtin_bit_cast(v8bf, w);
 }
 
-// 8 e4m3 codes -> 8 bf16 (exact: f32 from the hardware conversion, then its
-// upper half, which carries every e4m3 value without rounding).
+// 8 e4m3 codes -> 8 bf16 with the hardware pair conversion at scale 1
+// (exact: every e4m3 value, subnormals included, is a bf16 value).
 __device__ inline v8bf fp8_to_bf16(v2u v) {
-  typedef float v2f __attribute__((ext_vector_type(2)));
-  const v2f f0 = __builtin_amdgcn_cvt_pk_f32_fp8(int(v.x), false);
-  const v2f f1 = __builtin_amdgcn_cvt_pk_f32_fp8(int(v.x), true);
-  const v2f f2 = __builtin_amdgcn_cvt_pk_f32_fp8(int(v.y), false);
-  const v2f f3 = __builtin_amdgcn_cvt_pk_f32_fp8(int(v.y), true);
-  auto pack = [](v2f f) {
-    return (__float_as_uint(f[0]) >> 16) | (__float_as_uint(f[1]) & 0xFFFF0000u);
-  };
+  typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
   v4u w;
-  w.x = pack(f0);
-  w.y = pack(f1);
-  w.z = pack(f2);
-  w.w = pack(f3);
+  w.x = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(int(v.x), 1.0f, false));
+  w.y = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(int(v.x), 1.0f, true));
+  w.z = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(int(v.y), 1.0f, false));
+  w.w = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(int(v.y), 1.0f, true));
   return __builtin_bit_cast(v8bf, w);
 }
 
@@ -363,7 +364,7 @@ bstep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, B
 #pragma unroll
       for (int qb = 0; qb < QB; ++qb) {
         if constexpr (FIELD == kBN) {
-          const v8bf bx = bits_to_bf16((S.b[qb].v >> (8 * lk)) & 0xFFu);
+          const v8bf bx = bits_to_bf16(S.b[qb].v, 8 * lk);
 #pragma unroll
           for (int rb = 0; rb < RB; ++rb) acc[rb][qb] = mfma_bf16(av[rb], bx, acc[rb][qb]);
         } else {
