@@ -290,6 +290,8 @@ def serving_bench(args, torch, L, W, dev):
     def serve(arrivals):
         """Serve every request; arrivals are offsets (s) from the start."""
         server = L.l0cim_server_create(cim, sp, args.slots, max_n, arena)
+        if args.step_budget_mb > 0:
+            L.l0cim_server_set_step_budget(server, int(args.step_budget_mb * 1e6))
         t0 = L.l0cim_server_clock(server)
         nxt, done, lat = 0, 0, {}
         L.l0cim_profile_begin()
@@ -334,7 +336,7 @@ def serving_bench(args, torch, L, W, dev):
         runs.append({"rate_frac": frac, "arrival_rate": frac * thr, "req_per_s": len(specs) / span, "p50_s": p50,
                      "p99_s": p99, "ticks": ticks})
     # the single-instance path on the same requests, one at a time (FIFO)
-    k_plain = min(len(specs), args.plain_sample)
+    k_plain = len(specs) if args.plain_sample < 0 else min(len(specs), args.plain_sample)
     svc = []
     ws = None
     print(f"[serving] single-instance path on {k_plain} requests", file=sys.stderr, flush=True)
@@ -351,6 +353,8 @@ def serving_bench(args, torch, L, W, dev):
         L.l0cim_solve(A, y, cim, sps, R_out=R, sigma_out=sg, stats=st, ws=ws)
         torch.cuda.synchronize()
         svc.append(time.perf_counter() - t1)
+        if (k + 1) % 20 == 0:
+            print(f"[serving] single-instance path {k + 1}/{k_plain}", file=sys.stderr, flush=True)
     plain_thr = k_plain / sum(svc) if svc else None
     plain_spin = sum(specs[k].N for k in range(k_plain)) * P * steps * outer / sum(svc) if svc else None
     # FIFO replay of the measured service times under each rate's arrivals
@@ -370,7 +374,8 @@ def serving_bench(args, torch, L, W, dev):
         "config": {"workload": "serving: Gaussian L0RBCS requests, N log-uniform [512, 8192], alpha U[0.2, 0.6], "
                                "sparsity U[0.05, 0.2], noise 0.01, 8 replicas, 1000 Euler steps x 30 alternations, "
                                "FP32 couplings, continuous batching (one alternation per tick)",
-                   "requests": len(specs), "max_slots": args.slots, "arena_GB": arena_bytes / 1e9},
+                   "requests": len(specs), "max_slots": args.slots, "arena_GB": arena_bytes / 1e9,
+                   "step_budget_MB": args.step_budget_mb or None},
         "requests_per_s": thr, "runs": runs,
         "single_instance_path": {"requests_measured": k_plain, "req_per_s": plain_thr, "spin_steps_per_s": plain_spin,
                                  "fifo_latency_at_rates": plain_p,
@@ -395,8 +400,10 @@ def main():
     ap.add_argument("--slots", type=int, default=48, help="serving form: resident requests at most")
     ap.add_argument("--rates", type=float, nargs="*", default=[0.5, 0.9],
                     help="serving form: Poisson arrival rates as fractions of the saturation throughput")
-    ap.add_argument("--plain-sample", type=int, default=24,
-                    help="serving form: requests timed on the single-instance path")
+    ap.add_argument("--plain-sample", type=int, default=-1,
+                    help="serving form: requests timed on the single-instance path (-1: all, 0: none)")
+    ap.add_argument("--step-budget-mb", type=float, default=300.0,
+                    help="serving form: cap on the couplings MB one Euler step of the resident set streams (0: none)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--euler-steps", type=int, default=0,
                     help="precision form: Euler steps per alternation instead of 1000 (profiling runs)")

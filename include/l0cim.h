@@ -311,6 +311,15 @@ l0cim_status l0cim_solve_batched(l0cim_batch_plan plan, const float* A_pool, con
  * L0CIM_ERR_WORKSPACE for a request larger than the whole arena heap, and
  * L0CIM_ERR_SHAPE for n above max_n.
  *
+ * set_step_budget: a cap on the couplings bytes (round_up16(n) *
+ * round_up32(n) * coupling size per request) that one Euler step of the
+ * resident set streams; 0, the default, sets none.  The head of the queue
+ * waits while admitting it would pass the cap, unless nothing is resident, so
+ * a request alone always runs and no request overtakes another.  Once one
+ * launch already streams enough bytes to keep HBM busy, more co-resident work
+ * only lengthens every tick; the cap bounds that slowdown of the largest
+ * requests, which set the tail latency.  Takes effect at the next admission.
+ *
  * step: admission, one alternation, reports; enqueued on the server's stream
  * and waited for before it returns (the tick boundary is where requests join
  * and leave).  `completed` receives the number of requests reported.
@@ -339,6 +348,7 @@ double l0cim_server_clock(l0cim_server server);
 l0cim_status l0cim_server_submit(l0cim_server server, int32_t m, int32_t n, const float* A, int64_t lda,
                                  const float* y, uint64_t seed, int64_t tag, float* R_out,
                                  uint8_t* sigma_out, l0cim_stats* stats_out);
+l0cim_status l0cim_server_set_step_budget(l0cim_server server, size_t bytes);
 l0cim_status l0cim_server_step(l0cim_server server, int32_t* completed);
 int32_t l0cim_server_completed(l0cim_server server, l0cim_completion* out, int32_t max);
 l0cim_status l0cim_server_info(l0cim_server server, int32_t* active, int32_t* pending, size_t* bytes_in_use,

@@ -26,7 +26,7 @@ __all__ = [
     "l0cim_batch_plan_info", "l0cim_batch_plan_destroy", "l0cim_solve_batched", "pack_instances",
     "Completion", "l0cim_server_request_bytes", "l0cim_server_arena_overhead", "l0cim_server_create",
     "l0cim_server_clock", "l0cim_server_submit", "l0cim_server_step", "l0cim_server_completed",
-    "l0cim_server_info", "l0cim_server_destroy",
+    "l0cim_server_info", "l0cim_server_destroy", "l0cim_server_set_step_budget",
 ]
 
 F32, F64, BF16, FP8E4M3 = 0, 1, 2, 3
@@ -158,6 +158,8 @@ def lib():
         L.l0cim_server_submit.argtypes = [c_void_p, c_int32, c_int32, vp, c_int64, vp, c_uint64, c_int64, vp, vp,
                                           vp]
         L.l0cim_server_submit.restype = st
+        L.l0cim_server_set_step_budget.argtypes = [c_void_p, c_size_t]
+        L.l0cim_server_set_step_budget.restype = st
         L.l0cim_server_step.argtypes = [c_void_p, POINTER(c_int32)]
         L.l0cim_server_step.restype = st
         L.l0cim_server_completed.argtypes = [c_void_p, POINTER(Completion), c_int32]
@@ -434,6 +436,10 @@ def l0cim_server_submit(server, A, y, seed: int, tag: int, R_out, sigma_out, sta
     m, n = A.shape
     _check(lib().l0cim_server_submit(server, m, n, _ptr(A), _ld(A), _ptr(y), seed, tag, _ptr(R_out),
                                      _ptr(sigma_out), _ptr(stats_out)), "l0cim_server_submit")
+
+
+def l0cim_server_set_step_budget(server, nbytes: int) -> None:
+    _check(lib().l0cim_server_set_step_budget(server, int(nbytes)), "l0cim_server_set_step_budget")
 
 
 def l0cim_server_step(server) -> int:

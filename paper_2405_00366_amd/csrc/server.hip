@@ -2,8 +2,10 @@
 // caller-provided device arena.
 //
 // Requests are queued on submit.  Each tick admits queued requests in
-// arrival order while a slot is free and the request's footprint fits in the
-// arena (first fit), then advances every resident request by one
+// arrival order while a slot is free, the request's footprint fits in the
+// arena (first fit) and, when the caller set one, the couplings bytes that
+// one Euler step of the resident set streams stay within the step budget;
+// then advances every resident request by one
 // alternation of Algorithm 1 (couplings, one CIM run, replica choice, Jacobi
 // CDP) with the batched kernels: requests of different N, M and sparsity
 // share every launch, each with its own alternation index, eta and random
@@ -102,7 +104,7 @@ struct Req {
   uint8_t* sig_out;
   l0cim_stats* st_out;
   double t_submit, t_admit;
-  size_t off, bytes;
+  size_t off, bytes, cost;   // cost: couplings bytes streamed per Euler step
   int slot, alt;
 };
 
@@ -119,6 +121,7 @@ struct l0cim_server_s {
   hipStream_t stream;
   std::map<size_t, size_t> free_blocks;   // offset -> bytes, coalesced
   size_t in_use = 0;
+  size_t step_budget = 0, step_active = 0;
   std::deque<Req> pending;
   std::vector<Req> active;
   std::vector<int> free_slots;
@@ -238,10 +241,13 @@ l0cim_status tick(l0cim_server_s* sv, int* n_done) {
   hipStream_t s = sv->stream;
   const double t_start = sv->now();
   // admission: arrival order, stop at the first request that does not fit
+  // (in memory, or in the step budget unless nothing is resident)
   while (!sv->pending.empty() && !sv->free_slots.empty()) {
     Req& r = sv->pending.front();
+    if (sv->step_budget && !sv->active.empty() && sv->step_active + r.cost > sv->step_budget) break;
     size_t off = 0;
     if (!sv->alloc(r.bytes, &off)) break;
+    sv->step_active += r.cost;
     r.off = off;
     r.slot = sv->free_slots.back();
     sv->free_slots.pop_back();
@@ -365,6 +371,7 @@ l0cim_status tick(l0cim_server_s* sv, int* n_done) {
       c.t_finish = t_end;
       sv->done.push_back(c);
       sv->release(r.off, r.bytes);
+      sv->step_active -= r.cost;
       sv->free_slots.push_back(r.slot);
       ++*n_done;
     } else {
@@ -466,12 +473,19 @@ l0cim_status l0cim_server_submit(l0cim_server sv, int32_t m, int32_t n, const fl
   r.sig_out = sigma_out;
   r.st_out = stats_out;
   r.bytes = req_layout(m, n, sv->P, dtype_size(sv->jdt)).total;
+  r.cost = size_t(round_up16(n)) * size_t(round_up32(n)) * dtype_size(sv->jdt);
   if (r.bytes > sv->arena_bytes - sv->heap0)
     return set_error(L0CIM_ERR_WORKSPACE, "server_submit: request needs %zu bytes, the arena holds %zu", r.bytes,
                      sv->arena_bytes - sv->heap0);
   r.t_submit = sv->now();
   r.slot = -1;
   sv->pending.push_back(r);
+  return L0CIM_OK;
+}
+
+l0cim_status l0cim_server_set_step_budget(l0cim_server sv, size_t bytes) {
+  if (!sv) return set_error(L0CIM_ERR_ARG, "server_set_step_budget: NULL server");
+  sv->step_budget = bytes;
   return L0CIM_OK;
 }
 

@@ -182,6 +182,7 @@ def test_server_create_rejects_bad_arguments_on_host():
     assert create(nbytes=1024) == 3
     assert "arena" in _err(lib)
     assert lib.l0cim_server_step(None, None) == 1
+    assert lib.l0cim_server_set_step_budget(None, 0) == 1
     assert lib.l0cim_server_submit(None, 1, 1, FAKE, 1, FAKE, 0, 0, FAKE, FAKE, FAKE) == 1
 
 

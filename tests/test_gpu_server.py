@@ -46,7 +46,7 @@ class Requests:
         return (self.sig[k].cpu().numpy(), self.R[k].cpu().numpy(), L.read_stats(self.st[k]))
 
 
-def _serve(reqs, cim, sp, schedule, dev, max_slots=16, arena_bytes=None):
+def _serve(reqs, cim, sp, schedule, dev, max_slots=16, arena_bytes=None, budget=0):
     """schedule: list of lists; before tick t, submit the request indices schedule[t]."""
     max_n = max(i.N for i in reqs.insts)
     if arena_bytes is None:
@@ -54,6 +54,8 @@ def _serve(reqs, cim, sp, schedule, dev, max_slots=16, arena_bytes=None):
             L.l0cim_server_request_bytes(i.M, i.N, sp) for i in reqs.insts) + 4096
     arena = L.workspace(arena_bytes, dev)
     server = L.l0cim_server_create(cim, sp, max_slots, max_n, arena)
+    if budget:
+        L.l0cim_server_set_step_budget(server, budget)
     done, infos, t = [], [], 0
     try:
         while True:
@@ -147,6 +149,27 @@ def test_server_slot_limit(dev):
     done, infos = _serve(reqs, cim, sp, [[0, 1, 2, 3, 4]], dev, max_slots=2)
     assert max(i["active"] for i in infos) <= 2
     assert sorted(c.tag for c in done) == list(range(5))
+
+
+def test_server_step_budget(dev):
+    """A cap on the couplings bytes per Euler step bounds the resident set
+    (arrival order kept, a request alone always runs), and the results stay
+    bitwise those of the uncapped server."""
+    cim, sp = _params(n_steps=100, n_outer=3)
+    specs = [(801, 300, 150, 0.1), (802, 100, 60, 0.1), (803, 300, 150, 0.1), (804, 90, 50, 0.1),
+             (805, 500, 250, 0.1)]
+    cost = lambda n: ((n + 15) // 16 * 16) * ((n + 31) // 32 * 32) * 4
+    free = Requests(specs, dev)
+    _serve(free, cim, sp, [list(range(5))], dev)
+    capped = Requests(specs, dev)
+    budget = cost(300) + cost(100)
+    done, infos = _serve(capped, cim, sp, [list(range(5))], dev, budget=budget)
+    assert [c.tag for c in done] == [0, 1, 2, 3, 4]
+    assert infos[0]["active"] == 2 and infos[0]["pending"] == 3
+    # request 4 (cost above the cap) runs once it is alone
+    assert done[4].t_admit >= done[3].t_finish
+    for k in range(len(specs)):
+        assert _same(free.result(k), capped.result(k)), f"request {k}"
 
 
 def test_server_rejects_requests_it_can_never_hold(dev):
