@@ -37,10 +37,11 @@ __device__ bool grid_sync(int* ctl, int* arrive, int nblocks, int& gen) {
   if (threadIdx.x == 0) ok_sh = 1;
   __syncthreads();
   const int tid = threadIdx.x, wg = blockIdx.x;
-  if (tid == 0) {
-    __threadfence();
-    __hip_atomic_store(&arrive[wg * kSlot], gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  // Arrival: one device-scope release (the workgroup's writes, ordered before
+  // it by the workgroup barrier, become visible first).  Waits poll with
+  // relaxed loads and acquire once they succeed: an acquire per poll would
+  // invalidate the L2 of the poller's XCD on every iteration.
+  if (tid == 0) __hip_atomic_store(&arrive[wg * kSlot], gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   auto give_up = [&]() {
     ok_sh = 0;
     __hip_atomic_store(&ctl[C_ABORT], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -48,7 +49,7 @@ __device__ bool grid_sync(int* ctl, int* arrive, int nblocks, int& gen) {
   if (wg == 0) {
     for (int w = tid; w < nblocks; w += BS) {
       int64_t polls = 0;
-      while (__hip_atomic_load(&arrive[w * kSlot], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < gen) {
+      while (__hip_atomic_load(&arrive[w * kSlot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
         if (++polls > kBarrierLimit || ((polls & 255) == 0 &&
                                         __hip_atomic_load(&ctl[C_ABORT], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
           give_up();
@@ -58,21 +59,21 @@ __device__ bool grid_sync(int* ctl, int* arrive, int nblocks, int& gen) {
       }
     }
     __syncthreads();
-    if (tid == 0 && ok_sh) {
-      __threadfence();
-      __hip_atomic_store(&ctl[C_GEN], gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      if (ok_sh) __hip_atomic_store(&ctl[C_GEN], gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
   } else if (tid == 0) {
     int64_t polls = 0;
-    while (__hip_atomic_load(&ctl[C_GEN], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < gen) {
+    while (__hip_atomic_load(&ctl[C_GEN], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
       if (++polls > kBarrierLimit || __hip_atomic_load(&ctl[C_ABORT], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
         give_up();
         break;
       }
       __builtin_amdgcn_s_sleep(1);
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
-  if (tid == 0) __threadfence();
   __syncthreads();
   return ok_sh != 0;
 }
