@@ -47,6 +47,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cim_regs_kernel_plain_n2000_traff
 KERNEL_SOURCES = ("mfcim.hip", "common.h")
 PRECISION_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bstep_kernel_mri_bf16_traffic.txt")
 PRECISION_SOURCES = ("batch.hip", "batch.h", "mfcim_matrix.hip")
+BATCHED_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bstep_kernel_batched_256x16_traffic.txt")
+BATCHED_SOURCES = ("batch.hip", "batch.h", "batch_plan.hip")
 
 
 def kernel_source_hash(sources=KERNEL_SOURCES) -> str:
@@ -148,7 +150,7 @@ def percentiles(v):
 
 
 def batched_bench(args, torch, L, W, dev):
-    P, steps, outer = 16, 1000, 30
+    P, steps, outer = 16, args.euler_steps or 1000, args.alternations or 30
     specs = W.batch_specs(7, 256)
     insts = [sp.build() for sp in specs]
     descr, A, y, R, sig, stats = L.pack_instances([i.A for i in insts], [i.y for i in insts],
@@ -190,7 +192,9 @@ def batched_bench(args, torch, L, W, dev):
                          "parity of the batched form is covered by its GPU tests",
         "status_nonzero": sum(1 for x in st if x.status_bits),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "bstep_kernel<float, CN, 1, rb>",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(BATCHED_TRAFFIC_FILE, BATCHED_SOURCES, "hbm_bytes_per_step"),
+                     "kernel": "bstep_kernel<float, CN, 1, rb>",
                      "avg_launch_ms": cim_ms / launches / (steps + 1), "launches": launches * (steps + 1)},
     }
 
@@ -406,9 +410,9 @@ def main():
                     help="serving form: cap on the couplings MB one Euler step of the resident set streams (0: none)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--euler-steps", type=int, default=0,
-                    help="precision form: Euler steps per alternation instead of 1000 (profiling runs)")
+                    help="precision / batched forms: Euler steps per alternation instead of 1000 (profiling runs)")
     ap.add_argument("--alternations", type=int, default=0,
-                    help="precision form: alternations instead of 11 (profiling runs)")
+                    help="precision / batched forms: alternations instead of 11 / 30 (profiling runs)")
     ap.add_argument("--no-graph", action="store_true",
                     help="batched form: launch the Euler steps one by one (no HIP graph replay)")
     args = ap.parse_args()
