@@ -313,6 +313,9 @@ __global__ void select_kernel(int n, int P, const double* __restrict__ H,
   for (int i = threadIdx.x; i < n; i += blockDim.x) out[i] = src[i];
 }
 
+// Sleep (units of 64 clocks) before the first poll of each step of the
+// register-resident run.
+constexpr int kFirstPollSleep = 15;
 
 // Single-replica resident run with the couplings held in registers.  Thread t
 // of a 512-thread workgroup keeps J[r0 + rho][t + u*512] for its rows rho < R
@@ -366,6 +369,12 @@ cim_regs_kernel(const JT* __restrict__ J, int64_t ldj, const float* __restrict__
   bool aborted = false;
 
   for (int k = 0; k <= a.n_steps; ++k) {
+    // Every workgroup publishes its spins about the same time after its own
+    // barrier, and a poll that reaches memory before the words do comes back
+    // stale and costs a second round trip: the first poll of a step waits
+    // kFirstPollSleep x 64 clocks (about 0.4 us; at N = 2000 on MI355X the
+    // step went from 1.92 to 1.47 us, with 12 and 18 units 1.54 and 1.52 us).
+    if (k > 0) __builtin_amdgcn_s_sleep(kFirstPollSleep);
     const bool last = (k == a.n_steps);
     const uint64_t* src = ll + size_t(k & 1) * slot_words;
     const uint32_t flag = uint32_t(k + 1);

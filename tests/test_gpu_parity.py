@@ -256,27 +256,59 @@ def test_mfcim_full_run_matches_oracle_support(dev):
 
 
 def test_spin_limit_aborts_cleanly(dev):
-    """A tiny bound on the device waits forces the abort path: every workgroup
-    exits, the timeout bit is raised and nothing hangs."""
+    """A tiny bound on the device waits forces the abort path of the resident
+    run (FP64, couplings in LDS, every workgroup polls as soon as it has
+    published): every workgroup exits, the timeout bit is raised and nothing
+    hangs."""
     n = 2000
     _, G32, b32, R = problem(5, n)
     J, z = O.couplings(G32, b32, R)
-    c = t(f32(W.initial_amplitudes(5, 1, n)), torch.float32, dev)
+    c = t(W.initial_amplitudes(5, 1, n), torch.float64, dev)
     e = torch.ones_like(c)
     status = torch.zeros(1, dtype=torch.int32, device=dev)
     prm = L.cim_params(n_steps=500, launch=L.LAUNCH_RESIDENT, spin_limit=1)
-    L.l0cim_mfcim_run(t(f32(J), torch.float32, dev), t(f32(z), torch.float32, dev), 0.5, prm, c, e,
-                      status=status)
+    L.l0cim_mfcim_run(t(J, torch.float64, dev), t(z, torch.float64, dev), 0.5, prm, c, e, status=status)
     torch.cuda.synchronize()
     assert int(status.item()) & L.ST_TIMEOUT
     # the same workspace-free call works normally afterwards
-    c = t(f32(W.initial_amplitudes(5, 1, n)), torch.float32, dev)
+    c = t(W.initial_amplitudes(5, 1, n), torch.float64, dev)
     e = torch.ones_like(c)
     status.zero_()
-    L.l0cim_mfcim_run(t(f32(J), torch.float32, dev), t(f32(z), torch.float32, dev), 0.5,
+    L.l0cim_mfcim_run(t(J, torch.float64, dev), t(z, torch.float64, dev), 0.5,
                       L.cim_params(n_steps=50, launch=L.LAUNCH_RESIDENT), c, e, status=status)
     torch.cuda.synchronize()
     assert int(status.item()) == 0
+
+
+def test_spin_limit_register_resident_run_is_bounded(dev):
+    """The register-resident FP32 run sleeps before the first poll of a step,
+    so its waits are mostly satisfied at once and a tiny bound need not fire;
+    whichever way it goes the run ends, raises nothing but the timeout bit,
+    and the next run is clean and matches the oracle's first steps."""
+    n = 2000
+    _, G32, b32, R = problem(5, n)
+    J, z = O.couplings(G32, b32, R)
+    Jd, zd = t(f32(J), torch.float32, dev), t(f32(z), torch.float32, dev)
+    c = t(f32(W.initial_amplitudes(5, 1, n)), torch.float32, dev)
+    e = torch.ones_like(c)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    L.l0cim_mfcim_run(Jd, zd, 0.5, L.cim_params(n_steps=500, launch=L.LAUNCH_RESIDENT, spin_limit=1), c, e,
+                      status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) & ~L.ST_TIMEOUT == 0
+    c0 = f32(W.initial_amplitudes(5, 1, n))
+    c = t(c0, torch.float32, dev)
+    e = torch.ones_like(c)
+    status.zero_()
+    steps = 50
+    tr = torch.empty((steps, 2, 1, n), dtype=torch.float32, device=dev)
+    L.l0cim_mfcim_run(Jd, zd, 0.5, L.cim_params(n_steps=steps, launch=L.LAUNCH_RESIDENT), c, e, status=status,
+                      trace=tr, trace_steps=steps)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    _, _, tro = O.mfcim_run(f32(J), f32(z), 0.5, c0, np.ones((1, n)), O.CimParams(n_steps=steps), trace_steps=steps)
+    got = tr.double().cpu().numpy()
+    assert max(normwise(got[k, v], tro[k, v]) for k in range(steps) for v in range(2)) <= 1e-5
 
 
 # ---------------------------------------------------------------------------
