@@ -105,30 +105,34 @@ jacobi_support_kernel(int n, const float* __restrict__ G, int64_t ldg, const flo
   const float br = own ? b[r] : 0.0f;
   if (own) Rb[0][orow] = tiny ? 0.0f : R[r];
   float V = 0.0f;
+  // wavefront w holds rows 16 w .. 16 w + 15: the ones past the support skip the sweeps
+  const bool wave_on = 16 * (t / kWave) < ks;
   __syncthreads();
   for (int it = 0; it < iters; ++it) {
-    const float4* x4 = reinterpret_cast<const float4*>(Rb[it & 1] + 16 * cg);
-    float x[16];
+    if (wave_on) {
+      const float4* x4 = reinterpret_cast<const float4*>(Rb[it & 1] + 16 * cg);
+      float x[16];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const float4 v = x4[q];
-      x[4 * q] = v.x;
-      x[4 * q + 1] = v.y;
-      x[4 * q + 2] = v.z;
-      x[4 * q + 3] = v.w;
-    }
-    float acc[4];
+      for (int q = 0; q < 4; ++q) {
+        const float4 v = x4[q];
+        x[4 * q] = v.x;
+        x[4 * q + 1] = v.y;
+        x[4 * q + 2] = v.z;
+        x[4 * q + 3] = v.w;
+      }
+      float acc[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      acc[i] = 0.0f;
+      for (int i = 0; i < 4; ++i) {
+        acc[i] = 0.0f;
 #pragma unroll
-      for (int u = 0; u < 16; ++u) acc[i] += g[i][u] * x[u];
-    }
-    wave_sum_rows_level<float, 4, 4, 8>(acc, lane);
-    if (own) {
-      const float Rv = Rb[it & 1][orow];
-      V = (1.0f - dtc) * V + Rv;
-      Rb[(it + 1) & 1][orow] = tiny ? 0.0f : Rv + dtc * ((br - acc[0]) / d - Rv);
+        for (int u = 0; u < 16; ++u) acc[i] += g[i][u] * x[u];
+      }
+      wave_sum_rows_level<float, 4, 4, 8>(acc, lane);
+      if (own) {
+        const float Rv = Rb[it & 1][orow];
+        V = (1.0f - dtc) * V + Rv;
+        Rb[(it + 1) & 1][orow] = tiny ? 0.0f : Rv + dtc * ((br - acc[0]) / d - Rv);
+      }
     }
     __syncthreads();
   }
