@@ -211,6 +211,14 @@ def precision_bench(args, torch, L, W, dev):
             if line.strip() and line[0] != "#":
                 sd, k, rm, hx = line.split()
                 gold[int(sd)] = (int(hx, 16), float(rm))
+    # the oracle's x_hat on its own support (its final FP64 refit)
+    gold_R = {}
+    path = os.path.join(ROOT, "tests", "golden", "oracle_refit_mri.txt")
+    if os.path.exists(path):
+        for line in open(path):
+            if line.strip() and line[0] != "#":
+                f = line.split()
+                gold_R[int(f[0])] = np.array([float(v) for v in f[2:]])
     seeds = list(range(args.steps))
     cim = L.cim_params(n_steps=steps, field="BN", K=1.0, d=0.6)
     rows, total, cim_total, launches_total, match = [], 0.0, 0.0, 0, 0
@@ -246,11 +254,17 @@ def precision_bench(args, torch, L, W, dev):
         Rv = R.double().cpu().numpy()
         rmse = float(np.sqrt(np.mean((Rv * sig - inst.x * inst.xi) ** 2)))
         ok = sd in gold and mask_to_int(sig) == gold[sd][0] and (steps, outer) == (1000, 11)
+        xd = None
+        if sd in gold and sd in gold_R:
+            x_or = np.zeros(n)
+            S_or = [r for r in range(n) if (gold[sd][0] >> r) & 1]
+            x_or[S_or] = gold_R[sd]
+            xd = float(np.sqrt(np.mean((Rv * sig - x_or) ** 2)))
         match += int(ok)
         rows.append({"seed": sd, "support": int(sig.sum()), "rmse": rmse,
                      "oracle_rmse": gold[sd][1] if sd in gold else None, "oracle_support_match": ok,
                      "hamming_vs_oracle": (bin(mask_to_int(sig) ^ gold[sd][0]).count("1") / n) if sd in gold
-                     else None, "status": L.read_stats(st).status_bits, "solve_s": dt})
+                     else None, "xhat_rmse_vs_oracle": xd, "status": L.read_stats(st).status_bits, "solve_s": dt})
     spin_steps = n * P * steps * outer * len(seeds)
     run_bytes = step_bytes(n, P, jb) * (steps + 1)
     achieved = run_bytes / (cim_total / 1e3 / launches_total) / 1e9

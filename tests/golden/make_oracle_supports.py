@@ -14,6 +14,11 @@ Usage:  python tests/golden/make_oracle_supports.py {small|plain|mri} FIRST LAST
           FP64 couplings applied in factored form, FP64 refit.
 
 Each output line:  seed  support_size  rmse  hex(support bitmask, spin r = bit r)
+
+Usage:  python tests/golden/make_oracle_supports.py mri-refit
+  writes oracle_refit_mri.txt: for every seed of oracle_supports_mri.txt, the
+  oracle's final FP64 refit on its stored support (the R of its x_hat = sigma R),
+  one line per seed:  seed  support_size  R_S in increasing spin order.
 """
 import os
 import sys
@@ -78,7 +83,31 @@ def one(args):
     return seed, int(res.sigma.sum()), O.rmse(res.sigma, res.R, inst.x, inst.xi), bitmask_hex(res.sigma), dt
 
 
+def mri_refit():
+    from oracle import mri as OM
+    from workloads import mri as WM
+    src = os.path.join(HERE, "oracle_supports_mri.txt")
+    out = os.path.join(HERE, "oracle_refit_mri.txt")
+    with open(out, "w") as f:
+        f.write("# FP64 oracle final refit on its stored MRI-shaped supports (see make_oracle_supports.py)\n")
+        f.write("# seed support_size R_S (spins in increasing order)\n")
+        for line in open(src):
+            if not line.strip() or line[0] == "#":
+                continue
+            seed, k, _rm, hx = line.split()
+            inst = WM.mri_instance(int(seed))
+            v = int(hx, 16)
+            sigma = np.array([(v >> r) & 1 for r in range(inst.A.shape[1])], np.uint8)
+            assert int(sigma.sum()) == int(k)
+            S, R_S = OM.refit(inst.A, inst.y, sigma)
+            f.write(f"{seed} {len(S)} " + " ".join(f"{x:.12e}" for x in R_S) + "\n")
+            print(f"seed {seed}: |S| = {len(S)}", flush=True)
+
+
 def main():
+    if sys.argv[1] == "mri-refit":
+        mri_refit()
+        return
     name, first, last = sys.argv[1], int(sys.argv[2]), int(sys.argv[3])
     jobs = int(sys.argv[4]) if len(sys.argv) > 4 else 1
     out = os.path.join(HERE, f"oracle_supports_{name}.txt")
