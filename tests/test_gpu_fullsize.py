@@ -4,7 +4,8 @@ configurations the benchmark times, on outputs the oracle can afford.
   * MRI-shaped precision form (N = 16384, M = 4915, 64 replicas, BN field):
     BF16 / FP8 couplings with row scales bit-exact on sampled rows, then the
     first 10 Euler steps of the matrix-core run against the oracle on the same
-    rounded couplings (normwise 1e-5 per step, every spin and replica).
+    rounded couplings (normwise 1e-5 per step, every spin and replica); and
+    the whole solve's outcome against the oracle's stored result.
   * Batched form (the 256-instance batch, 16 replicas): one alternation of
     150 steps; for the smallest, a middle and the largest instance the chosen
     replica carries the oracle's support for that replica with the oracle's
@@ -50,7 +51,8 @@ def mri(dev):
     b = (A.astype(np.float64).T @ y.astype(np.float64)).astype(np.float32)
     R = (b / np.diag(G)).astype(np.float32)
     Gd = torch.from_numpy(G).to(dev)
-    return dict(G=G, b=b, R=R, Gd=Gd, bd=torch.from_numpy(b).to(dev), Rd=torch.from_numpy(R).to(dev))
+    return dict(G=G, b=b, R=R, Gd=Gd, bd=torch.from_numpy(b).to(dev), Rd=torch.from_numpy(R).to(dev),
+                A=A, y=y, inst=inst)
 
 
 @pytest.mark.parametrize("fmt,code", [("bf16", L.BF16), ("fp8", L.FP8E4M3)])
@@ -83,6 +85,50 @@ def test_mri_precision_couplings_and_first_steps(dev, mri, fmt, code):
     for k in range(steps):
         assert normwise(got[k, 0], tro[k, 0]) <= 1e-5, f"c, step {k}"
         assert normwise(got[k, 1], tro[k, 1]) <= 1e-5, f"e, step {k}"
+
+
+def _mri_golden(seed):
+    import os
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    sup = R_S = None
+    for line in open(os.path.join(here, "oracle_supports_mri.txt")):
+        if line.strip() and line[0] != "#" and int(line.split()[0]) == seed:
+            _, k, rm, hx = line.split()
+            sup = (int(hx, 16), float(rm))
+    for line in open(os.path.join(here, "oracle_refit_mri.txt")):
+        if line.strip() and line[0] != "#" and int(line.split()[0]) == seed:
+            R_S = np.array([float(v) for v in line.split()[2:]])
+    return sup, R_S
+
+
+@pytest.mark.parametrize("fmt,code", [("bf16", L.BF16), ("fp8", L.FP8E4M3)])
+def test_mri_precision_solve_outcome(dev, mri, fmt, code):
+    """The whole MRI-shaped solve the benchmark times (64 replicas, 11
+    alternations of 1000 steps, FP64 refit), seed 0.  After the bifurcation
+    the FP32-state trajectories part from the FP64 oracle's, so this checks the
+    outcome against the oracle's stored result: no status bits, a
+    reconstruction no worse than the oracle's by more than 1e-3 RMSE, supports
+    that differ in at most 2% of the spins, and an x_hat within 0.02 RMSE of
+    the oracle's (measured: 0.009 BF16, 0.010 FP8)."""
+    inst, n = mri["inst"], mri["G"].shape[0]
+    (mask, rm_or), R_S = _mri_golden(0)
+    A = torch.from_numpy(mri["A"]).to(dev)
+    y = torch.from_numpy(mri["y"]).to(dev)
+    cim = L.cim_params(n_steps=1000, field="BN", K=1.0, d=0.6)
+    sp = L.solve_params(eta_init=0.8, eta_end=0.03, velo=11, n_outer=11, replicas=64, j_dtype=code,
+                        final_refit_f64=1, seed=0)
+    R, sig, stats = L.l0cim_solve(A, y, cim, sp)
+    torch.cuda.synchronize()
+    assert L.read_stats(stats).status_bits == 0
+    sg = sig.cpu().numpy().astype(np.int64)
+    Rv = R.double().cpu().numpy()
+    sig_or = np.array([(mask >> r) & 1 for r in range(n)], np.int64)
+    x_or = np.zeros(n)
+    x_or[np.flatnonzero(sig_or)] = R_S
+    rm = O.rmse(sg, Rv, inst.x, inst.xi)
+    assert rm <= rm_or + 1e-3, (rm, rm_or)
+    assert np.mean(sg != sig_or) <= 0.02
+    assert np.sqrt(np.mean((Rv * sg - x_or) ** 2)) <= 0.02
 
 
 def _one_alternation(inst, seed, P, steps, eta):
