@@ -261,7 +261,7 @@ l0cim_status tick(l0cim_server_s* sv, int* n_done) {
   *n_done = 0;
   if (sv->active.empty()) return L0CIM_OK;
   const int count = int(sv->active.size());
-  // tile shape: the largest row block that still gives every CU two tiles
+  // tile shape: the largest row block that still gives every CU four tiles
   auto tiles_for = [&](int rb) {
     int64_t t = 0;
     for (const Req& r : sv->active) t += (r.n + 16 * rb - 1) / (16 * rb);
