@@ -229,7 +229,6 @@ __device__ inline v8bf bits_to_bf16(uint32_t word, int pos) {
 // 8 e4m3 codes -> 8 bf16 with the hardware pair conversion at scale 1
 // (exact: every e4m3 value, subnormals included, is a bf16 value).
 __device__ inline v8bf fp8_to_bf16(v2u v) {
-  typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
   v4u w;
   w.x = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(int(v.x), 1.0f, false));
   w.y = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(int(v.x), 1.0f, true));
