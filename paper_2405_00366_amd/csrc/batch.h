@@ -80,7 +80,12 @@ struct BatchDev {
   const double* eta;           // one eta for every instance, or NULL: each instance's own
 };
 
-const void* batch_step_kernel(l0cim_dtype jdt, int field, int qb, int rb);
+// A step kernel and its workgroup size (fn NULL: no kernel for that shape).
+struct StepKernel {
+  const void* fn;
+  int threads;
+};
+StepKernel batch_step_kernel(l0cim_dtype jdt, int field, int qb, int rb);
 l0cim_status launch_bcouplings(const BatchDev& d, l0cim_dtype jdt, int64_t total_rows, hipStream_t s);
 l0cim_status launch_binit(const BatchDev& d, int P, int alt, double std, int64_t total_state, hipStream_t s);
 l0cim_status launch_bbits(const BatchDev& d, int QB, int64_t total_words, hipStream_t s);
@@ -95,7 +100,7 @@ l0cim_status launch_bjacobi(const BatchDev& d, int ntiles, int rows_per_tile, do
 l0cim_status launch_bobjective(const BatchDev& d, double lam, int64_t steps_per_alt, int n_outer, int P,
                                hipStream_t s);
 l0cim_status launch_bstats_init(const BatchDev& d, hipStream_t s);
-l0cim_status enqueue_bsteps(const BatchDev& d, const void* fn, const BStepArgs& a, int ntiles, int k0, int k1,
+l0cim_status enqueue_bsteps(const BatchDev& d, StepKernel k, const BStepArgs& a, int ntiles, int k0, int k1,
                             hipStream_t s);
 l0cim_status launch_bfill(float* p, int64_t count, hipStream_t s);
 l0cim_status launch_bset_scalar(double* p, double v, hipStream_t s);

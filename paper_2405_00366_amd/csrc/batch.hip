@@ -159,12 +159,12 @@ binit_kernel(const BInst* __restrict__ insts, const int64_t* __restrict__ st_pre
 // ---------------------------------------------------------------------------
 //
 // A workgroup owns 16 * RB rows (RB panels) of one instance for all its
-// replicas (16 * QB columns of X) and its four wavefronts split the columns
-// of J into four contiguous ranges of 32-column chunks (boundaries fixed by
-// the instance's ld).  Each wavefront keeps D chunks of operands in flight,
-// sums its range on the matrix cores, and the four partial sums are added in
-// LDS in wavefront order before the fused Euler epilogue.  Every output
-// row's arithmetic is therefore a function of its instance only.
+// replicas (16 * QB columns of X) and its NW wavefronts split the columns of
+// J into NW contiguous ranges of 32-column chunks (boundaries fixed by the
+// instance's ld).  Each wavefront keeps D chunks of operands in flight, sums
+// its range on the matrix cores, and the NW partial sums are added in LDS in
+// wavefront order before the fused Euler epilogue.  Every output row's
+// arithmetic is therefore a function of its instance only.
 //
 // Operands of one chunk for lane (li = lane % 16, lk = lane / 16):
 //   A: J[16 p + li][32 c + 8 lk + t], t < 8, from the panel block (p, c);
@@ -237,14 +237,23 @@ __device__ inline v8bf fp8_to_bf16(v2u v) {
   return __builtin_bit_cast(v8bf, w);
 }
 
+// Wavefronts per workgroup: eight for FP8 couplings (their fastest tile at
+// the MRI shape, 64 rows, leaves one workgroup per CU: 47.4 against 49.9 us
+// per step with four), four for the others (eight measured slower for FP32).
+template <typename JT>
+constexpr int step_waves() {
+  return sizeof(JT) == 1 ? 8 : 4;
+}
+
 template <typename JT, int FIELD, int QB, int RB>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64 * step_waves<JT>())
 bstep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, BStepArgs a, int k,
              const double* __restrict__ etap) {
   constexpr bool kF32 = sizeof(JT) == 4;
+  constexpr int NW = step_waves<JT>();
   constexpr int D = pipe_depth(int(sizeof(JT)), FIELD, RB, QB);
-  static_assert(RB * QB <= 16, "partial sums must fit in 64 KB of LDS");
-  __shared__ v4f red[4][RB * QB][64];
+  static_assert(RB * QB * NW <= 128, "partial sums must fit in 128 KB of LDS");
+  __shared__ v4f red[NW][RB * QB][64];
   const BTile tl = tiles[blockIdx.x];
   const BInst I = insts[tl.inst];
   const int n = I.n, ld = I.ld, P = a.P, nch = ld >> 5;
@@ -256,7 +265,9 @@ bstep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, B
   const float* cin = (k & 1) ? I.c2 : I.c;
   const uint32_t* xin = (k & 1) ? I.xb2 : I.xb;
   const JT* J = static_cast<const JT*>(I.J);
-  const int c0 = (w * nch) >> 2, c1 = ((w + 1) * nch) >> 2;
+  constexpr int kNwLog = NW == 8 ? 3 : 2;
+  static_assert(NW == (1 << kNwLog), "four or eight wavefronts");
+  const int c0 = (w * nch) >> kNwLog, c1 = ((w + 1) * nch) >> kNwLog;
   const int lane_off = kF32 ? (li * 4 + lk) * 4 : (li * 4 + lk) * 8;
 
   // Rows of panels past the instance and replicas past P read valid
@@ -436,12 +447,18 @@ bstep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, B
   float* cout = (k & 1) ? I.c : I.c2;
   uint16_t* xout = reinterpret_cast<uint16_t*>((k & 1) ? I.xb : I.xb2);
   int bits = 0;
-  for (int b = w; b < RB * QB; b += 4) {
+  for (int b = w; b < RB * QB; b += NW) {
     const int rb = b / QB, qb = b - (b / QB) * QB;
     v4f sacc = red[0][b][lane];
     sacc += red[1][b][lane];
     sacc += red[2][b][lane];
     sacc += red[3][b][lane];
+    if constexpr (NW == 8) {
+      sacc += red[4][b][lane];
+      sacc += red[5][b][lane];
+      sacc += red[6][b][lane];
+      sacc += red[7][b][lane];
+    }
     const int q = qb * 16 + li;
     const int r0 = (p0 + rb) * 16 + 4 * lk;
     uint32_t nib = 0;
@@ -799,19 +816,22 @@ static const void* step_kernel_q(int qb, int rb) {
   return nullptr;
 }
 
-const void* batch_step_kernel(l0cim_dtype jdt, int field, int qb, int rb) {
+StepKernel batch_step_kernel(l0cim_dtype jdt, int field, int qb, int rb) {
   if (jdt == L0CIM_F32)
-    return field == L0CIM_FIELD_BN ? step_kernel_q<float, kBN>(qb, rb) : step_kernel_q<float, kCN>(qb, rb);
+    return {field == L0CIM_FIELD_BN ? step_kernel_q<float, kBN>(qb, rb) : step_kernel_q<float, kCN>(qb, rb),
+            64 * step_waves<float>()};
   if (jdt == L0CIM_BF16)
-    return field == L0CIM_FIELD_BN ? step_kernel_q<__hip_bfloat16, kBN>(qb, rb)
-                                   : step_kernel_q<__hip_bfloat16, kCN>(qb, rb);
+    return {field == L0CIM_FIELD_BN ? step_kernel_q<__hip_bfloat16, kBN>(qb, rb)
+                                    : step_kernel_q<__hip_bfloat16, kCN>(qb, rb),
+            64 * step_waves<__hip_bfloat16>()};
   if (jdt == L0CIM_FP8E4M3)
-    return field == L0CIM_FIELD_BN ? step_kernel_q<__hip_fp8_e4m3, kBN>(qb, rb)
-                                   : step_kernel_q<__hip_fp8_e4m3, kCN>(qb, rb);
-  return nullptr;
+    return {field == L0CIM_FIELD_BN ? step_kernel_q<__hip_fp8_e4m3, kBN>(qb, rb)
+                                    : step_kernel_q<__hip_fp8_e4m3, kCN>(qb, rb),
+            64 * step_waves<__hip_fp8_e4m3>()};
+  return {nullptr, 0};
 }
 
-l0cim_status enqueue_bsteps(const BatchDev& d, const void* fn, const BStepArgs& a, int ntiles, int k0, int k1,
+l0cim_status enqueue_bsteps(const BatchDev& d, StepKernel sk, const BStepArgs& a, int ntiles, int k0, int k1,
                             hipStream_t s) {
   for (int k = k0; k <= k1; ++k) {
     const BTile* tiles = d.tiles;
@@ -820,7 +840,7 @@ l0cim_status enqueue_bsteps(const BatchDev& d, const void* fn, const BStepArgs& 
     int kk = k;
     const double* eta = d.eta;
     void* args[] = {&tiles, &insts, &aa, &kk, &eta};
-    L0_HIP(hipLaunchKernel(fn, dim3(ntiles), dim3(256), args, 0, s));
+    L0_HIP(hipLaunchKernel(sk.fn, dim3(ntiles), dim3(sk.threads), args, 0, s));
   }
   return L0CIM_OK;
 }

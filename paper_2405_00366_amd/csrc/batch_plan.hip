@@ -179,8 +179,8 @@ BStepArgs step_args(const l0cim_batch_plan_s* p) {
 // Enqueue Euler steps k0..k1 (inclusive) of one CIM run.
 l0cim_status enqueue_steps(const l0cim_batch_plan_s* p, const BatchDev& d, int rb, int ntiles, int k0, int k1,
                            hipStream_t s) {
-  const void* fn = batch_step_kernel(p->jdt, p->cim.field, p->qb, rb);
-  if (!fn) return set_error(L0CIM_ERR_UNSUPPORTED, "batched step: no kernel for this shape");
+  const StepKernel fn = batch_step_kernel(p->jdt, p->cim.field, p->qb, rb);
+  if (!fn.fn) return set_error(L0CIM_ERR_UNSUPPORTED, "batched step: no kernel for this shape");
   return enqueue_bsteps(d, fn, step_args(p), ntiles, k0, k1, s);
 }
 

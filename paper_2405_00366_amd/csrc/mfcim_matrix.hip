@@ -252,7 +252,8 @@ l0cim_status launch_matrix_run(int n, int P, l0cim_dtype jdt, const void* J, int
       int nt = 0;
       st = setup(cand, &nt);
       if (st != L0CIM_OK) return st;
-      const void* fc = batch_step_kernel(jdt, a.field, qb, cand);
+      const StepKernel fc = batch_step_kernel(jdt, a.field, qb, cand);
+      if (!fc.fn) return set_error(L0CIM_ERR_UNSUPPORTED, "matrix run: no kernel for this shape");
       st = enqueue_bsteps(d, fc, ta, nt, 0, 1, s);
       if (st != L0CIM_OK) return st;
       L0_HIP(hipEventRecord(e0, s));
@@ -284,8 +285,8 @@ l0cim_status launch_matrix_run(int n, int P, l0cim_dtype jdt, const void* J, int
   int ntiles = 0;
   st = setup(rb, &ntiles);
   if (st != L0CIM_OK) return st;
-  const void* fn = batch_step_kernel(jdt, a.field, qb, rb);
-  if (!fn) return set_error(L0CIM_ERR_UNSUPPORTED, "matrix run: no kernel for this shape");
+  const StepKernel fn = batch_step_kernel(jdt, a.field, qb, rb);
+  if (!fn.fn) return set_error(L0CIM_ERR_UNSUPPORTED, "matrix run: no kernel for this shape");
   {
     ProfileScope prof(s);
     st = enqueue_bsteps(d, fn, sa, ntiles, 0, a.n_steps, s);

@@ -314,8 +314,8 @@ l0cim_status tick(l0cim_server_s* sv, int* n_done) {
   L0_TRY(launch_bcouplings(d, sv->jdt, hrow[count], s));
   L0_TRY(launch_binit(d, sv->P, -1, sv->cim.c0_std, hst[count], s));
   if (sv->cim.field == L0CIM_FIELD_BN) L0_TRY(launch_bbits(d, sv->qb, hst[count] / 32, s));
-  const void* fn = batch_step_kernel(sv->jdt, sv->cim.field, sv->qb, rb);
-  if (!fn) return set_error(L0CIM_ERR_UNSUPPORTED, "server: no step kernel for this shape");
+  const StepKernel fn = batch_step_kernel(sv->jdt, sv->cim.field, sv->qb, rb);
+  if (!fn.fn) return set_error(L0CIM_ERR_UNSUPPORTED, "server: no step kernel for this shape");
   BStepArgs a{};
   a.P = sv->P;
   a.n_steps = sv->cim.n_steps;
