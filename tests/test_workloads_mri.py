@@ -88,3 +88,26 @@ def test_factored_couplings_equal_dense_couplings():
     Ra, _ = OM.cdp_jacobi(op, b, sig[0], R, 0.1, 20)
     Rb, _ = O.cdp_jacobi(G, b, sig[0], R, 0.1, 20)
     np.testing.assert_allclose(Ra, Rb, atol=1e-10)
+
+
+def test_stored_oracle_refit_matches_the_stored_support():
+    """The stored oracle refit (tests/golden/oracle_refit_mri.txt) is the
+    oracle's least squares on the stored seed-0 support, and that support's
+    stored RMSE is the RMSE of that refit against the ground truth."""
+    import os
+    from oracle import mfcim as O, mri as OM
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    sup = [l.split() for l in open(os.path.join(here, "oracle_supports_mri.txt")) if l.strip() and l[0] != "#"]
+    ref = [l.split() for l in open(os.path.join(here, "oracle_refit_mri.txt")) if l.strip() and l[0] != "#"]
+    seed, k, rm, hx = next(r for r in sup if r[0] == "0")
+    R_S = np.array([float(v) for v in next(r for r in ref if r[0] == "0")[2:]])
+    inst = mri.mri_instance(0)
+    n = inst.A.shape[1]
+    v = int(hx, 16)
+    sigma = np.array([(v >> r) & 1 for r in range(n)], np.uint8)
+    assert int(sigma.sum()) == int(k) == len(R_S)
+    S, R_new = OM.refit(inst.A, inst.y, sigma)
+    np.testing.assert_allclose(R_new, R_S, rtol=1e-9, atol=1e-12)
+    R = np.zeros(n)
+    R[S] = R_S
+    assert abs(O.rmse(sigma, R, inst.x, inst.xi) - float(rm)) <= 1e-9 * float(rm)
