@@ -73,19 +73,24 @@ gram_kernel(int m, int n, const T* __restrict__ A, int64_t lda, T* __restrict__ 
 }
 
 typedef float v4f __attribute__((ext_vector_type(4)));
-constexpr int kMT = 128;   // output tile
-constexpr int kMK = 16;    // rows of A per chunk
+constexpr int kMT = 128;        // output tile
+constexpr int kMK = 32;         // rows of A per chunk
+constexpr int kLdsK = kMK + 4;  // padded LDS row: 16 consecutive rows fall in distinct banks
 
 // One workgroup per tile (I, J), I <= J, of the upper triangle; 4 wavefronts
-// of 64 x 64 (4 x 4 blocks of 16 x 16).  A chunk of 16 rows of A is staged
-// in LDS column-major (16 values of a column contiguous); the matrix-core
-// step s of lane group g uses row 4 g + s of the chunk on both operands, so
-// each lane reads its 4 values of a column with one 16-byte load.
+// of 64 x 64 (4 x 4 blocks of 16 x 16).  A chunk of 32 rows of A is staged
+// in LDS column-major (the 32 values of a column contiguous, padded to 36),
+// each thread loading four consecutive rows of one column per quad (the
+// wavefront's loads are coalesced along the row) and storing them with one
+// 16-byte write.  In half h of a chunk the matrix-core step s of lane group g
+// uses row 16 h + 4 g + s on both operands, so each lane reads its 4 values
+// of a column with one 16-byte load, and every G entry accumulates its
+// products in the same order for any chunk length.
 __global__ void __launch_bounds__(256)
 gram_mfma_kernel(int m, int n, const float* __restrict__ A, int64_t lda, float* __restrict__ G, int64_t ldg,
                  int tiles) {
-  __shared__ __align__(16) float As[kMT][kMK];
-  __shared__ __align__(16) float Bs[kMT][kMK];
+  __shared__ __align__(16) float As[kMT][kLdsK];
+  __shared__ __align__(16) float Bs[kMT][kLdsK];
   // tile (I, J) of the upper triangle, row by row
   int I = 0, rem = blockIdx.x;
   while (rem >= tiles - I) {
@@ -103,49 +108,48 @@ gram_mfma_kernel(int m, int n, const float* __restrict__ A, int64_t lda, float* 
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
-  // loader: thread t moves rows (t / 32) and (t / 32) + 8 of the chunk, columns 4 (t % 32) .. + 3
-  const int lr = t >> 5, lc = 4 * (t & 31);
-  auto fetch = [&](int k0, int col0, float (&v)[2][4]) {
+  // loader: thread t moves column t % 128 of the tile, row quads t / 128 + 2 q (q < 4)
+  const int lcol = t & (kMT - 1), lq = t >> 7;
+  auto fetch = [&](int k0, int col0, v4f (&v)[4]) {
+    const int col = col0 + lcol;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int k = k0 + lr + 8 * h;
+    for (int q = 0; q < 4; ++q) {
+      const int k = k0 + 4 * (lq + 2 * q);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int col = col0 + lc + u;
-        v[h][u] = (k < m && col < n) ? A[size_t(k) * lda + col] : 0.0f;
-      }
+      for (int u = 0; u < 4; ++u) v[q][u] = (k + u < m && col < n) ? A[size_t(k + u) * lda + col] : 0.0f;
     }
   };
-  float va[2][4], vb[2][4];
+  v4f va[4], vb[4];
   fetch(0, i0, va);
   if (!diag) fetch(0, j0, vb);
   for (int k0 = 0; k0 < m; k0 += kMK) {
     __syncthreads();
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        As[lc + u][lr + 8 * h] = va[h][u];
-        if (!diag) Bs[lc + u][lr + 8 * h] = vb[h][u];
-      }
+    for (int q = 0; q < 4; ++q) {
+      *reinterpret_cast<v4f*>(&As[lcol][4 * (lq + 2 * q)]) = va[q];
+      if (!diag) *reinterpret_cast<v4f*>(&Bs[lcol][4 * (lq + 2 * q)]) = vb[q];
+    }
     __syncthreads();
     if (k0 + kMK < m) {
       fetch(k0 + kMK, i0, va);
       if (!diag) fetch(k0 + kMK, j0, vb);
     }
-    const float(*Bp)[kMK] = diag ? As : Bs;
-    v4f ra[4], rb[4];
+    const float(*Bp)[kLdsK] = diag ? As : Bs;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) ra[a] = *reinterpret_cast<const v4f*>(&As[wr * 64 + a * 16 + c][4 * g]);
+    for (int h = 0; h < kMK / 16; ++h) {
+      v4f ra[4], rb[4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) rb[b] = *reinterpret_cast<const v4f*>(&Bp[wc * 64 + b * 16 + c][4 * g]);
+      for (int a = 0; a < 4; ++a) ra[a] = *reinterpret_cast<const v4f*>(&As[wr * 64 + a * 16 + c][16 * h + 4 * g]);
 #pragma unroll
-    for (int st = 0; st < 4; ++st)
+      for (int b = 0; b < 4; ++b) rb[b] = *reinterpret_cast<const v4f*>(&Bp[wc * 64 + b * 16 + c][16 * h + 4 * g]);
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int st = 0; st < 4; ++st)
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra[a][st], rb[b][st], acc[a][b], 0, 0, 0);
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra[a][st], rb[b][st], acc[a][b], 0, 0, 0);
+    }
   }
   // lane holds D[4 g + v][c] of block (a, b): row i0 + 64 wr + 16 a + 4 g + v, column j0 + 64 wc + 16 b + c
 #pragma unroll
