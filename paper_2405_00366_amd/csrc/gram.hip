@@ -108,24 +108,25 @@ gram_mfma_kernel(int m, int n, const float* __restrict__ A, int64_t lda, float* 
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
-  // loader: thread t moves column t % 128 of the tile, row quads t / 128 + 2 q (q < 4)
+  // loader: thread t moves column t % 128 of the tile, row quads t / 128 + 2 q (q < kMK / 8)
+  constexpr int NQ = kMK / 8;
   const int lcol = t & (kMT - 1), lq = t >> 7;
-  auto fetch = [&](int k0, int col0, v4f (&v)[4]) {
+  auto fetch = [&](int k0, int col0, v4f (&v)[NQ]) {
     const int col = col0 + lcol;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       const int k = k0 + 4 * (lq + 2 * q);
 #pragma unroll
       for (int u = 0; u < 4; ++u) v[q][u] = (k + u < m && col < n) ? A[size_t(k + u) * lda + col] : 0.0f;
     }
   };
-  v4f va[4], vb[4];
+  v4f va[NQ], vb[NQ];
   fetch(0, i0, va);
   if (!diag) fetch(0, j0, vb);
   for (int k0 = 0; k0 < m; k0 += kMK) {
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       *reinterpret_cast<v4f*>(&As[lcol][4 * (lq + 2 * q)]) = va[q];
       if (!diag) *reinterpret_cast<v4f*>(&Bs[lcol][4 * (lq + 2 * q)]) = vb[q];
     }
