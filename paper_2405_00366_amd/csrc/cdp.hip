@@ -254,41 +254,54 @@ jacobi_resident_kernel(int n, const T* __restrict__ G, int64_t ldg, const T* __r
 
 // Streamed Jacobi sweep (G too large for the resident form): one launch per
 // sweep, one wavefront per row.
+// Streamed sweeps in one cooperative launch (when the support form did not
+// run): s = sigma o R (R held at 0 where G_rr is tiny), then K synchronous
+// sweeps, one wavefront per row reading its row of G, with a grid barrier
+// before each.  Returns at once in every workgroup when the support form has
+// updated R.
 template <typename T>
 __global__ void __launch_bounds__(256)
-jacobi_sweep_kernel(int n, const T* __restrict__ G, int64_t ldg, const T* __restrict__ b,
-                    const uint8_t* __restrict__ sigma, T dtc, const T* __restrict__ sin,
-                    T* __restrict__ sout, T* __restrict__ R, int* __restrict__ status, int first,
-                    const int* __restrict__ done) {
-  if (done[0]) return;   // the support form has updated R
+jacobi_streamed_kernel(int n, const T* __restrict__ G, int64_t ldg, const T* __restrict__ b,
+                       const uint8_t* __restrict__ sigma, T dtc, int iters, T* __restrict__ s0, T* __restrict__ s1,
+                       T* __restrict__ R, int* __restrict__ status, const int* __restrict__ done, int* __restrict__ bar,
+                       int64_t limit) {
+  if (done[0]) return;
+  int gen = 0;
+  for (int r = blockIdx.x * 256 + threadIdx.x; r < n; r += gridDim.x * 256) {
+    const T d = G[size_t(r) * ldg + r];
+    if (!(d >= T(1e-12))) R[r] = T(0);
+    s0[r] = sigma[r] ? R[r] : T(0);
+  }
   const int lane = threadIdx.x & (kWave - 1);
-  const int r = blockIdx.x * 4 + threadIdx.x / kWave;
-  if (r >= n) return;
-  const T* gr = G + size_t(r) * ldg;
-  const T d = gr[r];
-  const bool tiny = !(d >= T(1e-12));
-  T acc = T(0);
-  for (int j = lane; j < n; j += kWave)
-    if (j != r) acc += gr[j] * sin[j];
-  acc = wave_sum(acc);
-  if (lane == 0) {
-    T Rv = R[r];
-    if (first && tiny) raise_status(status, L0CIM_ST_TINY_DIAG);
-    jacobi_update(Rv, acc, b[r], d, dtc, tiny);
-    R[r] = Rv;
-    sout[r] = sigma[r] ? Rv : T(0);
+  for (int it = 0; it < iters; ++it) {
+    if (!grid_barrier<256>(bar, bar + 1, bar + 64, gridDim.x, gen, limit)) {
+      if (threadIdx.x == 0) raise_status(status, L0CIM_ST_TIMEOUT);
+      return;
+    }
+    const T* sin = (it & 1) ? s1 : s0;
+    T* sout = (it & 1) ? s0 : s1;
+    for (int r = blockIdx.x * 4 + threadIdx.x / kWave; r < n; r += gridDim.x * 4) {
+      const T* gr = G + size_t(r) * ldg;
+      const T d = gr[r];
+      const bool tiny = !(d >= T(1e-12));
+      T acc = T(0);
+      for (int j = lane; j < n; j += kWave)
+        if (j != r) acc += gr[j] * sin[j];
+      acc = wave_sum(acc);
+      if (lane == 0) {
+        T Rv = R[r];
+        if (it == 0 && tiny) raise_status(status, L0CIM_ST_TINY_DIAG);
+        jacobi_update(Rv, acc, b[r], d, dtc, tiny);
+        R[r] = Rv;
+        sout[r] = sigma[r] ? Rv : T(0);
+      }
+    }
   }
 }
 
-template <typename T>
-__global__ void masked_copy_kernel(int n, const T* __restrict__ G, int64_t ldg, const uint8_t* __restrict__ sigma,
-                                   T* __restrict__ R, T* __restrict__ s, const int* __restrict__ done) {
-  if (done[0]) return;
-  int r = blockIdx.x * 256 + threadIdx.x;
-  if (r >= n) return;
-  T d = G[size_t(r) * ldg + r];
-  if (!(d >= T(1e-12))) R[r] = T(0);
-  s[r] = sigma[r] ? R[r] : T(0);
+// Zeroes the words of the streamed sweeps' grid barrier.
+__global__ void grid_bar_clear_kernel(int* __restrict__ bar, size_t words) {
+  for (size_t i = threadIdx.x; i < words; i += blockDim.x) bar[i] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -396,6 +409,9 @@ sup_compact_kernel(const T* __restrict__ G, int64_t ldg, SupWs<T> w) {
 }
 
 // One synchronous sweep over the support rows; V accumulates the input.
+// (One launch per sweep: a grid barrier between sweeps inside one
+// cooperative launch measured 28 us per sweep against 13.9 us, as its
+// device-scope release and acquire write back and invalidate L2.)
 template <typename T>
 __global__ void __launch_bounds__(256)
 sup_sweep_kernel(const T* __restrict__ b, T dtc, int it, SupWs<T> w) {
@@ -496,7 +512,8 @@ __global__ void finalize_kernel(int n, int nparts, const double* __restrict__ pa
 size_t jacobi_ws_bytes(l0cim_dtype dt, int n) {
   size_t words = (dt == L0CIM_F64) ? 2 : 1;
   return align_up(size_t(2) * n * words * sizeof(uint64_t)) + kAlign + 2 * align_up(size_t(n) * dtype_size(dt)) +
-         support_ctl_bytes() + (dt == L0CIM_F64 ? sup_ws_bytes<double>(n) : sup_ws_bytes<float>(n));
+         support_ctl_bytes() + align_up(grid_barrier_bytes()) +
+         (dt == L0CIM_F64 ? sup_ws_bytes<double>(n) : sup_ws_bytes<float>(n));
 }
 
 namespace {
@@ -517,6 +534,9 @@ l0cim_status jacobi_typed(int n, const T* G, int64_t ldg, const T* b, const uint
   p += align_up(size_t(n) * sizeof(T));
   void* ctl = p;
   p += align_up(support_ctl_bytes());
+  int* bar = reinterpret_cast<int*>(p);   // grid barrier of the streamed sweeps
+  const size_t bar_words = align_up(grid_barrier_bytes()) / sizeof(int);
+  p += align_up(grid_barrier_bytes());
   const SupWs<T> sw = sup_ws<T>(p, n);
   if (iters <= 0) return L0CIM_OK;
 
@@ -570,6 +590,11 @@ l0cim_status jacobi_typed(int n, const T* G, int64_t ldg, const T* b, const uint
     return L0CIM_OK;
   }
   // support form first; the streamed sweeps return at once when it ran
+  hipLaunchKernelGGL(grid_bar_clear_kernel, dim3(1), dim3(256), 0, s, bar, bar_words);
+  L0_LAUNCHED("grid_bar_clear_kernel");
+  T dtcT = T(dtc);
+  int64_t lim = limit;
+  int itn = iters;
   {
     const int kmax = sup_kmax<T>(n);
     int grid = (kmax + 3) / 4;
@@ -585,18 +610,17 @@ l0cim_status jacobi_typed(int n, const T* G, int64_t ldg, const T* b, const uint
     hipLaunchKernelGGL(sup_final_kernel<T>, dim3((n + 3) / 4), dim3(256), 0, s, n, G, ldg, b, T(dtc), iters, R, sw);
     L0_LAUNCHED("sup_final_kernel");
   }
-  const int* done = sw.ctl;
-  hipLaunchKernelGGL(masked_copy_kernel<T>, dim3((n + 255) / 256), dim3(256), 0, s, n, G, ldg, sigma, R, s0, done);
-  L0_LAUNCHED("masked_copy_kernel");
-  T* cur = s0;
-  T* nxt = s1;
-  for (int it = 0; it < iters; ++it) {
-    hipLaunchKernelGGL(jacobi_sweep_kernel<T>, dim3((n + 3) / 4), dim3(256), 0, s, n, G, ldg, b, sigma,
-                       T(dtc), cur, nxt, R, status, it == 0 ? 1 : 0, done);
-    L0_LAUNCHED("jacobi_sweep_kernel");
-    T* t = cur;
-    cur = nxt;
-    nxt = t;
+  {
+    const int* done = sw.ctl;
+    int per_cu = 0;
+    L0_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void*>(jacobi_streamed_kernel<T>), 256, 0));
+    int cgrid = std::min({(n + 3) / 4, dev.cu_count * std::max(per_cu, 1), 4 * dev.cu_count, kGridMaxWg});
+    int nn = n;
+    int* b1 = bar;
+    void* args[] = {&nn, &G, &ldg, &b, &sigma, &dtcT, &itn, &s0, &s1, &R, &status, &done, &b1, &lim};
+    L0_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(jacobi_streamed_kernel<T>), dim3(cgrid),
+                                      dim3(256), args, 0, s));
   }
   return L0CIM_OK;
 }

@@ -23,67 +23,13 @@ constexpr int64_t kBarrierLimit = int64_t(1) << 24;
 // attempt (never reset, so no workgroup can miss a flag)
 enum { C_GEN = 1, C_ABORT = 2, C_K = 3, C_BAD0 = 4, C_BAD1 = 5 };
 
-// Bounded grid barrier for a cooperative launch (every workgroup resident).
-// Each workgroup publishes its arrival in a slot of its own (no contended
-// atomic), workgroup 0 waits for every slot and then publishes the new
-// generation, which the others wait for.  `gen` counts the barriers passed
-// and is the same in every workgroup.  A wait that exceeds the poll bound, or
-// sees the abort word, fails the barrier and raises the abort word.
-constexpr int kSlot = 16;   // ints between arrival slots (64 bytes)
-
-__device__ bool grid_sync(int* ctl, int* arrive, int nblocks, int& gen) {
-  __shared__ int ok_sh;
-  ++gen;
-  if (threadIdx.x == 0) ok_sh = 1;
-  __syncthreads();
-  const int tid = threadIdx.x, wg = blockIdx.x;
-  // Arrival: one device-scope release (the workgroup's writes, ordered before
-  // it by the workgroup barrier, become visible first).  Waits poll with
-  // relaxed loads and acquire once they succeed: an acquire per poll would
-  // invalidate the L2 of the poller's XCD on every iteration.
-  if (tid == 0) __hip_atomic_store(&arrive[wg * kSlot], gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-  auto give_up = [&]() {
-    ok_sh = 0;
-    __hip_atomic_store(&ctl[C_ABORT], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  };
-  if (wg == 0) {
-    for (int w = tid; w < nblocks; w += BS) {
-      int64_t polls = 0;
-      while (__hip_atomic_load(&arrive[w * kSlot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
-        if (++polls > kBarrierLimit || ((polls & 255) == 0 &&
-                                        __hip_atomic_load(&ctl[C_ABORT], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
-          give_up();
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-    }
-    __syncthreads();
-    if (tid == 0) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      if (ok_sh) __hip_atomic_store(&ctl[C_GEN], gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  } else if (tid == 0) {
-    int64_t polls = 0;
-    while (__hip_atomic_load(&ctl[C_GEN], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
-      if (++polls > kBarrierLimit || __hip_atomic_load(&ctl[C_ABORT], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-        give_up();
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  }
-  __syncthreads();
-  return ok_sh != 0;
-}
-
-#define L0_GRID_SYNC()                                              \
-  do {                                                              \
-    if (!grid_sync(ctl, arrive, nwg, gen)) {                        \
-      if (tid == 0) raise_status(status, L0CIM_ST_TIMEOUT);         \
-      return;                                                       \
-    }                                                               \
+// Phases are separated by the bounded grid barrier of common.h.
+#define L0_GRID_SYNC()                                                                  \
+  do {                                                                                  \
+    if (!grid_barrier<BS>(&ctl[C_GEN], &ctl[C_ABORT], arrive, nwg, gen, kBarrierLimit)) { \
+      if (tid == 0) raise_status(status, L0CIM_ST_TIMEOUT);                             \
+      return;                                                                           \
+    }                                                                                   \
   } while (0)
 
 template <typename T>
@@ -341,7 +287,6 @@ chol_kernel(int n, const T* __restrict__ G, int64_t ldg, const T* __restrict__ b
 struct CholLayout {
   size_t idx, L, w, ctl, red, arrive, total;
 };
-constexpr int kMaxGrid = 1024;
 
 CholLayout chol_layout(int n) {
   const size_t np = size_t(n + NB - 1) / NB * NB;
@@ -357,14 +302,14 @@ CholLayout chol_layout(int n) {
   c.w = take(np * sizeof(double));
   c.ctl = take(8 * sizeof(int));
   c.red = take(4 * sizeof(double));
-  c.arrive = take(size_t(kMaxGrid) * kSlot * sizeof(int));
+  c.arrive = take(size_t(kGridMaxWg) * kGridSlot * sizeof(int));
   c.total = o;
   return c;
 }
 
 __global__ void chol_ctl_clear_kernel(int* ctl, int* arrive) {
   if (threadIdx.x < 8) ctl[threadIdx.x] = 0;
-  for (int i = threadIdx.x; i < kMaxGrid; i += blockDim.x) arrive[i * kSlot] = 0;
+  for (int i = threadIdx.x; i < kGridMaxWg; i += blockDim.x) arrive[i * kGridSlot] = 0;
 }
 
 template <typename T>
@@ -386,7 +331,7 @@ l0cim_status chol_typed(int n, const T* G, int64_t ldg, const T* b, const uint8_
   int per_cu = 0;
   L0_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(chol_kernel<T>), BS, 0));
   int grid = dev.cu_count * (per_cu > 0 ? 1 : 0);
-  if (grid > kMaxGrid) grid = kMaxGrid;
+  if (grid > kGridMaxWg) grid = kGridMaxWg;
   if (grid < 1) return set_error(L0CIM_ERR_HIP, "chol refit: kernel does not fit on a CU");
   int nn = n;
   void* args[] = {&nn, &G, &ldg, &b, &sigma, &R, &status, &idx, &L, &w, &ctl, &red, &arrive};

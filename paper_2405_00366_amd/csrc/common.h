@@ -86,6 +86,65 @@ __device__ inline double pump_at(const CimArgs& a, int k) {
   return (a.p_thr - a.d) + 2.0 * a.d / (1.0 + exp(-(t - a.t_c) / a.t_w));
 }
 
+// Bounded grid barrier for a cooperative launch (every workgroup resident).
+// Workgroup w publishes its arrival in a slot of its own, arrive[w *
+// kGridSlot] (no contended atomic); workgroup 0 waits for every slot and then
+// publishes the generation in *gen_word, which the others wait for.  `gen`
+// counts the barriers passed and is the same in every workgroup; the words
+// start at zero for each launch.  Arrival is one device-scope release (the
+// workgroup's writes, ordered before it by the workgroup barrier, become
+// visible first); waits poll with relaxed loads and acquire once they
+// succeed (an acquire per poll would invalidate the poller's L2 on every
+// iteration).  A wait beyond `limit` polls, or one that sees *abort_word set,
+// raises the abort word and returns false.
+constexpr int kGridSlot = 16;      // ints between arrival slots (64 bytes)
+constexpr int kGridMaxWg = 1024;   // arrival slots
+inline size_t grid_barrier_bytes() { return 256 + size_t(kGridMaxWg) * kGridSlot * sizeof(int); }
+
+template <int BS>
+__device__ bool grid_barrier(int* gen_word, int* abort_word, int* arrive, int nblocks, int& gen, int64_t limit) {
+  __shared__ int ok_sh;
+  ++gen;
+  if (threadIdx.x == 0) ok_sh = 1;
+  __syncthreads();
+  const int tid = threadIdx.x, wg = blockIdx.x;
+  if (tid == 0) __hip_atomic_store(&arrive[wg * kGridSlot], gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  auto give_up = [&]() {
+    ok_sh = 0;
+    __hip_atomic_store(abort_word, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
+  if (wg == 0) {
+    for (int w = tid; w < nblocks; w += BS) {
+      int64_t polls = 0;
+      while (__hip_atomic_load(&arrive[w * kGridSlot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
+        if (++polls > limit ||
+            ((polls & 255) == 0 && __hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+          give_up();
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      if (ok_sh) __hip_atomic_store(gen_word, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  } else if (tid == 0) {
+    int64_t polls = 0;
+    while (__hip_atomic_load(gen_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen) {
+      if (++polls > limit || __hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        give_up();
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+  return ok_sh != 0;
+}
+
 template <typename T>
 __device__ inline T wave_sum(T v) {
 #pragma unroll
