@@ -408,31 +408,145 @@ sup_compact_kernel(const T* __restrict__ G, int64_t ldg, SupWs<T> w) {
   }
 }
 
-// One synchronous sweep over the support rows; V accumulates the input.
-// (One launch per sweep: a grid barrier between sweeps inside one
-// cooperative launch measured 28 us per sweep against 13.9 us, as its
-// device-scope release and acquire write back and invalidate L2.)
+// The K synchronous sweeps over the support rows in one cooperative launch
+// without grid barriers: the support's R travel as step-tagged words (as in
+// the resident runs), every workgroup gathers all of them into LDS, and
+// wavefront gw = 4 blockIdx + wave updates rows i = gw, gw + 4 gridDim, ...
+// of the compacted block G_SS, accumulating V from each sweep's input.  (A
+// grid barrier between sweeps measured 28 us per sweep, as its device-scope
+// release and acquire write back and invalidate L2; one launch per sweep
+// 13.9 us.)  Two word slots suffice: a wavefront can only overwrite slot
+// it & 1 after gathering every row's sweep-it word, which each owner
+// publishes after its own gather of slot it & 1.
+// Sleep (units of 64 clocks) before the first poll of a sweep.
+constexpr int kFirstPollSleepCdp = 15;
+
 template <typename T>
 __global__ void __launch_bounds__(256)
-sup_sweep_kernel(const T* __restrict__ b, T dtc, int it, SupWs<T> w) {
-  if (!w.ctl[0]) return;
+sup_ll_kernel(const T* __restrict__ b, T dtc, int iters, SupWs<T> w, uint64_t* __restrict__ ll,
+              int* __restrict__ abort_word, int* __restrict__ status, int64_t limit) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int lds_abort;
+  if (!w.ctl[0]) return;   // the same in every workgroup
+  constexpr int W = LL<T>::kWords;
+  T* sx = reinterpret_cast<T*>(smem);
   const int ks = w.ctl[1];
-  const T* sin = w.sR + size_t(it & 1) * ks;
-  T* sout = w.sR + size_t((it + 1) & 1) * ks;
+  const size_t slot = size_t(ks) * W;
   const int lane = threadIdx.x & (kWave - 1);
-  for (int i = blockIdx.x * 4 + threadIdx.x / kWave; i < ks; i += gridDim.x * 4) {
-    const T* g = w.Gss + size_t(i) * ks;
-    T acc = T(0);
-    for (int j = lane; j < ks; j += kWave)
-      if (j != i) acc += g[j] * sin[j];
+  const int gw = blockIdx.x * 4 + threadIdx.x / kWave, nw = gridDim.x * 4;
+  if (lane == 0)
+    for (int i = gw; i < ks; i += nw) LL<T>::put(ll + size_t(i) * W, w.sR[i], 1u);
+  // the wavefront's rows of G_SS stay in registers when they fit (at most two
+  // rows of at most 64 kRegCols columns); otherwise they are read every sweep
+  constexpr int kRegCols = 32;
+  const bool in_regs = ks <= kRegCols * kWave && ks <= 2 * nw;
+  T greg[2][kRegCols];
+  if (in_regs) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int i = gw + r * nw;
+#pragma unroll
+      for (int u = 0; u < kRegCols; ++u) {
+        const int j = lane + u * kWave;
+        greg[r][u] = (i < ks && j < ks) ? w.Gss[size_t(i) * ks + j] : T(0);
+      }
+    }
+  }
+  auto finish = [&](int i, T acc, int it) {
     acc = wave_sum(acc);
     if (lane == 0) {
-      const T d = g[i];
-      T Rv = sin[i];
+      const T d = w.Gss[size_t(i) * ks + i];
+      T Rv = sx[i];
       w.V[i] = (T(1) - dtc) * w.V[i] + Rv;
       jacobi_update(Rv, acc, b[w.S[i]], d, dtc, !(d >= T(1e-12)));
-      sout[i] = Rv;
+      LL<T>::put(ll + size_t((it + 1) & 1) * slot + size_t(i) * W, Rv, uint32_t(it + 2));
+      if (it + 1 == iters) w.sR[size_t(iters & 1) * ks + i] = Rv;
     }
+  };
+  if (threadIdx.x == 0) lds_abort = 0;
+  __syncthreads();
+  for (int it = 0; it < iters; ++it) {
+    const uint64_t* src = ll + size_t(it & 1) * slot;
+    const uint32_t flag = uint32_t(it + 1);
+    bool ok = true;
+    // 2048 words at a time, 8 per thread: issue them all, re-poll the late ones together
+    if (it > 0) __builtin_amdgcn_s_sleep(kFirstPollSleepCdp);
+    for (int base = 0; base < ks && ok; base += 8 * 256) {
+      uint64_t wv[8][W];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int j = base + threadIdx.x + u * 256;
+#pragma unroll
+        for (int v = 0; v < W; ++v) wv[u][v] = j < ks ? ll_load(src + size_t(j) * W + v) : (uint64_t(flag) << 32);
+      }
+      int64_t polls = 0;
+      for (;;) {
+        bool ready = true;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int v = 0; v < W; ++v) ready = ready && (uint32_t(wv[u][v] >> 32) == flag);
+        if (ready) break;
+        if (++polls > limit || ((polls & 1023) == 0 && abort_seen(abort_word))) {
+          ok = false;
+          break;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int j = base + threadIdx.x + u * 256;
+#pragma unroll
+          for (int v = 0; v < W; ++v)
+            if (uint32_t(wv[u][v] >> 32) != flag) wv[u][v] = ll_load(src + size_t(j) * W + v);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int j = base + threadIdx.x + u * 256;
+        if (j < ks) sx[j] = ll_decode<T>(wv[u]);
+      }
+    }
+    if (!ok) lds_abort = 1;
+    __syncthreads();
+    if (lds_abort) {
+      if (threadIdx.x == 0) {
+        __hip_atomic_store(abort_word, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        raise_status(status, L0CIM_ST_TIMEOUT);
+      }
+      return;
+    }
+    if (in_regs) {
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int i = gw + r * nw;
+        if (i >= ks) break;
+        T acc = T(0);
+#pragma unroll
+        for (int u = 0; u < kRegCols; ++u) {
+          const int j = lane + u * kWave;
+          if (j < ks && j != i) acc += greg[r][u] * sx[j];
+        }
+        finish(i, acc, it);
+      }
+    } else {
+      for (int i = gw; i < ks; i += nw) {
+        const T* g = w.Gss + size_t(i) * ks;
+        // the row's loads issued eight at a time, the products added in column order
+        T acc = T(0);
+        int j = lane;
+        for (; j + 7 * kWave < ks; j += 8 * kWave) {
+          T gv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) gv[u] = g[j + u * kWave];
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (j + u * kWave != i) acc += gv[u] * sx[j + u * kWave];
+        }
+        for (; j < ks; j += kWave)
+          if (j != i) acc += g[j] * sx[j];
+        finish(i, acc, it);
+      }
+    }
+    __syncthreads();   // sx is gathered again
   }
 }
 
@@ -603,10 +717,20 @@ l0cim_status jacobi_typed(int n, const T* G, int64_t ldg, const T* b, const uint
     L0_LAUNCHED("sup_prep_kernel");
     hipLaunchKernelGGL(sup_compact_kernel<T>, dim3(grid), dim3(256), 0, s, G, ldg, sw);
     L0_LAUNCHED("sup_compact_kernel");
-    for (int it = 0; it < iters; ++it) {
-      hipLaunchKernelGGL(sup_sweep_kernel<T>, dim3(grid), dim3(256), 0, s, b, T(dtc), it, sw);
-      L0_LAUNCHED("sup_sweep_kernel");
-    }
+    hipLaunchKernelGGL(ll_clear_kernel, dim3(64), dim3(256), 0, s, ll, size_t(2) * kmax * LL<T>::kWords,
+                       abort_word);
+    L0_LAUNCHED("clear exchange buffer");
+    const unsigned lds = unsigned(size_t(kmax) * sizeof(T));
+    L0_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(sup_ll_kernel<T>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+    int per_cu = 0;
+    L0_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void*>(sup_ll_kernel<T>), 256, lds));
+    const int cgrid = std::min(dev.cu_count * std::max(per_cu, 1), dev.cu_count);
+    SupWs<T> swa = sw;
+    void* args[] = {&b, &dtcT, &itn, &swa, &ll, &abort_word, &status, &lim};
+    L0_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(sup_ll_kernel<T>), dim3(cgrid), dim3(256),
+                                      args, lds, s));
     hipLaunchKernelGGL(sup_final_kernel<T>, dim3((n + 3) / 4), dim3(256), 0, s, n, G, ldg, b, T(dtc), iters, R, sw);
     L0_LAUNCHED("sup_final_kernel");
   }
