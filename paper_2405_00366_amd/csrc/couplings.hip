@@ -42,13 +42,25 @@ couplings_quant_kernel(int n, const float* __restrict__ G, int64_t ldg, const fl
                        const float* __restrict__ R, Q* __restrict__ J, int64_t ldj,
                        float* __restrict__ rscale, float* __restrict__ z) {
   __shared__ float red[256];
+  constexpr int kRowRegs = 64;   // rows of up to 256 * 64 couplings stay in registers between the passes
   const int r = blockIdx.x;
   const float Rr = R[r];
   const float* Gr = G + size_t(r) * ldg;
+  const bool in_regs = n <= 256 * kRowRegs;
+  float vals[kRowRegs];
   float amax = 0.0f;
-  for (int j = threadIdx.x; j < n; j += 256) {
-    float v = (j == r) ? 0.0f : -(Gr[j] * (Rr * R[j]));
-    amax = fmaxf(amax, fabsf(v));
+  if (in_regs) {
+#pragma unroll
+    for (int u = 0; u < kRowRegs; ++u) {
+      const int j = threadIdx.x + 256 * u;
+      vals[u] = (j < n && j != r) ? -(Gr[j] * (Rr * R[j])) : 0.0f;
+      amax = fmaxf(amax, fabsf(vals[u]));
+    }
+  } else {
+    for (int j = threadIdx.x; j < n; j += 256) {
+      float v = (j == r) ? 0.0f : -(Gr[j] * (Rr * R[j]));
+      amax = fmaxf(amax, fabsf(v));
+    }
   }
   red[threadIdx.x] = amax;
   __syncthreads();
@@ -58,9 +70,17 @@ couplings_quant_kernel(int n, const float* __restrict__ G, int64_t ldg, const fl
   }
   amax = red[0];
   const float scale = amax > 0.0f ? amax / QTraits<Q>::kMax : 1.0f;
-  for (int j = threadIdx.x; j < n; j += 256) {
-    float v = (j == r) ? 0.0f : -(Gr[j] * (Rr * R[j]));
-    J[size_t(r) * ldj + j] = QTraits<Q>::enc(v / scale);
+  if (in_regs) {
+#pragma unroll
+    for (int u = 0; u < kRowRegs; ++u) {
+      const int j = threadIdx.x + 256 * u;
+      if (j < n) J[size_t(r) * ldj + j] = QTraits<Q>::enc(vals[u] / scale);
+    }
+  } else {
+    for (int j = threadIdx.x; j < n; j += 256) {
+      float v = (j == r) ? 0.0f : -(Gr[j] * (Rr * R[j]));
+      J[size_t(r) * ldj + j] = QTraits<Q>::enc(v / scale);
+    }
   }
   if (threadIdx.x == 0) {
     rscale[r] = scale;

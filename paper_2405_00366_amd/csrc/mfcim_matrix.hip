@@ -42,12 +42,29 @@ mat_setup_kernel(BInst I, BTile* __restrict__ tiles, int ntiles, int tr, BInst* 
 }
 
 // Row r (< n16) of the caller's couplings into the panel layout, zero padded.
+// A thread moves columns 8 g .. 8 g + 7, which land in the panel as one
+// contiguous run (two runs of 4 for 4-byte elements): one wide store each.
 template <typename JT>
 __global__ void __launch_bounds__(256)
 mat_copyJ_kernel(const JT* __restrict__ J, int64_t ldj, JT* __restrict__ Jp, int n, int ld) {
   const int r = blockIdx.y;
-  for (int j = blockIdx.x * 256 + threadIdx.x; j < ld; j += gridDim.x * 256)
-    Jp[jpanel_offset(r, j, ld, int(sizeof(JT)))] = (r < n && j < n) ? J[size_t(r) * ldj + j] : JT(0.0f);
+  for (int j0 = 8 * (blockIdx.x * 256 + threadIdx.x); j0 < ld; j0 += 8 * gridDim.x * 256) {
+    JT v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) v[t] = (r < n && j0 + t < n) ? J[size_t(r) * ldj + j0 + t] : JT(0.0f);
+    if constexpr (sizeof(JT) == 4) {
+      *reinterpret_cast<float4*>(Jp + jpanel_offset(r, j0, ld, 4)) =
+          make_float4(float(v[0]), float(v[1]), float(v[2]), float(v[3]));
+      *reinterpret_cast<float4*>(Jp + jpanel_offset(r, j0 + 4, ld, 4)) =
+          make_float4(float(v[4]), float(v[5]), float(v[6]), float(v[7]));
+    } else {
+      struct alignas(8 * sizeof(JT)) Run { JT e[8]; };
+      Run run;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) run.e[t] = v[t];
+      *reinterpret_cast<Run*>(Jp + jpanel_offset(r, j0, ld, int(sizeof(JT)))) = run;
+    }
+  }
 }
 
 __global__ void __launch_bounds__(256)
@@ -160,7 +177,7 @@ l0cim_status launch_matrix_run(int n, int P, l0cim_dtype jdt, const void* J, int
   uint32_t* dxb2 = reinterpret_cast<uint32_t*>(b + Lw.xb2);
   void* Jp = b + Lw.J;
   {
-    dim3 g((ld + 255) / 256, round_up16(n));
+    dim3 g((ld / 8 + 255) / 256, round_up16(n));
     if (jdt == L0CIM_F32)
       hipLaunchKernelGGL(mat_copyJ_kernel<float>, g, dim3(256), 0, s, (const float*)J, ldj, (float*)Jp, n, ld);
     else if (jdt == L0CIM_BF16)
