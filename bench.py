@@ -45,7 +45,8 @@ WORKLOAD = ("plain Gaussian L0RBCS: N=2000, M=1000 (alpha 0.5), Bernoulli(0.1) s
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cim_regs_kernel_plain_n2000_traffic.txt")
 KERNEL_SOURCES = ("mfcim.hip", "common.h")
-PRECISION_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bstep_kernel_mri_bf16_traffic.txt")
+PRECISION_TRAFFIC_FILES = {dt: os.path.join(ROOT, "profiles", f"bstep_kernel_mri_{dt}_traffic.txt")
+                           for dt in ("bf16", "fp8")}
 PRECISION_SOURCES = ("batch.hip", "batch.h", "mfcim_matrix.hip")
 BATCHED_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bstep_kernel_batched_256x16_traffic.txt")
 BATCHED_SOURCES = ("batch.hip", "batch.h", "batch_plan.hip")
@@ -279,8 +280,8 @@ def precision_bench(args, torch, L, W, dev):
         "couplings": args.jdtype, "support_match": f"{match}/{len(seeds)}", "per_seed": rows,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(PRECISION_TRAFFIC_FILE, PRECISION_SOURCES, "hbm_bytes_per_step")
-                     if args.jdtype == "bf16" else None,
+                     "traffic": measured_traffic(PRECISION_TRAFFIC_FILES[args.jdtype], PRECISION_SOURCES,
+                                                 "hbm_bytes_per_step"),
                      "kernel": f"bstep_kernel<{args.jdtype}, BN, 4, rb>",
                      "avg_launch_ms": cim_total / launches_total / (steps + 1)},
     }
