@@ -315,7 +315,7 @@ __global__ void select_kernel(int n, int P, const double* __restrict__ H,
 
 // Sleep (units of 64 clocks) before the first poll of each step of the
 // register-resident run.
-constexpr int kFirstPollSleep = 15;
+constexpr int kFirstPollSleep = 17;
 
 // Single-replica resident run with the couplings held in registers.  Thread t
 // of a 512-thread workgroup keeps J[r0 + rho][t + u*512] for its rows rho < R
@@ -371,16 +371,17 @@ cim_regs_kernel(const JT* __restrict__ J, int64_t ldj, const float* __restrict__
   for (int k = 0; k <= a.n_steps; ++k) {
     // Every workgroup publishes its spins about the same time after its own
     // barrier, and a poll that reaches memory before the words do comes back
-    // stale and costs a second round trip: the first poll of a step waits
-    // kFirstPollSleep x 64 clocks (about 0.4 us; at N = 2000 on MI355X the
-    // step went from 1.92 to 1.47 us, with 12 and 18 units 1.54 and 1.52 us).
+    // stale and costs a second round trip (about 0.3 us): the first poll of a
+    // step waits kFirstPollSleep x 64 clocks (about 0.45 us).  At N = 2000 on
+    // MI355X, 2000 steps took 2.90 ms with 17 units, 3.20 / 2.92 / 2.96 ms with
+    // 15 / 18 / 19, and 3.8 ms with no sleep.  A second poll issued a little
+    // after the first, to catch late words without a round trip, and several
+    // copies of the exchange words, to spread the polls, were both slower: the
+    // polls of all workgroups arrive together and extra requests queue.
     if (k > 0) __builtin_amdgcn_s_sleep(kFirstPollSleep);
     const bool last = (k == a.n_steps);
     const uint64_t* src = ll + size_t(k & 1) * slot_words;
     const uint32_t flag = uint32_t(k + 1);
-    // the pump value of this step is evaluated while the gather is in flight
-    T lin = T(0);
-    if (owner && !last) lin = T(pump_at(a, k) - 1.0 - (a.linear_j ? a.j : 0.0));
     // 1. gather this thread's columns: issue every load, then re-poll the late ones together
     uint64_t w[C][W];
 #pragma unroll
@@ -389,6 +390,11 @@ cim_regs_kernel(const JT* __restrict__ J, int64_t ldj, const float* __restrict__
 #pragma unroll
       for (int v = 0; v < W; ++v) w[u][v] = (j < n) ? ll_load(src + size_t(j) * W + v) : (uint64_t(flag) << 32);
     }
+    // The pump value of this step (an FP64 exp and two divisions) is evaluated
+    // after the loads are issued, in their shadow: before them it delayed the
+    // owner wavefront's gather, and with it the whole step.
+    T lin = T(0);
+    if (owner && !last) lin = T(pump_at(a, k) - 1.0 - (a.linear_j ? a.j : 0.0));
     int64_t polls = 0;
     bool ok = true;
     for (;;) {
