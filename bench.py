@@ -18,7 +18,11 @@ Prints one JSON line.
   serving    a stream of Gaussian requests (N log-uniform in [512, 8192]),
              8 replicas, 1000 x 30, served by the continuous-batching server
              at saturation and at Poisson arrival rates below it, beside the
-             single-instance path serving the same requests one at a time.
+             single-instance path serving the same requests one at a time;
+  accuracy   the paper's random-data accuracy studies on the device path:
+             RMSE vs sparseness (alpha 0.6 / 0.8, noise 0.05 / 0.1, CN and
+             BN), tau = 0.15 beside tau = 1, per-alternation RMSE and Hamming
+             loss, late-time amplitudes; the FP64 oracle repeats a few solves.
 """
 from __future__ import annotations
 
@@ -405,6 +409,204 @@ def serving_bench(args, torch, L, W, dev):
     }
 
 
+# ---------------------------------------------------------------------------
+# accuracy form: the paper's random-data studies on the device path
+# ---------------------------------------------------------------------------
+
+ACC_N, ACC_STEPS, ACC_VELO = 2000, 1000, 51
+ACC_A = (0.05, 0.1, 0.15, 0.2, 0.25, 0.3)
+# (alpha, noise std, eta_end) of the noisy-observation study
+ACC_CONFIGS = ((0.6, 0.05, 0.18), (0.8, 0.05, 0.18), (0.6, 0.1, 0.35), (0.8, 0.1, 0.35))
+
+
+def acc_rmse(sig, R, x, xi) -> float:
+    """RMSE against the truth, sqrt(mean((R sigma - x xi)^2))."""
+    d = np.asarray(R, float) * sig - x * xi
+    return float(np.sqrt(np.mean(d * d)))
+
+
+def acc_hamming(sig, xi) -> float:
+    return float(np.mean(np.abs(np.asarray(sig, int) - np.asarray(xi, int))))
+
+
+def acc_seed(alpha: float, nu: float, ia: int, k: int) -> int:
+    return 100000 * int(round(alpha * 10)) + 10000 * int(round(nu * 100)) + 100 * ia + k
+
+
+def acc_instance(W, alpha, nu, ia, k):
+    """Random data as the paper draws it: exactly round(aN) non-zeros."""
+    return W.gaussian_instance(acc_seed(alpha, nu, ia, k), ACC_N, int(round(alpha * ACC_N)), ACC_A[ia], nu,
+                               support="exact").rounded_f32()
+
+
+def acc_oracle_sample(W, device_rows, count):
+    """The FP64 oracle on `count` solves of the alpha 0.6 / noise 0.05 sweep
+    (the same FP32-rounded instances and counter-generator seeds): support and
+    RMSE beside the device's, and the oracle's time."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import mfcim as O
+
+    cores = len(os.sched_getaffinity(0))
+    out, spent, steps = [], 0.0, 0
+    for row in device_rows[:count]:
+        inst = acc_instance(W, 0.6, 0.05, row["ia"], row["k"])
+        cim = O.CimParams(n_steps=ACC_STEPS, field=row["field"])
+        outer = O.OuterParams(eta_init=0.8, eta_end=0.18, velo=ACC_VELO, n_outer=ACC_VELO,
+                              seed=acc_seed(0.6, 0.05, row["ia"], row["k"]))
+        t1 = time.perf_counter()
+        res = O.solve(inst.A, inst.y, cim, outer, keep_history=False)
+        spent += time.perf_counter() - t1
+        steps += ACC_N * ACC_STEPS * ACC_VELO
+        rm = acc_rmse(res.sigma, res.R, inst.x, inst.xi)
+        out.append({"a": ACC_A[row["ia"]], "field": row["field"], "seed_index": row["k"],
+                    "support_identical": bool(np.array_equal(res.sigma, row["sigma"])),
+                    "hamming_vs_oracle": acc_hamming(res.sigma, row["sigma"]),
+                    "rmse_device": row["rmse"], "rmse_oracle": rm, "rmse_diff": abs(rm - row["rmse"])})
+        print(f"[accuracy] oracle a={ACC_A[row['ia']]} {row['field']}: identical={out[-1]['support_identical']} "
+              f"|drmse|={out[-1]['rmse_diff']:.2e}", file=sys.stderr, flush=True)
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return {"value": steps / spent if spent else None, "unit": "spin-steps/s", "cores": int(min(threads, cores)),
+            "kind": "oracle",
+            "sample": f"{len(out)} whole solves of the alpha 0.6 / noise 0.05 sweep (FP64 NumPy), {spent:.1f} s",
+            "agreement": out}
+
+
+def accuracy_bench(args, torch, L, W, dev):
+    """The paper's random-data accuracy studies, run on the device path (FP32
+    solve, N = 2000, 1000 Euler steps x 51 alternations, eta 0.8 -> eta_end
+    over velo = 51, 100 Jacobi CDP sweeps, K = 1, d = 0.4, exactly round(aN)
+    non-zeros as the paper draws its random data):
+      rmse_vs_a  average RMSE against the truth (and Hamming loss) for each
+                 sparseness a, at alpha 0.6 / 0.8 and noise std 0.05
+                 (eta_end 0.18) / 0.1 (eta_end 0.35), CN and BN fields
+                 (the noisy-observation figure of the Results);
+      tau        the same at alpha 0.6, noise 0.1 with tau = 0.15 beside
+                 tau = 1 (the sparseness / tau figure of the Supplement);
+      history    RMSE and Hamming loss after each alternation, median and
+                 quartiles over the datasets, at alpha 0.6, a = 0.2, noise
+                 0.05, through the step-level entry points (the field
+                 comparison figure), and the median |c| at the end of the
+                 second alternation for tau = 1 and 0.15 (the amplitude figure);
+      oracle     (cpu_baseline) the FP64 oracle on a few of the same solves."""
+    seeds = range(args.acc_seeds)
+    spin_steps, busy = 0, 0.0
+    ws = {}
+
+    def solve(inst, field, tau, eta_end, seed):
+        nonlocal spin_steps, busy
+        A = torch.tensor(inst.A, dtype=torch.float32, device=dev)
+        y = torch.tensor(inst.y, dtype=torch.float32, device=dev)
+        cim = L.cim_params(n_steps=ACC_STEPS, field=field, tau=tau)
+        sp = L.solve_params(eta_init=0.8, eta_end=eta_end, velo=ACC_VELO, n_outer=ACC_VELO, seed=seed)
+        key = A.shape
+        if key not in ws:
+            ws[key] = L.workspace(L.l0cim_solve_workspace_bytes(L.F32, A.shape[0], ACC_N, cim, sp), dev)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        R, sig, st = L.l0cim_solve(A, y, cim, sp, ws=ws[key])
+        torch.cuda.synchronize()
+        busy += time.perf_counter() - t1
+        spin_steps += ACC_N * ACC_STEPS * ACC_VELO
+        status = L.read_stats(st).status_bits
+        sg = sig.cpu().numpy()
+        return sg, R.double().cpu().numpy(), status
+
+    rmse_tab, tau_tab, sample_rows, bad = {}, {}, [], 0
+    for alpha, nu, eta_end in ACC_CONFIGS:
+        key = f"alpha={alpha} nu={nu}"
+        taus = (1.0, 0.15) if (alpha, nu) == (0.6, 0.1) else (1.0,)
+        acc = {(f, tau): ([], []) for f in ("CN", "BN") for tau in taus}
+        for ia, a in enumerate(ACC_A):
+            per = {kk: ([], []) for kk in acc}
+            for k in seeds:
+                inst = acc_instance(W, alpha, nu, ia, k)
+                for (field, tau) in acc:
+                    sg, R, st = solve(inst, field, tau, eta_end, acc_seed(alpha, nu, ia, k))
+                    bad += int(st != 0)
+                    rm = acc_rmse(sg, R, inst.x, inst.xi)
+                    per[(field, tau)][0].append(rm)
+                    per[(field, tau)][1].append(acc_hamming(sg, inst.xi))
+                    if (alpha, nu) == (0.6, 0.05) and tau == 1.0 and k == 0:
+                        sample_rows.append({"ia": ia, "k": k, "field": field, "sigma": sg, "rmse": rm})
+            for kk in acc:
+                acc[kk][0].append(float(np.mean(per[kk][0])))
+                acc[kk][1].append(float(np.mean(per[kk][1])))
+            print(f"[accuracy] {key} a={a}: " + ", ".join(
+                f"{f}/tau{tau} {acc[(f, tau)][0][-1]:.4f}" for f, tau in acc), file=sys.stderr, flush=True)
+        rmse_tab[key] = {f: {"rmse": acc[(f, 1.0)][0], "hamming": acc[(f, 1.0)][1]} for f in ("CN", "BN")}
+        if len(taus) > 1:
+            tau_tab[key] = {f"{f} tau={tau}": acc[(f, tau)][0] for f, tau in acc}
+
+    # per-alternation history through the step-level entry points
+    def history(inst, field, tau, seed, n_alt):
+        n = ACC_N
+        A = torch.tensor(inst.A, dtype=torch.float32, device=dev)
+        y = torch.tensor(inst.y, dtype=torch.float32, device=dev)
+        G, b = L.l0cim_gram(A, y)
+        status = torch.zeros(1, dtype=torch.int32, device=dev)
+        R = L.l0cim_init_r(G, b, status=status)
+        c = torch.empty((1, n), dtype=torch.float32, device=dev)
+        e = torch.empty_like(c)
+        H = torch.empty(1, dtype=torch.float64, device=dev)
+        prm = L.cim_params(n_steps=ACC_STEPS, field=field, tau=tau)
+        ws_run = L.workspace(L.l0cim_mfcim_run_workspace_bytes(L.F32, n, 1, L.F32), dev)
+        ws_cdp = L.workspace(L.l0cim_update_r_workspace_bytes(L.F32, n, L.CDP_JACOBI), dev)
+        rms, hls, camp = [], [], None
+        for i in range(n_alt):
+            eta = max(0.8 * (1.0 - i / ACC_VELO), 0.18)
+            J, _, z = L.l0cim_build_couplings(G, b, R)
+            L.l0cim_init_state(n, 1, seed, i, prm.c0_std, c, e)
+            sig = L.l0cim_mfcim_run(J, z, eta, prm, c, e, H=H, status=status, ws=ws_run)
+            sel = L.l0cim_select_replica(H, sig)
+            L.l0cim_update_r(G, b, sel, R, iters=100, status=status, ws=ws_cdp)
+            sg = sel.cpu().numpy()
+            if i == 1:
+                camp = float(np.median(np.abs(c.double().cpu().numpy())))
+            rms.append(acc_rmse(sg, R.double().cpu().numpy(), inst.x, inst.xi))
+            hls.append(acc_hamming(sg, inst.xi))
+        return rms, hls, camp, int(status.item())
+
+    hist_tab, amp_tab = {}, {}
+    for field in ("CN", "BN"):
+        runs, amps, amps_015 = [], [], []
+        for k in seeds:
+            inst = W.gaussian_instance(acc_seed(0.6, 0.05, 3, 50 + k), ACC_N, int(0.6 * ACC_N), 0.2, 0.05,
+                                       support="exact").rounded_f32()
+            rms, hls, camp, st = history(inst, field, 1.0, acc_seed(0.6, 0.05, 3, 50 + k), ACC_VELO)
+            bad += int(st != 0)
+            runs.append((rms, hls))
+            amps.append(camp)
+            _, _, camp2, st = history(inst, field, 0.15, acc_seed(0.6, 0.05, 3, 50 + k), 2)
+            amps_015.append(camp2)
+        rm = np.array([r[0] for r in runs])
+        hl = np.array([r[1] for r in runs])
+        pick = sorted(set(range(0, ACC_VELO, 5)) | {ACC_VELO - 1})
+        hist_tab[field] = {"alternation": pick,
+                           "rmse_median": [float(np.median(rm[:, i])) for i in pick],
+                           "rmse_q25": [float(np.percentile(rm[:, i], 25)) for i in pick],
+                           "rmse_q75": [float(np.percentile(rm[:, i], 75)) for i in pick],
+                           "hamming_median": [float(np.median(hl[:, i])) for i in pick]}
+        amp_tab[field] = {"tau=1": float(np.median(amps)), "tau=0.15": float(np.median(amps_015))}
+        print(f"[accuracy] history {field}: final median RMSE {hist_tab[field]['rmse_median'][-1]:.4f}, "
+              f"median |c| {amp_tab[field]}", file=sys.stderr, flush=True)
+
+    out = {"metric": "MF-CIM accuracy studies on random data (RMSE vs sparseness, per-alternation RMSE and "
+                     "Hamming loss, tau = 0.15)",
+           "value": spin_steps / busy, "unit": "spin-steps/s", "n_gpus": 1, "steps": len(seeds), "warmup": 0,
+           "ms_per_step": busy * 1e3 / max(1, spin_steps // (ACC_N * ACC_STEPS * ACC_VELO)),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"random Gaussian L0RBCS, N={ACC_N}, alpha in {{0.6, 0.8}}, exactly round(aN) "
+                                  f"non-zeros, a in {list(ACC_A)}, noise 0.05 / 0.1, {ACC_STEPS} Euler steps x "
+                                  f"{ACC_VELO} alternations, eta 0.8 -> 0.18 / 0.35 (velo {ACC_VELO}), Jacobi CDP, "
+                                  f"{len(seeds)} datasets per point, FP32"},
+           "status_nonzero": bad, "rmse_vs_a": {"a": list(ACC_A), **rmse_tab}, "tau": tau_tab,
+           "history": hist_tab, "median_abs_c_second_alternation": amp_tab}
+    if args.acc_oracle > 0 and not args.no_cpu:
+        out["cpu_baseline"] = acc_oracle_sample(W, sample_rows, args.acc_oracle)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -413,7 +615,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run a 512 MiB fill and copy first (HBM counter calibration)")
-    ap.add_argument("--form", choices=["plain", "batched", "precision", "serving"], default="plain")
+    ap.add_argument("--form", choices=["plain", "batched", "precision", "serving", "accuracy"], default="plain")
     ap.add_argument("--jdtype", choices=["bf16", "fp8"], default="bf16", help="precision form couplings")
     ap.add_argument("--requests", type=int, default=200, help="serving form: number of requests")
     ap.add_argument("--slots", type=int, default=48, help="serving form: resident requests at most")
@@ -424,6 +626,9 @@ def main():
     ap.add_argument("--step-budget-mb", type=float, default=300.0,
                     help="serving form: cap on the couplings MB one Euler step of the resident set streams (0: none)")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--acc-seeds", type=int, default=10, help="accuracy form: datasets per point")
+    ap.add_argument("--acc-oracle", type=int, default=4,
+                    help="accuracy form: solves of the sweep the FP64 oracle repeats (0: none)")
     ap.add_argument("--euler-steps", type=int, default=0,
                     help="precision / batched forms: Euler steps per alternation instead of 1000 (profiling runs)")
     ap.add_argument("--alternations", type=int, default=0,
@@ -447,7 +652,8 @@ def main():
     if args.traffic_probe:
         traffic_probe(torch, dev)
     if args.form != "plain":
-        fn = {"batched": batched_bench, "precision": precision_bench, "serving": serving_bench}[args.form]
+        fn = {"batched": batched_bench, "precision": precision_bench, "serving": serving_bench,
+              "accuracy": accuracy_bench}[args.form]
         print(json.dumps(fn(args, torch, L, W, dev)), flush=True)
         return
     gold = golden_supports()

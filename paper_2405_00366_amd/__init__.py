@@ -18,7 +18,7 @@ import torch
 __all__ = [
     "F32", "F64", "BF16", "FP8E4M3", "FIELD_CN", "FIELD_BN", "CDP_JACOBI", "CDP_CHOL_F64",
     "CimParams", "SolveParams", "Stats", "L0cimError", "lib", "library_path",
-    "l0cim_version", "l0cim_gram", "l0cim_build_couplings", "l0cim_init_state",
+    "l0cim_version", "l0cim_gram", "l0cim_build_couplings", "l0cim_init_r", "l0cim_init_state",
     "l0cim_mfcim_run", "l0cim_select_replica", "l0cim_update_r", "l0cim_solve",
     "l0cim_mfcim_run_workspace_bytes", "l0cim_update_r_workspace_bytes",
     "l0cim_solve_workspace_bytes", "l0cim_profile_begin", "l0cim_profile_end",
@@ -114,6 +114,8 @@ def lib():
         L.l0cim_build_couplings.argtypes = [c_int, c_int32, vp, c_int64, vp, vp, c_int, vp, c_int64,
                                             vp, vp, vp]
         L.l0cim_build_couplings.restype = st
+        L.l0cim_init_r.argtypes = [c_int, c_int32, vp, c_int64, vp, vp, vp, vp]
+        L.l0cim_init_r.restype = st
         L.l0cim_init_state.argtypes = [c_int, c_int32, c_int32, c_uint64, c_int32, c_double, vp, vp, vp]
         L.l0cim_init_state.restype = st
         L.l0cim_mfcim_run_workspace_bytes.argtypes = [c_int, c_int32, c_int32, c_int]
@@ -273,6 +275,14 @@ def l0cim_build_couplings(G, b, R, j_dtype: int = None, J=None, row_scale=None, 
                                        _ld(J), _ptr(row_scale), _ptr(z), _stream(stream)),
            "l0cim_build_couplings")
     return J, row_scale, z
+
+
+def l0cim_init_r(G, b, R=None, status=None, stream=None):
+    n = G.shape[0]
+    R = torch.empty(n, dtype=G.dtype, device=G.device) if R is None else R
+    _check(lib().l0cim_init_r(_dtype_code(G), n, _ptr(G), _ld(G), _ptr(b), _ptr(R), _ptr(status),
+                              _stream(stream)), "l0cim_init_r")
+    return R
 
 
 def l0cim_init_state(n: int, P: int, seed: int, alt: int, c0_std: float, c, e, stream=None):

@@ -77,6 +77,15 @@ def test_gram_rejects_bad_arguments_on_host():
     assert lib.l0cim_gram(L.BF16, 4, 4, FAKE, 4, FAKE, FAKE, 4, FAKE, None) == 5
 
 
+def test_init_r_rejects_bad_arguments_on_host():
+    lib = L.lib()
+    assert lib.l0cim_init_r(L.F32, 4, None, 4, FAKE, FAKE, None, None) == 1
+    assert "NULL" in _err(lib)
+    assert lib.l0cim_init_r(L.F32, 4, FAKE, 3, FAKE, FAKE, None, None) == 2
+    assert lib.l0cim_init_r(L.F64, 0, FAKE, 4, FAKE, FAKE, None, None) == 2
+    assert lib.l0cim_init_r(L.FP8E4M3, 4, FAKE, 4, FAKE, FAKE, None, None) == 5
+
+
 def test_couplings_rejects_bad_arguments_on_host():
     lib = L.lib()
     # FP8 storage needs row scales

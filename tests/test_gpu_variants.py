@@ -1,0 +1,162 @@
+"""GPU parity of the model variants the paper studies, and of the history of
+the alternating minimisation, through the C ABI.
+
+* tau = 0.15 (the smaller target amplitude of the sparseness/tau comparison in
+  the Supplementary figures) and the variant whose linear term is
+  (-1 + p - j - c^2), on every launch form of the CIM run: the first 200 Euler
+  steps against the FP64 oracle, normwise relative 1e-5 (FP32) / 1e-12 (FP64)
+  at every step, as for the default model.
+* Algorithm 1 driven alternation by alternation through the step-level entry
+  points (couplings, initial state, CIM run, replica choice, CDP): at FP64 the
+  support chosen in every alternation is the oracle's, bit for bit, and R
+  after every CDP agrees to 1e-10 relative.  The per-alternation RMSE and
+  Hamming loss of the paper's field comparison are computed from these.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2405_00366_amd as L
+import workloads as W
+from oracle import mfcim as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    return torch.device("cuda:0")
+
+
+def t(x, dtype, dev):
+    return torch.tensor(np.asarray(x), dtype=dtype, device=dev)
+
+
+def f32(x):
+    return np.asarray(x, np.float64).astype(np.float32).astype(np.float64)
+
+
+def normwise(got, ref):
+    den = np.max(np.abs(ref))
+    return float(np.max(np.abs(got - ref)) / (den if den > 0 else 1.0))
+
+
+VARIANT_CASES = [
+    # n,    P, field, launch,             dtype,         tau,  linear_j
+    (2000,  1, "CN", L.LAUNCH_AUTO,      torch.float32, 0.15, False),
+    (2000,  1, "BN", L.LAUNCH_AUTO,      torch.float32, 0.15, False),
+    (2000,  1, "CN", L.LAUNCH_AUTO,      torch.float32, 1.0,  True),
+    (2000,  1, "BN", L.LAUNCH_AUTO,      torch.float32, 0.15, True),
+    (777,   2, "CN", L.LAUNCH_RESIDENT,  torch.float32, 0.15, True),
+    (1500,  1, "BN", L.LAUNCH_STREAMED,  torch.float32, 0.15, False),
+    (300,   4, "CN", L.LAUNCH_MATRIX,    torch.float32, 0.15, False),
+    (257,  16, "BN", L.LAUNCH_MATRIX,    torch.float32, 1.0,  True),
+    (64,    1, "CN", L.LAUNCH_AUTO,      torch.float64, 0.15, True),
+    (300,   2, "BN", L.LAUNCH_STREAMED,  torch.float64, 0.15, False),
+]
+
+
+@pytest.mark.parametrize("n,P,field,launch,dtype,tau,linear_j", VARIANT_CASES)
+def test_variant_trace_parity(dev, n, P, field, launch, dtype, tau, linear_j):
+    steps, eta, seed = 200, 0.6, 31 + n
+    inst = W.gaussian_instance(seed, n, max(1, n // 2), 0.1, 0.01).rounded_f32()
+    G, b = O.gram(inst.A, inst.y)
+    G, b = f32(G), f32(b)
+    R = f32(b / np.diag(G))
+    J, z = O.couplings(G, b, R)
+    if dtype == torch.float32:
+        J, z = f32(J), f32(z)
+    c0 = W.initial_amplitudes(seed, P, n)
+    if dtype == torch.float32:
+        c0 = f32(c0)
+    c = t(c0, dtype, dev)
+    e = torch.ones_like(c)
+    tr = torch.empty((steps, 2, P, n), dtype=dtype, device=dev)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    prm = L.cim_params(n_steps=steps, field=field, launch=launch, tau=tau, linear_j=int(linear_j))
+    sig = L.l0cim_mfcim_run(t(J, dtype, dev), t(z, dtype, dev), eta, prm, c, e, trace=tr,
+                            trace_steps=steps, status=status)
+    torch.cuda.synchronize()
+    _, _, ref = O.mfcim_run(J, z, eta, c0, np.ones((P, n)),
+                            O.CimParams(n_steps=steps, field=field, tau=tau, linear_j=linear_j),
+                            trace_steps=steps)
+    got = tr.double().cpu().numpy()
+    assert int(status.item()) == 0
+    tol = 1e-5 if dtype == torch.float32 else 1e-12
+    worst = max(normwise(got[k, v], ref[k, v]) for k in range(steps) for v in range(2))
+    assert worst <= tol, f"worst normwise error {worst:.3g}"
+    cf = c.double().cpu().numpy()
+    assert np.array_equal(sig.cpu().numpy(), (cf > 0).astype(np.uint8))
+
+
+def gpu_history(dev, A, y, cim, outer, dtype):
+    """Algorithm 1 through the step-level entry points; per alternation the
+    chosen support and R after the CDP (host copies)."""
+    n = A.shape[1]
+    P = outer.replicas
+    Ad, yd = t(A, dtype, dev), t(y, dtype, dev)
+    G, b = L.l0cim_gram(Ad, yd)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    R = L.l0cim_init_r(G, b, status=status)
+    c = torch.empty((P, n), dtype=dtype, device=dev)
+    e = torch.empty_like(c)
+    H = torch.empty(P, dtype=torch.float64, device=dev)
+    prm = L.cim_params(n_steps=cim.n_steps, field=cim.field, tau=cim.tau, linear_j=int(cim.linear_j))
+    hist = []
+    for i in range(outer.n_outer):
+        eta = O.eta_schedule(i, outer)
+        J, _, z = L.l0cim_build_couplings(G, b, R)
+        L.l0cim_init_state(n, P, outer.seed, i, cim.c0_std, c, e)
+        sig = L.l0cim_mfcim_run(J, z, eta, prm, c, e, H=H, status=status)
+        sel = L.l0cim_select_replica(H, sig)
+        L.l0cim_update_r(G, b, sel, R, dtc=outer.dtc, iters=outer.cdp_iters, status=status)
+        torch.cuda.synchronize()
+        hist.append((sel.cpu().numpy().copy(), R.double().cpu().numpy().copy()))
+    assert int(status.item()) == 0
+    return hist
+
+
+@pytest.mark.parametrize("field,P,tau,linear_j", [("CN", 1, 1.0, False), ("BN", 1, 1.0, False),
+                                                  ("CN", 4, 0.15, False), ("BN", 3, 1.0, True)])
+def test_alternation_history_fp64(dev, field, P, tau, linear_j):
+    n, m, seed = 64, 40, 5
+    inst = W.gaussian_instance(seed, n, m, 0.15, 0.05)
+    cim = O.CimParams(n_steps=1000, field=field, tau=tau, linear_j=linear_j)
+    outer = O.OuterParams(eta_init=0.8, eta_end=0.18, velo=12, n_outer=14, replicas=P, seed=seed)
+    res = O.solve(inst.A, inst.y, cim, outer)
+    ref_R = [h["R_in"] for h in res.history[1:]] + [res.R]
+    got = gpu_history(dev, inst.A, inst.y, cim, outer, torch.float64)
+    assert len(got) == len(res.history)
+    for i, ((sg, Rg), h, Ro) in enumerate(zip(got, res.history, ref_R)):
+        assert np.array_equal(sg, h["sigma"]), f"alternation {i}: support differs"
+        assert normwise(Rg, Ro) <= 1e-10, f"alternation {i}: R differs"
+    # the per-alternation figures the field comparison plots
+    rm_g = [O.rmse(sg, Rg, inst.x, inst.xi) for sg, Rg in got]
+    rm_o = [O.rmse(h["sigma"], Ro, inst.x, inst.xi) for h, Ro in zip(res.history, ref_R)]
+    np.testing.assert_allclose(rm_g, rm_o, rtol=1e-9, atol=1e-12)
+    hl_g = [O.hamming_loss(sg, inst.xi) for sg, _ in got]
+    hl_o = [O.hamming_loss(h["sigma"], inst.xi) for h in res.history]
+    assert hl_g == hl_o
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_init_r_is_b_over_diagonal(dev, dtype):
+    """R_r = b_r / G_rr, the CDP fixed point for an empty support; a diagonal
+    below 1e-12 gives R_r = 0 and the TINY_DIAG status bit."""
+    n = 300
+    inst = W.gaussian_instance(3, n, 200, 0.1, 0.01)
+    G, b = O.gram(inst.A, inst.y)
+    G[7, 7] = 0.0
+    G[11, 11] = 1e-13
+    if dtype == torch.float32:
+        G, b = f32(G), f32(b)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    R = L.l0cim_init_r(t(G, dtype, dev), t(b, dtype, dev), status=status)
+    torch.cuda.synchronize()
+    D = np.diag(G)
+    want = np.where(D < 1e-12, 0.0, b / np.where(D < 1e-12, 1.0, D))
+    if dtype == torch.float32:
+        want = f32(want)
+    assert np.array_equal(R.double().cpu().numpy(), want)
+    assert int(status.item()) == L.ST_TINY_DIAG
