@@ -728,6 +728,8 @@ def main():
                    "alternations": OUTER, "seeds": seeds[args.warmup:]},
         "support_match": f"{match}/{args.steps}",
         "spin_steps_per_s_all": spin_steps * args.steps / elapsed,
+        # the same count over the CIM kernels' own time (HIP events around each launch)
+        "spin_steps_per_s_cim_only": N * P * STEPS * cim_launches / (cim_ms / 1e3) if cim_ms > 0 else None,
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
         "status_nonzero": status_bad,
