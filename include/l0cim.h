@@ -217,6 +217,28 @@ l0cim_status l0cim_mfcim_run(l0cim_dtype dtype, int32_t n, int32_t P, l0cim_dtyp
                              int32_t* status, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * l0cim_mri_mfcim_run -- the run of l0cim_mfcim_run (same dynamics, state
+ * layout, sigma, H, trace and status) for an MRI-shaped observation matrix
+ * A = S C Psi^T with the couplings applied in factored form instead of a
+ * stored J:  (J x)_r = -R_r (G (R o x))_r + D_r R_r^2 x_r  with
+ * G v = Psi C^T diag(mask) C Psi^T v, where Psi is the orthonormal 2-D Haar
+ * analysis over `levels` levels in Mallat layout (coarsest block at the top
+ * left), C the orthonormal 2-D DCT-II of the size x size image and mask[f]
+ * (size^2 bytes, row-major frequency index f = k_row * size + k_col) is 1 for
+ * the sampled frequencies -- the rows of A.  This is J = -(A^T A) o R R^T with
+ * a zero diagonal (eq. 13, 15, 16) for the sparse-MRI observation model of the
+ * paper (wavelet-sparse image, undersampled frequency data).  D_r = G_rr
+ * (from l0cim_gram), R, z: n = size^2 floats; c, e: P x n floats; FP32 only.
+ * size must be 128 (L0CIM_ERR_UNSUPPORTED otherwise); 2^levels <= size.  One
+ * workgroup per replica holds the image in LDS; no workspace.
+ */
+l0cim_status l0cim_mri_mfcim_run(int32_t size, int32_t levels, int32_t P, const uint8_t* mask,
+                                 const float* R, const float* D, const float* z, double eta,
+                                 const l0cim_cim_params* prm, float* c, float* e, uint8_t* sigma,
+                                 double* H, float* trace, int32_t trace_steps, int32_t* status,
+                                 void* stream);
+
+/*
  * l0cim_select_replica -- q* = argmin_q H[q] (lowest q on ties, NaN never
  * chosen unless all are NaN) and sigma_out = sigma[q*] (n bytes).
  * q_out (int32, may be NULL) receives q*.

@@ -18,7 +18,7 @@ import torch
 __all__ = [
     "F32", "F64", "BF16", "FP8E4M3", "FIELD_CN", "FIELD_BN", "CDP_JACOBI", "CDP_CHOL_F64",
     "CimParams", "SolveParams", "Stats", "L0cimError", "lib", "library_path",
-    "l0cim_version", "l0cim_gram", "l0cim_build_couplings", "l0cim_init_r", "l0cim_init_state",
+    "l0cim_version", "l0cim_gram", "l0cim_build_couplings", "l0cim_init_r", "l0cim_init_state", "l0cim_mri_mfcim_run",
     "l0cim_mfcim_run", "l0cim_select_replica", "l0cim_update_r", "l0cim_solve",
     "l0cim_mfcim_run_workspace_bytes", "l0cim_update_r_workspace_bytes",
     "l0cim_solve_workspace_bytes", "l0cim_profile_begin", "l0cim_profile_end",
@@ -124,6 +124,9 @@ def lib():
                                       POINTER(CimParams), vp, vp, vp, vp, vp, c_int32, vp, vp,
                                       c_size_t, vp]
         L.l0cim_mfcim_run.restype = st
+        L.l0cim_mri_mfcim_run.argtypes = [c_int32, c_int32, c_int32, vp, vp, vp, vp, c_double,
+                                          POINTER(CimParams), vp, vp, vp, vp, vp, c_int32, vp, vp]
+        L.l0cim_mri_mfcim_run.restype = st
         L.l0cim_select_replica.argtypes = [c_int32, c_int32, vp, vp, vp, vp, vp]
         L.l0cim_select_replica.restype = st
         L.l0cim_update_r_workspace_bytes.argtypes = [c_int, c_int32, c_int]
@@ -310,6 +313,16 @@ def l0cim_mfcim_run(J, z, eta: float, prm: CimParams, c, e, sigma=None, H=None, 
                                  ctypes.byref(prm), _ptr(c), _ptr(e), _ptr(sigma), _ptr(H),
                                  _ptr(trace), trace_steps, _ptr(status), _ptr(ws), ws.numel(),
                                  _stream(stream)), "l0cim_mfcim_run")
+    return sigma
+
+
+def l0cim_mri_mfcim_run(size: int, levels: int, mask, R, D, z, eta: float, prm: CimParams, c, e, sigma=None,
+                        H=None, trace=None, trace_steps: int = 0, status=None, stream=None):
+    P = c.shape[0]
+    sigma = torch.empty(c.shape, dtype=torch.uint8, device=c.device) if sigma is None else sigma
+    _check(lib().l0cim_mri_mfcim_run(size, levels, P, _ptr(mask), _ptr(R), _ptr(D), _ptr(z), eta,
+                                     ctypes.byref(prm), _ptr(c), _ptr(e), _ptr(sigma), _ptr(H), _ptr(trace),
+                                     trace_steps, _ptr(status), _stream(stream)), "l0cim_mri_mfcim_run")
     return sigma
 
 

@@ -1,0 +1,489 @@
+// MF-CIM run for an MRI-shaped observation matrix A = S C Psi^T (a subset S
+// of the frequencies of the orthonormal 2-D DCT-II C of a 2-D image, Psi the
+// orthonormal multi-level 2-D Haar analysis in Mallat layout), with the
+// couplings J = -(A^T A) o R R^T (zero diagonal) applied in factored form:
+//
+//   (J x)_r = -R_r (G (R o x))_r + G_rr R_r^2 x_r,
+//   G v     = Psi C^T M C Psi^T v        (M: 0/1 mask of the sampled frequencies)
+//
+// which is the product with the dense couplings (eq. 13, 15, 16) without the
+// N x N matrix: per replica and Euler step an inverse Haar transform, a 2-D
+// DCT-II, the mask, a 2-D DCT-III and a Haar transform of the 128 x 128 image,
+// O(N log N) FP32 work instead of N^2 coupling bytes.
+//
+// One workgroup of 512 threads owns one replica for the whole run (512 rather
+// than 1024 so that a thread may hold 256 registers).  The image lives in LDS
+// (two 128 x 129 float buffers); thread t keeps c, e and R of spins t + 512 i,
+// i < 32, in registers, and each 8-lane group transforms two rows or columns
+// per pass.  Each length-128 DCT is the
+// length-128 complex FFT of a reordered sequence with a phase factor
+// (Makhoul's algorithm): the FFT is split 128 = 16 x 8, a 16-point DFT in the
+// registers of each of 8 lanes, a twiddle, a transpose through the row's own
+// LDS storage within the wavefront, and 8-point DFTs.  The inverse transform
+// runs the same steps backwards, so the forward output layout feeds it
+// without reordering.
+#include <cmath>
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace l0 {
+namespace {
+
+constexpr int kS = 128;            // image side
+constexpr int kLd = kS + 1;        // LDS row stride (floats)
+constexpr int kBS = 512;           // threads per workgroup
+constexpr int kPer = kS * kS / kBS; // spins per thread
+constexpr int kRows = kS / (kBS / 8);   // rows an 8-lane group transforms per pass
+constexpr int kQuads = (kS / 2) * (kS / 2) / kBS;   // Haar quads per thread at the finest level
+static_assert(kRows * 16 <= 32, "mask bits of a thread's column frequencies fit one word");
+
+struct MriLds {
+  float A[kS * kLd];
+  float B[kS * kLd];
+  float2 tw[kS];     // exp(-2 pi i m / 128)
+  float2 ph[kS];     // exp(-i pi k / 256)
+  double red[kBS / kWave];
+  float lin[4096];   // p_k - 1 (- j) of the first steps (eq. 21)
+};
+constexpr int kLinSteps = 4096;
+
+// cos and sin of 2 pi m / 16
+__device__ constexpr float kCos16[16] = {
+    1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f,
+    0.0f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f,
+    -1.0f, -0.92387953251128674f, -0.70710678118654752f, -0.38268343236508977f,
+    0.0f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f};
+__device__ constexpr float kSin16[16] = {
+    0.0f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f,
+    1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f,
+    0.0f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f,
+    -1.0f, -0.92387953251128674f, -0.70710678118654752f, -0.38268343236508977f};
+
+template <int BITS>
+__host__ __device__ constexpr int brev(int p) {
+  int r = 0;
+  for (int i = 0; i < BITS; ++i) r |= ((p >> i) & 1) << (BITS - 1 - i);
+  return r;
+}
+
+// In-place radix-2 decimation-in-frequency DFT of length L <= 16 with kernel
+// exp(SIGN 2 pi i n k / L): natural-order input, bit-reversed output.
+template <int L, int SIGN>
+__device__ __forceinline__ void dif(float (&re)[L], float (&im)[L]) {
+#pragma unroll
+  for (int half = L / 2; half >= 1; half >>= 1) {
+#pragma unroll
+    for (int base = 0; base < L; base += 2 * half) {
+#pragma unroll
+      for (int q = 0; q < half; ++q) {
+        const int i0 = base + q, i1 = i0 + half;
+        const float ar = re[i0], ai = im[i0], br = re[i1], bi = im[i1];
+        re[i0] = ar + br;
+        im[i0] = ai + bi;
+        const float dr = ar - br, di = ai - bi;
+        const int m = q * (L / (2 * half));
+        if (m == 0) {
+          re[i1] = dr;
+          im[i1] = di;
+        } else if (4 * m == L) {
+          re[i1] = -float(SIGN) * di;
+          im[i1] = float(SIGN) * dr;
+        } else {
+          const float cr = kCos16[m * (16 / L)], ci = float(SIGN) * kSin16[m * (16 / L)];
+          re[i1] = dr * cr - di * ci;
+          im[i1] = dr * ci + di * cr;
+        }
+      }
+    }
+  }
+}
+
+// Orders the LDS accesses of the lanes of one wavefront (a transpose within
+// an 8-lane group) without a workgroup barrier.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ int opaque_tid() {
+  int t;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"(int(threadIdx.x)));
+  return t;
+}
+
+// Position in a length-128 row of element m of the reordered DCT sequence:
+// v[m] = x[2m] for m < 64, x[255 - 2m] otherwise.
+__device__ __forceinline__ int perm_col(int m) { return m < kS / 2 ? 2 * m : 2 * kS - 1 - 2 * m; }
+
+__device__ __forceinline__ float dct_gain(int k) {
+  return k == 0 ? 0.08838834764831845f : 0.125f;   // sqrt(1/128), sqrt(2/128)
+}
+
+// Forward orthonormal DCT-II of the 128 values at src[perm_col(m)] (one row of
+// an 8-lane group, lane n2 of the group).  scr_re / scr_im: 128 floats of
+// scratch of the group (free once the group has read its input).  Output:
+// y[h * 8 + p] = coefficient k = 2 j + h + 16 brev3(p), j = n2.
+__device__ __forceinline__ void dct_fwd(const float* src, float* scr_re, float* scr_im, int n2,
+                                        const MriLds& s, float (&y)[16]) {
+  float re[16], im[16];
+#pragma unroll
+  for (int n1 = 0; n1 < 16; ++n1) {
+    re[n1] = src[perm_col(8 * n1 + n2)];
+    im[n1] = 0.0f;
+  }
+  wave_sync();
+  dif<16, -1>(re, im);
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const int k1 = brev<4>(p);
+    const float2 t = s.tw[(n2 * k1) & (kS - 1)];
+    scr_re[k1 * 8 + n2] = re[p] * t.x - im[p] * t.y;
+    scr_im[k1 * 8 + n2] = re[p] * t.y + im[p] * t.x;
+  }
+  wave_sync();
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int k1 = 2 * n2 + h;
+    float r8[8], i8[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      r8[q] = scr_re[k1 * 8 + q];
+      i8[q] = scr_im[k1 * 8 + q];
+    }
+    dif<8, -1>(r8, i8);
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      const int k = k1 + 16 * brev<3>(p);
+      const float2 f = s.ph[k];
+      y[h * 8 + p] = dct_gain(k) * (f.x * r8[p] - f.y * i8[p]);
+    }
+  }
+  wave_sync();
+  __builtin_amdgcn_sched_barrier(0);   // one row at a time: keeps the working set small
+}
+
+// Inverse (orthonormal DCT-III) of coefficients held as wn[h * 8 + k2] =
+// coefficient k = 2 j + h + 16 k2 (natural k2), j = n2.  Output: x[p] = value
+// at position perm_col(8 brev4(p) + n2) of the row.
+__device__ __forceinline__ void dct_inv(const float (&wn)[16], float* scr_re, float* scr_im, int n2,
+                                        const MriLds& s, float (&x)[16]) {
+  wave_sync();   // the caller may have read its input from the scratch row
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int k1 = 2 * n2 + h;
+    float r8[8], i8[8];
+#pragma unroll
+    for (int k2 = 0; k2 < 8; ++k2) {
+      const int k = k1 + 16 * k2;
+      const float2 f = s.ph[k];          // multiply by conj(f) = exp(+i pi k / 256)
+      const float v = dct_gain(k) * wn[h * 8 + k2];
+      r8[k2] = v * f.x;
+      i8[k2] = -v * f.y;
+    }
+    dif<8, 1>(r8, i8);
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      const int q = brev<3>(p);          // n2 of this output
+      const float2 t = s.tw[(q * k1) & (kS - 1)];   // conj twiddle
+      scr_re[k1 * 8 + q] = r8[p] * t.x + i8[p] * t.y;
+      scr_im[k1 * 8 + q] = i8[p] * t.x - r8[p] * t.y;
+    }
+  }
+  wave_sync();
+  float re[16], im[16];
+#pragma unroll
+  for (int k1 = 0; k1 < 16; ++k1) {
+    re[k1] = scr_re[k1 * 8 + n2];
+    im[k1] = scr_im[k1 * 8 + n2];
+  }
+  wave_sync();
+  dif<16, 1>(re, im);
+#pragma unroll
+  for (int p = 0; p < 16; ++p) x[p] = re[p];
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// G v for the workgroup's replica: the values u (R o x) of the thread's spins
+// go in, (Psi C^T M C Psi^T u) of the same spins comes out.  mbits: the mask
+// bits of the (kr, kc) the thread holds in the column pass.  t is the thread
+// index, passed as a value the compiler cannot see through (opaque_tid) so
+// that the few hundred LDS addresses derived from it are formed inside each
+// call rather than hoisted out of the step loop and kept live (which spilled).
+__device__ void gram_apply(MriLds& s, float (&u)[kPer], int levels, uint32_t mbits, int t) {
+  const int g = t >> 3, n2 = t & 7;
+  const int col = t & (kS - 1), row0 = t / kS;
+  constexpr int kRowStep = kBS / kS;
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) s.A[(row0 + kRowStep * i) * kLd + col] = u[i];
+  __syncthreads();
+  // inverse Haar, coarsest level first: out(2i+p, 2j+q) = 1/2 sum (-1)^(ap+bq) c(i+ah, j+bh)
+  for (int lev = levels - 1; lev >= 0; --lev) {
+    const int h = (kS >> lev) >> 1;
+    float v[kQuads][4];
+#pragma unroll
+    for (int nq = 0; nq < kQuads; ++nq) {
+      const int q = t + nq * kBS;
+      if (q >= h * h) break;
+      const int i = q / h, j = q - i * h;
+      const float c00 = s.A[i * kLd + j], c01 = s.A[i * kLd + j + h];
+      const float c10 = s.A[(i + h) * kLd + j], c11 = s.A[(i + h) * kLd + j + h];
+      v[nq][0] = 0.5f * ((c00 + c10) + (c01 + c11));
+      v[nq][1] = 0.5f * ((c00 + c10) - (c01 + c11));
+      v[nq][2] = 0.5f * ((c00 - c10) + (c01 - c11));
+      v[nq][3] = 0.5f * ((c00 - c10) - (c01 - c11));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int nq = 0; nq < kQuads; ++nq) {
+      const int q = t + nq * kBS;
+      if (q >= h * h) break;
+      const int i = q / h, j = q - i * h;
+      s.A[(2 * i) * kLd + 2 * j] = v[nq][0];
+      s.A[(2 * i) * kLd + 2 * j + 1] = v[nq][1];
+      s.A[(2 * i + 1) * kLd + 2 * j] = v[nq][2];
+      s.A[(2 * i + 1) * kLd + 2 * j + 1] = v[nq][3];
+    }
+    __syncthreads();
+  }
+  // rows: DCT-II along each image row; the result is stored transposed in B
+  float y[kRows][16];
+#pragma unroll
+  for (int rr = 0; rr < kRows; ++rr) {
+    const int row = g + (kBS / 8) * rr;
+    dct_fwd(s.A + row * kLd, s.A + row * kLd, s.B + row * kLd, n2, s, y[rr]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int rr = 0; rr < kRows; ++rr)
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int p = 0; p < 8; ++p)
+        s.B[(2 * n2 + h + 16 * brev<3>(p)) * kLd + g + (kBS / 8) * rr] = y[rr][h * 8 + p];
+  __syncthreads();
+  // columns (row kc of B): DCT-II, mask, DCT-III
+  float x[kRows][16];
+#pragma unroll
+  for (int rr = 0; rr < kRows; ++rr) {
+    const int kc = g + (kBS / 8) * rr;
+    float yc[16], wn[16];
+    dct_fwd(s.B + kc * kLd, s.B + kc * kLd, s.A + kc * kLd, n2, s, yc);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int k2 = 0; k2 < 8; ++k2) {
+        const int p = brev<3>(k2);
+        wn[h * 8 + k2] = ((mbits >> (16 * rr + h * 8 + p)) & 1u) ? yc[h * 8 + p] : 0.0f;
+      }
+    dct_inv(wn, s.B + kc * kLd, s.A + kc * kLd, n2, s, x[rr]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int rr = 0; rr < kRows; ++rr)
+#pragma unroll
+    for (int p = 0; p < 16; ++p) s.A[perm_col(8 * brev<4>(p) + n2) * kLd + g + (kBS / 8) * rr] = x[rr][p];
+  __syncthreads();
+  // rows: DCT-III along each image row (frequencies read in the inverse's input layout)
+#pragma unroll
+  for (int rr = 0; rr < kRows; ++rr) {
+    const int row = g + (kBS / 8) * rr;
+    float wn[16];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int k2 = 0; k2 < 8; ++k2) wn[h * 8 + k2] = s.A[row * kLd + 2 * n2 + h + 16 * k2];
+    dct_inv(wn, s.A + row * kLd, s.B + row * kLd, n2, s, x[rr]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int rr = 0; rr < kRows; ++rr)
+#pragma unroll
+    for (int p = 0; p < 16; ++p) s.A[(g + (kBS / 8) * rr) * kLd + perm_col(8 * brev<4>(p) + n2)] = x[rr][p];
+  __syncthreads();
+  // Haar analysis, finest level first: out(i+ah, j+bh) = 1/2 sum (-1)^(ap+bq) x(2i+p, 2j+q)
+  for (int lev = 0; lev < levels; ++lev) {
+    const int h = (kS >> lev) >> 1;
+    float v[kQuads][4];
+#pragma unroll
+    for (int nq = 0; nq < kQuads; ++nq) {
+      const int q = t + nq * kBS;
+      if (q >= h * h) break;
+      const int i = q / h, j = q - i * h;
+      const float x00 = s.A[(2 * i) * kLd + 2 * j], x01 = s.A[(2 * i) * kLd + 2 * j + 1];
+      const float x10 = s.A[(2 * i + 1) * kLd + 2 * j], x11 = s.A[(2 * i + 1) * kLd + 2 * j + 1];
+      v[nq][0] = 0.5f * ((x00 + x01) + (x10 + x11));
+      v[nq][1] = 0.5f * ((x00 - x01) + (x10 - x11));
+      v[nq][2] = 0.5f * ((x00 + x01) - (x10 + x11));
+      v[nq][3] = 0.5f * ((x00 - x01) - (x10 - x11));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int nq = 0; nq < kQuads; ++nq) {
+      const int q = t + nq * kBS;
+      if (q >= h * h) break;
+      const int i = q / h, j = q - i * h;
+      s.A[i * kLd + j] = v[nq][0];
+      s.A[i * kLd + j + h] = v[nq][1];
+      s.A[(i + h) * kLd + j] = v[nq][2];
+      s.A[(i + h) * kLd + j + h] = v[nq][3];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) u[i] = s.A[(row0 + kRowStep * i) * kLd + col];
+  __syncthreads();
+}
+
+// p_k - 1 (- j) of eq. 21 for steps k0 .. k0 + kLinSteps - 1 into LDS (its own
+// function, so that the FP64 exp is not part of the step loop's code).
+__device__ __noinline__ void fill_lin(float* lin, int k0, int n_steps, double dt, double p_thr, double d,
+                                     double t_c, double t_w, double lj) {
+  for (int k = k0 + int(threadIdx.x); k < n_steps && k < k0 + kLinSteps; k += kBS) {
+    const double tk = double(k) * dt;
+    lin[k - k0] = float((p_thr - d) + 2.0 * d / (1.0 + exp(-(tk - t_c) / t_w)) - 1.0 - lj);
+  }
+}
+
+template <int FIELD>
+__global__ void __launch_bounds__(kBS)
+mri_cim_kernel(const uint8_t* __restrict__ mask, const float* __restrict__ R, const float* __restrict__ D,
+               const float* __restrict__ z, CimArgs a, int levels, float* __restrict__ c,
+               float* __restrict__ e, uint8_t* __restrict__ sigma, double* __restrict__ H,
+               float* __restrict__ trace, int* __restrict__ status) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  MriLds& s = *reinterpret_cast<MriLds*>(smem);
+  const int t = threadIdx.x, q = blockIdx.x, n = kS * kS;
+  const int g = t >> 3, n2 = t & 7;
+  if (t < kS) {
+    double sn, cs;
+    sincospi(-2.0 * t / kS, &sn, &cs);
+    s.tw[t] = make_float2(float(cs), float(sn));
+    sincospi(-double(t) / (2 * kS), &sn, &cs);
+    s.ph[t] = make_float2(float(cs), float(sn));
+  }
+  const double lj = a.linear_j ? a.j : 0.0;
+  fill_lin(s.lin, 0, a.n_steps, a.dt, a.p_thr, a.d, a.t_c, a.t_w, lj);
+  // mask bits of the frequencies (kr, kc = g) this thread holds in the column pass
+  uint32_t mbits = 0;
+#pragma unroll
+  for (int rr = 0; rr < kRows; ++rr)
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int p = 0; p < 8; ++p) {
+        const int kr = 2 * n2 + h + 16 * brev<3>(p);
+        if (mask[kr * kS + g + (kBS / 8) * rr]) mbits |= 1u << (16 * rr + h * 8 + p);
+      }
+  float cv[kPer], ev[kPer], Rv[kPer];
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int r = t + kBS * i;
+    cv[i] = c[size_t(q) * n + r];
+    ev[i] = e[size_t(q) * n + r];
+    Rv[i] = R[r];
+  }
+  __syncthreads();
+  const float st = float(sqrt(a.tau)), half_st = float(0.5 * sqrt(a.tau));
+  const float theta = float(a.eta * a.eta * sqrt(a.tau) * 0.25);
+  const float jj = float(a.j), KK = float(a.K), beta = float(a.beta), tau = float(a.tau), dt = float(a.dt);
+  const bool bn = (FIELD == int(L0CIM_FIELD_BN));
+  for (int k = 0; k < a.n_steps; ++k) {
+    if (k > 0 && k % kLinSteps == 0) {
+      __syncthreads();
+      fill_lin(s.lin, k, a.n_steps, a.dt, a.p_thr, a.d, a.t_c, a.t_w, lj);
+      __syncthreads();
+    }
+    float u[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const float x = bn ? (cv[i] > 0.0f ? 1.0f : 0.0f) : (cv[i] + st) * 0.25f;
+      u[i] = Rv[i] * x;
+    }
+    gram_apply(s, u, levels, mbits, opaque_tid());
+    const float lin = s.lin[k % kLinSteps];
+    // D and z are read again every step (from the caches) through an opaque
+    // index: held across the steps they would take 64 more registers
+    const int tk = opaque_tid();
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int r = tk + kBS * i;
+      const float x = bn ? (cv[i] > 0.0f ? 1.0f : 0.0f) : (cv[i] + st) * 0.25f;
+      const float Rr = Rv[i];
+      const float y = -Rr * u[i] + (D[r] * Rr * Rr) * x;     // (J x)_r, zero diagonal
+      const float zr = z[r];
+      const float phi = bn ? half_st * (y + zr) : y + half_st * zr;
+      const float inj = jj * ev[i] * (phi - theta);
+      const float c2 = cv[i] * cv[i];
+      const float dc = (lin - c2) * cv[i] + KK * inj;
+      const float de = -beta * (c2 - tau) * ev[i];
+      cv[i] = cv[i] + dt * dc;
+      ev[i] = ev[i] + dt * de;
+      if (k < a.trace_steps) {
+        trace[(size_t(2 * k) * a.P + q) * n + r] = cv[i];
+        trace[(size_t(2 * k + 1) * a.P + q) * n + r] = ev[i];
+      }
+    }
+  }
+  // final state, support and the eq. 4 energy of the support (addresses from
+  // an opaque index again, so that they are not shared with the loads at the
+  // start and kept live through the run)
+  float u[kPer];
+  int bits = 0;
+  const int tf = opaque_tid();
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int r = tf + kBS * i;
+    c[size_t(q) * n + r] = cv[i];
+    e[size_t(q) * n + r] = ev[i];
+    sigma[size_t(q) * n + r] = cv[i] > 0.0f ? 1 : 0;
+    u[i] = cv[i] > 0.0f ? Rv[i] : 0.0f;
+    if (!(isfinite(cv[i]) && isfinite(ev[i]))) bits |= L0CIM_ST_NONFINITE;
+    else if (fabsf(cv[i]) > 1e3f) bits |= L0CIM_ST_BLOWUP;
+  }
+  if (bits) raise_status(status, bits);
+  if (H) {
+    gram_apply(s, u, levels, mbits, opaque_tid());
+    const double lam = 0.5 * a.eta * a.eta;
+    double hs = 0.0;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int r = tf + kBS * i;
+      if (cv[i] > 0.0f) {
+        const double Rr = Rv[i];
+        const double js = -Rr * double(u[i]) + double(D[r]) * Rr * Rr;   // (J sigma)_r
+        hs += -0.5 * js - double(z[r]) + lam;
+      }
+    }
+    // fixed-order reduction: wavefront partials, then wavefront 0
+    for (int off = kWave / 2; off > 0; off >>= 1) hs += __shfl_down(hs, off, kWave);
+    if ((t & (kWave - 1)) == 0) s.red[t / kWave] = hs;
+    __syncthreads();
+    if (t == 0) {
+      double tot = 0.0;
+      for (int w = 0; w < kBS / kWave; ++w) tot += s.red[w];
+      H[q] = tot;
+    }
+  }
+}
+
+}  // namespace
+
+size_t mri_lds_bytes() { return sizeof(MriLds); }
+
+l0cim_status launch_mri_mfcim(int size, int levels, int P, const uint8_t* mask, const float* R,
+                              const float* D, const float* z, const CimArgs& a, float* c, float* e,
+                              uint8_t* sigma, double* H, float* trace, int* status, hipStream_t s) {
+  if (size != kS) return set_error(L0CIM_ERR_UNSUPPORTED, "mri_mfcim_run: image side %d (128 supported)", size);
+  const size_t lds = sizeof(MriLds);
+  void (*k)(const uint8_t*, const float*, const float*, const float*, CimArgs, int, float*, float*, uint8_t*,
+            double*, float*, int*) =
+      a.field == L0CIM_FIELD_BN ? mri_cim_kernel<int(L0CIM_FIELD_BN)> : mri_cim_kernel<int(L0CIM_FIELD_CN)>;
+  L0_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             int(lds)));
+  hipLaunchKernelGGL(k, dim3(P), dim3(kBS), lds, s, mask, R, D, z, a, levels, c, e, sigma, H, trace, status);
+  L0_LAUNCHED("mri_cim_kernel");
+  return L0CIM_OK;
+}
+
+}  // namespace l0

@@ -86,6 +86,19 @@ def test_init_r_rejects_bad_arguments_on_host():
     assert lib.l0cim_init_r(L.FP8E4M3, 4, FAKE, 4, FAKE, FAKE, None, None) == 5
 
 
+def test_mri_run_rejects_bad_arguments_on_host():
+    lib = L.lib()
+    prm = L.cim_params()
+    call = lambda size=128, levels=3, P=2, mask=FAKE, ts=0, tr=None: lib.l0cim_mri_mfcim_run(
+        size, levels, P, mask, FAKE, FAKE, FAKE, 0.1, ctypes.byref(prm), FAKE, FAKE, FAKE, None, tr, ts,
+        None, None)
+    assert call(mask=None) == 1
+    assert call(P=0) == 2
+    assert call(levels=8) == 2
+    assert call(ts=5) == 1
+    assert call(size=64) == 5          # the 128 x 128 image only
+
+
 def test_couplings_rejects_bad_arguments_on_host():
     lib = L.lib()
     # FP8 storage needs row scales
