@@ -41,6 +41,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MF-CIM spin-steps/s & %roofline at oracle support match; p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFS = 157.3
 N, M, STEPS, OUTER, P = 2000, 1000, 2000, 30, 1
 WORKLOAD = ("plain Gaussian L0RBCS: N=2000, M=1000 (alpha 0.5), Bernoulli(0.1) support, N(0,1) values, "
             "A iid N(0,1/M), noise std 0.01, 1 replica, 2000 Euler steps x 30 alternations, "
@@ -204,8 +205,131 @@ def batched_bench(args, torch, L, W, dev):
     }
 
 
+def factored_mri_solve(torch, L, inst, dev, cim, P, outer, seed):
+    """Algorithm 1 on the MRI-shaped instance with the couplings applied in
+    factored form (l0cim_mri_mfcim_run), through the step-level entry points:
+    Gram prep, R_init, then per alternation the initial state, the CIM run,
+    the replica choice and the Jacobi CDP on G; the FP64 Cholesky refit last."""
+    n = inst.N
+    A = torch.tensor(inst.A, dtype=torch.float32, device=dev)
+    y = torch.tensor(inst.y, dtype=torch.float32, device=dev)
+    mask_h = np.zeros(n, np.uint8)
+    mask_h[inst.meta["freqs"]] = 1
+    mask = torch.from_numpy(mask_h).to(dev)
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    c = torch.empty((P, n), device=dev)
+    e = torch.empty_like(c)
+    sig = torch.empty((P, n), dtype=torch.uint8, device=dev)
+    H = torch.empty(P, dtype=torch.float64, device=dev)
+    sel = torch.empty(n, dtype=torch.uint8, device=dev)
+    ws_j = L.workspace(L.l0cim_update_r_workspace_bytes(L.F32, n, L.CDP_JACOBI), dev)
+    ws_c = L.workspace(L.l0cim_update_r_workspace_bytes(L.F32, n, L.CDP_CHOL_F64), dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    G, b = L.l0cim_gram(A, y)
+    R = L.l0cim_init_r(G, b, status=st)
+    for i in range(outer):
+        eta = max(0.8 * (1.0 - i / 11), 0.03)
+        L.l0cim_init_state(n, P, seed, i, cim.c0_std, c, e)
+        L.l0cim_mri_mfcim_run(128, 3, mask, R, G, b, eta, cim, c, e, sigma=sig, H=H, status=st)
+        L.l0cim_select_replica(H, sig, sel)
+        L.l0cim_update_r(G, b, sel, R, iters=100, status=st, ws=ws_j)
+    L.l0cim_update_r(G, b, sel, R, cdp=L.CDP_CHOL_F64, status=st, ws=ws_c)
+    torch.cuda.synchronize()
+    return R, sel, int(st.item()), time.perf_counter() - t0
+
+
+def mri_golden():
+    """The oracle's stored MRI supports and its FP64 refit on them."""
+    gold, gold_R = {}, {}
+    path = os.path.join(ROOT, "tests", "golden", "oracle_supports_mri.txt")
+    if os.path.exists(path):
+        for line in open(path):
+            if line.strip() and line[0] != "#":
+                sd, k, rm, hx = line.split()
+                gold[int(sd)] = (int(hx, 16), float(rm))
+    path = os.path.join(ROOT, "tests", "golden", "oracle_refit_mri.txt")
+    if os.path.exists(path):
+        for line in open(path):
+            if line.strip() and line[0] != "#":
+                f = line.split()
+                gold_R[int(f[0])] = np.array([float(v) for v in f[2:]])
+    return gold, gold_R
+
+
+def mri_flops_per_replica_step(size: int = 128, levels: int = 3) -> float:
+    """Algorithmic FP32 work of one factored-couplings Euler step of one
+    replica: two 2-D DCTs (forward and inverse), each 2 x size length-size
+    complex FFTs at 5 S log2 S flops plus 6 S for the phase factors; the
+    inverse and forward Haar levels (3 flops per output); the mask; and
+    about 20 flops per spin for the field and Euler update."""
+    S = size
+    dct2 = 2 * S * (5 * S * math.log2(S) + 6 * S)
+    haar = 2 * sum(3 * (S >> l) ** 2 for l in range(levels))
+    return 2 * dct2 + haar + S * S + 20 * S * S
+
+
+def factored_bench(args, torch, L, W, dev):
+    from workloads import mri as WM
+    P, steps, outer = 64, args.euler_steps or 1000, args.alternations or 11
+    gold, gold_R = mri_golden()
+    seeds = list(range(args.steps))
+    cim = L.cim_params(n_steps=steps, field="BN", K=1.0, d=0.6)
+    rows, total, cim_total, launches_total, match = [], 0.0, 0.0, 0, 0
+    n = 128 * 128
+    for sd in seeds:
+        print(f"[factored] building the MRI-shaped instance of seed {sd}", file=sys.stderr, flush=True)
+        inst = WM.mri_instance(sd)
+        if sd == seeds[0]:
+            factored_mri_solve(torch, L, inst, dev, L.cim_params(n_steps=4, field="BN", K=1.0, d=0.6), P, 1, sd)
+        print(f"[factored] solving ({outer} x {steps} steps)", file=sys.stderr, flush=True)
+        L.l0cim_profile_begin()
+        R, sel, status, dt = factored_mri_solve(torch, L, inst, dev, cim, P, outer, sd)
+        ms, cnt = L.l0cim_profile_end()
+        total += dt
+        cim_total += ms
+        launches_total += cnt
+        sig = sel.cpu().numpy()
+        Rv = R.double().cpu().numpy()
+        rmse = float(np.sqrt(np.mean((Rv * sig - inst.x * inst.xi) ** 2)))
+        ok = sd in gold and mask_to_int(sig) == gold[sd][0] and (steps, outer) == (1000, 11)
+        xd = None
+        if sd in gold and sd in gold_R:
+            x_or = np.zeros(n)
+            x_or[[r for r in range(n) if (gold[sd][0] >> r) & 1]] = gold_R[sd]
+            xd = float(np.sqrt(np.mean((Rv * sig - x_or) ** 2)))
+        match += int(ok)
+        rows.append({"seed": sd, "support": int(sig.sum()), "rmse": rmse,
+                     "oracle_rmse": gold[sd][1] if sd in gold else None, "oracle_support_match": ok,
+                     "hamming_vs_oracle": (bin(mask_to_int(sig) ^ gold[sd][0]).count("1") / n) if sd in gold
+                     else None, "xhat_rmse_vs_oracle": xd, "status": status, "solve_s": dt})
+        print(f"[factored] seed {sd}: {dt:.3f} s, support {int(sig.sum())}, oracle match {ok}",
+              file=sys.stderr, flush=True)
+    spin_steps = n * P * steps * outer * len(seeds)
+    run_ms = cim_total / launches_total
+    flops = mri_flops_per_replica_step() * P * steps
+    achieved = flops / (run_ms / 1e3) / 1e12
+    return {
+        "metric": METRIC, "value": spin_steps / total, "unit": "spin-steps/s", "n_gpus": 1, "steps": len(seeds),
+        "warmup": 1, "ms_per_step": total * 1e3 / len(seeds), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "MRI-shaped L0RBCS stand-in: 128x128 random-ellipse phantom, 3-level Haar (N=16384), "
+                               "30% variable-density DCT-II rows (M=4915), noise 1e-3, 64 replicas, BN field, K=1, "
+                               "d=0.6, eta 0.8->0.03 over 11 alternations of 1000 steps, FP32 couplings applied in "
+                               "factored form (Haar, FFT-based DCT, mask), Jacobi CDP on G, FP64 Cholesky refit"},
+        "couplings": "factored", "support_match": f"{match}/{len(seeds)}", "per_seed": rows,
+        "spin_steps_per_s_cim_only": n * P * steps * launches_total / (cim_total / 1e3),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_VECTOR_PEAK_TFS, "traffic": None, "kernel": "mri_cim_kernel<BN>",
+                     "flops_per_replica_step": mri_flops_per_replica_step(),
+                     "avg_launch_ms": run_ms, "us_per_step": run_ms * 1e3 / steps},
+    }
+
+
 def precision_bench(args, torch, L, W, dev):
     from workloads import mri as WM
+    if args.jdtype == "factored":
+        return factored_bench(args, torch, L, W, dev)
     jdt = {"bf16": L.BF16, "fp8": L.FP8E4M3}[args.jdtype]
     jb = {"bf16": 2, "fp8": 1}[args.jdtype]
     P, steps, outer = 64, args.euler_steps or 1000, args.alternations or 11
@@ -616,7 +740,8 @@ def main():
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run a 512 MiB fill and copy first (HBM counter calibration)")
     ap.add_argument("--form", choices=["plain", "batched", "precision", "serving", "accuracy"], default="plain")
-    ap.add_argument("--jdtype", choices=["bf16", "fp8"], default="bf16", help="precision form couplings")
+    ap.add_argument("--jdtype", choices=["bf16", "fp8", "factored"], default="bf16",
+                    help="precision form couplings (factored: FP32, applied through the MRI operator)")
     ap.add_argument("--requests", type=int, default=200, help="serving form: number of requests")
     ap.add_argument("--slots", type=int, default=48, help="serving form: resident requests at most")
     ap.add_argument("--rates", type=float, nargs="*", default=[0.5, 0.9],

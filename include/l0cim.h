@@ -228,15 +228,17 @@ l0cim_status l0cim_mfcim_run(l0cim_dtype dtype, int32_t n, int32_t P, l0cim_dtyp
  * the sampled frequencies -- the rows of A.  This is J = -(A^T A) o R R^T with
  * a zero diagonal (eq. 13, 15, 16) for the sparse-MRI observation model of the
  * paper (wavelet-sparse image, undersampled frequency data).  D_r = G_rr
- * (from l0cim_gram), R, z: n = size^2 floats; c, e: P x n floats; FP32 only.
+ * (from l0cim_gram) is read as D[r * incd] (incd = ldg + 1 reads the diagonal
+ * of G in place, 1 a vector), b = A^T y (from l0cim_gram; z = R o b as in
+ * l0cim_build_couplings), R: n = size^2 floats; c, e: P x n floats; FP32 only.
  * size must be 128 (L0CIM_ERR_UNSUPPORTED otherwise); 2^levels <= size.  One
  * workgroup per replica holds the image in LDS; no workspace.
  */
 l0cim_status l0cim_mri_mfcim_run(int32_t size, int32_t levels, int32_t P, const uint8_t* mask,
-                                 const float* R, const float* D, const float* z, double eta,
-                                 const l0cim_cim_params* prm, float* c, float* e, uint8_t* sigma,
-                                 double* H, float* trace, int32_t trace_steps, int32_t* status,
-                                 void* stream);
+                                 const float* R, const float* D, int64_t incd, const float* b,
+                                 double eta, const l0cim_cim_params* prm, float* c, float* e,
+                                 uint8_t* sigma, double* H, float* trace, int32_t trace_steps,
+                                 int32_t* status, void* stream);
 
 /*
  * l0cim_select_replica -- q* = argmin_q H[q] (lowest q on ties, NaN never

@@ -124,7 +124,7 @@ def lib():
                                       POINTER(CimParams), vp, vp, vp, vp, vp, c_int32, vp, vp,
                                       c_size_t, vp]
         L.l0cim_mfcim_run.restype = st
-        L.l0cim_mri_mfcim_run.argtypes = [c_int32, c_int32, c_int32, vp, vp, vp, vp, c_double,
+        L.l0cim_mri_mfcim_run.argtypes = [c_int32, c_int32, c_int32, vp, vp, vp, c_int64, vp, c_double,
                                           POINTER(CimParams), vp, vp, vp, vp, vp, c_int32, vp, vp]
         L.l0cim_mri_mfcim_run.restype = st
         L.l0cim_select_replica.argtypes = [c_int32, c_int32, vp, vp, vp, vp, vp]
@@ -316,11 +316,13 @@ def l0cim_mfcim_run(J, z, eta: float, prm: CimParams, c, e, sigma=None, H=None, 
     return sigma
 
 
-def l0cim_mri_mfcim_run(size: int, levels: int, mask, R, D, z, eta: float, prm: CimParams, c, e, sigma=None,
+def l0cim_mri_mfcim_run(size: int, levels: int, mask, R, D, b, eta: float, prm: CimParams, c, e, sigma=None,
                         H=None, trace=None, trace_steps: int = 0, status=None, stream=None):
+    """D: a vector of G_rr, or G itself (its diagonal is read in place)."""
     P = c.shape[0]
     sigma = torch.empty(c.shape, dtype=torch.uint8, device=c.device) if sigma is None else sigma
-    _check(lib().l0cim_mri_mfcim_run(size, levels, P, _ptr(mask), _ptr(R), _ptr(D), _ptr(z), eta,
+    incd = 1 if D.dim() == 1 else D.stride(0) + 1
+    _check(lib().l0cim_mri_mfcim_run(size, levels, P, _ptr(mask), _ptr(R), _ptr(D), incd, _ptr(b), eta,
                                      ctypes.byref(prm), _ptr(c), _ptr(e), _ptr(sigma), _ptr(H), _ptr(trace),
                                      trace_steps, _ptr(status), _stream(stream)), "l0cim_mri_mfcim_run")
     return sigma

@@ -291,20 +291,20 @@ l0cim_status l0cim_mfcim_run(l0cim_dtype dtype, int32_t n, int32_t P, l0cim_dtyp
 }
 
 l0cim_status l0cim_mri_mfcim_run(int32_t size, int32_t levels, int32_t P, const uint8_t* mask,
-                                 const float* R, const float* D, const float* z, double eta,
-                                 const l0cim_cim_params* prm, float* c, float* e, uint8_t* sigma,
-                                 double* H, float* trace, int32_t trace_steps, int32_t* status,
-                                 void* stream) {
+                                 const float* R, const float* D, int64_t incd, const float* b,
+                                 double eta, const l0cim_cim_params* prm, float* c, float* e,
+                                 uint8_t* sigma, double* H, float* trace, int32_t trace_steps,
+                                 int32_t* status, void* stream) {
   l0cim_status st = check_cim(prm);
   if (st != L0CIM_OK) return st;
-  if (!mask || !R || !D || !z || !c || !e || !sigma) return set_error(L0CIM_ERR_ARG, "mri_mfcim_run: NULL pointer");
-  if (size <= 0 || P <= 0 || P > (1 << 16)) return set_error(L0CIM_ERR_SHAPE, "mri_mfcim_run: bad shape");
+  if (!mask || !R || !D || !b || !c || !e || !sigma) return set_error(L0CIM_ERR_ARG, "mri_mfcim_run: NULL pointer");
+  if (size <= 0 || P <= 0 || P > (1 << 16) || incd < 1) return set_error(L0CIM_ERR_SHAPE, "mri_mfcim_run: bad shape");
   if (levels < 0 || (1 << levels) > size) return set_error(L0CIM_ERR_SHAPE, "mri_mfcim_run: %d Haar levels", levels);
   if (trace_steps < 0 || (trace_steps > 0 && !trace))
     return set_error(L0CIM_ERR_ARG, "mri_mfcim_run: trace_steps > 0 needs a trace buffer");
   const int n = size * size;
   CimArgs a = make_args(n, P, prm, eta, trace_steps < prm->n_steps ? trace_steps : prm->n_steps);
-  return launch_mri_mfcim(size, levels, P, mask, R, D, z, a, c, e, sigma, H, trace, status,
+  return launch_mri_mfcim(size, levels, P, mask, R, D, incd, b, a, c, e, sigma, H, trace, status,
                           static_cast<hipStream_t>(stream));
 }
 

@@ -16,7 +16,7 @@ l0cim_status launch_couplings(l0cim_dtype dt, int n, const void* G, int64_t ldg,
 l0cim_status launch_init_state(l0cim_dtype dt, int n, int P, uint64_t seed, int alt, double std,
                                void* c, void* e, hipStream_t s);
 l0cim_status launch_mri_mfcim(int size, int levels, int P, const uint8_t* mask, const float* R,
-                              const float* D, const float* z, const CimArgs& a, float* c, float* e,
+                              const float* D, int64_t incd, const float* b, const CimArgs& a, float* c, float* e,
                               uint8_t* sigma, double* H, float* trace, int* status, hipStream_t s);
 l0cim_status launch_r_init(l0cim_dtype dt, int n, const void* G, int64_t ldg, const void* b,
                            const void* R_init, void* R, int* status, hipStream_t s);

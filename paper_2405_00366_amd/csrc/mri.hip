@@ -347,8 +347,8 @@ __device__ __noinline__ void fill_lin(float* lin, int k0, int n_steps, double dt
 
 template <int FIELD>
 __global__ void __launch_bounds__(kBS)
-mri_cim_kernel(const uint8_t* __restrict__ mask, const float* __restrict__ R, const float* __restrict__ D,
-               const float* __restrict__ z, CimArgs a, int levels, float* __restrict__ c,
+mri_cim_kernel(const uint8_t* __restrict__ mask, const float* __restrict__ R, const float* __restrict__ D, int64_t incd,
+               const float* __restrict__ b, CimArgs a, int levels, float* __restrict__ c,
                float* __restrict__ e, uint8_t* __restrict__ sigma, double* __restrict__ H,
                float* __restrict__ trace, int* __restrict__ status) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -410,8 +410,8 @@ mri_cim_kernel(const uint8_t* __restrict__ mask, const float* __restrict__ R, co
       const int r = tk + kBS * i;
       const float x = bn ? (cv[i] > 0.0f ? 1.0f : 0.0f) : (cv[i] + st) * 0.25f;
       const float Rr = Rv[i];
-      const float y = -Rr * u[i] + (D[r] * Rr * Rr) * x;     // (J x)_r, zero diagonal
-      const float zr = z[r];
+      const float y = -Rr * u[i] + (D[r * incd] * Rr * Rr) * x;   // (J x)_r, zero diagonal
+      const float zr = Rr * b[r];                            // z = R o b
       const float phi = bn ? half_st * (y + zr) : y + half_st * zr;
       const float inj = jj * ev[i] * (phi - theta);
       const float c2 = cv[i] * cv[i];
@@ -451,8 +451,8 @@ mri_cim_kernel(const uint8_t* __restrict__ mask, const float* __restrict__ R, co
       const int r = tf + kBS * i;
       if (cv[i] > 0.0f) {
         const double Rr = Rv[i];
-        const double js = -Rr * double(u[i]) + double(D[r]) * Rr * Rr;   // (J sigma)_r
-        hs += -0.5 * js - double(z[r]) + lam;
+        const double js = -Rr * double(u[i]) + double(D[r * incd]) * Rr * Rr;   // (J sigma)_r
+        hs += -0.5 * js - double(Rv[i] * b[r]) + lam;
       }
     }
     // fixed-order reduction: wavefront partials, then wavefront 0
@@ -472,16 +472,20 @@ mri_cim_kernel(const uint8_t* __restrict__ mask, const float* __restrict__ R, co
 size_t mri_lds_bytes() { return sizeof(MriLds); }
 
 l0cim_status launch_mri_mfcim(int size, int levels, int P, const uint8_t* mask, const float* R,
-                              const float* D, const float* z, const CimArgs& a, float* c, float* e,
+                              const float* D, int64_t incd, const float* b, const CimArgs& a, float* c, float* e,
                               uint8_t* sigma, double* H, float* trace, int* status, hipStream_t s) {
   if (size != kS) return set_error(L0CIM_ERR_UNSUPPORTED, "mri_mfcim_run: image side %d (128 supported)", size);
   const size_t lds = sizeof(MriLds);
-  void (*k)(const uint8_t*, const float*, const float*, const float*, CimArgs, int, float*, float*, uint8_t*,
-            double*, float*, int*) =
+  void (*k)(const uint8_t*, const float*, const float*, int64_t, const float*, CimArgs, int, float*, float*,
+            uint8_t*, double*, float*, int*) =
       a.field == L0CIM_FIELD_BN ? mri_cim_kernel<int(L0CIM_FIELD_BN)> : mri_cim_kernel<int(L0CIM_FIELD_CN)>;
   L0_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
                              int(lds)));
-  hipLaunchKernelGGL(k, dim3(P), dim3(kBS), lds, s, mask, R, D, z, a, levels, c, e, sigma, H, trace, status);
+  {
+    ProfileScope prof(s);
+    hipLaunchKernelGGL(k, dim3(P), dim3(kBS), lds, s, mask, R, D, incd, b, a, levels, c, e, sigma, H, trace,
+                       status);
+  }
   L0_LAUNCHED("mri_cim_kernel");
   return L0CIM_OK;
 }

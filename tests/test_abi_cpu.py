@@ -90,7 +90,7 @@ def test_mri_run_rejects_bad_arguments_on_host():
     lib = L.lib()
     prm = L.cim_params()
     call = lambda size=128, levels=3, P=2, mask=FAKE, ts=0, tr=None: lib.l0cim_mri_mfcim_run(
-        size, levels, P, mask, FAKE, FAKE, FAKE, 0.1, ctypes.byref(prm), FAKE, FAKE, FAKE, None, tr, ts,
+        size, levels, P, mask, FAKE, FAKE, 1, FAKE, 0.1, ctypes.byref(prm), FAKE, FAKE, FAKE, None, tr, ts,
         None, None)
     assert call(mask=None) == 1
     assert call(P=0) == 2

@@ -5,7 +5,8 @@ The couplings are J = -(A^T A) o R R^T with a zero diagonal for A = S C Psi^T
 (the sampled rows of the orthonormal 2-D DCT-II of the image of the 3-level
 Haar synthesis).  The oracle applies J with scipy's DCT and its own Haar
 transform in FP64; the device with FFT-based DCTs and its Haar transform in
-FP32.  Both sides get the same FP32 R, D = diag(A^T A), z = R o A^T y and c0.
+FP32.  Both sides get the same FP32 R, D = diag(A^T A), b = A^T y and c0 (z = R o b
+rounded to FP32, as the device forms it).
 Gates: normwise relative 1e-5 per Euler step over the first 200 steps for c
 and e (as for the dense couplings), sigma = H(c) of the device's own final
 state, and the eq. 4 energy of that sigma to 1e-5 relative.
@@ -81,7 +82,7 @@ def test_mri_run_trace_parity(dev, mri_case, field, P, levels, Rkind):
     tr = torch.empty((steps, 2, P, n), dtype=torch.float32, device=dev)
     H = torch.empty(P, dtype=torch.float64, device=dev)
     status = torch.zeros(1, dtype=torch.int32, device=dev)
-    sig = L.l0cim_mri_mfcim_run(128, levels, t(mri_case["mask"], torch.uint8), t(R), t(D), t(z), eta,
+    sig = L.l0cim_mri_mfcim_run(128, levels, t(mri_case["mask"], torch.uint8), t(R), t(D), t(b), eta,
                                 L.cim_params(n_steps=steps, field=field, K=0.1, d=0.6), c, e, H=H, trace=tr,
                                 trace_steps=steps, status=status)
     torch.cuda.synchronize()
@@ -111,7 +112,7 @@ def test_mri_run_zero_steps_energy(dev, mri_case):
     c = t(c0)
     e = torch.ones_like(c)
     H = torch.empty(P, dtype=torch.float64, device=dev)
-    sig = L.l0cim_mri_mfcim_run(128, 3, t(mri_case["mask"], torch.uint8), t(R), t(D), t(z), 0.05,
+    sig = L.l0cim_mri_mfcim_run(128, 3, t(mri_case["mask"], torch.uint8), t(R), t(D), t(b), 0.05,
                                 L.cim_params(n_steps=0), c, e, H=H)
     torch.cuda.synchronize()
     sg = sig.cpu().numpy()
@@ -120,3 +121,28 @@ def test_mri_run_zero_steps_energy(dev, mri_case):
     Hs = MRI.ising_energy(op, R, z, sg, 0.5 * 0.05 ** 2)
     np.testing.assert_allclose(H.cpu().numpy(), Hs, rtol=1e-5, atol=1e-6)
     assert H.cpu().numpy()[3] == 0.0
+
+
+def test_mri_run_reads_the_gram_diagonal_in_place(dev, mri_case):
+    """D given as G itself (stride ldg + 1 over its diagonal) gives the same
+    bits as the diagonal copied out as a vector."""
+    from workloads import mri as WM
+    n, P = 128 * 128, 2
+    inst = WM.mri_instance(0)
+    A = torch.tensor(f32(inst.A), dtype=torch.float32, device=dev)
+    y = torch.tensor(f32(inst.y), dtype=torch.float32, device=dev)
+    G, b = L.l0cim_gram(A, y)
+    R = L.l0cim_init_r(G, b)
+    Dv = torch.diagonal(G).contiguous()
+    mask = torch.tensor(mri_case["mask"], dtype=torch.uint8, device=dev)
+    c0 = torch.tensor(f32(W.initial_amplitudes(2, P, n)), dtype=torch.float32, device=dev)
+    prm = L.cim_params(n_steps=50, field="BN", K=1.0, d=0.6)
+    outs = []
+    for D in (G, Dv):
+        c, e = c0.clone(), torch.ones_like(c0)
+        H = torch.empty(P, dtype=torch.float64, device=dev)
+        L.l0cim_mri_mfcim_run(128, 3, mask, R, D, b, 0.1, prm, c, e, H=H)
+        torch.cuda.synchronize()
+        outs.append((c.cpu().numpy(), e.cpu().numpy(), H.cpu().numpy()))
+    for u, v in zip(*outs):
+        assert np.array_equal(u, v)
