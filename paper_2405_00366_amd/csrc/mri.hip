@@ -204,13 +204,114 @@ __device__ __forceinline__ void dct_inv(const float (&wn)[16], float* scr_re, fl
   __builtin_amdgcn_sched_barrier(0);
 }
 
+// Inverse Haar of LV levels on the image in A, in one pass: with LV levels an
+// aligned block of 2^LV x 2^LV pixels depends only on its own coefficients
+// (at level lev, the (2^LV >> lev)/2 square of quads at block position (a, b)
+// of each subband), so a thread gathers them for each of its blocks, runs the
+// levels in registers, and after one barrier writes the pixels.
+// out(2i+p, 2j+q) = 1/2 sum (-1)^(ap+bq) c(i+ah, j+bh).
+template <int LV>
+__device__ __forceinline__ void ihaar_fused(MriLds& s, int t) {
+  constexpr int Bk = 1 << LV, NB = kS / Bk, NBLK = NB * NB;
+  constexpr int PER = (NBLK + kBS - 1) / kBS;
+  float x[PER][Bk][Bk];
+#pragma unroll
+  for (int w = 0; w < PER; ++w) {
+    const int blk = t + w * kBS;
+    if (blk >= NBLK) break;
+    const int a = blk / NB, b = blk - a * NB;
+    x[w][0][0] = s.A[a * kLd + b];
+#pragma unroll
+    for (int lev = LV - 1; lev >= 0; --lev) {
+      const int half = (Bk >> lev) / 2, hg = (kS >> lev) / 2;
+      float nx[Bk][Bk];
+#pragma unroll
+      for (int i = 0; i < half; ++i)
+#pragma unroll
+        for (int j = 0; j < half; ++j) {
+          const int gi = a * half + i, gj = b * half + j;
+          const float c00 = x[w][i][j], c01 = s.A[gi * kLd + gj + hg];
+          const float c10 = s.A[(gi + hg) * kLd + gj], c11 = s.A[(gi + hg) * kLd + gj + hg];
+          nx[2 * i][2 * j] = 0.5f * ((c00 + c10) + (c01 + c11));
+          nx[2 * i][2 * j + 1] = 0.5f * ((c00 + c10) - (c01 + c11));
+          nx[2 * i + 1][2 * j] = 0.5f * ((c00 - c10) + (c01 - c11));
+          nx[2 * i + 1][2 * j + 1] = 0.5f * ((c00 - c10) - (c01 - c11));
+        }
+#pragma unroll
+      for (int i = 0; i < 2 * half; ++i)
+#pragma unroll
+        for (int j = 0; j < 2 * half; ++j) x[w][i][j] = nx[i][j];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int w = 0; w < PER; ++w) {
+    const int blk = t + w * kBS;
+    if (blk >= NBLK) break;
+    const int a = blk / NB, b = blk - a * NB;
+#pragma unroll
+    for (int i = 0; i < Bk; ++i)
+#pragma unroll
+      for (int j = 0; j < Bk; ++j) s.A[(a * Bk + i) * kLd + b * Bk + j] = x[w][i][j];
+  }
+  __syncthreads();
+}
+
+// Haar analysis of LV levels in one pass (the inverse of ihaar_fused):
+// out(i+ah, j+bh) = 1/2 sum (-1)^(ap+bq) x(2i+p, 2j+q), level by level on the
+// block's low-pass part; after one barrier every coefficient is written where
+// it belongs.
+template <int LV>
+__device__ __forceinline__ void haar_fused(MriLds& s, int t) {
+  constexpr int Bk = 1 << LV, NB = kS / Bk, NBLK = NB * NB;
+  constexpr int PER = (NBLK + kBS - 1) / kBS;
+  float x[PER][Bk][Bk];
+#pragma unroll
+  for (int w = 0; w < PER; ++w) {
+    const int blk = t + w * kBS;
+    if (blk >= NBLK) break;
+    const int a = blk / NB, b = blk - a * NB;
+#pragma unroll
+    for (int i = 0; i < Bk; ++i)
+#pragma unroll
+      for (int j = 0; j < Bk; ++j) x[w][i][j] = s.A[(a * Bk + i) * kLd + b * Bk + j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int w = 0; w < PER; ++w) {
+    const int blk = t + w * kBS;
+    if (blk >= NBLK) break;
+    const int a = blk / NB, b = blk - a * NB;
+#pragma unroll
+    for (int lev = 0; lev < LV; ++lev) {
+      const int half = (Bk >> lev) / 2, hg = (kS >> lev) / 2;
+#pragma unroll
+      for (int i = 0; i < half; ++i)
+#pragma unroll
+        for (int j = 0; j < half; ++j) {
+          const float x00 = x[w][2 * i][2 * j], x01 = x[w][2 * i][2 * j + 1];
+          const float x10 = x[w][2 * i + 1][2 * j], x11 = x[w][2 * i + 1][2 * j + 1];
+          const int gi = a * half + i, gj = b * half + j;
+          s.A[gi * kLd + gj + hg] = 0.5f * ((x00 - x01) + (x10 - x11));
+          s.A[(gi + hg) * kLd + gj] = 0.5f * ((x00 + x01) - (x10 + x11));
+          s.A[(gi + hg) * kLd + gj + hg] = 0.5f * ((x00 - x01) - (x10 - x11));
+          x[w][i][j] = 0.5f * ((x00 + x01) + (x10 + x11));   // (i, j) <= (2i, 2j): already read
+        }
+    }
+    s.A[a * kLd + b] = x[w][0][0];
+  }
+  __syncthreads();
+}
+
 // G v for the workgroup's replica: the values u (R o x) of the thread's spins
 // go in, (Psi C^T M C Psi^T u) of the same spins comes out.  mbits: the mask
 // bits of the (kr, kc) the thread holds in the column pass.  t is the thread
 // index, passed as a value the compiler cannot see through (opaque_tid) so
 // that the few hundred LDS addresses derived from it are formed inside each
 // call rather than hoisted out of the step loop and kept live (which spilled).
-__device__ void gram_apply(MriLds& s, float (&u)[kPer], int levels, uint32_t mbits, int t) {
+__device__ void gram_apply(MriLds& s, float (&u)[kPer], int levels, uint32_t mbits, int t,
+                           const float* __restrict__ D, int64_t incd, const float* __restrict__ bv,
+                           float (&dq)[kPer], float (&zb)[kPer]) {
   const int g = t >> 3, n2 = t & 7;
   const int col = t & (kS - 1), row0 = t / kS;
   constexpr int kRowStep = kBS / kS;
@@ -218,7 +319,10 @@ __device__ void gram_apply(MriLds& s, float (&u)[kPer], int levels, uint32_t mbi
   for (int i = 0; i < kPer; ++i) s.A[(row0 + kRowStep * i) * kLd + col] = u[i];
   __syncthreads();
   // inverse Haar, coarsest level first: out(2i+p, 2j+q) = 1/2 sum (-1)^(ap+bq) c(i+ah, j+bh)
-  for (int lev = levels - 1; lev >= 0; --lev) {
+  if (levels == 3) ihaar_fused<3>(s, t);
+  else if (levels == 2) ihaar_fused<2>(s, t);
+  else if (levels == 1) ihaar_fused<1>(s, t);
+  else for (int lev = levels - 1; lev >= 0; --lev) {
     const int h = (kS >> lev) >> 1;
     float v[kQuads][4];
 #pragma unroll
@@ -301,8 +405,19 @@ __device__ void gram_apply(MriLds& s, float (&u)[kPer], int levels, uint32_t mbi
 #pragma unroll
     for (int p = 0; p < 16; ++p) s.A[(g + (kBS / 8) * rr) * kLd + perm_col(8 * brev<4>(p) + n2)] = x[rr][p];
   __syncthreads();
+  // D and b of the thread's spins for the epilogue, requested here so that
+  // their latency is spent under the Haar transform
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int r = t + kBS * i;
+    dq[i] = D[r * incd];
+    zb[i] = bv[r];
+  }
   // Haar analysis, finest level first: out(i+ah, j+bh) = 1/2 sum (-1)^(ap+bq) x(2i+p, 2j+q)
-  for (int lev = 0; lev < levels; ++lev) {
+  if (levels == 3) haar_fused<3>(s, t);
+  else if (levels == 2) haar_fused<2>(s, t);
+  else if (levels == 1) haar_fused<1>(s, t);
+  else for (int lev = 0; lev < levels; ++lev) {
     const int h = (kS >> lev) >> 1;
     float v[kQuads][4];
 #pragma unroll
@@ -400,18 +515,19 @@ mri_cim_kernel(const uint8_t* __restrict__ mask, const float* __restrict__ R, co
       const float x = bn ? (cv[i] > 0.0f ? 1.0f : 0.0f) : (cv[i] + st) * 0.25f;
       u[i] = Rv[i] * x;
     }
-    gram_apply(s, u, levels, mbits, opaque_tid());
+    float dq[kPer], zb[kPer];
+    gram_apply(s, u, levels, mbits, opaque_tid(), D, incd, b, dq, zb);
     const float lin = s.lin[k % kLinSteps];
-    // D and z are read again every step (from the caches) through an opaque
-    // index: held across the steps they would take 64 more registers
+    // D and b were read again in this step (from the caches, through an
+    // opaque index): held across the steps they would take 64 more registers
     const int tk = opaque_tid();
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
       const int r = tk + kBS * i;
       const float x = bn ? (cv[i] > 0.0f ? 1.0f : 0.0f) : (cv[i] + st) * 0.25f;
       const float Rr = Rv[i];
-      const float y = -Rr * u[i] + (D[r * incd] * Rr * Rr) * x;   // (J x)_r, zero diagonal
-      const float zr = Rr * b[r];                            // z = R o b
+      const float y = -Rr * u[i] + (dq[i] * Rr * Rr) * x;    // (J x)_r, zero diagonal
+      const float zr = Rr * zb[i];                           // z = R o b
       const float phi = bn ? half_st * (y + zr) : y + half_st * zr;
       const float inj = jj * ev[i] * (phi - theta);
       const float c2 = cv[i] * cv[i];
@@ -443,7 +559,8 @@ mri_cim_kernel(const uint8_t* __restrict__ mask, const float* __restrict__ R, co
   }
   if (bits) raise_status(status, bits);
   if (H) {
-    gram_apply(s, u, levels, mbits, opaque_tid());
+    float dq[kPer], zb[kPer];
+    gram_apply(s, u, levels, mbits, opaque_tid(), D, incd, b, dq, zb);
     const double lam = 0.5 * a.eta * a.eta;
     double hs = 0.0;
 #pragma unroll
