@@ -227,11 +227,12 @@ def factored_mri_solve(torch, L, inst, dev, cim, P, outer, seed):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     G, b = L.l0cim_gram(A, y)
-    R = L.l0cim_init_r(G, b, status=st)
+    D = torch.empty(n, device=dev)
+    R = L.l0cim_init_r(G, b, D_out=D, status=st)
     for i in range(outer):
         eta = max(0.8 * (1.0 - i / 11), 0.03)
         L.l0cim_init_state(n, P, seed, i, cim.c0_std, c, e)
-        L.l0cim_mri_mfcim_run(128, 3, mask, R, G, b, eta, cim, c, e, sigma=sig, H=H, status=st)
+        L.l0cim_mri_mfcim_run(128, 3, mask, R, D, b, eta, cim, c, e, sigma=sig, H=H, status=st)
         L.l0cim_select_replica(H, sig, sel)
         L.l0cim_update_r(G, b, sel, R, iters=100, status=st, ws=ws_j)
     L.l0cim_update_r(G, b, sel, R, cdp=L.CDP_CHOL_F64, status=st, ws=ws_c)

@@ -174,12 +174,13 @@ l0cim_status l0cim_build_couplings(l0cim_dtype dtype, int32_t n, const void* G, 
  * l0cim_init_r -- the starting amplitudes of Algorithm 1 when the caller has
  * none: R_r = b_r / G_rr, the fixed point of the CDP step (below) for an empty
  * support; r with G_rr < 1e-12 get R_r = 0 and raise status bit TINY_DIAG.
- * G: n x n (ldg >= n), b: n, R: n, all in dtype (F32 or F64); status (int32,
- * may be NULL) is OR-ed with L0CIM_ST_* bits.  l0cim_solve applies the same
- * rule where R_init is NULL.
+ * G: n x n (ldg >= n), b: n, R: n, all in dtype (F32 or F64).  D_out (n, may
+ * be NULL) receives the diagonal G_rr as a contiguous vector (for
+ * l0cim_mri_mfcim_run).  status (int32, may be NULL) is OR-ed with L0CIM_ST_*
+ * bits.  l0cim_solve applies the same rule where R_init is NULL.
  */
 l0cim_status l0cim_init_r(l0cim_dtype dtype, int32_t n, const void* G, int64_t ldg, const void* b,
-                          void* R, int32_t* status, void* stream);
+                          void* R, void* D_out, int32_t* status, void* stream);
 
 /*
  * l0cim_init_state -- initial CIM state for alternation `alt`:

@@ -114,7 +114,7 @@ def lib():
         L.l0cim_build_couplings.argtypes = [c_int, c_int32, vp, c_int64, vp, vp, c_int, vp, c_int64,
                                             vp, vp, vp]
         L.l0cim_build_couplings.restype = st
-        L.l0cim_init_r.argtypes = [c_int, c_int32, vp, c_int64, vp, vp, vp, vp]
+        L.l0cim_init_r.argtypes = [c_int, c_int32, vp, c_int64, vp, vp, vp, vp, vp]
         L.l0cim_init_r.restype = st
         L.l0cim_init_state.argtypes = [c_int, c_int32, c_int32, c_uint64, c_int32, c_double, vp, vp, vp]
         L.l0cim_init_state.restype = st
@@ -280,10 +280,10 @@ def l0cim_build_couplings(G, b, R, j_dtype: int = None, J=None, row_scale=None, 
     return J, row_scale, z
 
 
-def l0cim_init_r(G, b, R=None, status=None, stream=None):
+def l0cim_init_r(G, b, R=None, D_out=None, status=None, stream=None):
     n = G.shape[0]
     R = torch.empty(n, dtype=G.dtype, device=G.device) if R is None else R
-    _check(lib().l0cim_init_r(_dtype_code(G), n, _ptr(G), _ld(G), _ptr(b), _ptr(R), _ptr(status),
+    _check(lib().l0cim_init_r(_dtype_code(G), n, _ptr(G), _ld(G), _ptr(b), _ptr(R), _ptr(D_out), _ptr(status),
                               _stream(stream)), "l0cim_init_r")
     return R
 

@@ -243,11 +243,11 @@ l0cim_status l0cim_build_couplings(l0cim_dtype dtype, int32_t n, const void* G, 
 }
 
 l0cim_status l0cim_init_r(l0cim_dtype dtype, int32_t n, const void* G, int64_t ldg, const void* b,
-                          void* R, int32_t* status, void* stream) {
+                          void* R, void* D_out, int32_t* status, void* stream) {
   if (!is_state_dtype(dtype)) return set_error(L0CIM_ERR_UNSUPPORTED, "init_r: dtype %d", int(dtype));
   if (!G || !b || !R) return set_error(L0CIM_ERR_ARG, "init_r: NULL pointer");
   if (n <= 0 || ldg < n) return set_error(L0CIM_ERR_SHAPE, "init_r: bad shape");
-  return launch_r_init(dtype, n, G, ldg, b, nullptr, R, status, static_cast<hipStream_t>(stream));
+  return launch_r_init_diag(dtype, n, G, ldg, b, nullptr, R, D_out, status, static_cast<hipStream_t>(stream));
 }
 
 l0cim_status l0cim_init_state(l0cim_dtype dtype, int32_t n, int32_t P, uint64_t seed, int32_t alt,

@@ -118,10 +118,11 @@ init_state_kernel(int n, int P, uint64_t seed, int alt, double std, T* __restric
 template <typename T>
 __global__ void __launch_bounds__(256)
 r_init_kernel(int n, const T* __restrict__ G, int64_t ldg, const T* __restrict__ b,
-              const T* __restrict__ Rin, T* __restrict__ R, int* __restrict__ status) {
+              const T* __restrict__ Rin, T* __restrict__ R, T* __restrict__ Dout, int* __restrict__ status) {
   const int r = blockIdx.x * 256 + threadIdx.x;
   if (r >= n) return;
   const T d = G[size_t(r) * ldg + r];
+  if (Dout) Dout[r] = d;
   const bool tiny = !(d >= T(1e-12));
   if (tiny) raise_status(status, L0CIM_ST_TINY_DIAG);
   if (Rin) R[r] = tiny ? T(0) : Rin[r];
@@ -173,19 +174,24 @@ l0cim_status launch_init_state(l0cim_dtype dt, int n, int P, uint64_t seed, int 
   return L0CIM_OK;
 }
 
-l0cim_status launch_r_init(l0cim_dtype dt, int n, const void* G, int64_t ldg, const void* b,
-                           const void* R_init, void* R, int* status, hipStream_t s) {
+l0cim_status launch_r_init_diag(l0cim_dtype dt, int n, const void* G, int64_t ldg, const void* b,
+                                const void* R_init, void* R, void* D_out, int* status, hipStream_t s) {
   dim3 grid((n + 255) / 256);
   if (dt == L0CIM_F32)
     hipLaunchKernelGGL(r_init_kernel<float>, grid, dim3(256), 0, s, n, (const float*)G, ldg,
-                       (const float*)b, (const float*)R_init, (float*)R, status);
+                       (const float*)b, (const float*)R_init, (float*)R, (float*)D_out, status);
   else if (dt == L0CIM_F64)
     hipLaunchKernelGGL(r_init_kernel<double>, grid, dim3(256), 0, s, n, (const double*)G, ldg,
-                       (const double*)b, (const double*)R_init, (double*)R, status);
+                       (const double*)b, (const double*)R_init, (double*)R, (double*)D_out, status);
   else
     return set_error(L0CIM_ERR_UNSUPPORTED, "r_init: dtype %d", int(dt));
   L0_LAUNCHED("r_init_kernel");
   return L0CIM_OK;
+}
+
+l0cim_status launch_r_init(l0cim_dtype dt, int n, const void* G, int64_t ldg, const void* b,
+                           const void* R_init, void* R, int* status, hipStream_t s) {
+  return launch_r_init_diag(dt, n, G, ldg, b, R_init, R, nullptr, status, s);
 }
 
 }  // namespace l0

@@ -20,6 +20,9 @@ l0cim_status launch_mri_mfcim(int size, int levels, int P, const uint8_t* mask, 
                               uint8_t* sigma, double* H, float* trace, int* status, hipStream_t s);
 l0cim_status launch_r_init(l0cim_dtype dt, int n, const void* G, int64_t ldg, const void* b,
                            const void* R_init, void* R, int* status, hipStream_t s);
+// the same, also writing the diagonal G_rr to D_out (n, may be NULL)
+l0cim_status launch_r_init_diag(l0cim_dtype dt, int n, const void* G, int64_t ldg, const void* b,
+                                const void* R_init, void* R, void* D_out, int* status, hipStream_t s);
 
 // ---- CIM run ---------------------------------------------------------------
 size_t mfcim_ws_bytes(l0cim_dtype dt, int n, int P);

@@ -79,11 +79,11 @@ def test_gram_rejects_bad_arguments_on_host():
 
 def test_init_r_rejects_bad_arguments_on_host():
     lib = L.lib()
-    assert lib.l0cim_init_r(L.F32, 4, None, 4, FAKE, FAKE, None, None) == 1
+    assert lib.l0cim_init_r(L.F32, 4, None, 4, FAKE, FAKE, None, None, None) == 1
     assert "NULL" in _err(lib)
-    assert lib.l0cim_init_r(L.F32, 4, FAKE, 3, FAKE, FAKE, None, None) == 2
-    assert lib.l0cim_init_r(L.F64, 0, FAKE, 4, FAKE, FAKE, None, None) == 2
-    assert lib.l0cim_init_r(L.FP8E4M3, 4, FAKE, 4, FAKE, FAKE, None, None) == 5
+    assert lib.l0cim_init_r(L.F32, 4, FAKE, 3, FAKE, FAKE, None, None, None) == 2
+    assert lib.l0cim_init_r(L.F64, 0, FAKE, 4, FAKE, FAKE, None, None, None) == 2
+    assert lib.l0cim_init_r(L.FP8E4M3, 4, FAKE, 4, FAKE, FAKE, None, None, None) == 5
 
 
 def test_mri_run_rejects_bad_arguments_on_host():

@@ -159,4 +159,8 @@ def test_init_r_is_b_over_diagonal(dev, dtype):
     if dtype == torch.float32:
         want = f32(want)
     assert np.array_equal(R.double().cpu().numpy(), want)
+    Dv = torch.empty(n, dtype=dtype, device=dev)
+    L.l0cim_init_r(t(G, dtype, dev), t(b, dtype, dev), D_out=Dv)
+    torch.cuda.synchronize()
+    assert np.array_equal(Dv.double().cpu().numpy(), D)
     assert int(status.item()) == L.ST_TINY_DIAG
