@@ -120,17 +120,20 @@ __device__ __forceinline__ float dct_gain(int k) {
   return k == 0 ? 0.08838834764831845f : 0.125f;   // sqrt(1/128), sqrt(2/128)
 }
 
-// Forward orthonormal DCT-II of the 128 values at src[perm_col(m)] (one row of
-// an 8-lane group, lane n2 of the group).  scr_re / scr_im: 128 floats of
-// scratch of the group (free once the group has read its input).  Output:
-// y[h * 8 + p] = coefficient k = 2 j + h + 16 brev3(p), j = n2.
-__device__ __forceinline__ void dct_fwd(const float* src, float* scr_re, float* scr_im, int n2,
-                                        const MriLds& s, float (&y)[16]) {
+// Forward orthonormal DCT-II of two rows at once: the reordered sequences
+// v_a[m] = a[perm_col(m)], v_b[m] = b[perm_col(m)] (one 8-lane group, lane n2)
+// go through one complex FFT of z = v_a + i v_b; with Z[k] and Z[N - k],
+// V_a = (Z[k] + conj Z[N-k]) / 2 and V_b = (Z[k] - conj Z[N-k]) / 2i, and
+// y[k] = g_k Re(exp(-i pi k / 256) V[k]).  scr_re / scr_im: 128 floats of the
+// group's scratch each (the two input rows may serve, once read).  Output:
+// ya/yb[h * 8 + p] = coefficient k = 2 j + h + 16 brev3(p), j = n2.
+__device__ __forceinline__ void dct_fwd2(const float* srca, const float* srcb, float* scr_re, float* scr_im,
+                                         int n2, const MriLds& s, float (&ya)[16], float (&yb)[16]) {
   float re[16], im[16];
 #pragma unroll
   for (int n1 = 0; n1 < 16; ++n1) {
-    re[n1] = src[perm_col(8 * n1 + n2)];
-    im[n1] = 0.0f;
+    re[n1] = srca[perm_col(8 * n1 + n2)];
+    im[n1] = srcb[perm_col(8 * n1 + n2)];
   }
   wave_sync();
   dif<16, -1>(re, im);
@@ -142,6 +145,7 @@ __device__ __forceinline__ void dct_fwd(const float* src, float* scr_re, float* 
     scr_im[k1 * 8 + n2] = re[p] * t.y + im[p] * t.x;
   }
   wave_sync();
+  float zr[16], zi[16];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int k1 = 2 * n2 + h;
@@ -154,21 +158,50 @@ __device__ __forceinline__ void dct_fwd(const float* src, float* scr_re, float* 
     dif<8, -1>(r8, i8);
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
-      const int k = k1 + 16 * brev<3>(p);
-      const float2 f = s.ph[k];
-      y[h * 8 + p] = dct_gain(k) * (f.x * r8[p] - f.y * i8[p]);
+      zr[h * 8 + p] = r8[p];
+      zi[h * 8 + p] = i8[p];
     }
   }
   wave_sync();
-  __builtin_amdgcn_sched_barrier(0);   // one row at a time: keeps the working set small
+  // Z[k] of every k of the row, then each lane reads its partners Z[N - k]
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      const int k = 2 * n2 + h + 16 * brev<3>(p);
+      scr_re[k] = zr[h * 8 + p];
+      scr_im[k] = zi[h * 8 + p];
+    }
+  wave_sync();
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      const int k = 2 * n2 + h + 16 * brev<3>(p);
+      const int kp = (kS - k) & (kS - 1);
+      const float rr = scr_re[kp], ri = scr_im[kp];
+      const float Ar = 0.5f * (zr[h * 8 + p] + rr), Ai = 0.5f * (zi[h * 8 + p] - ri);
+      const float Br = 0.5f * (zi[h * 8 + p] + ri), Bi = -0.5f * (zr[h * 8 + p] - rr);
+      const float2 f = s.ph[k];
+      const float gk = dct_gain(k);
+      ya[h * 8 + p] = gk * (f.x * Ar - f.y * Ai);
+      yb[h * 8 + p] = gk * (f.x * Br - f.y * Bi);
+    }
+  wave_sync();
+  __builtin_amdgcn_sched_barrier(0);
 }
 
-// Inverse (orthonormal DCT-III) of coefficients held as wn[h * 8 + k2] =
-// coefficient k = 2 j + h + 16 k2 (natural k2), j = n2.  Output: x[p] = value
-// at position perm_col(8 brev4(p) + n2) of the row.
-__device__ __forceinline__ void dct_inv(const float (&wn)[16], float* scr_re, float* scr_im, int n2,
-                                        const MriLds& s, float (&x)[16]) {
-  wave_sync();   // the caller may have read its input from the scratch row
+// Inverse (orthonormal DCT-III) of two rows at once.  For each row the
+// coefficients y[k] and their partners y[N - k] are held as
+// w[h * 8 + k2] / wp[h * 8 + k2] for k = 2 j + h + 16 k2 (natural k2), j = n2
+// (wp of k = 0 unused).  With Z = g y, W[0] = Z[0] and
+// W[k] = exp(i pi k / 256) (Z[k] - i Z[N-k]) / 2 is Hermitian, so the inverse
+// FFT of W_a + i W_b is v_a + i v_b.  Output: xa/xb[p] = value at position
+// perm_col(8 brev4(p) + n2) of the row.
+__device__ __forceinline__ void dct_inv2(const float (&wa)[16], const float (&wpa)[16], const float (&wb)[16],
+                                         const float (&wpb)[16], float* scr_re, float* scr_im, int n2,
+                                         const MriLds& s, float (&xa)[16], float (&xb)[16]) {
+  wave_sync();   // the caller may have read its input from the scratch rows
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int k1 = 2 * n2 + h;
@@ -176,10 +209,22 @@ __device__ __forceinline__ void dct_inv(const float (&wn)[16], float* scr_re, fl
 #pragma unroll
     for (int k2 = 0; k2 < 8; ++k2) {
       const int k = k1 + 16 * k2;
-      const float2 f = s.ph[k];          // multiply by conj(f) = exp(+i pi k / 256)
-      const float v = dct_gain(k) * wn[h * 8 + k2];
-      r8[k2] = v * f.x;
-      i8[k2] = -v * f.y;
+      const int kp = (kS - k) & (kS - 1);
+      const float2 f = s.ph[k];
+      const float cx = f.x, sx = -f.y;                 // exp(+i pi k / 256)
+      const float za = dct_gain(k) * wa[h * 8 + k2], zna = dct_gain(kp) * wpa[h * 8 + k2];
+      const float zb = dct_gain(k) * wb[h * 8 + k2], znb = dct_gain(kp) * wpb[h * 8 + k2];
+      float War, Wai, Wbr, Wbi;
+      if (k == 0) {
+        War = za; Wai = 0.0f; Wbr = zb; Wbi = 0.0f;
+      } else {
+        War = 0.5f * (cx * za + sx * zna);
+        Wai = 0.5f * (sx * za - cx * zna);
+        Wbr = 0.5f * (cx * zb + sx * znb);
+        Wbi = 0.5f * (sx * zb - cx * znb);
+      }
+      r8[k2] = War - Wbi;
+      i8[k2] = Wai + Wbr;
     }
     dif<8, 1>(r8, i8);
 #pragma unroll
@@ -200,7 +245,10 @@ __device__ __forceinline__ void dct_inv(const float (&wn)[16], float* scr_re, fl
   wave_sync();
   dif<16, 1>(re, im);
 #pragma unroll
-  for (int p = 0; p < 16; ++p) x[p] = re[p];
+  for (int p = 0; p < 16; ++p) {
+    xa[p] = re[p];
+    xb[p] = im[p];
+  }
   __builtin_amdgcn_sched_barrier(0);
 }
 
@@ -350,61 +398,87 @@ __device__ void gram_apply(MriLds& s, float (&u)[kPer], int levels, uint32_t mbi
     }
     __syncthreads();
   }
-  // rows: DCT-II along each image row; the result is stored transposed in B
-  float y[kRows][16];
-#pragma unroll
-  for (int rr = 0; rr < kRows; ++rr) {
-    const int row = g + (kBS / 8) * rr;
-    dct_fwd(s.A + row * kLd, s.A + row * kLd, s.B + row * kLd, n2, s, y[rr]);
-  }
-  __syncthreads();
-#pragma unroll
-  for (int rr = 0; rr < kRows; ++rr)
+  // rows: DCT-II along each image row, rows g and g + 64 as one complex FFT;
+  // the result is stored transposed in B
+  constexpr int H = kS / 2;
+  static_assert(kBS / 8 == H, "one 8-lane group per row pair");
+  {
+    float ya[16], yb[16];
+    dct_fwd2(s.A + g * kLd, s.A + (g + H) * kLd, s.A + g * kLd, s.A + (g + H) * kLd, n2, s, ya, yb);
+    __syncthreads();
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int p = 0; p < 8; ++p)
-        s.B[(2 * n2 + h + 16 * brev<3>(p)) * kLd + g + (kBS / 8) * rr] = y[rr][h * 8 + p];
-  __syncthreads();
-  // columns (row kc of B): DCT-II, mask, DCT-III
-  float x[kRows][16];
+      for (int p = 0; p < 8; ++p) {
+        const int k = 2 * n2 + h + 16 * brev<3>(p);
+        s.B[k * kLd + g] = ya[h * 8 + p];
+        s.B[k * kLd + g + H] = yb[h * 8 + p];
+      }
+    __syncthreads();
+  }
+  // columns kc = g and g + 64 (rows of B): DCT-II, mask, DCT-III
+  {
+    float ya[16], yb[16];
+    float* ra = s.B + g * kLd;
+    float* rb = s.B + (g + H) * kLd;
+    dct_fwd2(ra, rb, ra, rb, n2, s, ya, yb);
 #pragma unroll
-  for (int rr = 0; rr < kRows; ++rr) {
-    const int kc = g + (kBS / 8) * rr;
-    float yc[16], wn[16];
-    dct_fwd(s.B + kc * kLd, s.B + kc * kLd, s.A + kc * kLd, n2, s, yc);
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int p = 0; p < 8; ++p) {
+        const int k = 2 * n2 + h + 16 * brev<3>(p);
+        ra[k] = ((mbits >> (h * 8 + p)) & 1u) ? ya[h * 8 + p] : 0.0f;
+        rb[k] = ((mbits >> (16 + h * 8 + p)) & 1u) ? yb[h * 8 + p] : 0.0f;
+      }
+    wave_sync();
+    float wa[16], wpa[16], wb[16], wpb[16];
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int k2 = 0; k2 < 8; ++k2) {
-        const int p = brev<3>(k2);
-        wn[h * 8 + k2] = ((mbits >> (16 * rr + h * 8 + p)) & 1u) ? yc[h * 8 + p] : 0.0f;
+        const int k = 2 * n2 + h + 16 * k2, kp = (kS - k) & (kS - 1);
+        wa[h * 8 + k2] = ra[k];
+        wpa[h * 8 + k2] = ra[kp];
+        wb[h * 8 + k2] = rb[k];
+        wpb[h * 8 + k2] = rb[kp];
       }
-    dct_inv(wn, s.B + kc * kLd, s.A + kc * kLd, n2, s, x[rr]);
+    float xa[16], xb[16];
+    dct_inv2(wa, wpa, wb, wpb, ra, rb, n2, s, xa, xb);
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < 16; ++p) {
+      const int r = perm_col(8 * brev<4>(p) + n2);
+      s.A[r * kLd + g] = xa[p];
+      s.A[r * kLd + g + H] = xb[p];
+    }
+    __syncthreads();
   }
-  __syncthreads();
-#pragma unroll
-  for (int rr = 0; rr < kRows; ++rr)
-#pragma unroll
-    for (int p = 0; p < 16; ++p) s.A[perm_col(8 * brev<4>(p) + n2) * kLd + g + (kBS / 8) * rr] = x[rr][p];
-  __syncthreads();
-  // rows: DCT-III along each image row (frequencies read in the inverse's input layout)
-#pragma unroll
-  for (int rr = 0; rr < kRows; ++rr) {
-    const int row = g + (kBS / 8) * rr;
-    float wn[16];
+  // rows: DCT-III along image rows g and g + 64
+  {
+    float* ra = s.A + g * kLd;
+    float* rb = s.A + (g + H) * kLd;
+    float wa[16], wpa[16], wb[16], wpb[16];
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int k2 = 0; k2 < 8; ++k2) wn[h * 8 + k2] = s.A[row * kLd + 2 * n2 + h + 16 * k2];
-    dct_inv(wn, s.A + row * kLd, s.B + row * kLd, n2, s, x[rr]);
+      for (int k2 = 0; k2 < 8; ++k2) {
+        const int k = 2 * n2 + h + 16 * k2, kp = (kS - k) & (kS - 1);
+        wa[h * 8 + k2] = ra[k];
+        wpa[h * 8 + k2] = ra[kp];
+        wb[h * 8 + k2] = rb[k];
+        wpb[h * 8 + k2] = rb[kp];
+      }
+    float xa[16], xb[16];
+    dct_inv2(wa, wpa, wb, wpb, ra, rb, n2, s, xa, xb);
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < 16; ++p) {
+      const int c = perm_col(8 * brev<4>(p) + n2);
+      ra[c] = xa[p];
+      rb[c] = xb[p];
+    }
+    __syncthreads();
   }
-  __syncthreads();
-#pragma unroll
-  for (int rr = 0; rr < kRows; ++rr)
-#pragma unroll
-    for (int p = 0; p < 16; ++p) s.A[(g + (kBS / 8) * rr) * kLd + perm_col(8 * brev<4>(p) + n2)] = x[rr][p];
-  __syncthreads();
   // D and b of the thread's spins for the epilogue, requested here so that
   // their latency is spent under the Haar transform
 #pragma unroll

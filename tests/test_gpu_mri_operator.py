@@ -7,9 +7,16 @@ Haar synthesis).  The oracle applies J with scipy's DCT and its own Haar
 transform in FP64; the device with FFT-based DCTs and its Haar transform in
 FP32.  Both sides get the same FP32 R, D = diag(A^T A), b = A^T y and c0 (z = R o b
 rounded to FP32, as the device forms it).
-Gates: normwise relative 1e-5 per Euler step over the first 200 steps for c
-and e (as for the dense couplings), sigma = H(c) of the device's own final
-state, and the eq. 4 energy of that sigma to 1e-5 relative.
+Gates: for the continuous field, normwise relative 1e-5 per Euler step over
+the first 200 steps for c and e (as for the dense couplings).  For the
+binarised field X = H(c) jumps where an amplitude crosses zero, and a
+rounding-level difference can move a crossing by one step, after which the
+two trajectories differ by more than rounding; there every device step is
+checked against the oracle's step taken from the device's previous state
+(normwise 1e-5), and crossings that land on different steps than in the
+oracle's own trajectory are counted, not gated.  Always: sigma = H(c) of the
+device's own final state, and the eq. 4 energy of that sigma to 1e-5
+relative.
 """
 import numpy as np
 import pytest
@@ -88,7 +95,18 @@ def test_mri_run_trace_parity(dev, mri_case, field, P, levels, Rkind):
     torch.cuda.synchronize()
     assert int(status.item()) == 0
     got = tr.double().cpu().numpy()
-    worst = max(normwise(got[k, v], ref[k, v]) for k in range(steps) for v in range(2))
+    if field == "CN":
+        worst = max(normwise(got[k, v], ref[k, v]) for k in range(steps) for v in range(2))
+    else:
+        worst = 0.0
+        cp, ep = c0, np.ones_like(c0)
+        for k in range(steps):
+            phi = MRI.scaled_field(op, R, z, cp, prm)
+            cn, en = O.euler_step(cp, ep, phi, O.pump(k * prm.dt, prm), eta, prm)
+            worst = max(worst, normwise(got[k, 0], cn), normwise(got[k, 1], en))
+            cp, ep = got[k, 0], got[k, 1]
+        flips = sum(int(np.sum((got[k, 0] > 0) != (ref[k, 0] > 0))) for k in range(steps))
+        print(f"binarised field: {flips} spin-steps on the other side of zero than in the oracle's trajectory")
     assert worst <= 1e-5, f"worst normwise error {worst:.3g}"
     cf = c.double().cpu().numpy()
     sg = sig.cpu().numpy()
