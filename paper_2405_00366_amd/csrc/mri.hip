@@ -14,14 +14,18 @@
 // One workgroup of 512 threads owns one replica for the whole run (512 rather
 // than 1024 so that a thread may hold 256 registers).  The image lives in LDS
 // (two 128 x 129 float buffers); thread t keeps c, e and R of spins t + 512 i,
-// i < 32, in registers, and each 8-lane group transforms two rows or columns
-// per pass.  Each length-128 DCT is the
-// length-128 complex FFT of a reordered sequence with a phase factor
-// (Makhoul's algorithm): the FFT is split 128 = 16 x 8, a 16-point DFT in the
-// registers of each of 8 lanes, a twiddle, a transpose through the row's own
-// LDS storage within the wavefront, and 8-point DFTs.  The inverse transform
-// runs the same steps backwards, so the forward output layout feeds it
-// without reordering.
+// i < 32, in registers.  The Haar transforms take one pass each (an aligned
+// 2^levels square of pixels depends only on its own coefficients).  Each
+// length-128 DCT is the length-128 complex FFT of a reordered sequence with a
+// phase factor (Makhoul's algorithm), and each 8-lane group transforms rows
+// (or columns) g and g + 64 with one FFT of v_a + i v_b: the forward results
+// are separated with Z[k] and Z[N - k]; the inverse uses the Hermitian form
+// of the coefficients, whose inverse FFT is real, so the two rows are its
+// real and imaginary parts.  The FFT is split 128 = 16 x 8: a 16-point DFT in
+// the registers of each of 8 lanes, a twiddle, a transpose through the rows'
+// own LDS storage within the wavefront, and 8-point DFTs; the inverse runs
+// the same steps backwards, so the forward output layout feeds it without
+// reordering.
 #include <cmath>
 #include <cstdint>
 
