@@ -13,7 +13,7 @@
 //
 // One workgroup of 512 threads owns one replica for the whole run (512 rather
 // than 1024 so that a thread may hold 256 registers).  The image lives in LDS
-// (two 128 x 129 float buffers); thread t keeps c, e and R of spins t + 512 i,
+// (two 128 x 136 float buffers); thread t keeps c, e and R of spins t + 512 i,
 // i < 32, in registers.  The Haar transforms take one pass each (an aligned
 // 2^levels square of pixels depends only on its own coefficients).  Each
 // length-128 DCT is the length-128 complex FFT of a reordered sequence with a
@@ -35,7 +35,12 @@ namespace l0 {
 namespace {
 
 constexpr int kS = 128;            // image side
-constexpr int kLd = kS + 1;        // LDS row stride (floats)
+// LDS row stride (floats).  The lanes of one instruction touch up to eight
+// rows (the 8-lane groups of a wavefront); with a stride of 8 mod 64 those
+// rows fall in different banks in the transposes, which were most of the
+// bank conflicts (61% of LDS cycles at a stride of 129).  Per Euler step of
+// 64 replicas on MI355X: 129 -> 27.1 us, 132 -> 27.2, 136 -> 24.2, 137 -> 26.0.
+constexpr int kLd = kS + 8;
 constexpr int kBS = 512;           // threads per workgroup
 constexpr int kPer = kS * kS / kBS; // spins per thread
 constexpr int kRows = kS / (kBS / 8);   // rows an 8-lane group transforms per pass
