@@ -299,7 +299,8 @@ l0cim_status l0cim_mri_mfcim_run(int32_t size, int32_t levels, int32_t P, const 
   if (st != L0CIM_OK) return st;
   if (!mask || !R || !D || !b || !c || !e || !sigma) return set_error(L0CIM_ERR_ARG, "mri_mfcim_run: NULL pointer");
   if (size <= 0 || P <= 0 || P > (1 << 16) || incd < 1) return set_error(L0CIM_ERR_SHAPE, "mri_mfcim_run: bad shape");
-  if (levels < 0 || (1 << levels) > size) return set_error(L0CIM_ERR_SHAPE, "mri_mfcim_run: %d Haar levels", levels);
+  if (levels < 0 || levels > 30 || (1 << levels) > size)
+    return set_error(L0CIM_ERR_SHAPE, "mri_mfcim_run: %d Haar levels", levels);
   if (trace_steps < 0 || (trace_steps > 0 && !trace))
     return set_error(L0CIM_ERR_ARG, "mri_mfcim_run: trace_steps > 0 needs a trace buffer");
   const int n = size * size;

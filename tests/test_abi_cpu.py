@@ -95,6 +95,8 @@ def test_mri_run_rejects_bad_arguments_on_host():
     assert call(mask=None) == 1
     assert call(P=0) == 2
     assert call(levels=8) == 2
+    assert call(levels=40) == 2
+    assert call(levels=-1) == 2
     assert call(ts=5) == 1
     assert call(size=64) == 5          # the 128 x 128 image only
 
