@@ -140,9 +140,19 @@ def cpu_baseline(seconds_target: float = 12.0):
             seeds += 1
         steps, sample = seeds * OUTER * STEPS, f"{seeds} whole solves (seeds 0-{seeds - 1})"
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    # the same oracle with its BLAS on one thread, on a shorter sample
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        n1 = 1
+        d1 = timed(0, n1)
+        while d1 < seconds_target / 3 and n1 < OUTER:
+            n1 = min(OUTER, 2 * n1)
+            d1 = timed(0, n1)
     return {"value": N * P * steps / dt, "unit": "spin-steps/s", "cores": int(min(threads, cores)),
             "kind": "oracle",
-            "sample": f"{sample} of the same workload ({steps} Euler steps, FP64 NumPy), {dt:.1f} s"}
+            "sample": f"{sample} of the same workload ({steps} Euler steps, FP64 NumPy), {dt:.1f} s",
+            "value_1_thread": N * P * n1 * STEPS / d1,
+            "sample_1_thread": f"seed 0, first {n1} of {OUTER} alternations with BLAS on one thread, {d1:.1f} s"}
 
 
 def step_bytes(n: int, P: int, jbytes: int) -> int:
