@@ -233,7 +233,9 @@ l0cim_status l0cim_mfcim_run(l0cim_dtype dtype, int32_t n, int32_t P, l0cim_dtyp
  * of G in place, 1 a vector), b = A^T y (from l0cim_gram; z = R o b as in
  * l0cim_build_couplings), R: n = size^2 floats; c, e: P x n floats; FP32 only.
  * size must be 128 (L0CIM_ERR_UNSUPPORTED otherwise); 2^levels <= size.  One
- * workgroup per replica holds the image in LDS; no workspace.
+ * workgroup per replica holds the image in LDS (about 158 KB, so the device
+ * needs gfx950's 160 KB per workgroup; elsewhere the launch fails with
+ * L0CIM_ERR_HIP); no workspace.
  */
 l0cim_status l0cim_mri_mfcim_run(int32_t size, int32_t levels, int32_t P, const uint8_t* mask,
                                  const float* R, const float* D, int64_t incd, const float* b,
