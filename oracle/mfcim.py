@@ -237,31 +237,38 @@ def cdp_jacobi(G, b, sigma, R, dtc: float, iters: int):
     return R, (ST_TINY_DIAG if tiny.any() else 0)
 
 
+def support_lstsq(G_SS, b_S):
+    """R_S = G_SS^{-1} b_S in FP64 through a Cholesky factor, forward then back
+    substitution.  If a pivot is <= 1e-12 * max diag(G_SS) (or the matrix is
+    not positive definite) a ridge of 1e-10 * tr(G_SS) / |S| is added and the
+    status bit ST_CHOL_RIDGE is returned.  Returns (R_S, status)."""
+    G_SS = np.asarray(G_SS, float)
+    k = G_SS.shape[0]
+    if k == 0:
+        return np.zeros(0), 0
+    st = 0
+    dmax = float(np.max(np.diag(G_SS)))
+    try:
+        L = np.linalg.cholesky(G_SS)
+        ok = float(np.min(np.diag(L))) ** 2 > 1e-12 * dmax
+    except np.linalg.LinAlgError:
+        ok = False
+    if not ok:
+        st |= ST_CHOL_RIDGE
+        L = np.linalg.cholesky(G_SS + (1e-10 * float(np.trace(G_SS)) / k) * np.eye(k))
+    w = np.linalg.solve(L, np.asarray(b_S, float))   # forward substitution
+    return np.linalg.solve(L.T, w), st                 # back substitution
+
+
 def chol_refit(G, b, sigma):
     """Least squares on the support, in FP64 through a Cholesky factor:
-    R_S = G_SS^{-1} b_S; off the support R_r = (b_r - G_rS R_S) / G_rr.
-
-    If a pivot is <= 1e-12 * max diag(G_SS) (or the matrix is not positive
-    definite) a ridge of 1e-10 * tr(G_SS) / |S| is added and the status bit
-    ST_CHOL_RIDGE is set.  Returns (R, status)."""
+    R_S = G_SS^{-1} b_S (support_lstsq, with its ridge rule); off the support
+    R_r = (b_r - G_rS R_S) / G_rr.  Returns (R, status)."""
     G = np.asarray(G, float)
     S = np.flatnonzero(np.asarray(sigma))
     D = np.diag(G)
-    st = 0
     R = np.zeros(G.shape[0])
-    if S.size:
-        GSS = G[np.ix_(S, S)]
-        dmax = float(np.max(np.diag(GSS)))
-        try:
-            L = np.linalg.cholesky(GSS)
-            ok = float(np.min(np.diag(L))) ** 2 > 1e-12 * dmax
-        except np.linalg.LinAlgError:
-            ok = False
-        if not ok:
-            st |= ST_CHOL_RIDGE
-            L = np.linalg.cholesky(GSS + (1e-10 * float(np.trace(GSS)) / S.size) * np.eye(S.size))
-        w = np.linalg.solve(L, b[S])          # forward substitution
-        R[S] = np.linalg.solve(L.T, w)         # back substitution
+    R[S], st = support_lstsq(G[np.ix_(S, S)], b[S])
     tiny = D < 1e-12
     if tiny.any():
         st |= ST_TINY_DIAG

@@ -107,14 +107,21 @@ def scaled_field(op, R, z, c, prm: O.CimParams):
     return (st / 2.0) * (coupling_apply(op, R, (c > 0).astype(float)) + z)
 
 
-def mfcim_run(op, R, z, eta, c0, e0, prm: O.CimParams):
+def mfcim_run(op, R, z, eta, c0, e0, prm: O.CimParams, trace_steps: int = 0):
+    """The Euler integration of the dense oracle's mfcim_run with the field
+    taken through the factored couplings.  Returns (c, e, trace), trace[k] =
+    (c, e) after k + 1 steps for k < trace_steps (None when trace_steps = 0)."""
     c = np.array(np.atleast_2d(c0), float)
     e = np.array(np.atleast_2d(e0), float)
+    trace = np.empty((trace_steps, 2) + c.shape) if trace_steps else None
     for k in range(prm.n_steps):
         p = O.pump(k * prm.dt, prm)
         phi = scaled_field(op, R, z, c, prm)
         c, e = O.euler_step(c, e, phi, p, eta, prm)
-    return c, e
+        if k < trace_steps:
+            trace[k, 0] = c
+            trace[k, 1] = e
+    return c, e, trace
 
 
 def ising_energy(op, R, z, sigma, lam):
@@ -139,17 +146,23 @@ def cdp_jacobi(op, b, sigma, R, dtc, iters):
 
 
 def refit(A, y, sigma):
-    """FP64 least squares on the support (columns of the dense A)."""
+    """FP64 least squares on the support from the columns of the dense A:
+    G_SS = A_S^T A_S and b_S = A_S^T y formed in FP64, then the dense
+    oracle's Cholesky solve with its ridge rule.  Returns (S, R_S, status)."""
     S = np.flatnonzero(sigma)
-    G_SS = A[:, S].T @ A[:, S]
-    b_S = A[:, S].T @ y
-    L = np.linalg.cholesky(G_SS)
-    R_S = np.linalg.solve(L.T, np.linalg.solve(L, b_S))
-    return S, R_S
+    A_S = np.asarray(A, float)[:, S]
+    R_S, st = O.support_lstsq(A_S.T @ A_S, A_S.T @ np.asarray(y, float))
+    return S, R_S, st
 
 
 def solve(op: MriOperator, y, cim: O.CimParams, outer: O.OuterParams, progress=None):
-    """Algorithm 1 with the factored couplings; returns (sigma, R, history)."""
+    """Algorithm 1 with the factored couplings; returns (sigma, R, history).
+
+    The same steps as the dense oracle's solve: R_init = b / diag(G), then per
+    alternation eta_i (eq. 22), z = R o b, the counter-generator start, the
+    MFZ-CIM run, the lowest-energy replica (eq. 4) and the Jacobi CDP.
+    history[i] holds eta, support size, H, replica, the R the run used
+    (R_in) and the selected sigma."""
     b = op.AT(y)[0]
     D = op.colnorm2
     R = np.where(D < 1e-12, 0.0, b / np.where(D < 1e-12, 1.0, D))
@@ -161,13 +174,15 @@ def solve(op: MriOperator, y, cim: O.CimParams, outer: O.OuterParams, progress=N
         lam = O.lam_from_eta(eta)
         z = R * b
         c0, e0 = _rng.initial_state(outer.seed, i, P, N, cim.c0_std)
-        c, e = mfcim_run(op, R, z, eta, c0, e0, cim)
+        c, e, _ = mfcim_run(op, R, z, eta, c0, e0, cim)
         sig = O.threshold(c)
         H = ising_energy(op, R, z, sig, lam)
         q = int(np.argmin(H))
         sigma = sig[q]
+        R_in = R
         R, _ = cdp_jacobi(op, b, sigma, R, outer.dtc, outer.cdp_iters)
-        hist.append(dict(eta=eta, support=int(sigma.sum()), H=float(H[q]), replica=q))
+        hist.append(dict(eta=eta, support=int(sigma.sum()), H=float(H[q]), replica=q,
+                         R_in=R_in, sigma=sigma.copy()))
         if progress:
-            progress(i, hist[-1])
+            progress(i, {k: v for k, v in hist[-1].items() if k not in ("R_in", "sigma")})
     return sigma, R, hist

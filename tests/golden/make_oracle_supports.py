@@ -13,7 +13,19 @@ Usage:  python tests/golden/make_oracle_supports.py {small|plain|mri} FIRST LAST
           eta 0.8 -> 0.03 over 11 alternations of 1000 steps, binarised field,
           FP64 couplings applied in factored form, FP64 refit.
 
-Each output line:  seed  support_size  rmse  hex(support bitmask, spin r = bit r)
+  batched : 16 of the 256 instances of the batched workload (batch seed 7: N
+          log-uniform in [256, 4096], alpha U[0.3, 0.7], sparsity U[0.05, 0.2],
+          noise 0.01), instances 0, 16, ..., 240; 16 replicas, eta 0.8 -> 0.18
+          over 30 alternations of 1000 steps, inputs rounded to FP32.
+          FIRST/LAST index the sample (0..15); the key is the instance index.
+  serving : 50 of the first 200 requests of the serving stream (stream seed 0:
+          N log-uniform in [512, 8192], alpha U[0.2, 0.6], sparsity U[0.05,
+          0.2], noise 0.01), requests 0, 4, ..., 196; 8 replicas, eta 0.8 ->
+          0.18 over 30 alternations of 1000 steps, inputs rounded to FP32.
+          FIRST/LAST index the sample (0..49); the key is the request index.
+
+Each output line:  key  support_size  rmse  hex(support bitmask, spin r = bit r)
+(key = seed for small / plain / mri, the instance or request index otherwise)
 
 Usage:  python tests/golden/make_oracle_supports.py mri-refit
   writes oracle_refit_mri.txt: for every seed of oracle_supports_mri.txt, the
@@ -62,17 +74,42 @@ def one_mri(seed):
     t = time.perf_counter()
     sigma, R, hist = OM.solve(op, inst.y, MRI_CIM, O.with_params(MRI_OUTER, seed=seed),
                               progress=lambda i, h: print(f"  seed {seed} alternation {i}: {h}", flush=True))
-    S, R_S = OM.refit(inst.A, inst.y, sigma)
+    S, R_S, _st = OM.refit(inst.A, inst.y, sigma)
     Rf = np.zeros(op.N)
     Rf[S] = R_S
     dt = time.perf_counter() - t
     return seed, int(sigma.sum()), O.rmse(sigma, Rf, inst.x, inst.xi), bitmask_hex(sigma), dt
 
 
+BATCH_SEED, BATCH_COUNT, BATCH_SAMPLE = 7, 256, list(range(0, 256, 16))
+SERVE_SEED, SERVE_COUNT, SERVE_SAMPLE = 0, 200, list(range(0, 200, 4))
+MULTI = {
+    "batched": dict(specs=lambda: W.batch_specs(BATCH_SEED, BATCH_COUNT), sample=BATCH_SAMPLE, replicas=16),
+    "serving": dict(specs=lambda: W.serving_specs(SERVE_SEED, SERVE_COUNT), sample=SERVE_SAMPLE, replicas=8),
+}
+
+
+def one_multi(name, key):
+    """One sampled instance of the batched or serving workload: FP32-rounded
+    inputs, 16 (batched) or 8 (serving) replicas keyed by the instance's
+    seed, 1000 steps x 30 alternations, eta 0.8 -> 0.18 (velo 30)."""
+    w = MULTI[name]
+    spec = w["specs"]()[key]
+    inst = spec.build().rounded_f32()
+    cim = O.CimParams(n_steps=1000)
+    outer = O.OuterParams(eta_init=0.8, eta_end=0.18, velo=30, n_outer=30, replicas=w["replicas"], seed=spec.seed)
+    t = time.perf_counter()
+    res = O.solve(inst.A, inst.y, cim, outer, keep_history=False)
+    dt = time.perf_counter() - t
+    return key, int(res.sigma.sum()), O.rmse(res.sigma, res.R, inst.x, inst.xi), bitmask_hex(res.sigma), dt
+
+
 def one(args):
     name, seed = args
     if name == "mri":
         return one_mri(seed)
+    if name in MULTI:
+        return one_multi(name, seed)
     w = WORKLOADS[name]
     inst = w["make"](seed)
     if w["f32"]:
@@ -99,7 +136,7 @@ def mri_refit():
             v = int(hx, 16)
             sigma = np.array([(v >> r) & 1 for r in range(inst.A.shape[1])], np.uint8)
             assert int(sigma.sum()) == int(k)
-            S, R_S = OM.refit(inst.A, inst.y, sigma)
+            S, R_S, _st = OM.refit(inst.A, inst.y, sigma)
             f.write(f"{seed} {len(S)} " + " ".join(f"{x:.12e}" for x in R_S) + "\n")
             print(f"seed {seed}: |S| = {len(S)}", flush=True)
 
@@ -114,7 +151,13 @@ def main():
     done = set()
     if os.path.exists(out):
         done = {int(l.split()[0]) for l in open(out) if l.strip() and l[0] != "#"}
-    todo = [(name, s) for s in range(first, last + 1) if s not in done]
+    if name in MULTI:
+        keys = MULTI[name]["sample"][first:last + 1]
+        specs = MULTI[name]["specs"]()
+        keys = sorted(keys, key=lambda k: -specs[k].N)     # largest first: the pool drains evenly
+    else:
+        keys = list(range(first, last + 1))
+    todo = [(name, s) for s in keys if s not in done]
     if not os.path.exists(out):
         with open(out, "w") as f:
             f.write(f"# FP64 oracle final supports, workload '{name}' (see make_oracle_supports.py)\n")

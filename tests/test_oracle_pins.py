@@ -423,3 +423,24 @@ def test_metrics_simple_cases():
     assert O.rmse(xi, x, x, xi) == 0.0
     assert O.rmse(np.zeros(4), x, x, xi) == pytest.approx(math.sqrt(5 / 4))
     assert O.hamming_loss(np.array([1, 1, 0, 0]), xi) == 0.5
+
+
+def test_threshold_heaviside_at_zero():
+    """sigma = H(c) with H(0) = 0: exactly zero (either sign) maps to 0, the
+    smallest positive and negative numbers to 1 and 0."""
+    c = np.array([0.0, -0.0, 5e-324, -5e-324, 1.0, -1.0, np.inf, -np.inf])
+    assert O.threshold(c).tolist() == [0, 0, 1, 0, 1, 0, 1, 0]
+    assert O.threshold(c).dtype == np.uint8
+
+
+def test_run_status_bits():
+    """Status of a CIM run: non-finite c or e sets bit 0 (and nothing else);
+    a finite |c| above 1e3 sets bit 1; |c| = 1e3 exactly and ordinary states
+    set none."""
+    ok = np.array([[0.5, -1.0, 1e3, -1e3]])
+    e = np.ones_like(ok)
+    assert O.run_status(ok, e) == 0
+    assert O.run_status(np.array([[0.5, 1000.5]]), np.ones((1, 2))) == O.ST_BLOWUP
+    assert O.run_status(np.array([[np.nan, 1.0]]), np.ones((1, 2))) == O.ST_NONFINITE
+    assert O.run_status(np.array([[2e3, np.inf]]), np.ones((1, 2))) == O.ST_NONFINITE
+    assert O.run_status(ok, np.array([[1.0, np.nan, 1.0, 1.0]])) == O.ST_NONFINITE

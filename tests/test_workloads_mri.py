@@ -2,8 +2,10 @@
 import math
 
 import numpy as np
+import pytest
 from scipy import fft as sfft
 
+import workloads as W
 from workloads import mri
 
 
@@ -106,8 +108,87 @@ def test_stored_oracle_refit_matches_the_stored_support():
     v = int(hx, 16)
     sigma = np.array([(v >> r) & 1 for r in range(n)], np.uint8)
     assert int(sigma.sum()) == int(k) == len(R_S)
-    S, R_new = OM.refit(inst.A, inst.y, sigma)
+    S, R_new, _st = OM.refit(inst.A, inst.y, sigma)
     np.testing.assert_allclose(R_new, R_S, rtol=1e-9, atol=1e-12)
     R = np.zeros(n)
     R[S] = R_S
     assert abs(O.rmse(sigma, R, inst.x, inst.xi) - float(rm)) <= 1e-9 * float(rm)
+
+
+def _mri16(seed=2):
+    from oracle import mri as OM
+    inst = mri.mri_instance(seed, size=16, sparseness=0.2, alpha=0.4)
+    return inst, OM.MriOperator(16, inst.meta["freqs"])
+
+
+@pytest.mark.parametrize("field", ["CN", "BN"])
+def test_factored_run_trace_equals_dense_run(field):
+    """The MRI oracle's Euler integration (factored couplings) follows the
+    dense oracle's mfcim_run step for step on a 16 x 16 instance: 400 steps,
+    three replicas, a random R, both fields."""
+    from oracle import mfcim as O
+    from oracle import mri as OM
+
+    inst, op = _mri16()
+    G, b = O.gram(inst.A, inst.y)
+    R = np.random.default_rng(7).standard_normal(256)
+    J, z = O.couplings(G, b, R)
+    prm = O.CimParams(n_steps=400, field=field, K=1.0, d=0.6)
+    c0 = W.initial_amplitudes(11, 3, 256)
+    e0 = np.ones_like(c0)
+    cd, ed, trd = O.mfcim_run(J, z, 0.3, c0, e0, prm, trace_steps=400)
+    cf, ef, trf = OM.mfcim_run(op, R, z, 0.3, c0, e0, prm, trace_steps=400)
+    for k in range(400):
+        for v in range(2):
+            err = np.max(np.abs(trf[k, v] - trd[k, v])) / np.max(np.abs(trd[k, v]))
+            assert err <= 1e-10, (k, v, err)
+    np.testing.assert_array_equal(O.threshold(cf), O.threshold(cd))
+
+
+@pytest.mark.parametrize("field", ["CN", "BN"])
+def test_factored_solve_equals_dense_solve(field):
+    """Algorithm 1 in the MRI oracle (R warm start, eta schedule, counter
+    generator, replica choice by eq. 4, Jacobi CDP) equals the dense oracle's
+    solve on the same 16 x 16 instance and seed: the same selected sigma in
+    every alternation and the same R to 1e-10."""
+    from oracle import mfcim as O
+    from oracle import mri as OM
+
+    inst, op = _mri16(3)
+    cim = O.CimParams(n_steps=1000, field=field, K=1.0, d=0.6)
+    outer = O.OuterParams(eta_init=0.8, eta_end=0.03, velo=3, n_outer=3, replicas=4, seed=5)
+    ref = O.solve(inst.A, inst.y, cim, outer)
+    sig, R, hist = OM.solve(op, inst.y, cim, outer)
+    assert len(hist) == len(ref.history) == 3
+    for i, (h, hr) in enumerate(zip(hist, ref.history)):
+        assert h["replica"] == hr["replica"], i
+        np.testing.assert_array_equal(h["sigma"], hr["sigma"], err_msg=f"alternation {i}")
+        np.testing.assert_allclose(h["R_in"], hr["R_in"], rtol=0, atol=1e-10)
+        assert h["H"] == pytest.approx(hr["H"], rel=1e-9, abs=1e-12)
+    assert 0 < int(sig.sum()) < 256
+    np.testing.assert_array_equal(sig, ref.sigma)
+    np.testing.assert_allclose(R, ref.R, rtol=0, atol=1e-10)
+
+
+def test_factored_refit_equals_dense_refit_and_ridge():
+    """The MRI oracle's refit (G_SS and b_S formed from the columns of A)
+    equals the dense oracle's Cholesky refit on the same support, and on a
+    support larger than M (G_SS singular: A A^T = I, so rank(G) = M) it takes
+    the ridge rule and raises the ridge status bit, as the dense one does."""
+    from oracle import mfcim as O
+    from oracle import mri as OM
+
+    inst, _ = _mri16(4)
+    G, b = O.gram(inst.A, inst.y)
+    sig = inst.xi.copy()
+    S, R_S, st = OM.refit(inst.A, inst.y, sig)
+    R_ref, st_ref = O.chol_refit(G, b, sig)
+    assert st == 0 and st_ref == 0
+    np.testing.assert_allclose(R_S, R_ref[S], rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(R_S, np.linalg.lstsq(inst.A[:, S], inst.y, rcond=None)[0], rtol=1e-8, atol=1e-10)
+    big = np.zeros(256, np.uint8)
+    big[: inst.A.shape[0] + 20] = 1
+    S, R_S, st = OM.refit(inst.A, inst.y, big)
+    _, st_ref = O.chol_refit(G, b, big)
+    assert st & O.ST_CHOL_RIDGE and st_ref & O.ST_CHOL_RIDGE
+    assert np.all(np.isfinite(R_S))
