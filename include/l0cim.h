@@ -324,6 +324,34 @@ l0cim_status l0cim_solve_batched(l0cim_batch_plan plan, const float* A_pool, con
                                  size_t ws_bytes, void* stream);
 
 /*
+ * Stepwise batched solve (Algorithm 1 split at its alternation boundaries):
+ * l0cim_solve_batched is exactly l0cim_batch_begin, then
+ * l0cim_batch_alternations(0, n_outer), then l0cim_batch_finish, with the same
+ * arguments.  A caller can enqueue the alternations in chunks (to time them,
+ * or to inspect R and sigma between them); the device state between two
+ * alternations is R (R_pool) and the workspace, and the next alternation
+ * starts from R alone (its initial amplitudes come from the generator).
+ *   begin:        uploads the tables, clears the stats, forms G = A^T A and
+ *                 b = A^T y and R_init = b / diag(G) for every instance (and
+ *                 times the tile shapes on the first solve of a shape class);
+ *   alternations: alternations i0 <= i < i1 (0 <= i0 <= i1 <= n_outer) of
+ *                 Algorithm 1: eta_i (eq. 22), couplings, initial state, the
+ *                 CIM run, the lowest-energy replica (eq. 4) and the Jacobi CDP;
+ *                 L0CIM_ERR_ARG for a range outside [0, n_outer] or when no
+ *                 begin was enqueued on this workspace;
+ *   finish:       the optional FP64 refit and the eq. 3 objective at
+ *                 lambda = eta_{n_outer-1}^2 / 2 into the stats.
+ * Every call must pass the pools and the workspace of the begin it follows.
+ */
+l0cim_status l0cim_batch_begin(l0cim_batch_plan plan, const float* A_pool, const float* y_pool, float* R_pool,
+                               uint8_t* sigma_pool, l0cim_stats* stats, void* ws, size_t ws_bytes, void* stream);
+l0cim_status l0cim_batch_alternations(l0cim_batch_plan plan, int32_t i0, int32_t i1, const float* A_pool,
+                                      const float* y_pool, float* R_pool, uint8_t* sigma_pool, l0cim_stats* stats,
+                                      void* ws, size_t ws_bytes, void* stream);
+l0cim_status l0cim_batch_finish(l0cim_batch_plan plan, const float* A_pool, const float* y_pool, float* R_pool,
+                                uint8_t* sigma_pool, l0cim_stats* stats, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * Serving form: continuous batching of solves over one device arena.
  *
  * A server runs Algorithm 1 (the batched form's kernels, one CIM

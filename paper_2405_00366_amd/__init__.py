@@ -24,6 +24,7 @@ __all__ = [
     "l0cim_solve_workspace_bytes", "l0cim_profile_begin", "l0cim_profile_end",
     "cim_params", "solve_params", "Instance", "l0cim_batch_plan_create", "l0cim_batch_plan_workspace_bytes",
     "l0cim_batch_plan_info", "l0cim_batch_plan_destroy", "l0cim_solve_batched", "pack_instances",
+    "l0cim_batch_begin", "l0cim_batch_alternations", "l0cim_batch_finish",
     "Completion", "l0cim_server_request_bytes", "l0cim_server_arena_overhead", "l0cim_server_create",
     "l0cim_server_clock", "l0cim_server_submit", "l0cim_server_step", "l0cim_server_completed",
     "l0cim_server_info", "l0cim_server_destroy", "l0cim_server_set_step_budget",
@@ -151,6 +152,12 @@ def lib():
         L.l0cim_batch_plan_destroy.restype = st
         L.l0cim_solve_batched.argtypes = [c_void_p, vp, vp, vp, vp, vp, vp, c_size_t, vp]
         L.l0cim_solve_batched.restype = st
+        L.l0cim_batch_begin.argtypes = [c_void_p, vp, vp, vp, vp, vp, vp, c_size_t, vp]
+        L.l0cim_batch_begin.restype = st
+        L.l0cim_batch_alternations.argtypes = [c_void_p, c_int32, c_int32, vp, vp, vp, vp, vp, vp, c_size_t, vp]
+        L.l0cim_batch_alternations.restype = st
+        L.l0cim_batch_finish.argtypes = [c_void_p, vp, vp, vp, vp, vp, vp, c_size_t, vp]
+        L.l0cim_batch_finish.restype = st
         L.l0cim_server_request_bytes.argtypes = [c_int32, c_int32, POINTER(SolveParams)]
         L.l0cim_server_request_bytes.restype = c_size_t
         L.l0cim_server_arena_overhead.argtypes = [c_int32, c_int32, POINTER(SolveParams)]
@@ -410,6 +417,24 @@ def l0cim_solve_batched(plan, A_pool, y_pool, R_pool, sigma_pool, stats, ws, str
     _check(lib().l0cim_solve_batched(plan, _ptr(A_pool), _ptr(y_pool), _ptr(R_pool), _ptr(sigma_pool),
                                      _ptr(stats), _ptr(ws), ws.numel(), _stream(stream)),
            "l0cim_solve_batched")
+
+
+def l0cim_batch_begin(plan, A_pool, y_pool, R_pool, sigma_pool, stats, ws, stream=None):
+    _check(lib().l0cim_batch_begin(plan, _ptr(A_pool), _ptr(y_pool), _ptr(R_pool), _ptr(sigma_pool),
+                                   _ptr(stats), _ptr(ws), ws.numel(), _stream(stream)),
+           "l0cim_batch_begin")
+
+
+def l0cim_batch_alternations(plan, i0: int, i1: int, A_pool, y_pool, R_pool, sigma_pool, stats, ws, stream=None):
+    _check(lib().l0cim_batch_alternations(plan, i0, i1, _ptr(A_pool), _ptr(y_pool), _ptr(R_pool),
+                                          _ptr(sigma_pool), _ptr(stats), _ptr(ws), ws.numel(), _stream(stream)),
+           "l0cim_batch_alternations")
+
+
+def l0cim_batch_finish(plan, A_pool, y_pool, R_pool, sigma_pool, stats, ws, stream=None):
+    _check(lib().l0cim_batch_finish(plan, _ptr(A_pool), _ptr(y_pool), _ptr(R_pool), _ptr(sigma_pool),
+                                    _ptr(stats), _ptr(ws), ws.numel(), _stream(stream)),
+           "l0cim_batch_finish")
 
 
 def pack_instances(As, ys, seeds, device="cuda"):

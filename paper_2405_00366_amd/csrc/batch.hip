@@ -5,9 +5,8 @@
 //   * FP32 couplings: v_mfma_f32_16x16x4_f32,
 //   * BF16 couplings: v_mfma_f32_16x16x32_bf16 (binarised field exact;
 //     continuous field as a bf16 hi + lo pair of the operand),
-//   * FP8 e4m3 couplings: v_mfma_f32_16x16x32_fp8_fp8 for the binarised field
-//     (sigma in {0,1} is exact in fp8); continuous field through the bf16 path
-//     (e4m3 values are exact in bf16),
+//   * FP8 e4m3 couplings: widened to bf16 in registers (exact: every e4m3
+//     value is a bf16 value) and multiplied on the bf16 matrix cores as above,
 // with FP32 accumulation, the per-row scale and the Euler update of eq. 12-14
 // fused into the epilogue.  One launch per Euler step covers every row tile
 // of every instance; the launches of one CIM run form a HIP graph.
@@ -37,9 +36,6 @@ __device__ inline v4f mfma_f32(float a, float b, v4f c) {
 }
 __device__ inline v4f mfma_bf16(v8bf a, v8bf b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-__device__ inline v4f mfma_fp8(long a, long b, v4f c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
 }
 
 // Field operand of a spin: (c + sqrt(tau))/4 for the continuous field,

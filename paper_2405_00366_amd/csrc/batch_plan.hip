@@ -43,6 +43,9 @@ struct l0cim_batch_plan_s {
   hipGraphExec_t exec = nullptr;
   const void* graph_ws = nullptr;
   int graph_rb = 0;
+  // workspace and tile count of the solve opened by l0cim_batch_begin
+  const void* open_ws = nullptr;
+  int open_ntiles = 0;
   // pinned staging buffer of the device tables; an upload waits for the
   // previous one to have left it before writing it again
   void* staging = nullptr;
@@ -246,6 +249,50 @@ l0cim_status autotune(l0cim_batch_plan_s* p, const BatchDev& d, const Pools& pl,
 
 }  // namespace
 
+namespace {
+
+double plan_eta(const l0cim_batch_plan_s* p, int i) {
+  double v = p->sp.eta_init * (1.0 - double(i) / double(p->sp.velo));
+  return v > p->sp.eta_end ? v : p->sp.eta_end;
+}
+
+l0cim_status check_solve_args(l0cim_batch_plan p, const float* A, const float* y, float* R, uint8_t* sigma,
+                              l0cim_stats* stats, void* ws, size_t ws_bytes, const char* who) {
+  if (!p) return set_error(L0CIM_ERR_ARG, "%s: NULL plan", who);
+  if (!A || !y || !R || !sigma || !stats) return set_error(L0CIM_ERR_ARG, "%s: NULL pointer", who);
+  if (!ws || ws_bytes < p->off.total)
+    return set_error(L0CIM_ERR_WORKSPACE, "%s: workspace needs %zu bytes", who, p->off.total);
+  return L0CIM_OK;
+}
+
+// The HIP graph of one CIM run (n_steps + 1 launches), rebuilt when the
+// workspace or the tile shape changes.
+l0cim_status ensure_graph(l0cim_batch_plan_s* p, const BatchDev& d, const void* ws, int ntiles) {
+  if (p->graph_ws == ws && p->graph_rb == p->rb && p->exec) return L0CIM_OK;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->exec = nullptr;
+  p->graph = nullptr;
+  p->graph_ws = nullptr;
+  if (!p->cap_stream) L0_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+  L0_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+  l0cim_status st = enqueue_steps(p, d, p->rb, ntiles, 0, p->cim.n_steps, p->cap_stream);
+  hipGraph_t g = nullptr;
+  hipError_t ce = hipStreamEndCapture(p->cap_stream, &g);
+  if (st != L0CIM_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+  p->graph = g;
+  L0_HIP(hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0));
+  p->graph_ws = ws;
+  p->graph_rb = p->rb;
+  return L0CIM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 l0cim_status l0cim_batch_plan_create(int32_t count, const l0cim_instance* inst, const l0cim_cim_params* cim,
@@ -380,12 +427,10 @@ l0cim_status l0cim_batch_plan_destroy(l0cim_batch_plan plan) {
   return L0CIM_OK;
 }
 
-l0cim_status l0cim_solve_batched(l0cim_batch_plan p, const float* A, const float* y, float* R, uint8_t* sigma,
-                                 l0cim_stats* stats, void* ws, size_t ws_bytes, void* stream) {
-  if (!p) return set_error(L0CIM_ERR_ARG, "solve_batched: NULL plan");
-  if (!A || !y || !R || !sigma || !stats) return set_error(L0CIM_ERR_ARG, "solve_batched: NULL pointer");
-  if (!ws || ws_bytes < p->off.total)
-    return set_error(L0CIM_ERR_WORKSPACE, "solve_batched: workspace needs %zu bytes", p->off.total);
+l0cim_status l0cim_batch_begin(l0cim_batch_plan p, const float* A, const float* y, float* R, uint8_t* sigma,
+                               l0cim_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+  l0cim_status cs = check_solve_args(p, A, y, R, sigma, stats, ws, ws_bytes, "batch_begin");
+  if (cs != L0CIM_OK) return cs;
   hipStream_t s = static_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(ws);
   BatchDev d = carve(p, base);
@@ -395,6 +440,7 @@ l0cim_status l0cim_solve_batched(l0cim_batch_plan p, const float* A, const float
     l0cim_status _s = (x);         \
     if (_s != L0CIM_OK) return _s; \
   } while (0)
+  p->open_ws = nullptr;
   int ntiles = 0;
   L0_TRY(upload_tables(p, d, pl, p->rb ? p->rb : 2, s, &ntiles));
   L0_TRY(launch_bstats_init(d, s));
@@ -406,6 +452,8 @@ l0cim_status l0cim_solve_batched(l0cim_batch_plan p, const float* A, const float
   const int64_t total_rows = p->row_prefix[p->count];
   const int64_t total_state = p->st_prefix[p->count];
   if (!p->tuned) {
+    // the candidate tiles are timed on the first alternation's state, which
+    // the real first alternation rebuilds from scratch
     L0_TRY(launch_bset_scalar(const_cast<double*>(d.eta), p->sp.eta_init, s));
     L0_TRY(launch_bcouplings(d, p->jdt, total_rows, s));
     L0_TRY(launch_binit(d, p->P, 0, p->cim.c0_std, total_state, s));
@@ -413,30 +461,29 @@ l0cim_status l0cim_solve_batched(l0cim_batch_plan p, const float* A, const float
     L0_TRY(autotune(p, d, pl, s));
   }
   L0_TRY(upload_tables(p, d, pl, p->rb, s, &ntiles));
-  // graph of one CIM run (n_steps + 1 launches), rebuilt when the workspace or tile shape changes
+  p->open_ws = ws;
+  p->open_ntiles = ntiles;
+  return L0CIM_OK;
+}
+
+l0cim_status l0cim_batch_alternations(l0cim_batch_plan p, int32_t i0, int32_t i1, const float* A, const float* y,
+                                      float* R, uint8_t* sigma, l0cim_stats* stats, void* ws, size_t ws_bytes,
+                                      void* stream) {
+  l0cim_status cs = check_solve_args(p, A, y, R, sigma, stats, ws, ws_bytes, "batch_alternations");
+  if (cs != L0CIM_OK) return cs;
+  if (p->open_ws != ws) return set_error(L0CIM_ERR_ARG, "batch_alternations: no batch_begin on this workspace");
+  if (i0 < 0 || i1 < i0 || i1 > p->sp.n_outer)
+    return set_error(L0CIM_ERR_ARG, "batch_alternations: range [%d, %d) outside [0, %d)", i0, i1, p->sp.n_outer);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  BatchDev d = carve(p, base);
+  const int ntiles = p->open_ntiles;
+  const int64_t total_rows = p->row_prefix[p->count];
+  const int64_t total_state = p->st_prefix[p->count];
   const bool use_graph = p->cim.n_steps >= 16 && !(p->sp.flags & L0CIM_SOLVE_NO_GRAPH);
-  if (use_graph && (p->graph_ws != ws || p->graph_rb != p->rb || !p->exec)) {
-    if (p->exec) (void)hipGraphExecDestroy(p->exec);
-    if (p->graph) (void)hipGraphDestroy(p->graph);
-    p->exec = nullptr;
-    p->graph = nullptr;
-    if (!p->cap_stream) L0_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
-    L0_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
-    l0cim_status st = enqueue_steps(p, d, p->rb, ntiles, 0, p->cim.n_steps, p->cap_stream);
-    hipGraph_t g = nullptr;
-    hipError_t ce = hipStreamEndCapture(p->cap_stream, &g);
-    if (st != L0CIM_OK) return st;
-    if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
-    p->graph = g;
-    L0_HIP(hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0));
-    p->graph_ws = ws;
-    p->graph_rb = p->rb;
-  }
-  double eta = p->sp.eta_init;
-  for (int i = 0; i < p->sp.n_outer; ++i) {
-    double v = p->sp.eta_init * (1.0 - double(i) / double(p->sp.velo));
-    eta = v > p->sp.eta_end ? v : p->sp.eta_end;
-    L0_TRY(launch_bset_scalar(const_cast<double*>(d.eta), eta, s));
+  if (use_graph && i1 > i0) L0_TRY(ensure_graph(p, d, ws, ntiles));
+  for (int i = i0; i < i1; ++i) {
+    L0_TRY(launch_bset_scalar(const_cast<double*>(d.eta), plan_eta(p, i), s));
     L0_TRY(launch_bcouplings(d, p->jdt, total_rows, s));
     L0_TRY(launch_binit(d, p->P, i, p->cim.c0_std, total_state, s));
     if (p->cim.field == L0CIM_FIELD_BN) L0_TRY(launch_bbits(d, p->qb, total_state / 32, s));
@@ -451,6 +498,18 @@ l0cim_status l0cim_solve_batched(l0cim_batch_plan p, const float* A, const float
     L0_TRY(launch_bselect(d, p->P, s));
     L0_TRY(launch_bjacobi(d, ntiles, 16 * p->rb, p->sp.dtc, p->sp.cdp_iters, s));
   }
+  return L0CIM_OK;
+}
+
+l0cim_status l0cim_batch_finish(l0cim_batch_plan p, const float* A, const float* y, float* R, uint8_t* sigma,
+                                l0cim_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+  l0cim_status cs = check_solve_args(p, A, y, R, sigma, stats, ws, ws_bytes, "batch_finish");
+  if (cs != L0CIM_OK) return cs;
+  if (p->open_ws != ws) return set_error(L0CIM_ERR_ARG, "batch_finish: no batch_begin on this workspace");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  BatchDev d = carve(p, base);
+  const Pools pl{base, A, y, R, sigma, stats};
   if (p->sp.final_refit_f64) {
     void* cws = base + p->off.chol;
     for (int k = 0; k < p->count; ++k) {
@@ -459,9 +518,18 @@ l0cim_status l0cim_solve_batched(l0cim_batch_plan p, const float* A, const float
                                s));
     }
   }
+  const double eta = plan_eta(p, p->sp.n_outer - 1);
   L0_TRY(launch_bobjective(d, 0.5 * eta * eta, p->cim.n_steps, p->sp.n_outer, p->P, s));
-#undef L0_TRY
   return L0CIM_OK;
 }
+
+l0cim_status l0cim_solve_batched(l0cim_batch_plan p, const float* A, const float* y, float* R, uint8_t* sigma,
+                                 l0cim_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+  L0_TRY(l0cim_batch_begin(p, A, y, R, sigma, stats, ws, ws_bytes, stream));
+  L0_TRY(l0cim_batch_alternations(p, 0, p->sp.n_outer, A, y, R, sigma, stats, ws, ws_bytes, stream));
+  L0_TRY(l0cim_batch_finish(p, A, y, R, sigma, stats, ws, ws_bytes, stream));
+  return L0CIM_OK;
+}
+#undef L0_TRY
 
 }  // extern "C"

@@ -133,3 +133,40 @@ def test_batch_narrow_couplings_match_oracle(dev, jdt, fmt, field):
         good += int(np.array_equal(sg, sig[q]) and H[q] <= H.min() + 1e-5 * max(1.0, abs(H.min())))
     # the device's G (FP32 sums) may move a rounded coupling across a tie; allow one instance
     assert good >= 3
+
+
+def test_stepwise_batched_solve_equals_one_call(dev):
+    """l0cim_batch_begin + l0cim_batch_alternations in chunks + l0cim_batch_finish
+    gives bitwise the result of l0cim_solve_batched (the same launches in the
+    same order); ranges outside [0, n_outer] and alternations on a workspace
+    with no begin are refused before anything is enqueued."""
+    specs = SPECS[:3]
+    insts = [W.gaussian_instance(s, N, M, a, 0.01).rounded_f32() for (s, N, M, a) in specs]
+
+    def pools():
+        return L.pack_instances([i.A for i in insts], [i.y for i in insts], [s for (s, *_r) in specs], device=dev)
+
+    cim = L.cim_params(n_steps=120)
+    sp = L.solve_params(eta_init=0.8, eta_end=0.4, velo=4, n_outer=4, replicas=8, j_dtype=L.F32)
+    descr, A, y, R, sig, stats = pools()
+    plan = L.l0cim_batch_plan_create(descr, cim, sp)
+    ws = L.workspace(L.l0cim_batch_plan_workspace_bytes(plan), dev)
+    L.l0cim_solve_batched(plan, A, y, R, sig, stats, ws)
+    torch.cuda.synchronize()
+    ref = (R.clone(), sig.clone(), stats.clone())
+    _, A2, y2, R2, sig2, stats2 = pools()
+    ws2 = L.workspace(L.l0cim_batch_plan_workspace_bytes(plan), dev)
+    with pytest.raises(L.L0cimError):
+        L.l0cim_batch_alternations(plan, 0, 1, A2, y2, R2, sig2, stats2, ws2)
+    L.l0cim_batch_begin(plan, A2, y2, R2, sig2, stats2, ws2)
+    with pytest.raises(L.L0cimError):
+        L.l0cim_batch_alternations(plan, 3, 5, A2, y2, R2, sig2, stats2, ws2)
+    with pytest.raises(L.L0cimError):
+        L.l0cim_batch_alternations(plan, 2, 1, A2, y2, R2, sig2, stats2, ws2)
+    L.l0cim_batch_alternations(plan, 0, 1, A2, y2, R2, sig2, stats2, ws2)
+    L.l0cim_batch_alternations(plan, 1, 1, A2, y2, R2, sig2, stats2, ws2)
+    L.l0cim_batch_alternations(plan, 1, 4, A2, y2, R2, sig2, stats2, ws2)
+    L.l0cim_batch_finish(plan, A2, y2, R2, sig2, stats2, ws2)
+    torch.cuda.synchronize()
+    L.l0cim_batch_plan_destroy(plan)
+    assert torch.equal(R2, ref[0]) and torch.equal(sig2, ref[1]) and torch.equal(stats2, ref[2])
