@@ -193,6 +193,19 @@ def oracle_threads():
     return int(min(threads, len(os.sched_getaffinity(0))))
 
 
+def calibrated_steps(timed, n0: int, n_max: int, seconds_target: float):
+    """Pick the Euler step count of a bounded oracle sample: time n0 and 3 n0
+    steps, fit t = a + b n (a: the per-sample set-up such as Gram prep and
+    CDP), and take the n that lands near `seconds_target` (capped at n_max).
+    Returns (n, seconds at n)."""
+    t1 = timed(n0)
+    t3 = timed(3 * n0)
+    per = max((t3 - t1) / (2 * n0), 1e-6)
+    fixed = max(t1 - n0 * per, 0.0)
+    n = int(max(n0, min(n_max, (seconds_target - fixed) / per)))
+    return n, timed(n)
+
+
 def batched_cpu_baseline(W, specs, sample, P, seconds_target: float = 15.0):
     """The FP64 oracle on a bounded sample of the batched workload: the first
     alternation of every sampled instance (every 16th of the batch, so the
@@ -211,10 +224,7 @@ def batched_cpu_baseline(W, specs, sample, P, seconds_target: float = 15.0):
             O.solve(insts[k].A, insts[k].y, cim, outer, keep_history=False)
         return time.perf_counter() - t
 
-    n = 20
-    dt = timed(n)
-    n = int(max(20, min(BATCH_STEPS, n * seconds_target / max(dt, 1e-3))))
-    dt = timed(n)
+    n, dt = calibrated_steps(timed, 20, BATCH_STEPS, seconds_target)
     spin = sum(specs[k].N for k in sample) * P * n
     return {"value": spin / dt, "unit": "spin-steps/s", "cores": oracle_threads(), "kind": "oracle",
             "sample": f"first alternation ({n} of {BATCH_STEPS} Euler steps, Gram prep, replica choice and "
@@ -360,7 +370,8 @@ def factored_mri_solve(torch, L, inst, dev, cim, P, outer, seed):
     """Algorithm 1 on the MRI-shaped instance with the couplings applied in
     factored form (l0cim_mri_mfcim_run), through the step-level entry points:
     Gram prep, R_init, then per alternation the initial state, the CIM run,
-    the replica choice and the Jacobi CDP on G; the FP64 Cholesky refit last."""
+    the replica choice and the Jacobi CDP on G; the FP64 Cholesky refit (G_SS
+    and b_S from A in FP64) last."""
     n = inst.N
     A = torch.tensor(inst.A, dtype=torch.float32, device=dev)
     y = torch.tensor(inst.y, dtype=torch.float32, device=dev)
@@ -374,7 +385,7 @@ def factored_mri_solve(torch, L, inst, dev, cim, P, outer, seed):
     H = torch.empty(P, dtype=torch.float64, device=dev)
     sel = torch.empty(n, dtype=torch.uint8, device=dev)
     ws_j = L.workspace(L.l0cim_update_r_workspace_bytes(L.F32, n, L.CDP_JACOBI), dev)
-    ws_c = L.workspace(L.l0cim_update_r_workspace_bytes(L.F32, n, L.CDP_CHOL_F64), dev)
+    ws_c = L.workspace(L.l0cim_refit_f64_workspace_bytes(inst.A.shape[0], n), dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     G, b = L.l0cim_gram(A, y)
@@ -386,7 +397,7 @@ def factored_mri_solve(torch, L, inst, dev, cim, P, outer, seed):
         L.l0cim_mri_mfcim_run(128, 3, mask, R, D, b, eta, cim, c, e, sigma=sig, H=H, status=st)
         L.l0cim_select_replica(H, sig, sel)
         L.l0cim_update_r(G, b, sel, R, iters=100, status=st, ws=ws_j)
-    L.l0cim_update_r(G, b, sel, R, cdp=L.CDP_CHOL_F64, status=st, ws=ws_c)
+    L.l0cim_refit_f64(A, y, sel, R, status=st, ws=ws_c)
     torch.cuda.synchronize()
     return R, sel, int(st.item()), time.perf_counter() - t0
 
@@ -444,10 +455,7 @@ def precision_cpu_baseline(P: int, seconds_target: float = 15.0):
         OM.mfcim_run(op, R, z, 0.8, c0, e0, cim)
         return time.perf_counter() - t
 
-    n = 4
-    dt = timed(n)
-    n = int(max(4, min(1000, n * seconds_target / max(dt, 1e-3))))
-    dt = timed(n)
+    n, dt = calibrated_steps(timed, 4, 1000, seconds_target)
     return {"value": op.N * P * n / dt, "unit": "spin-steps/s", "cores": oracle_threads(), "kind": "oracle",
             "sample": f"seed 0, alternation 0: {n} Euler steps of all {P} replicas (N = {op.N}), couplings applied "
                       f"in factored form (FP64 NumPy/SciPy DCT), {dt:.1f} s"}
@@ -617,10 +625,7 @@ def serving_cpu_baseline(specs, P, seconds_target: float = 15.0):
             O.solve(insts[k].A, insts[k].y, O.CimParams(n_steps=n_steps), outer, keep_history=False)
         return time.perf_counter() - t
 
-    n = 10
-    dt = timed(n)
-    n = int(max(10, min(1000, n * seconds_target / max(dt, 1e-3))))
-    dt = timed(n)
+    n, dt = calibrated_steps(timed, 10, 1000, seconds_target)
     return {"value": sum(specs[k].N for k in sample) * P * n / dt, "unit": "spin-steps/s", "cores": oracle_threads(),
             "kind": "oracle",
             "sample": f"first alternation ({n} of 1000 Euler steps) of {len(sample)} requests (every 20th), "

@@ -267,12 +267,36 @@ l0cim_status l0cim_update_r(l0cim_dtype dtype, int32_t n, const void* G, int64_t
                             void* R, int32_t* status, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * l0cim_refit_f64 -- the least-squares refit of R on support sigma (the
+ * R-minimisation of eq. 3 with sigma fixed; the final step of Algorithm 1 in
+ * the precision form), with every quantity taken from A and y in FP64:
+ *   G_SS = A_S^T A_S and b_S = A_S^T y accumulated in FP64 (products of FP32
+ *   entries are exact in FP64), R_S = G_SS^-1 b_S through an FP64 Cholesky
+ *   factor (ridge 1e-10 tr(G_SS)/|S| if a pivot is <= 1e-12 max diag, status
+ *   bit CHOL_RIDGE), and off the support R_r = a_r^T (y - A_S R_S) / a_r^T a_r,
+ *   which is (b_r - G_rS R_S) / G_rr; r with a_r^T a_r < 1e-12 is held at 0
+ *   (status bit TINY_DIAG).  Unlike l0cim_update_r(CHOL_F64), an FP32 Gram's
+ *   rounding does not enter the factor.
+ * A: m x n row-major (leading dimension lda >= n), y: m, sigma: n bytes, R:
+ * n (overwritten), all device memory of `dtype` (F32 or F64); status (device
+ * int32, may be NULL) is OR-ed.  ws: device scratch of at least
+ * l0cim_refit_f64_workspace_bytes(m, n) bytes (the padded factor,
+ * round_up(n, 64)^2 doubles).  One cooperative launch on `stream`.
+ */
+size_t l0cim_refit_f64_workspace_bytes(int32_t m, int32_t n);
+l0cim_status l0cim_refit_f64(l0cim_dtype dtype, int32_t m, int32_t n, const void* A, int64_t lda, const void* y,
+                             const uint8_t* sigma, void* R, int32_t* status, void* ws, size_t ws_bytes,
+                             void* stream);
+
+/*
  * l0cim_solve -- Algorithm 1 end to end on one instance:
  *   G, b = gram(A, y);  R = R_init (or b_r / G_rr where R_init is NULL);
  *   for i < n_outer: eta_i (eq. 22); J, z = couplings(G, b, R);
  *     init_state(seed, i); mfcim_run; select_replica (lambda_i = eta_i^2/2);
  *     update_r(JACOBI, dtc, cdp_iters);
- *   optional FP64 Cholesky refit on the final support.
+ *   optional FP64 Cholesky refit on the final support (l0cim_refit_f64: G_SS
+ *   and b_S from A and y in FP64; the same with cdp = CHOL_F64 every
+ *   alternation).
  * Outputs R_out (n, dtype), sigma_out (n bytes) and *stats (device memory).
  * A: m x n (lda >= n), y: m, R_init: n or NULL.
  */

@@ -135,6 +135,10 @@ def lib():
         L.l0cim_update_r.argtypes = [c_int, c_int32, vp, c_int64, vp, vp, c_int, c_double, c_int32,
                                      vp, vp, vp, c_size_t, vp]
         L.l0cim_update_r.restype = st
+        L.l0cim_refit_f64_workspace_bytes.argtypes = [c_int32, c_int32]
+        L.l0cim_refit_f64_workspace_bytes.restype = c_size_t
+        L.l0cim_refit_f64.argtypes = [c_int, c_int32, c_int32, vp, c_int64, vp, vp, vp, vp, vp, c_size_t, vp]
+        L.l0cim_refit_f64.restype = st
         L.l0cim_solve_workspace_bytes.argtypes = [c_int, c_int32, c_int32, POINTER(CimParams),
                                                   POINTER(SolveParams)]
         L.l0cim_solve_workspace_bytes.restype = c_size_t
@@ -354,6 +358,20 @@ def l0cim_update_r(G, b, sigma, R, cdp: int = CDP_JACOBI, dtc: float = 0.1, iter
     ws = workspace(l0cim_update_r_workspace_bytes(dt, n, cdp), G.device) if ws is None else ws
     _check(lib().l0cim_update_r(dt, n, _ptr(G), _ld(G), _ptr(b), _ptr(sigma), cdp, dtc, iters, _ptr(R),
                                 _ptr(status), _ptr(ws), ws.numel(), _stream(stream)), "l0cim_update_r")
+    return R
+
+
+def l0cim_refit_f64_workspace_bytes(m: int, n: int) -> int:
+    return lib().l0cim_refit_f64_workspace_bytes(m, n)
+
+
+def l0cim_refit_f64(A, y, sigma, R, status=None, ws=None, stream=None):
+    """FP64 least-squares refit of R on the support, G_SS and b_S from A, y."""
+    m, n = A.shape
+    dt = _dtype_code(A)
+    ws = workspace(l0cim_refit_f64_workspace_bytes(m, n), A.device) if ws is None else ws
+    _check(lib().l0cim_refit_f64(dt, m, n, _ptr(A), _ld(A), _ptr(y), _ptr(sigma), _ptr(R), _ptr(status),
+                                 _ptr(ws), ws.numel(), _stream(stream)), "l0cim_refit_f64")
     return R
 
 

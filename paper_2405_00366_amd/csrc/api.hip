@@ -158,7 +158,7 @@ SolveLayout solve_layout(l0cim_dtype dt, int m, int n, int P, l0cim_dtype jdt, b
   L.run_bytes = mfcim_ws_bytes(dt, n, P);
   L.run = take(L.run_bytes);
   L.cdp_bytes = jacobi_ws_bytes(dt, n);
-  if (chol && chol_ws_bytes(n) > L.cdp_bytes) L.cdp_bytes = chol_ws_bytes(n);
+  if (chol && chol_a_ws_bytes(n, m) > L.cdp_bytes) L.cdp_bytes = chol_a_ws_bytes(n, m);
   L.cdp = take(L.cdp_bytes);
   L.obj_bytes = objective_ws_bytes(m);
   L.obj = take(L.obj_bytes);
@@ -337,6 +337,22 @@ l0cim_status l0cim_update_r(l0cim_dtype dtype, int32_t n, const void* G, int64_t
   return launch_jacobi(dtype, n, G, ldg, b, sigma, dtc, iters, R, status, ws, ws_bytes, s, kDefaultSpinLimit);
 }
 
+size_t l0cim_refit_f64_workspace_bytes(int32_t m, int32_t n) {
+  if (m <= 0 || n <= 0) return 0;
+  return chol_a_ws_bytes(n, m);
+}
+
+l0cim_status l0cim_refit_f64(l0cim_dtype dtype, int32_t m, int32_t n, const void* A, int64_t lda, const void* y,
+                             const uint8_t* sigma, void* R, int32_t* status, void* ws, size_t ws_bytes,
+                             void* stream) {
+  if (!is_state_dtype(dtype)) return set_error(L0CIM_ERR_UNSUPPORTED, "refit_f64: dtype %d", int(dtype));
+  if (!A || !y || !sigma || !R) return set_error(L0CIM_ERR_ARG, "refit_f64: NULL pointer");
+  if (m <= 0 || n <= 0 || lda < n) return set_error(L0CIM_ERR_SHAPE, "refit_f64: bad shape");
+  const size_t need = chol_a_ws_bytes(n, m);
+  if (!ws || ws_bytes < need) return set_error(L0CIM_ERR_WORKSPACE, "refit_f64: workspace needs %zu bytes", need);
+  return launch_chol_refit_a(dtype, m, n, A, lda, y, sigma, R, status, ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
 size_t l0cim_solve_workspace_bytes(l0cim_dtype dtype, int32_t m, int32_t n, const l0cim_cim_params* cim,
                                    const l0cim_solve_params* sp) {
   (void)cim;
@@ -407,13 +423,13 @@ l0cim_status l0cim_solve(l0cim_dtype dtype, int32_t m, int32_t n, const void* A,
                         status, run_ws, L.run_bytes, s));
     L0_TRY(launch_select(n, P, H, sig, sigma_out, &stats->selected_replica, &stats->H, s));
     if (sp->cdp == L0CIM_CDP_CHOL_F64)
-      L0_TRY(launch_chol_refit(dtype, n, G, n, b, sigma_out, R_out, status, cdp_ws, L.cdp_bytes, s));
+      L0_TRY(launch_chol_refit_a(dtype, m, n, A, lda, y, sigma_out, R_out, status, cdp_ws, L.cdp_bytes, s));
     else
       L0_TRY(launch_jacobi(dtype, n, G, n, b, sigma_out, sp->dtc, sp->cdp_iters, R_out, status, cdp_ws,
                            L.cdp_bytes, s, a.spin_limit));
   }
   if (sp->final_refit_f64)
-    L0_TRY(launch_chol_refit(dtype, n, G, n, b, sigma_out, R_out, status, cdp_ws, L.cdp_bytes, s));
+    L0_TRY(launch_chol_refit_a(dtype, m, n, A, lda, y, sigma_out, R_out, status, cdp_ws, L.cdp_bytes, s));
   const int64_t spin_steps = int64_t(n) * P * cim->n_steps * sp->n_outer;
   L0_TRY(launch_objective(dtype, m, n, A, lda, y, sigma_out, R_out, 0.5 * eta * eta, stats, spin_steps,
                           sp->n_outer, obj_ws, L.obj_bytes, s));

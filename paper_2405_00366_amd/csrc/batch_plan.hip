@@ -31,7 +31,7 @@ struct l0cim_batch_plan_s {
   std::vector<PoolSlot> base;
   std::vector<int64_t> row_prefix, st_prefix;
   int64_t nG = 0, nJ = 0, nV = 0, nS = 0, nSig = 0, nW = 0, nB = 0, max_tiles = 0;
-  int max_ld = 0, max_n = 0;
+  int max_ld = 0, max_n = 0, max_m = 0;
   struct {
     size_t insts, tiles, rowp, stp, eta, G, Gc, b, z, rs, J, c, c2, e, xb, xb2, sig, hpart, jw, chol, total;
   } off{};
@@ -354,6 +354,7 @@ l0cim_status l0cim_batch_plan_create(int32_t count, const l0cim_instance* inst, 
     p->max_tiles += (b.n + 15) / 16;
     p->max_ld = b.ld > p->max_ld ? b.ld : p->max_ld;
     p->max_n = b.n > p->max_n ? b.n : p->max_n;
+    p->max_m = b.m > p->max_m ? b.m : p->max_m;
     p->row_prefix[k + 1] = p->row_prefix[k] + round_up16(b.n);
     p->st_prefix[k + 1] = p->st_prefix[k] + int64_t(p->P) * b.ld;
     p->base[k] = b;
@@ -383,7 +384,7 @@ l0cim_status l0cim_batch_plan_create(int32_t count, const l0cim_instance* inst, 
   p->off.sig = take(size_t(p->nSig));
   p->off.hpart = take(size_t(p->nSig) * sizeof(double));
   p->off.jw = take(size_t(p->nW) * 4);
-  p->off.chol = take(sp->final_refit_f64 ? chol_ws_bytes(p->max_n) : 0);
+  p->off.chol = take(sp->final_refit_f64 ? chol_a_ws_bytes(p->max_n, p->max_m) : 0);
   p->off.total = o;
   p->key = shape_key(p);
   p->staging_bytes = align_up(count * sizeof(BInst)) + align_up(size_t(p->max_tiles) * sizeof(BTile)) +
@@ -514,8 +515,8 @@ l0cim_status l0cim_batch_finish(l0cim_batch_plan p, const float* A, const float*
     void* cws = base + p->off.chol;
     for (int k = 0; k < p->count; ++k) {
       const BInst I = make_inst(p, k, pl);
-      L0_TRY(launch_chol_refit(L0CIM_F32, I.n, I.G, I.ld, I.b, I.sig, I.R, I.status, cws, chol_ws_bytes(p->max_n),
-                               s));
+      L0_TRY(launch_chol_refit_a(L0CIM_F32, I.m, I.n, I.A, I.lda, I.y, I.sig, I.R, I.status, cws,
+                                 chol_a_ws_bytes(p->max_n, p->max_m), s));
     }
   }
   const double eta = plan_eta(p, p->sp.n_outer - 1);

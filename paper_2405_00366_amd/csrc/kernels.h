@@ -48,6 +48,12 @@ size_t chol_ws_bytes(int n);
 l0cim_status launch_chol_refit(l0cim_dtype dt, int n, const void* G, int64_t ldg, const void* b,
                                const uint8_t* sigma, void* R, int* status, void* ws, size_t ws_bytes,
                                hipStream_t s);
+// the same refit with G_SS, b_S and the off-support rows formed from A (m x n)
+// and y in FP64
+size_t chol_a_ws_bytes(int n, int m);
+l0cim_status launch_chol_refit_a(l0cim_dtype dt, int m, int n, const void* A, int64_t lda, const void* y,
+                                 const uint8_t* sigma, void* R, int* status, void* ws, size_t ws_bytes,
+                                 hipStream_t s);
 
 // ---- solve epilogue ------------------------------------------------------
 size_t objective_ws_bytes(int m);

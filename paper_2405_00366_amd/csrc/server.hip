@@ -343,8 +343,8 @@ l0cim_status tick(l0cim_server_s* sv, int* n_done) {
     dr.insts = reinterpret_cast<const BInst*>(sv->arena + sv->head.rinsts);
     if (sv->sp.final_refit_f64) {
       for (int k = 0; k < nret; ++k)
-        L0_TRY(launch_chol_refit(L0CIM_F32, hr[k].n, hr[k].G, hr[k].ld, hr[k].b, hr[k].sig, hr[k].R, hr[k].status,
-                                 sv->arena + sv->head.chol, chol_ws_bytes(sv->max_n), s));
+        L0_TRY(launch_chol_refit_a(L0CIM_F32, hr[k].m, hr[k].n, hr[k].A, hr[k].lda, hr[k].y, hr[k].sig, hr[k].R,
+                                   hr[k].status, sv->arena + sv->head.chol, chol_ws_bytes(sv->max_n), s));
     }
     L0_TRY(launch_bobjective(dr, -1.0, sv->cim.n_steps, 0, sv->P, s));
     for (const Req& r : sv->active) {
@@ -461,6 +461,8 @@ l0cim_status l0cim_server_submit(l0cim_server sv, int32_t m, int32_t n, const fl
   if (!A || !y || !R_out || !sigma_out || !stats_out) return set_error(L0CIM_ERR_ARG, "server_submit: NULL pointer");
   if (m <= 0 || n <= 0 || lda < n) return set_error(L0CIM_ERR_SHAPE, "server_submit: bad shape");
   if (n > sv->max_n) return set_error(L0CIM_ERR_SHAPE, "server_submit: n = %d above the server's %d", n, sv->max_n);
+  if (sv->sp.final_refit_f64 && chol_a_ws_bytes(n, m) > chol_ws_bytes(sv->max_n))
+    return set_error(L0CIM_ERR_SHAPE, "server_submit: m = %d too large for the FP64 refit scratch", m);
   Req r{};
   r.tag = tag;
   r.m = m;

@@ -24,6 +24,15 @@ Usage:  python tests/golden/make_oracle_supports.py {small|plain|mri} FIRST LAST
           0.18 over 30 alternations of 1000 steps, inputs rounded to FP32.
           FIRST/LAST index the sample (0..49); the key is the request index.
 
+  prec_f64 | prec_bf16 | prec_fp8 : the precision-form study at the plain
+          shape (N = 2000, M = 1000, Bernoulli(0.1), noise 0.01, inputs rounded
+          to FP32), 16 replicas, eta 0.8 -> 0.18 over 30 alternations of 1000
+          steps, final FP64 refit; the CIM runs on the exact couplings
+          (prec_f64) or on the couplings as BF16 / FP8 e4m3 rows with per-row
+          scales represent them (oracle solve with j_format), so that a
+          device-vs-oracle difference can be told apart from the change the
+          narrow couplings make to the method.  Key = seed.
+
 Each output line:  key  support_size  rmse  hex(support bitmask, spin r = bit r)
 (key = seed for small / plain / mri, the instance or request index otherwise)
 
@@ -83,6 +92,20 @@ def one_mri(seed):
 
 BATCH_SEED, BATCH_COUNT, BATCH_SAMPLE = 7, 256, list(range(0, 256, 16))
 SERVE_SEED, SERVE_COUNT, SERVE_SAMPLE = 0, 200, list(range(0, 200, 4))
+PREC_CIM = O.CimParams(n_steps=1000)
+PREC_OUTER = O.OuterParams(eta_init=0.8, eta_end=0.18, velo=30, n_outer=30, replicas=16, refit=True)
+PREC_FORMATS = {"prec_f64": None, "prec_bf16": "bf16", "prec_fp8": "fp8"}
+
+
+def one_prec(name, seed):
+    inst = W.plain_gaussian(seed).rounded_f32()
+    t = time.perf_counter()
+    res = O.solve(inst.A, inst.y, PREC_CIM, O.with_params(PREC_OUTER, seed=seed), keep_history=False,
+                  j_format=PREC_FORMATS[name])
+    dt = time.perf_counter() - t
+    return seed, int(res.sigma.sum()), O.rmse(res.sigma, res.R, inst.x, inst.xi), bitmask_hex(res.sigma), dt
+
+
 MULTI = {
     "batched": dict(specs=lambda: W.batch_specs(BATCH_SEED, BATCH_COUNT), sample=BATCH_SAMPLE, replicas=16),
     "serving": dict(specs=lambda: W.serving_specs(SERVE_SEED, SERVE_COUNT), sample=SERVE_SAMPLE, replicas=8),
@@ -108,6 +131,8 @@ def one(args):
     name, seed = args
     if name == "mri":
         return one_mri(seed)
+    if name in PREC_FORMATS:
+        return one_prec(name, seed)
     if name in MULTI:
         return one_multi(name, seed)
     w = WORKLOADS[name]

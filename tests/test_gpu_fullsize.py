@@ -101,6 +101,46 @@ def _mri_golden(seed):
     return sup, R_S
 
 
+def test_mri_refit_f64_on_oracle_support(dev, mri):
+    """The FP64 refit on an ill-conditioned MRI-shaped support (the oracle's
+    final seed-0 support, |S| = 1074 of N = 16384, M = 4915).  FP64 A: R_S
+    equals the oracle's stored refit to 1e-10, and 256 sampled off-support
+    rows equal (b_r - G_rS R_S) / G_rr.  FP32 A: G_SS is formed from A in
+    FP64, so R_S is within the FP32 rounding of R of the oracle's refit on the
+    FP32-rounded A; the Cholesky CDP on the FP32 Gram is printed beside it."""
+    from oracle import mri as OM
+    inst, n = mri["inst"], mri["G"].shape[0]
+    (mask, _rm), R_S = _mri_golden(0)
+    sigma = np.array([(mask >> r) & 1 for r in range(n)], np.uint8)
+    S = np.flatnonzero(sigma)
+    sig_d = torch.from_numpy(sigma).to(dev)
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    A64 = torch.from_numpy(inst.A).to(dev)
+    R64 = torch.zeros(n, dtype=torch.float64, device=dev)
+    L.l0cim_refit_f64(A64, torch.from_numpy(inst.y).to(dev), sig_d, R64, status=st)
+    torch.cuda.synchronize()
+    del A64
+    assert int(st.item()) == 0
+    Rg = R64.cpu().numpy()
+    assert normwise(Rg[S], R_S) <= 1e-10
+    off = np.random.default_rng(1).choice(np.flatnonzero(sigma == 0), 256, replace=False)
+    fit = inst.A[:, S] @ R_S
+    Ro_off = np.array([(inst.A[:, r] @ inst.y - inst.A[:, r] @ fit) / (inst.A[:, r] @ inst.A[:, r]) for r in off])
+    assert normwise(Rg[off], Ro_off) <= 1e-10
+    # FP32 inputs
+    _, R_S32, st32 = OM.refit(mri["A"], mri["y"], sigma)
+    R32 = torch.zeros(n, dtype=torch.float32, device=dev)
+    L.l0cim_refit_f64(torch.from_numpy(mri["A"]).to(dev), torch.from_numpy(mri["y"]).to(dev), sig_d, R32)
+    Rc = torch.zeros(n, dtype=torch.float32, device=dev)
+    L.l0cim_update_r(mri["Gd"], mri["bd"], sig_d, Rc, cdp=L.CDP_CHOL_F64)
+    torch.cuda.synchronize()
+    err_a = normwise(R32.double().cpu().numpy()[S], R_S32)
+    err_g = normwise(Rc.double().cpu().numpy()[S], R_S32)
+    print(f"MRI seed-0 support: refit from A {err_a:.3g}, Cholesky CDP on the FP32 Gram {err_g:.3g} "
+          f"(normwise against the oracle's refit on the FP32-rounded A)")
+    assert st32 == 0 and err_a <= 2 ** -23
+
+
 @pytest.mark.parametrize("fmt,code", [("bf16", L.BF16), ("fp8", L.FP8E4M3)])
 def test_mri_precision_solve_outcome(dev, mri, fmt, code):
     """The whole MRI-shaped solve the benchmark times (64 replicas, 11

@@ -455,6 +455,54 @@ def test_cholesky_refit_parity_large_support(dev, n, m, density):
     assert normwise(R.cpu().numpy(), Ro) <= 1e-9
 
 
+def _refit_a(dev, A, y, sigma, dtype):
+    R = torch.zeros(A.shape[1], dtype=dtype, device=dev)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    L.l0cim_refit_f64(t(A, dtype, dev), t(y, dtype, dev), t(sigma, torch.uint8, dev), R, status=status)
+    torch.cuda.synchronize()
+    return R.double().cpu().numpy(), int(status.item())
+
+
+@pytest.mark.parametrize("n,m,density", [(300, 200, 0.1), (64, 32, 0.1), (500, 400, 0.3), (3000, 2600, 0.5),
+                                         (10, 5000, 0.5), (200, 100, 0.0)])
+def test_refit_f64_from_a_parity(dev, n, m, density):
+    """G_SS, b_S and the off-support rows from A in FP64 against the oracle's
+    refit on the Gram of the same A: FP64 inputs at 1e-10; FP32 inputs against
+    the oracle on the FP32-rounded A, bounded by the FP32 rounding of R.
+    Covers several 64-blocks with a ragged last one (|S| ~ 1500), m far above
+    the padded factor (n = 10, m = 5000) and the empty support."""
+    inst = W.gaussian_instance(900 + n, n, m, density, 0.01)
+    sigma = inst.xi
+    G, b = O.gram(inst.A, inst.y)
+    Ro, st = O.chol_refit(G, b, sigma)
+    R, status = _refit_a(dev, inst.A, inst.y, sigma, torch.float64)
+    assert status == st
+    assert normwise(R, Ro) <= 1e-10
+    A32, y32 = f32(inst.A), f32(inst.y)
+    G32, b32 = O.gram(A32, y32)
+    Ro32, _ = O.chol_refit(G32, b32, sigma)
+    R32, _ = _refit_a(dev, A32, y32, sigma, torch.float32)
+    assert np.all(np.abs(R32 - Ro32) <= 2 ** -24 * np.abs(Ro32) + 1e-12 * np.max(np.abs(Ro32)))
+
+
+def test_refit_f64_from_a_ridge_and_tiny_column(dev):
+    """A rank-deficient support (10 columns, 6 rows) takes the ridge branch on
+    both sides; an all-zero column is held at 0 with the tiny-diagonal bit."""
+    inst = W.gaussian_instance(14, 20, 6, 0.5, 0.0)
+    A = inst.A.copy()
+    A[:, 15] = 0.0
+    sigma = np.zeros(20, np.uint8)
+    sigma[:10] = 1
+    G, b = O.gram(A, inst.y)
+    Ro, st = O.chol_refit(G, b, sigma)
+    R, status = _refit_a(dev, A, inst.y, sigma, torch.float64)
+    assert st & O.ST_CHOL_RIDGE and st & O.ST_TINY_DIAG and status == st
+    assert R[15] == 0.0
+    res_g = A @ (sigma * R) - inst.y
+    res_o = A @ (sigma * Ro) - inst.y
+    assert abs(np.linalg.norm(res_g) - np.linalg.norm(res_o)) < 1e-6
+
+
 def test_cholesky_refit_ridge_on_singular_support(dev):
     inst = W.gaussian_instance(14, 20, 6, 0.5, 0.0)
     G, b = O.gram(inst.A, inst.y)
