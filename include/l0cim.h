@@ -218,6 +218,34 @@ l0cim_status l0cim_mfcim_run(l0cim_dtype dtype, int32_t n, int32_t P, l0cim_dtyp
                              int32_t* status, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * l0cim_mfcim_run_noalloc -- l0cim_mfcim_run for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments and results without
+ * ws / ws_bytes: the run's scratch (exchange words, abort word, per-workgroup
+ * energies, the streamed form's copy of c) lives in a library-owned device
+ * array of l0cim_noalloc_scratch_bytes() (8 MiB) that each device the library
+ * runs on holds until the process ends.  The call allocates and frees
+ * nothing.  The matrix-core launch form is never taken (its panel copy of J
+ * would not fit): prm->launch = MATRIX returns L0CIM_ERR_UNSUPPORTED and AUTO
+ * chooses among the other forms, which for a given problem are the ones
+ * l0cim_mfcim_run takes whenever it does not take the matrix cores, with the
+ * same bits.  A problem whose scratch exceeds the array returns
+ * L0CIM_ERR_WORKSPACE before anything is enqueued; the scratch is 16 P n
+ * bytes of exchange words (32 P n with FP64 state), 8 P n of energies and
+ * P n state values, each rounded up to 256 bytes, plus 256 (FP32, P = 1:
+ * n up to about 290 000).  Every call on one
+ * device shares that device's array and leaves its contents behind (the
+ * launch sequence itself clears what must start at zero): calls that overlap
+ * on one device race, so serialise them (one stream, or events).
+ */
+size_t l0cim_noalloc_scratch_bytes(void);
+l0cim_status l0cim_mfcim_run_noalloc(l0cim_dtype dtype, int32_t n, int32_t P, l0cim_dtype j_dtype,
+                                     const void* J, int64_t ldj, const float* row_scale, const void* z,
+                                     double eta, const l0cim_cim_params* prm, void* c, void* e,
+                                     uint8_t* sigma, double* H, void* trace, int32_t trace_steps,
+                                     int32_t* status, void* stream);
+
+/*
  * l0cim_mri_mfcim_run -- the run of l0cim_mfcim_run (same dynamics, state
  * layout, sigma, H, trace and status) for an MRI-shaped observation matrix
  * A = S C Psi^T with the couplings applied in factored form instead of a

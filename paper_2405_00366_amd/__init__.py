@@ -125,6 +125,11 @@ def lib():
                                       POINTER(CimParams), vp, vp, vp, vp, vp, c_int32, vp, vp,
                                       c_size_t, vp]
         L.l0cim_mfcim_run.restype = st
+        L.l0cim_noalloc_scratch_bytes.argtypes = []
+        L.l0cim_noalloc_scratch_bytes.restype = c_size_t
+        L.l0cim_mfcim_run_noalloc.argtypes = [c_int, c_int32, c_int32, c_int, vp, c_int64, vp, vp, c_double,
+                                              POINTER(CimParams), vp, vp, vp, vp, vp, c_int32, vp, vp]
+        L.l0cim_mfcim_run_noalloc.restype = st
         L.l0cim_mri_mfcim_run.argtypes = [c_int32, c_int32, c_int32, vp, vp, vp, c_int64, vp, c_double,
                                           POINTER(CimParams), vp, vp, vp, vp, vp, c_int32, vp, vp]
         L.l0cim_mri_mfcim_run.restype = st
@@ -324,6 +329,22 @@ def l0cim_mfcim_run(J, z, eta: float, prm: CimParams, c, e, sigma=None, H=None, 
                                  ctypes.byref(prm), _ptr(c), _ptr(e), _ptr(sigma), _ptr(H),
                                  _ptr(trace), trace_steps, _ptr(status), _ptr(ws), ws.numel(),
                                  _stream(stream)), "l0cim_mfcim_run")
+    return sigma
+
+
+def l0cim_mfcim_run_noalloc(J, z, eta: float, prm: CimParams, c, e, sigma, H=None, trace=None,
+                            trace_steps: int = 0, row_scale=None, status=None, j_dtype: int = None, stream=None):
+    """l0cim_mfcim_run on the library's own device scratch: nothing is
+    allocated here or in the library (sigma is the caller's)."""
+    P, n = c.shape
+    dt = _dtype_code(c)
+    if j_dtype is None:
+        j_dtype = {torch.float32: F32, torch.float64: F64, torch.bfloat16: BF16,
+                   torch.float8_e4m3fn: FP8E4M3}[J.dtype]
+    _check(lib().l0cim_mfcim_run_noalloc(dt, n, P, j_dtype, _ptr(J), _ld(J), _ptr(row_scale), _ptr(z), eta,
+                                         ctypes.byref(prm), _ptr(c), _ptr(e), _ptr(sigma), _ptr(H),
+                                         _ptr(trace), trace_steps, _ptr(status), _stream(stream)),
+           "l0cim_mfcim_run_noalloc")
     return sigma
 
 

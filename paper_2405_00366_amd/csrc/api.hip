@@ -167,6 +167,30 @@ SolveLayout solve_layout(l0cim_dtype dt, int m, int n, int P, l0cim_dtype jdt, b
 }
 
 }  // namespace
+
+l0cim_status mfcim_run_checked(l0cim_dtype dtype, int n, int P, l0cim_dtype j_dtype, const void* J, int64_t ldj,
+                               const float* row_scale, const void* z, double eta, const l0cim_cim_params* prm,
+                               void* c, void* e, uint8_t* sigma, double* H, void* trace, int trace_steps,
+                               int* status, void* ws, size_t ws_bytes, bool allow_matrix, hipStream_t s) {
+  if (!is_state_dtype(dtype)) return set_error(L0CIM_ERR_UNSUPPORTED, "mfcim_run: dtype %d", int(dtype));
+  l0cim_status st = check_jdtype(dtype, j_dtype);
+  if (st != L0CIM_OK) return st;
+  st = check_cim(prm);
+  if (st != L0CIM_OK) return st;
+  if (!J || !z || !c || !e || !sigma) return set_error(L0CIM_ERR_ARG, "mfcim_run: NULL pointer");
+  if ((j_dtype == L0CIM_BF16 || j_dtype == L0CIM_FP8E4M3) && !row_scale)
+    return set_error(L0CIM_ERR_ARG, "mfcim_run: row_scale required for BF16/FP8");
+  if (n <= 0 || P <= 0 || ldj < n) return set_error(L0CIM_ERR_SHAPE, "mfcim_run: bad shape");
+  if (trace_steps < 0 || (trace_steps > 0 && !trace))
+    return set_error(L0CIM_ERR_ARG, "mfcim_run: trace_steps > 0 needs a trace buffer");
+  const size_t need = allow_matrix ? mfcim_ws_bytes(dtype, n, P) : mfcim_base_ws_bytes(dtype, n, P);
+  if (!ws || ws_bytes < need) return set_error(L0CIM_ERR_WORKSPACE, "mfcim_run: workspace needs %zu bytes", need);
+  CimArgs a = make_args(n, P, prm, eta, trace_steps < prm->n_steps ? trace_steps : prm->n_steps);
+  return launch_mfcim(dtype, n, P, j_dtype, J, ldj,
+                      j_dtype == L0CIM_F32 || j_dtype == L0CIM_F64 ? nullptr : row_scale, z, a, c, e, sigma, H,
+                      trace, status, ws, ws_bytes, s, allow_matrix);
+}
+
 }  // namespace l0
 
 using namespace l0;
@@ -271,23 +295,8 @@ l0cim_status l0cim_mfcim_run(l0cim_dtype dtype, int32_t n, int32_t P, l0cim_dtyp
                              double eta, const l0cim_cim_params* prm, void* c, void* e,
                              uint8_t* sigma, double* H, void* trace, int32_t trace_steps,
                              int32_t* status, void* ws, size_t ws_bytes, void* stream) {
-  if (!is_state_dtype(dtype)) return set_error(L0CIM_ERR_UNSUPPORTED, "mfcim_run: dtype %d", int(dtype));
-  l0cim_status st = check_jdtype(dtype, j_dtype);
-  if (st != L0CIM_OK) return st;
-  st = check_cim(prm);
-  if (st != L0CIM_OK) return st;
-  if (!J || !z || !c || !e || !sigma) return set_error(L0CIM_ERR_ARG, "mfcim_run: NULL pointer");
-  if ((j_dtype == L0CIM_BF16 || j_dtype == L0CIM_FP8E4M3) && !row_scale)
-    return set_error(L0CIM_ERR_ARG, "mfcim_run: row_scale required for BF16/FP8");
-  if (n <= 0 || P <= 0 || ldj < n) return set_error(L0CIM_ERR_SHAPE, "mfcim_run: bad shape");
-  if (trace_steps < 0 || (trace_steps > 0 && !trace))
-    return set_error(L0CIM_ERR_ARG, "mfcim_run: trace_steps > 0 needs a trace buffer");
-  if (!ws || ws_bytes < mfcim_ws_bytes(dtype, n, P))
-    return set_error(L0CIM_ERR_WORKSPACE, "mfcim_run: workspace needs %zu bytes",
-                     mfcim_ws_bytes(dtype, n, P));
-  CimArgs a = make_args(n, P, prm, eta, trace_steps < prm->n_steps ? trace_steps : prm->n_steps);
-  return launch_mfcim(dtype, n, P, j_dtype, J, ldj, j_dtype == L0CIM_F32 || j_dtype == L0CIM_F64 ? nullptr : row_scale,
-                      z, a, c, e, sigma, H, trace, status, ws, ws_bytes, static_cast<hipStream_t>(stream));
+  return mfcim_run_checked(dtype, n, P, j_dtype, J, ldj, row_scale, z, eta, prm, c, e, sigma, H, trace, trace_steps,
+                           status, ws, ws_bytes, true, static_cast<hipStream_t>(stream));
 }
 
 l0cim_status l0cim_mri_mfcim_run(int32_t size, int32_t levels, int32_t P, const uint8_t* mask,

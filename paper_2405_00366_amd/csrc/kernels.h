@@ -26,11 +26,20 @@ l0cim_status launch_r_init_diag(l0cim_dtype dt, int n, const void* G, int64_t ld
 
 // ---- CIM run ---------------------------------------------------------------
 size_t mfcim_ws_bytes(l0cim_dtype dt, int n, int P);
+// the part of a run's workspace the launches other than the matrix-core form use
+size_t mfcim_base_ws_bytes(l0cim_dtype dt, int n, int P);
 size_t matrix_ws_offset(int n, int P);
+// allow_matrix = false never takes the matrix-core form (whose panel copy of J
+// lives past mfcim_base_ws_bytes in the workspace)
 l0cim_status launch_mfcim(l0cim_dtype dt, int n, int P, l0cim_dtype jdt, const void* J, int64_t ldj,
                           const float* rscale, const void* z, const CimArgs& a, void* c, void* e,
                           uint8_t* sigma, double* H, void* trace, int* status, void* ws,
-                          size_t ws_bytes, hipStream_t s);
+                          size_t ws_bytes, hipStream_t s, bool allow_matrix = true);
+// argument checks of l0cim_mfcim_run, then the run on workspace ws
+l0cim_status mfcim_run_checked(l0cim_dtype dtype, int n, int P, l0cim_dtype j_dtype, const void* J, int64_t ldj,
+                               const float* row_scale, const void* z, double eta, const l0cim_cim_params* prm,
+                               void* c, void* e, uint8_t* sigma, double* H, void* trace, int trace_steps,
+                               int* status, void* ws, size_t ws_bytes, bool allow_matrix, hipStream_t s);
 size_t matrix_ws_bytes(int n, int P, size_t jsize);
 bool matrix_supported(int n, int P, int64_t ldj);
 l0cim_status launch_matrix_run(int n, int P, l0cim_dtype jdt, const void* J, int64_t ldj, const float* rscale,

@@ -506,7 +506,7 @@ RunWs carve_run_ws(void* ws, int n, int P) {
 template <typename T, typename JT, int FIELD>
 l0cim_status run_typed(int n, int P, const JT* J, int64_t ldj, const float* rscale, const T* z,
                        const CimArgs& a, T* c, T* e, uint8_t* sigma, double* H, T* trace,
-                       int* status, void* ws, hipStream_t s) {
+                       int* status, void* ws, bool allow_matrix, hipStream_t s) {
   DeviceInfo dev;
   l0cim_status st = device_info(&dev);
   if (st != L0CIM_OK) return st;
@@ -522,8 +522,8 @@ l0cim_status run_typed(int n, int P, const JT* J, int64_t ldj, const float* rsca
   if constexpr (sizeof(T) == 4) {
     const bool small = n <= 256 && resident_layout<T, JT>(n, P, n).total <= size_t(dev.max_lds);
     const bool lds_fits = resident_layout<T, JT>(n, P, rpw_cu).total <= size_t(dev.max_lds);
-    const bool want = a.launch == L0CIM_LAUNCH_MATRIX ||
-                      (a.launch == L0CIM_LAUNCH_AUTO && P >= 2 && !small && !(lds_fits && P <= 4));
+    const bool want = allow_matrix && (a.launch == L0CIM_LAUNCH_MATRIX ||
+                                       (a.launch == L0CIM_LAUNCH_AUTO && P >= 2 && !small && !(lds_fits && P <= 4)));
     if (want) {
       l0cim_dtype jdt = std::is_same<JT, float>::value ? L0CIM_F32
                         : (sizeof(JT) == 2 ? L0CIM_BF16 : L0CIM_FP8E4M3);
@@ -641,15 +641,15 @@ l0cim_status run_typed(int n, int P, const JT* J, int64_t ldj, const float* rsca
 template <typename T, typename JT>
 l0cim_status run_field(int n, int P, const void* J, int64_t ldj, const float* rscale, const void* z,
                        const CimArgs& a, void* c, void* e, uint8_t* sigma, double* H, void* trace,
-                       int* status, void* ws, hipStream_t s) {
+                       int* status, void* ws, bool allow_matrix, hipStream_t s) {
   auto Jp = static_cast<const JT*>(J);
   auto zp = static_cast<const T*>(z);
   auto cp = static_cast<T*>(c);
   auto ep = static_cast<T*>(e);
   auto tp = static_cast<T*>(trace);
   if (a.field == L0CIM_FIELD_BN)
-    return run_typed<T, JT, kBN>(n, P, Jp, ldj, rscale, zp, a, cp, ep, sigma, H, tp, status, ws, s);
-  return run_typed<T, JT, kCN>(n, P, Jp, ldj, rscale, zp, a, cp, ep, sigma, H, tp, status, ws, s);
+    return run_typed<T, JT, kBN>(n, P, Jp, ldj, rscale, zp, a, cp, ep, sigma, H, tp, status, ws, allow_matrix, s);
+  return run_typed<T, JT, kCN>(n, P, Jp, ldj, rscale, zp, a, cp, ep, sigma, H, tp, status, ws, allow_matrix, s);
 }
 
 }  // namespace
@@ -657,17 +657,17 @@ l0cim_status run_field(int n, int P, const void* J, int64_t ldj, const float* rs
 // Workspace of a run: the exchange words, the abort word, per-workgroup
 // energies and the streamed ping-pong copy, followed (FP32 state) by the
 // matrix-core run's tables and padded state.
-static size_t base_ws_bytes(l0cim_dtype dt, int n, int P) {
+size_t mfcim_base_ws_bytes(l0cim_dtype dt, int n, int P) {
   size_t ts = dtype_size(dt);
   size_t words = (dt == L0CIM_F64) ? 2 : 1;
   return align_up(size_t(2) * P * n * words * sizeof(uint64_t)) + kAlign +
          align_up(size_t(n) * P * sizeof(double)) + align_up(size_t(P) * n * ts);
 }
 
-size_t matrix_ws_offset(int n, int P) { return base_ws_bytes(L0CIM_F32, n, P); }
+size_t matrix_ws_offset(int n, int P) { return mfcim_base_ws_bytes(L0CIM_F32, n, P); }
 
 size_t mfcim_ws_bytes(l0cim_dtype dt, int n, int P) {
-  size_t b = base_ws_bytes(dt, n, P);
+  size_t b = mfcim_base_ws_bytes(dt, n, P);
   if (dt == L0CIM_F32 && P <= 64) b += matrix_ws_bytes(n, P, 4);
   return b;
 }
@@ -675,22 +675,23 @@ size_t mfcim_ws_bytes(l0cim_dtype dt, int n, int P) {
 l0cim_status launch_mfcim(l0cim_dtype dt, int n, int P, l0cim_dtype jdt, const void* J, int64_t ldj,
                           const float* rscale, const void* z, const CimArgs& a, void* c, void* e,
                           uint8_t* sigma, double* H, void* trace, int* status, void* ws,
-                          size_t ws_bytes, hipStream_t s) {
+                          size_t ws_bytes, hipStream_t s, bool allow_matrix) {
   (void)ws_bytes;
+  const bool am = allow_matrix;
   if (dt == L0CIM_F32) {
     switch (jdt) {
       case L0CIM_F32:
-        return run_field<float, float>(n, P, J, ldj, rscale, z, a, c, e, sigma, H, trace, status, ws, s);
+        return run_field<float, float>(n, P, J, ldj, rscale, z, a, c, e, sigma, H, trace, status, ws, am, s);
       case L0CIM_BF16:
         return run_field<float, __hip_bfloat16>(n, P, J, ldj, rscale, z, a, c, e, sigma, H, trace,
-                                                status, ws, s);
+                                                status, ws, am, s);
       case L0CIM_FP8E4M3:
         return run_field<float, __hip_fp8_e4m3>(n, P, J, ldj, rscale, z, a, c, e, sigma, H, trace,
-                                                status, ws, s);
+                                                status, ws, am, s);
       default: break;
     }
   } else if (dt == L0CIM_F64 && jdt == L0CIM_F64) {
-    return run_field<double, double>(n, P, J, ldj, rscale, z, a, c, e, sigma, H, trace, status, ws, s);
+    return run_field<double, double>(n, P, J, ldj, rscale, z, a, c, e, sigma, H, trace, status, ws, am, s);
   }
   return set_error(L0CIM_ERR_UNSUPPORTED, "mfcim_run: dtype %d with coupling dtype %d", int(dt), int(jdt));
 }
