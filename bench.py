@@ -16,7 +16,9 @@ Prints one JSON line.
              alternations, FP32 (one step = one whole solve);
   precision  the MRI-shaped instance (N = 16384, M = 4915), 64 replicas,
              BF16 or FP8 couplings (--jdtype), FP64 refit, 1000 x 11, or the
-             couplings applied in factored form (--jdtype factored);
+             couplings applied in factored form (--jdtype factored), or the
+             paper's MRI pipeline around it (--jdtype pipeline: L2 term,
+             LASSO start, CG CDP);
   serving    a stream of Gaussian requests (N log-uniform in [512, 8192]),
              8 replicas, 1000 x 30, served by the continuous-batching server
              at saturation and at Poisson arrival rates below it, beside the
@@ -366,40 +368,35 @@ def batched_bench(args, torch, L, W, dev):
     return out
 
 
-def factored_mri_solve(torch, L, inst, dev, cim, P, outer, seed):
+MRI_PIPELINE = dict(gamma=1e-4, lasso_iters=200, lasso_lam1=3e-4, cg_max_iter=10000, cg_tol=1e-5)
+
+
+def factored_mri_solve(torch, L, inst, dev, cim, P, outer, seed, pipeline=False):
     """Algorithm 1 on the MRI-shaped instance with the couplings applied in
-    factored form (l0cim_mri_mfcim_run), through the step-level entry points:
-    Gram prep, R_init, then per alternation the initial state, the CIM run,
-    the replica choice and the Jacobi CDP on G; the FP64 Cholesky refit (G_SS
-    and b_S from A in FP64) last."""
+    factored form, one call of l0cim_mri_solve: b and diag(A^T A) from A,
+    R_init, then per alternation the initial state, the factored run, the
+    replica choice and the CDP.  Plain: R_init = b / D, Jacobi CDP in factored
+    form, FP64 refit (G_SS and b_S from A).  Pipeline: the L2 term of eq. 20
+    (gamma = 1e-4), the LASSO start and the CG CDP, no refit."""
     n = inst.N
     A = torch.tensor(inst.A, dtype=torch.float32, device=dev)
     y = torch.tensor(inst.y, dtype=torch.float32, device=dev)
     mask_h = np.zeros(n, np.uint8)
     mask_h[inst.meta["freqs"]] = 1
     mask = torch.from_numpy(mask_h).to(dev)
-    st = torch.zeros(1, dtype=torch.int32, device=dev)
-    c = torch.empty((P, n), device=dev)
-    e = torch.empty_like(c)
-    sig = torch.empty((P, n), dtype=torch.uint8, device=dev)
-    H = torch.empty(P, dtype=torch.float64, device=dev)
-    sel = torch.empty(n, dtype=torch.uint8, device=dev)
-    ws_j = L.workspace(L.l0cim_update_r_workspace_bytes(L.F32, n, L.CDP_JACOBI), dev)
-    ws_c = L.workspace(L.l0cim_refit_f64_workspace_bytes(inst.A.shape[0], n), dev)
+    if pipeline:
+        mp = L.mri_params(cdp=L.CDP_CG, **MRI_PIPELINE)
+    else:
+        mp = L.mri_params()
+    sp = L.solve_params(eta_init=0.8, eta_end=0.03, velo=11, n_outer=outer, replicas=P, seed=seed,
+                        final_refit_f64=0 if pipeline else 1)
+    ws = L.workspace(L.lib().l0cim_mri_solve_workspace_bytes(A.shape[0], P, sp.final_refit_f64), dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    G, b = L.l0cim_gram(A, y)
-    D = torch.empty(n, device=dev)
-    R = L.l0cim_init_r(G, b, D_out=D, status=st)
-    for i in range(outer):
-        eta = max(0.8 * (1.0 - i / 11), 0.03)
-        L.l0cim_init_state(n, P, seed, i, cim.c0_std, c, e)
-        L.l0cim_mri_mfcim_run(128, 3, mask, R, D, b, eta, cim, c, e, sigma=sig, H=H, status=st)
-        L.l0cim_select_replica(H, sig, sel)
-        L.l0cim_update_r(G, b, sel, R, iters=100, status=st, ws=ws_j)
-    L.l0cim_refit_f64(A, y, sel, R, status=st, ws=ws_c)
+    R, sel, stats = L.l0cim_mri_solve(mp, A, y, mask, cim, sp, ws=ws)
     torch.cuda.synchronize()
-    return R, sel, int(st.item()), time.perf_counter() - t0
+    dt = time.perf_counter() - t0
+    return R, sel, L.read_stats(stats).status_bits, dt
 
 
 def mri_golden():
@@ -464,7 +461,10 @@ def precision_cpu_baseline(P: int, seconds_target: float = 15.0):
 def factored_bench(args, torch, L, W, dev):
     from workloads import mri as WM
     P, steps, outer = 64, args.euler_steps or 1000, args.alternations or 11
+    pipeline = args.jdtype == "pipeline"
     gold, gold_R = mri_golden()
+    if pipeline:
+        gold, gold_R = {k: (v[0], v[2]) for k, v in golden_file("mri_l2").items()}, {}
     seeds = list(range(args.steps))
     cim = L.cim_params(n_steps=steps, field="BN", K=1.0, d=0.6)
     rows, total, cim_total, launches_total, match = [], 0.0, 0.0, 0, 0
@@ -473,10 +473,11 @@ def factored_bench(args, torch, L, W, dev):
         print(f"[factored] building the MRI-shaped instance of seed {sd}", file=sys.stderr, flush=True)
         inst = WM.mri_instance(sd)
         if sd == seeds[0]:
-            factored_mri_solve(torch, L, inst, dev, L.cim_params(n_steps=4, field="BN", K=1.0, d=0.6), P, 1, sd)
+            factored_mri_solve(torch, L, inst, dev, L.cim_params(n_steps=4, field="BN", K=1.0, d=0.6), P, 1, sd,
+                               pipeline)
         print(f"[factored] solving ({outer} x {steps} steps)", file=sys.stderr, flush=True)
         L.l0cim_profile_begin()
-        R, sel, status, dt = factored_mri_solve(torch, L, inst, dev, cim, P, outer, sd)
+        R, sel, status, dt = factored_mri_solve(torch, L, inst, dev, cim, P, outer, sd, pipeline)
         ms, cnt = L.l0cim_profile_end()
         total += dt
         cim_total += ms
@@ -508,8 +509,11 @@ def factored_bench(args, torch, L, W, dev):
         "config": {"workload": "MRI-shaped L0RBCS stand-in: 128x128 random-ellipse phantom, 3-level Haar (N=16384), "
                                "30% variable-density DCT-II rows (M=4915), noise 1e-3, 64 replicas, BN field, K=1, "
                                "d=0.6, eta 0.8->0.03 over 11 alternations of 1000 steps, FP32 couplings applied in "
-                               "factored form (Haar, FFT-based DCT, mask), Jacobi CDP on G, FP64 Cholesky refit"},
-        "couplings": "factored", "support_match": f"{match}/{len(seeds)}", "per_seed": rows,
+                               "factored form (Haar, FFT-based DCT, mask), " +
+                               ("L2 term of eq. 20 (gamma 1e-4), LASSO start (FISTA, lam1 3e-4, 200 iterations), "
+                                "CG CDP (relative residual 1e-5, at most 1e4 iterations)" if pipeline else
+                                "Jacobi CDP in factored form, FP64 Cholesky refit")},
+        "couplings": "factored" + (" + MRI pipeline" if pipeline else ""), "support_match": f"{match}/{len(seeds)}", "per_seed": rows,
         "spin_steps_per_s_cim_only": n * P * steps * launches_total / (cim_total / 1e3),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_VECTOR_PEAK_TFS, "traffic": None, "kernel": "mri_cim_kernel<BN>",
@@ -521,7 +525,7 @@ def factored_bench(args, torch, L, W, dev):
 
 def precision_bench(args, torch, L, W, dev):
     from workloads import mri as WM
-    if args.jdtype == "factored":
+    if args.jdtype in ("factored", "pipeline"):
         return factored_bench(args, torch, L, W, dev)
     jdt = {"bf16": L.BF16, "fp8": L.FP8E4M3}[args.jdtype]
     jb = {"bf16": 2, "fp8": 1}[args.jdtype]
@@ -977,8 +981,9 @@ def main():
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run a 512 MiB fill and copy first (HBM counter calibration)")
     ap.add_argument("--form", choices=["plain", "batched", "precision", "serving", "accuracy"], default="batched")
-    ap.add_argument("--jdtype", choices=["bf16", "fp8", "factored"], default="bf16",
-                    help="precision form couplings (factored: FP32, applied through the MRI operator)")
+    ap.add_argument("--jdtype", choices=["bf16", "fp8", "factored", "pipeline"], default="bf16",
+                    help="precision form couplings (factored: FP32, applied through the MRI operator; pipeline: "
+                         "the same with the L2 term of eq. 20, the LASSO start and the CG CDP)")
     ap.add_argument("--requests", type=int, default=200, help="serving form: number of requests")
     ap.add_argument("--slots", type=int, default=48, help="serving form: resident requests at most")
     ap.add_argument("--rates", type=float, nargs="*", default=[0.5, 0.9],

@@ -78,7 +78,8 @@ typedef enum {
 
 typedef enum {
   L0CIM_CDP_JACOBI = 0,       /* damped Jacobi sweeps over all r */
-  L0CIM_CDP_CHOL_F64 = 1      /* FP64 Cholesky least squares on the support */
+  L0CIM_CDP_CHOL_F64 = 1,     /* FP64 Cholesky least squares on the support */
+  L0CIM_CDP_CG = 2            /* conjugate gradients on the support (MRI form) */
 } l0cim_cdp;
 
 /* Device status bits. */
@@ -246,30 +247,114 @@ l0cim_status l0cim_mfcim_run_noalloc(l0cim_dtype dtype, int32_t n, int32_t P, l0
                                      int32_t* status, void* stream);
 
 /*
+ * MRI-shaped form.  A = S C Psi^T: Psi is the orthonormal 2-D Haar analysis
+ * over `levels` levels in Mallat layout (coarsest block at the top left), C
+ * the orthonormal 2-D DCT-II of the size x size image and S the sampled rows,
+ * given as mask[f] (size^2 bytes, row-major frequency index
+ * f = k_row * size + k_col, 1 where sampled) -- the sparse-MRI observation
+ * model of the paper (wavelet-sparse image, undersampled frequency data).
+ * The couplings are applied in factored form instead of a stored J:
+ *   (J x)_r = -R_r (G_gamma (R o x))_r + D_r R_r^2 x_r,
+ *   G_gamma = A^T A + gamma Psi (D_v^T D_v + D_h^T D_h) Psi^T,
+ * J = -G_gamma o R R^T with a zero diagonal (eq. 13, 15, 16; eq. 20 for the
+ * L2 term, whose weight gamma is 1e-4 in the paper's MRI runs).  D_v and D_h
+ * are the vertical and horizontal second differences with the reflecting
+ * boundary (x[-1] = x[0], x[S] = x[S-1]; the paper leaves the boundary rows
+ * open); this operator is diagonal in the DCT-II basis, so G_gamma v =
+ * Psi C^T diag(mask + gamma (lam_kr^2 + lam_kc^2)) C Psi^T v with
+ * lam_k = 4 sin^2(pi k / (2 size)).  gamma = 0 gives A^T A exactly.
+ * size must be 128 (L0CIM_ERR_UNSUPPORTED otherwise) and 2^levels <= size;
+ * FP32 throughout.  The kernels hold the image in LDS (about 158 KB per
+ * workgroup, gfx950's 160 KB; elsewhere the launch fails with L0CIM_ERR_HIP).
+ *
  * l0cim_mri_mfcim_run -- the run of l0cim_mfcim_run (same dynamics, state
- * layout, sigma, H, trace and status) for an MRI-shaped observation matrix
- * A = S C Psi^T with the couplings applied in factored form instead of a
- * stored J:  (J x)_r = -R_r (G (R o x))_r + D_r R_r^2 x_r  with
- * G v = Psi C^T diag(mask) C Psi^T v, where Psi is the orthonormal 2-D Haar
- * analysis over `levels` levels in Mallat layout (coarsest block at the top
- * left), C the orthonormal 2-D DCT-II of the size x size image and mask[f]
- * (size^2 bytes, row-major frequency index f = k_row * size + k_col) is 1 for
- * the sampled frequencies -- the rows of A.  This is J = -(A^T A) o R R^T with
- * a zero diagonal (eq. 13, 15, 16) for the sparse-MRI observation model of the
- * paper (wavelet-sparse image, undersampled frequency data).  D_r = G_rr
- * (from l0cim_gram) is read as D[r * incd] (incd = ldg + 1 reads the diagonal
- * of G in place, 1 a vector), b = A^T y (from l0cim_gram; z = R o b as in
- * l0cim_build_couplings), R: n = size^2 floats; c, e: P x n floats; FP32 only.
- * size must be 128 (L0CIM_ERR_UNSUPPORTED otherwise); 2^levels <= size.  One
- * workgroup per replica holds the image in LDS (about 158 KB, so the device
- * needs gfx950's 160 KB per workgroup; elsewhere the launch fails with
- * L0CIM_ERR_HIP); no workspace.
+ * layout, sigma, H, trace and status) with these couplings.  D_r = G_gamma,rr
+ * is read as D[r * incd] (incd = ldg + 1 reads the diagonal of a stored G in
+ * place, 1 a vector; for gamma > 0 from l0cim_mri_l2_diag), b = A^T y (z =
+ * R o b as in l0cim_build_couplings), R: n = size^2 floats; c, e: P x n.  One
+ * workgroup per replica; no workspace.
  */
 l0cim_status l0cim_mri_mfcim_run(int32_t size, int32_t levels, int32_t P, const uint8_t* mask,
                                  const float* R, const float* D, int64_t incd, const float* b,
-                                 double eta, const l0cim_cim_params* prm, float* c, float* e,
+                                 double gamma, double eta, const l0cim_cim_params* prm, float* c, float* e,
                                  uint8_t* sigma, double* H, float* trace, int32_t trace_steps,
                                  int32_t* status, void* stream);
+
+/*
+ * l0cim_mri_l2_diag -- D_out[r] = D_in[r * incd] + gamma [Psi (D_v^T D_v +
+ * D_h^T D_h) Psi^T]_rr: the diagonal of G_gamma from that of A^T A.  The Haar
+ * basis image of coefficient r is a product of two unit-norm 1-D Haar
+ * functions v(row) h(col), so the added entry is ||D v||^2 + ||D h||^2,
+ * evaluated in FP64 per coefficient.  D_out: size^2 floats (may not alias
+ * D_in unless incd = 1).
+ */
+l0cim_status l0cim_mri_l2_diag(int32_t size, int32_t levels, double gamma, const float* D_in, int64_t incd,
+                               float* D_out, void* stream);
+
+/*
+ * l0cim_mri_lasso -- the LASSO initial R of the paper's MRI runs: FISTA (Beck
+ * and Teboulle) on (1/2) r^T G_gamma r - b^T r + lam1 ||r||_1 (eq. 18 with the
+ * L0 term replaced by an L1 term, up to a constant) from r = 0, step
+ * 1 / (1 + 32 gamma) (an upper bound of ||G_gamma||_2: A A^T = I and
+ * ||D||_2 <= 4), `iters` iterations.  b = A^T y; R_out: size^2 floats.  One
+ * workgroup.
+ */
+l0cim_status l0cim_mri_lasso(int32_t size, int32_t levels, double gamma, const uint8_t* mask, const float* b,
+                             double lam1, int32_t iters, float* R_out, void* stream);
+
+/*
+ * l0cim_mri_update_r -- the CDP step of Algorithm 1 with G_gamma in factored
+ * form, on support sigma (size^2 bytes):
+ *   L0CIM_CDP_JACOBI: `iters` synchronous sweeps over every r,
+ *     R_r <- R_r + dtc [(b_r - sum_{r' != r} G_rr' sigma_r' R_r') / G_rr - R_r];
+ *   L0CIM_CDP_CG: conjugate gradients on (G_gamma)_SS R_S = b_S from the
+ *     current R_S (the paper's MRI CDP, at most 10^4 iterations there) until
+ *     ||residual|| <= cg_tol ||b_S|| or cg_max_iter iterations, dot products in
+ *     FP64; then off the support R_r = (b_r - (G_gamma R_S)_r) / D_r, the
+ *     Jacobi step's fixed point.  iters_out (device int32, may be NULL)
+ *     receives the iteration count.
+ * r with D_r < 1e-12 is held at 0 (status bit TINY_DIAG).  D as for
+ * l0cim_mri_mfcim_run.  R (size^2) is read and overwritten.  One workgroup.
+ */
+l0cim_status l0cim_mri_update_r(int32_t size, int32_t levels, double gamma, const uint8_t* mask, const float* D,
+                                int64_t incd, const float* b, const uint8_t* sigma, l0cim_cdp cdp, double dtc,
+                                int32_t iters, int32_t cg_max_iter, double cg_tol, float* R, int32_t* iters_out,
+                                int32_t* status, void* stream);
+
+/* Parameters of the MRI-shaped solve. */
+typedef struct {
+  int32_t size;              /* image side (128) */
+  int32_t levels;            /* Haar levels */
+  double gamma;              /* L2 weight of eq. 18 / 20 (0: the plain couplings) */
+  int32_t lasso_iters;       /* 0: R_init = b / D; > 0: LASSO start, this many FISTA iterations */
+  double lasso_lam1;         /* L1 weight of the LASSO start */
+  int32_t cdp;               /* L0CIM_CDP_JACOBI (dtc, cdp_iters of the solve params) or L0CIM_CDP_CG */
+  int32_t cg_max_iter;       /* CG iteration cap (10^4 in the paper) */
+  double cg_tol;             /* CG stop: ||residual|| <= cg_tol ||b_S|| */
+} l0cim_mri_params;
+
+void l0cim_mri_params_default(l0cim_mri_params* p);
+
+/*
+ * l0cim_mri_solve -- Algorithm 1 end to end on the MRI-shaped operator:
+ *   b = A^T y, D = diag(A^T A) (FP64 sums over the stored A); D += gamma
+ *   diag(L2 term) (l0cim_mri_l2_diag) if gamma > 0;
+ *   R = LASSO (lasso_iters > 0) or b / D;
+ *   for i < n_outer: eta_i (eq. 22), init_state(seed, i), mri_mfcim_run,
+ *     select_replica (lambda_i = eta_i^2 / 2), mri_update_r (Jacobi or CG);
+ *   optional FP64 refit on the final support (l0cim_refit_f64; gamma = 0
+ *   only, L0CIM_ERR_UNSUPPORTED otherwise); stats as l0cim_solve's (E is the
+ *   eq. 3 objective, without the L2 term).
+ * A: m x size^2 (lda >= size^2) FP32 device memory, used for b, D, the refit
+ * and E; sp supplies eta_init/eta_end/velo/n_outer, dtc/cdp_iters (Jacobi),
+ * replicas, seed and final_refit_f64.  ws: at least
+ * l0cim_mri_solve_workspace_bytes(m, replicas, final_refit_f64) bytes.
+ */
+size_t l0cim_mri_solve_workspace_bytes(int32_t m, int32_t P, int32_t final_refit_f64);
+l0cim_status l0cim_mri_solve(const l0cim_mri_params* mp, int32_t m, const float* A, int64_t lda, const float* y,
+                             const uint8_t* mask, const l0cim_cim_params* cim, const l0cim_solve_params* sp,
+                             float* R_out, uint8_t* sigma_out, l0cim_stats* stats, void* ws, size_t ws_bytes,
+                             void* stream);
 
 /*
  * l0cim_select_replica -- q* = argmin_q H[q] (lowest q on ties, NaN never

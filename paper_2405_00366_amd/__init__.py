@@ -32,7 +32,7 @@ __all__ = [
 
 F32, F64, BF16, FP8E4M3 = 0, 1, 2, 3
 FIELD_CN, FIELD_BN = 0, 1
-CDP_JACOBI, CDP_CHOL_F64 = 0, 1
+CDP_JACOBI, CDP_CHOL_F64, CDP_CG = 0, 1, 2
 LAUNCH_AUTO, LAUNCH_RESIDENT, LAUNCH_STREAMED, LAUNCH_MATRIX = 0, 1, 2, 3
 
 ST_NONFINITE, ST_BLOWUP, ST_CHOL_RIDGE, ST_TINY_DIAG, ST_TIMEOUT = 1, 2, 4, 8, 16
@@ -59,6 +59,11 @@ class SolveParams(ctypes.Structure):
         ("final_refit_f64", c_int32), ("replicas", c_int32), ("seed", c_uint64),
         ("j_dtype", c_int32), ("flags", c_int32),
     ]
+
+
+class MriParams(ctypes.Structure):
+    _fields_ = [("size", c_int32), ("levels", c_int32), ("gamma", c_double), ("lasso_iters", c_int32),
+                ("lasso_lam1", c_double), ("cdp", c_int32), ("cg_max_iter", c_int32), ("cg_tol", c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -130,9 +135,23 @@ def lib():
         L.l0cim_mfcim_run_noalloc.argtypes = [c_int, c_int32, c_int32, c_int, vp, c_int64, vp, vp, c_double,
                                               POINTER(CimParams), vp, vp, vp, vp, vp, c_int32, vp, vp]
         L.l0cim_mfcim_run_noalloc.restype = st
-        L.l0cim_mri_mfcim_run.argtypes = [c_int32, c_int32, c_int32, vp, vp, vp, c_int64, vp, c_double,
+        L.l0cim_mri_mfcim_run.argtypes = [c_int32, c_int32, c_int32, vp, vp, vp, c_int64, vp, c_double, c_double,
                                           POINTER(CimParams), vp, vp, vp, vp, vp, c_int32, vp, vp]
         L.l0cim_mri_mfcim_run.restype = st
+        L.l0cim_mri_l2_diag.argtypes = [c_int32, c_int32, c_double, vp, c_int64, vp, vp]
+        L.l0cim_mri_l2_diag.restype = st
+        L.l0cim_mri_lasso.argtypes = [c_int32, c_int32, c_double, vp, vp, c_double, c_int32, vp, vp]
+        L.l0cim_mri_lasso.restype = st
+        L.l0cim_mri_update_r.argtypes = [c_int32, c_int32, c_double, vp, vp, c_int64, vp, vp, c_int, c_double,
+                                         c_int32, c_int32, c_double, vp, vp, vp, vp]
+        L.l0cim_mri_update_r.restype = st
+        L.l0cim_mri_params_default.argtypes = [POINTER(MriParams)]
+        L.l0cim_mri_params_default.restype = None
+        L.l0cim_mri_solve_workspace_bytes.argtypes = [c_int32, c_int32, c_int32]
+        L.l0cim_mri_solve_workspace_bytes.restype = c_size_t
+        L.l0cim_mri_solve.argtypes = [POINTER(MriParams), c_int32, vp, c_int64, vp, vp, POINTER(CimParams),
+                                      POINTER(SolveParams), vp, vp, vp, vp, c_size_t, vp]
+        L.l0cim_mri_solve.restype = st
         L.l0cim_select_replica.argtypes = [c_int32, c_int32, vp, vp, vp, vp, vp]
         L.l0cim_select_replica.restype = st
         L.l0cim_update_r_workspace_bytes.argtypes = [c_int, c_int32, c_int]
@@ -349,15 +368,61 @@ def l0cim_mfcim_run_noalloc(J, z, eta: float, prm: CimParams, c, e, sigma, H=Non
 
 
 def l0cim_mri_mfcim_run(size: int, levels: int, mask, R, D, b, eta: float, prm: CimParams, c, e, sigma=None,
-                        H=None, trace=None, trace_steps: int = 0, status=None, stream=None):
+                        H=None, trace=None, trace_steps: int = 0, status=None, stream=None, gamma: float = 0.0):
     """D: a vector of G_rr, or G itself (its diagonal is read in place)."""
     P = c.shape[0]
     sigma = torch.empty(c.shape, dtype=torch.uint8, device=c.device) if sigma is None else sigma
     incd = 1 if D.dim() == 1 else D.stride(0) + 1
-    _check(lib().l0cim_mri_mfcim_run(size, levels, P, _ptr(mask), _ptr(R), _ptr(D), incd, _ptr(b), eta,
+    _check(lib().l0cim_mri_mfcim_run(size, levels, P, _ptr(mask), _ptr(R), _ptr(D), incd, _ptr(b), gamma, eta,
                                      ctypes.byref(prm), _ptr(c), _ptr(e), _ptr(sigma), _ptr(H), _ptr(trace),
                                      trace_steps, _ptr(status), _stream(stream)), "l0cim_mri_mfcim_run")
     return sigma
+
+
+def l0cim_mri_l2_diag(size: int, levels: int, gamma: float, D_in, D_out, stream=None):
+    incd = D_in.stride(0)
+    _check(lib().l0cim_mri_l2_diag(size, levels, gamma, _ptr(D_in), incd, _ptr(D_out), _stream(stream)),
+           "l0cim_mri_l2_diag")
+    return D_out
+
+
+def l0cim_mri_lasso(size: int, levels: int, gamma: float, mask, b, lam1: float, iters: int, R_out, stream=None):
+    _check(lib().l0cim_mri_lasso(size, levels, gamma, _ptr(mask), _ptr(b), lam1, iters, _ptr(R_out),
+                                 _stream(stream)), "l0cim_mri_lasso")
+    return R_out
+
+
+def l0cim_mri_update_r(size: int, levels: int, gamma: float, mask, D, b, sigma, R, cdp: int = CDP_JACOBI,
+                       dtc: float = 0.1, iters: int = 100, cg_max_iter: int = 10000, cg_tol: float = 1e-5,
+                       iters_out=None, status=None, stream=None):
+    incd = 1 if D.dim() == 1 else D.stride(0) + 1
+    _check(lib().l0cim_mri_update_r(size, levels, gamma, _ptr(mask), _ptr(D), incd, _ptr(b), _ptr(sigma), cdp, dtc,
+                                    iters, cg_max_iter, cg_tol, _ptr(R), _ptr(iters_out), _ptr(status),
+                                    _stream(stream)), "l0cim_mri_update_r")
+    return R
+
+
+def mri_params(**kw) -> MriParams:
+    p = MriParams()
+    lib().l0cim_mri_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def l0cim_mri_solve(mp: MriParams, A, y, mask, cim: CimParams, sp: SolveParams, R_out=None, sigma_out=None,
+                    stats=None, ws=None, stream=None):
+    """Algorithm 1 on the MRI-shaped operator.  Returns (R, sigma, stats_bytes_tensor)."""
+    m, n = A.shape
+    R_out = torch.empty(n, dtype=torch.float32, device=A.device) if R_out is None else R_out
+    sigma_out = torch.empty(n, dtype=torch.uint8, device=A.device) if sigma_out is None else sigma_out
+    stats = torch.zeros(STATS_BYTES, dtype=torch.uint8, device=A.device) if stats is None else stats
+    need = lib().l0cim_mri_solve_workspace_bytes(m, sp.replicas, sp.final_refit_f64)
+    ws = workspace(need, A.device) if ws is None else ws
+    _check(lib().l0cim_mri_solve(ctypes.byref(mp), m, _ptr(A), _ld(A), _ptr(y), _ptr(mask), ctypes.byref(cim),
+                                 ctypes.byref(sp), _ptr(R_out), _ptr(sigma_out), _ptr(stats), _ptr(ws), ws.numel(),
+                                 _stream(stream)), "l0cim_mri_solve")
+    return R_out, sigma_out, stats
 
 
 def l0cim_select_replica(H, sigma, sigma_out=None, q_out=None, stream=None):

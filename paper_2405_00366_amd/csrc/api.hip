@@ -299,25 +299,6 @@ l0cim_status l0cim_mfcim_run(l0cim_dtype dtype, int32_t n, int32_t P, l0cim_dtyp
                            status, ws, ws_bytes, true, static_cast<hipStream_t>(stream));
 }
 
-l0cim_status l0cim_mri_mfcim_run(int32_t size, int32_t levels, int32_t P, const uint8_t* mask,
-                                 const float* R, const float* D, int64_t incd, const float* b,
-                                 double eta, const l0cim_cim_params* prm, float* c, float* e,
-                                 uint8_t* sigma, double* H, float* trace, int32_t trace_steps,
-                                 int32_t* status, void* stream) {
-  l0cim_status st = check_cim(prm);
-  if (st != L0CIM_OK) return st;
-  if (!mask || !R || !D || !b || !c || !e || !sigma) return set_error(L0CIM_ERR_ARG, "mri_mfcim_run: NULL pointer");
-  if (size <= 0 || P <= 0 || P > (1 << 16) || incd < 1) return set_error(L0CIM_ERR_SHAPE, "mri_mfcim_run: bad shape");
-  if (levels < 0 || levels > 30 || (1 << levels) > size)
-    return set_error(L0CIM_ERR_SHAPE, "mri_mfcim_run: %d Haar levels", levels);
-  if (trace_steps < 0 || (trace_steps > 0 && !trace))
-    return set_error(L0CIM_ERR_ARG, "mri_mfcim_run: trace_steps > 0 needs a trace buffer");
-  const int n = size * size;
-  CimArgs a = make_args(n, P, prm, eta, trace_steps < prm->n_steps ? trace_steps : prm->n_steps);
-  return launch_mri_mfcim(size, levels, P, mask, R, D, incd, b, a, c, e, sigma, H, trace, status,
-                          static_cast<hipStream_t>(stream));
-}
-
 l0cim_status l0cim_select_replica(int32_t n, int32_t P, const double* H, const uint8_t* sigma,
                                   uint8_t* sigma_out, int32_t* q_out, void* stream) {
   if (!H || !sigma || !sigma_out) return set_error(L0CIM_ERR_ARG, "select_replica: NULL pointer");

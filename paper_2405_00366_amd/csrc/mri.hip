@@ -53,6 +53,7 @@ struct MriLds {
   float2 tw[kS];     // exp(-2 pi i m / 128)
   float2 ph[kS];     // exp(-i pi k / 256)
   double red[kBS / kWave];
+  float lam2[kS];    // (4 sin^2(pi k / 256))^2: D^T D of the reflecting second difference in the DCT-II basis
   float lin[4096];   // p_k - 1 (- j) of the first steps (eq. 21)
 };
 constexpr int kLinSteps = 4096;
@@ -366,7 +367,7 @@ __device__ __forceinline__ void haar_fused(MriLds& s, int t) {
 // index, passed as a value the compiler cannot see through (opaque_tid) so
 // that the few hundred LDS addresses derived from it are formed inside each
 // call rather than hoisted out of the step loop and kept live (which spilled).
-__device__ void gram_apply(MriLds& s, float (&u)[kPer], int levels, uint32_t mbits, int t,
+__device__ void gram_apply(MriLds& s, float (&u)[kPer], int levels, uint32_t mbits, float gamma, int t,
                            const float* __restrict__ D, int64_t incd, const float* __restrict__ bv,
                            float (&dq)[kPer], float (&zb)[kPer]) {
   const int g = t >> 3, n2 = t & 7;
@@ -431,14 +432,31 @@ __device__ void gram_apply(MriLds& s, float (&u)[kPer], int levels, uint32_t mbi
     float* ra = s.B + g * kLd;
     float* rb = s.B + (g + H) * kLd;
     dct_fwd2(ra, rb, ra, rb, n2, s, ya, yb);
+    if (gamma == 0.0f) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+      for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int p = 0; p < 8; ++p) {
-        const int k = 2 * n2 + h + 16 * brev<3>(p);
-        ra[k] = ((mbits >> (h * 8 + p)) & 1u) ? ya[h * 8 + p] : 0.0f;
-        rb[k] = ((mbits >> (16 + h * 8 + p)) & 1u) ? yb[h * 8 + p] : 0.0f;
-      }
+        for (int p = 0; p < 8; ++p) {
+          const int k = 2 * n2 + h + 16 * brev<3>(p);
+          ra[k] = ((mbits >> (h * 8 + p)) & 1u) ? ya[h * 8 + p] : 0.0f;
+          rb[k] = ((mbits >> (16 + h * 8 + p)) & 1u) ? yb[h * 8 + p] : 0.0f;
+        }
+    } else {
+      // the L2 term of eq. 20 is diagonal in this basis: weight mask(kr, kc)
+      // + gamma (lam2[kr] + lam2[kc]), kr = k, kc = g (row a) or g + 64 (row b)
+      const float la = s.lam2[g], lb = s.lam2[g + H];
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+          const int k = 2 * n2 + h + 16 * brev<3>(p);
+          const float lk = s.lam2[k];
+          const float ma = ((mbits >> (h * 8 + p)) & 1u) ? 1.0f : 0.0f;
+          const float mb = ((mbits >> (16 + h * 8 + p)) & 1u) ? 1.0f : 0.0f;
+          ra[k] = ya[h * 8 + p] * (ma + gamma * (lk + la));
+          rb[k] = yb[h * 8 + p] * (mb + gamma * (lk + lb));
+        }
+    }
     wave_sync();
     float wa[16], wpa[16], wb[16], wpb[16];
 #pragma unroll
@@ -543,15 +561,9 @@ __device__ __noinline__ void fill_lin(float* lin, int k0, int n_steps, double dt
   }
 }
 
-template <int FIELD>
-__global__ void __launch_bounds__(kBS)
-mri_cim_kernel(const uint8_t* __restrict__ mask, const float* __restrict__ R, const float* __restrict__ D, int64_t incd,
-               const float* __restrict__ b, CimArgs a, int levels, float* __restrict__ c,
-               float* __restrict__ e, uint8_t* __restrict__ sigma, double* __restrict__ H,
-               float* __restrict__ trace, int* __restrict__ status) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  MriLds& s = *reinterpret_cast<MriLds*>(smem);
-  const int t = threadIdx.x, q = blockIdx.x, n = kS * kS;
+// Twiddle, phase and L2-weight tables in LDS; returns the mask bits of the
+// frequencies (kr, kc = g) this thread holds in the column pass.
+__device__ uint32_t init_tables(MriLds& s, const uint8_t* __restrict__ mask, int t) {
   const int g = t >> 3, n2 = t & 7;
   if (t < kS) {
     double sn, cs;
@@ -559,10 +571,10 @@ mri_cim_kernel(const uint8_t* __restrict__ mask, const float* __restrict__ R, co
     s.tw[t] = make_float2(float(cs), float(sn));
     sincospi(-double(t) / (2 * kS), &sn, &cs);
     s.ph[t] = make_float2(float(cs), float(sn));
+    const double sq = sinpi(double(t) / (2 * kS));
+    const double lam = 4.0 * sq * sq;
+    s.lam2[t] = float(lam * lam);
   }
-  const double lj = a.linear_j ? a.j : 0.0;
-  fill_lin(s.lin, 0, a.n_steps, a.dt, a.p_thr, a.d, a.t_c, a.t_w, lj);
-  // mask bits of the frequencies (kr, kc = g) this thread holds in the column pass
   uint32_t mbits = 0;
 #pragma unroll
   for (int rr = 0; rr < kRows; ++rr)
@@ -573,6 +585,21 @@ mri_cim_kernel(const uint8_t* __restrict__ mask, const float* __restrict__ R, co
         const int kr = 2 * n2 + h + 16 * brev<3>(p);
         if (mask[kr * kS + g + (kBS / 8) * rr]) mbits |= 1u << (16 * rr + h * 8 + p);
       }
+  return mbits;
+}
+
+template <int FIELD>
+__global__ void __launch_bounds__(kBS)
+mri_cim_kernel(const uint8_t* __restrict__ mask, const float* __restrict__ R, const float* __restrict__ D, int64_t incd,
+               const float* __restrict__ b, float gamma, CimArgs a, int levels, float* __restrict__ c,
+               float* __restrict__ e, uint8_t* __restrict__ sigma, double* __restrict__ H,
+               float* __restrict__ trace, int* __restrict__ status) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  MriLds& s = *reinterpret_cast<MriLds*>(smem);
+  const int t = threadIdx.x, q = blockIdx.x, n = kS * kS;
+  const uint32_t mbits = init_tables(s, mask, t);
+  const double lj = a.linear_j ? a.j : 0.0;
+  fill_lin(s.lin, 0, a.n_steps, a.dt, a.p_thr, a.d, a.t_c, a.t_w, lj);
   float cv[kPer], ev[kPer], Rv[kPer];
 #pragma unroll
   for (int i = 0; i < kPer; ++i) {
@@ -599,7 +626,7 @@ mri_cim_kernel(const uint8_t* __restrict__ mask, const float* __restrict__ R, co
       u[i] = Rv[i] * x;
     }
     float dq[kPer], zb[kPer];
-    gram_apply(s, u, levels, mbits, opaque_tid(), D, incd, b, dq, zb);
+    gram_apply(s, u, levels, mbits, gamma, opaque_tid(), D, incd, b, dq, zb);
     const float lin = s.lin[k % kLinSteps];
     // D and b were read again in this step (from the caches, through an
     // opaque index): held across the steps they would take 64 more registers
@@ -643,7 +670,7 @@ mri_cim_kernel(const uint8_t* __restrict__ mask, const float* __restrict__ R, co
   if (bits) raise_status(status, bits);
   if (H) {
     float dq[kPer], zb[kPer];
-    gram_apply(s, u, levels, mbits, opaque_tid(), D, incd, b, dq, zb);
+    gram_apply(s, u, levels, mbits, gamma, opaque_tid(), D, incd, b, dq, zb);
     const double lam = 0.5 * a.eta * a.eta;
     double hs = 0.0;
 #pragma unroll
@@ -667,26 +694,337 @@ mri_cim_kernel(const uint8_t* __restrict__ mask, const float* __restrict__ R, co
   }
 }
 
+// ---- the MRI pipeline around the run: L2 diagonal, LASSO start, CG CDP ----
+
+// ||D f||^2 of the unit-norm 1-D Haar function of `len` = 2^l samples at
+// offset lo (high: + on its first half, - on its second), D the second
+// difference with the reflecting boundary f[-1] = f[0], f[S] = f[S-1].
+__device__ double d2_norm2(int lo, int len, bool high) {
+  const double v = rsqrt(double(len));
+  auto f = [&](int i) -> double {
+    i = i < 0 ? 0 : (i >= kS ? kS - 1 : i);
+    if (i < lo || i >= lo + len) return 0.0;
+    return (high && i - lo >= len / 2) ? -v : v;
+  };
+  double acc = 0.0;
+  const int i0 = lo > 0 ? lo - 1 : 0, i1 = lo + len < kS ? lo + len : kS - 1;
+  for (int i = i0; i <= i1; ++i) {
+    const double d = f(i - 1) - 2.0 * f(i) + f(i + 1);
+    acc += d * d;
+  }
+  return acc;
+}
+
+// D_out[r] = D_in[r * incd] + gamma [Psi (D_v^T D_v + D_h^T D_h) Psi^T]_rr.  The
+// Haar basis image of coefficient r is a product v(row) h(col) of unit-norm
+// 1-D Haar functions, so the diagonal entry is ||D v||^2 + ||D h||^2.
+__global__ void mri_l2_diag_kernel(int levels, double gamma, const float* __restrict__ D_in, int64_t incd,
+                                   float* __restrict__ D_out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= kS * kS) return;
+  const int i = r / kS, j = r - i * kS;
+  int lev = levels, pi = i, pj = j;
+  bool hv = false, hh = false;
+  for (int l = 1; l <= levels; ++l) {
+    const int h = kS >> l;
+    if (i < 2 * h && j < 2 * h && (i >= h || j >= h)) {
+      lev = l;
+      hv = i >= h;
+      hh = j >= h;
+      pi = hv ? i - h : i;
+      pj = hh ? j - h : j;
+      break;
+    }
+  }
+  const int len = 1 << lev;
+  const double dl = d2_norm2(pi * len, len, hv) + d2_norm2(pj * len, len, hh);
+  D_out[r] = float(double(D_in[size_t(r) * incd]) + gamma * dl);
+}
+
+// FP64 sum over the workgroup of per-thread partials; every thread gets it.
+__device__ double block_sum(MriLds& s, double v) {
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_down(v, off, kWave);
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) s.red[threadIdx.x / kWave] = v;
+  __syncthreads();
+  double tot = 0.0;
+  for (int w = 0; w < kBS / kWave; ++w) tot += s.red[w];
+  return tot;
+}
+
+// LASSO start of the MRI pipeline by FISTA: x minimises
+// (1/2) x^T G_gamma x - b^T x + lam1 ||x||_1 after `iters` iterations from 0,
+// step 1 / (1 + 32 gamma), G_gamma applied in factored form.  One workgroup.
+__global__ void __launch_bounds__(kBS)
+mri_lasso_kernel(const uint8_t* __restrict__ mask, int levels, float gamma, const float* __restrict__ b,
+                 double lam1, int iters, float* __restrict__ R_out) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  MriLds& s = *reinterpret_cast<MriLds*>(smem);
+  const int t = threadIdx.x;
+  const uint32_t mbits = init_tables(s, mask, t);
+  __syncthreads();
+  const double stepd = 1.0 / (1.0 + 32.0 * double(gamma));
+  const float step = float(stepd), thr = float(stepd * lam1);
+  float x[kPer], yk[kPer];
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) x[i] = yk[i] = 0.0f;
+  double tk = 1.0;
+  for (int it = 0; it < iters; ++it) {
+    float u[kPer], dq[kPer], zb[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) u[i] = yk[i];
+    gram_apply(s, u, levels, mbits, gamma, opaque_tid(), b, 1, b, dq, zb);
+    const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * tk * tk));
+    const float mom = float((tk - 1.0) / tn);
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const float v = yk[i] - step * (u[i] - zb[i]);
+      const float xn = v > thr ? v - thr : (v < -thr ? v + thr : 0.0f);
+      yk[i] = xn + mom * (xn - x[i]);
+      x[i] = xn;
+    }
+    tk = tn;
+  }
+  const int tf = opaque_tid();
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) R_out[tf + kBS * i] = x[i];
+}
+
+// CG CDP of the MRI pipeline: (G_gamma)_SS R_S = b_S from the current R_S
+// until ||r|| <= tol ||b_S|| or max_iter iterations, then off the support
+// R_r = (b_r - (G_gamma R_S)_r) / D_r (held at 0 where D_r < 1e-12).  Dot
+// products are accumulated in FP64 in a fixed order.  One workgroup.
+__global__ void __launch_bounds__(kBS)
+mri_cg_kernel(const uint8_t* __restrict__ mask, int levels, float gamma, const float* __restrict__ D, int64_t incd,
+              const float* __restrict__ b, const uint8_t* __restrict__ sigma, float* __restrict__ R, int max_iter,
+              double tol, int* __restrict__ iters_out, int* __restrict__ status) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  MriLds& s = *reinterpret_cast<MriLds*>(smem);
+  const int t = threadIdx.x;
+  const uint32_t mbits = init_tables(s, mask, t);
+  __syncthreads();
+  uint32_t sb = 0;
+  float x[kPer], r[kPer], p[kPer];
+  double bb = 0.0;
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int k = t + kBS * i;
+    const bool on = sigma[k] != 0;
+    sb |= on ? (1u << i) : 0u;
+    x[i] = on ? R[k] : 0.0f;
+  }
+  {
+    float u[kPer], dq[kPer], zb[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) u[i] = x[i];
+    gram_apply(s, u, levels, mbits, gamma, opaque_tid(), D, incd, b, dq, zb);
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const bool on = (sb >> i) & 1u;
+      r[i] = on ? zb[i] - u[i] : 0.0f;
+      p[i] = r[i];
+      bb += on ? double(zb[i]) * double(zb[i]) : 0.0;
+    }
+  }
+  double rr = 0.0;
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) rr += double(r[i]) * double(r[i]);
+  rr = block_sum(s, rr);
+  bb = block_sum(s, bb);
+  const double stop = tol * tol * bb;
+  int it = 0;
+  while (it < max_iter && rr > stop) {
+    float u[kPer], dq[kPer], zb[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) u[i] = p[i];
+    gram_apply(s, u, levels, mbits, gamma, opaque_tid(), D, incd, b, dq, zb);
+    double pap = 0.0;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      u[i] = ((sb >> i) & 1u) ? u[i] : 0.0f;
+      pap += double(p[i]) * double(u[i]);
+    }
+    pap = block_sum(s, pap);
+    if (!(pap > 0.0)) break;     // a breakdown (the support system is singular in FP32): keep x
+    const float alpha = float(rr / pap);
+    double rn = 0.0;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      x[i] += alpha * p[i];
+      r[i] -= alpha * u[i];
+      rn += double(r[i]) * double(r[i]);
+    }
+    rn = block_sum(s, rn);
+    const float beta = float(rn / rr);
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) p[i] = r[i] + beta * p[i];
+    rr = rn;
+    ++it;
+  }
+  float u[kPer], dq[kPer], zb[kPer];
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) u[i] = x[i];
+  gram_apply(s, u, levels, mbits, gamma, opaque_tid(), D, incd, b, dq, zb);
+  int bits = 0;
+  const int tf = opaque_tid();
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int k = tf + kBS * i;
+    const bool tiny = !(dq[i] >= 1e-12f);
+    if (tiny) bits |= L0CIM_ST_TINY_DIAG;
+    const float off = tiny ? 0.0f : (zb[i] - (u[i] - dq[i] * x[i])) / dq[i];
+    R[k] = ((sb >> i) & 1u) ? x[i] : off;
+  }
+  if (bits) raise_status(status, bits);
+  if (t == 0 && iters_out) *iters_out = it;
+}
+
+// Jacobi CDP with the couplings in factored form: `iters` synchronous sweeps
+// R_r <- R_r + dtc [(b_r - ((G_gamma s)_r - D_r s_r)) / D_r - R_r], s = sigma o R,
+// over every r (held at 0 where D_r < 1e-12).  One workgroup.
+__global__ void __launch_bounds__(kBS)
+mri_jacobi_kernel(const uint8_t* __restrict__ mask, int levels, float gamma, const float* __restrict__ D,
+                  int64_t incd, const float* __restrict__ b, const uint8_t* __restrict__ sigma, float* __restrict__ R,
+                  int iters, float dtc, int* __restrict__ status) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  MriLds& s = *reinterpret_cast<MriLds*>(smem);
+  const int t = threadIdx.x;
+  const uint32_t mbits = init_tables(s, mask, t);
+  __syncthreads();
+  uint32_t sb = 0;
+  float x[kPer];
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int k = t + kBS * i;
+    sb |= sigma[k] ? (1u << i) : 0u;
+    x[i] = R[k];
+  }
+  int bits = 0;
+  for (int it = 0; it < iters; ++it) {
+    float u[kPer], dq[kPer], zb[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) u[i] = ((sb >> i) & 1u) ? x[i] : 0.0f;
+    gram_apply(s, u, levels, mbits, gamma, opaque_tid(), D, incd, b, dq, zb);
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const float si = ((sb >> i) & 1u) ? x[i] : 0.0f;
+      const bool tiny = !(dq[i] >= 1e-12f);
+      if (tiny) bits |= L0CIM_ST_TINY_DIAG;
+      x[i] = tiny ? 0.0f : x[i] + dtc * ((zb[i] - (u[i] - dq[i] * si)) / dq[i] - x[i]);
+    }
+  }
+  const int tf = opaque_tid();
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) R[tf + kBS * i] = x[i];
+  if (bits) raise_status(status, bits);
+}
+
+// b = A^T y and D_r = sum_k A_kr^2 (FP64 accumulation), one column per thread.
+__global__ void mri_aty_colnorm_kernel(int m, int n, const float* __restrict__ A, int64_t lda,
+                                       const float* __restrict__ y, float* __restrict__ b, float* __restrict__ D) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double sb = 0.0, sd = 0.0;
+  for (int k = 0; k < m; ++k) {
+    const double a = A[size_t(k) * lda + r];
+    sb = fma(a, double(y[k]), sb);
+    sd = fma(a, a, sd);
+  }
+  b[r] = float(sb);
+  D[r] = float(sd);
+}
+
+// R_r = b_r / D_r (0 where D_r < 1e-12).
+__global__ void mri_r_init_kernel(int n, const float* __restrict__ b, const float* __restrict__ D,
+                                  float* __restrict__ R, int* __restrict__ status) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const bool tiny = !(D[r] >= 1e-12f);
+  R[r] = tiny ? 0.0f : b[r] / D[r];
+  if (tiny) raise_status(status, L0CIM_ST_TINY_DIAG);
+}
+
 }  // namespace
 
 size_t mri_lds_bytes() { return sizeof(MriLds); }
 
 l0cim_status launch_mri_mfcim(int size, int levels, int P, const uint8_t* mask, const float* R,
-                              const float* D, int64_t incd, const float* b, const CimArgs& a, float* c, float* e,
-                              uint8_t* sigma, double* H, float* trace, int* status, hipStream_t s) {
+                              const float* D, int64_t incd, const float* b, double gamma, const CimArgs& a, float* c,
+                              float* e, uint8_t* sigma, double* H, float* trace, int* status, hipStream_t s) {
   if (size != kS) return set_error(L0CIM_ERR_UNSUPPORTED, "mri_mfcim_run: image side %d (128 supported)", size);
   const size_t lds = sizeof(MriLds);
-  void (*k)(const uint8_t*, const float*, const float*, int64_t, const float*, CimArgs, int, float*, float*,
+  void (*k)(const uint8_t*, const float*, const float*, int64_t, const float*, float, CimArgs, int, float*, float*,
             uint8_t*, double*, float*, int*) =
       a.field == L0CIM_FIELD_BN ? mri_cim_kernel<int(L0CIM_FIELD_BN)> : mri_cim_kernel<int(L0CIM_FIELD_CN)>;
   L0_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
                              int(lds)));
   {
     ProfileScope prof(s);
-    hipLaunchKernelGGL(k, dim3(P), dim3(kBS), lds, s, mask, R, D, incd, b, a, levels, c, e, sigma, H, trace,
-                       status);
+    hipLaunchKernelGGL(k, dim3(P), dim3(kBS), lds, s, mask, R, D, incd, b, float(gamma), a, levels, c, e, sigma, H,
+                       trace, status);
   }
   L0_LAUNCHED("mri_cim_kernel");
+  return L0CIM_OK;
+}
+
+l0cim_status launch_mri_l2_diag(int size, int levels, double gamma, const float* D_in, int64_t incd, float* D_out,
+                                hipStream_t s) {
+  if (size != kS) return set_error(L0CIM_ERR_UNSUPPORTED, "mri_l2_diag: image side %d (128 supported)", size);
+  hipLaunchKernelGGL(mri_l2_diag_kernel, dim3(kS * kS / 256), dim3(256), 0, s, levels, gamma, D_in, incd, D_out);
+  L0_LAUNCHED("mri_l2_diag_kernel");
+  return L0CIM_OK;
+}
+
+l0cim_status launch_mri_lasso(int size, int levels, double gamma, const uint8_t* mask, const float* b, double lam1,
+                              int iters, float* R_out, hipStream_t s) {
+  if (size != kS) return set_error(L0CIM_ERR_UNSUPPORTED, "mri_lasso: image side %d (128 supported)", size);
+  const size_t lds = sizeof(MriLds);
+  L0_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(mri_lasso_kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+  hipLaunchKernelGGL(mri_lasso_kernel, dim3(1), dim3(kBS), lds, s, mask, levels, float(gamma), b, lam1, iters, R_out);
+  L0_LAUNCHED("mri_lasso_kernel");
+  return L0CIM_OK;
+}
+
+l0cim_status launch_mri_jacobi(int size, int levels, double gamma, const uint8_t* mask, const float* D,
+                               int64_t incd, const float* b, const uint8_t* sigma, float* R, int iters, double dtc,
+                               int* status, hipStream_t s) {
+  if (size != kS) return set_error(L0CIM_ERR_UNSUPPORTED, "mri_cdp: image side %d (128 supported)", size);
+  const size_t lds = sizeof(MriLds);
+  L0_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(mri_jacobi_kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+  hipLaunchKernelGGL(mri_jacobi_kernel, dim3(1), dim3(kBS), lds, s, mask, levels, float(gamma), D, incd, b, sigma, R,
+                     iters, float(dtc), status);
+  L0_LAUNCHED("mri_jacobi_kernel");
+  return L0CIM_OK;
+}
+
+l0cim_status launch_mri_aty_colnorm(int m, int n, const float* A, int64_t lda, const float* y, float* b, float* D,
+                                    hipStream_t s) {
+  hipLaunchKernelGGL(mri_aty_colnorm_kernel, dim3((n + 255) / 256), dim3(256), 0, s, m, n, A, lda, y, b, D);
+  L0_LAUNCHED("mri_aty_colnorm_kernel");
+  return L0CIM_OK;
+}
+
+l0cim_status launch_mri_r_init(int n, const float* b, const float* D, float* R, int* status, hipStream_t s) {
+  hipLaunchKernelGGL(mri_r_init_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, b, D, R, status);
+  L0_LAUNCHED("mri_r_init_kernel");
+  return L0CIM_OK;
+}
+
+l0cim_status launch_mri_cg(int size, int levels, double gamma, const uint8_t* mask, const float* D, int64_t incd,
+                           const float* b, const uint8_t* sigma, float* R, int max_iter, double tol, int* iters_out,
+                           int* status, hipStream_t s) {
+  if (size != kS) return set_error(L0CIM_ERR_UNSUPPORTED, "mri_cdp_cg: image side %d (128 supported)", size);
+  const size_t lds = sizeof(MriLds);
+  L0_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(mri_cg_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             int(lds)));
+  {
+    ProfileScope prof(s);
+    hipLaunchKernelGGL(mri_cg_kernel, dim3(1), dim3(kBS), lds, s, mask, levels, float(gamma), D, incd, b, sigma, R,
+                       max_iter, tol, iters_out, status);
+  }
+  L0_LAUNCHED("mri_cg_kernel");
   return L0CIM_OK;
 }
 

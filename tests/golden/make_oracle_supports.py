@@ -13,6 +13,18 @@ Usage:  python tests/golden/make_oracle_supports.py {small|plain|mri} FIRST LAST
           eta 0.8 -> 0.03 over 11 alternations of 1000 steps, binarised field,
           FP64 couplings applied in factored form, FP64 refit.
 
+  mri_f32in : the mri workload with A and y rounded to FP32 before the oracle
+          sees them (the device's inputs), to measure how far input rounding
+          alone moves the oracle's own final support.
+
+  mri_l2 : the MRI pipeline around the path on the same phantom instances:
+          couplings from G_gamma = A^T A + gamma Psi (D_v^T D_v + D_h^T D_h) Psi^T
+          (eq. 20, gamma = 1e-4, reflecting second differences), R_init from
+          the LASSO (FISTA, lam1 = 3e-4, 200 iterations), CG CDP (at most 10^4
+          iterations, relative residual 1e-5); 64 replicas, K = 1, d = 0.6,
+          eta 0.8 -> 0.03 over 11 alternations of 1000 steps, binarised field;
+          RMSE of the last CG solution on the final support.
+
   batched : 16 of the 256 instances of the batched workload (batch seed 7: N
           log-uniform in [256, 4096], alpha U[0.3, 0.7], sparsity U[0.05, 0.2],
           noise 0.01), instances 0, 16, ..., 240; 16 replicas, eta 0.8 -> 0.18
@@ -75,10 +87,12 @@ MRI_CIM = O.CimParams(n_steps=1000, field=O.BN, K=1.0, d=0.6)
 MRI_OUTER = O.OuterParams(eta_init=0.8, eta_end=0.03, velo=11, n_outer=11, replicas=64)
 
 
-def one_mri(seed):
+def one_mri(seed, f32_inputs=False):
     from oracle import mri as OM
     from workloads import mri as WM
     inst = WM.mri_instance(seed)
+    if f32_inputs:
+        inst = inst.rounded_f32()
     op = OM.MriOperator(128, inst.meta["freqs"], A=inst.A)
     t = time.perf_counter()
     sigma, R, hist = OM.solve(op, inst.y, MRI_CIM, O.with_params(MRI_OUTER, seed=seed),
@@ -88,6 +102,23 @@ def one_mri(seed):
     Rf[S] = R_S
     dt = time.perf_counter() - t
     return seed, int(sigma.sum()), O.rmse(sigma, Rf, inst.x, inst.xi), bitmask_hex(sigma), dt
+
+
+MRI_L2 = dict(gamma=1e-4, lam1=3e-4, lasso_iters=200, cg_max_iter=10000, cg_tol=1e-5)
+
+
+def one_mri_l2(seed):
+    from oracle import mri as OM
+    from oracle import mri_l2 as L2
+    from workloads import mri as WM
+    inst = WM.mri_instance(seed)
+    hop = L2.L2Operator(OM.MriOperator(128, inst.meta["freqs"], A=inst.A), MRI_L2["gamma"])
+    t = time.perf_counter()
+    sigma, R, hist = L2.solve(hop, inst.y, MRI_CIM, O.with_params(MRI_OUTER, seed=seed), MRI_L2["lam1"],
+                              MRI_L2["lasso_iters"], MRI_L2["cg_max_iter"], MRI_L2["cg_tol"],
+                              progress=lambda i, h: print(f"  seed {seed} alternation {i}: {h}", flush=True))
+    dt = time.perf_counter() - t
+    return seed, int(sigma.sum()), O.rmse(sigma, R, inst.x, inst.xi), bitmask_hex(sigma), dt
 
 
 BATCH_SEED, BATCH_COUNT, BATCH_SAMPLE = 7, 256, list(range(0, 256, 16))
@@ -131,6 +162,10 @@ def one(args):
     name, seed = args
     if name == "mri":
         return one_mri(seed)
+    if name == "mri_f32in":
+        return one_mri(seed, f32_inputs=True)
+    if name == "mri_l2":
+        return one_mri_l2(seed)
     if name in PREC_FORMATS:
         return one_prec(name, seed)
     if name in MULTI:

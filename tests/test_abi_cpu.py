@@ -89,8 +89,8 @@ def test_init_r_rejects_bad_arguments_on_host():
 def test_mri_run_rejects_bad_arguments_on_host():
     lib = L.lib()
     prm = L.cim_params()
-    call = lambda size=128, levels=3, P=2, mask=FAKE, ts=0, tr=None: lib.l0cim_mri_mfcim_run(
-        size, levels, P, mask, FAKE, FAKE, 1, FAKE, 0.1, ctypes.byref(prm), FAKE, FAKE, FAKE, None, tr, ts,
+    call = lambda size=128, levels=3, P=2, mask=FAKE, ts=0, tr=None, gamma=0.0: lib.l0cim_mri_mfcim_run(
+        size, levels, P, mask, FAKE, FAKE, 1, FAKE, gamma, 0.1, ctypes.byref(prm), FAKE, FAKE, FAKE, None, tr, ts,
         None, None)
     assert call(mask=None) == 1
     assert call(P=0) == 2
@@ -98,7 +98,36 @@ def test_mri_run_rejects_bad_arguments_on_host():
     assert call(levels=40) == 2
     assert call(levels=-1) == 2
     assert call(ts=5) == 1
+    assert call(gamma=-1.0) == 1
     assert call(size=64) == 5          # the 128 x 128 image only
+
+
+def test_mri_pipeline_entry_points_reject_bad_arguments_on_host():
+    lib = L.lib()
+    assert lib.l0cim_mri_l2_diag(128, 3, 1e-4, None, 1, FAKE, None) == 1
+    assert lib.l0cim_mri_l2_diag(128, 8, 1e-4, FAKE, 1, FAKE, None) == 2
+    assert lib.l0cim_mri_l2_diag(64, 3, 1e-4, FAKE, 1, FAKE, None) == 5
+    assert lib.l0cim_mri_l2_diag(128, 3, -1.0, FAKE, 1, FAKE, None) == 1
+    assert lib.l0cim_mri_lasso(128, 3, 1e-4, FAKE, FAKE, 3e-4, -1, FAKE, None) == 1
+    assert lib.l0cim_mri_lasso(128, 3, 1e-4, None, FAKE, 3e-4, 10, FAKE, None) == 1
+    upd = lambda cdp=L.CDP_CG, iters=100, cg_max=100, tol=1e-5: lib.l0cim_mri_update_r(
+        128, 3, 1e-4, FAKE, FAKE, 1, FAKE, FAKE, cdp, 0.1, iters, cg_max, tol, FAKE, None, None, None)
+    assert upd(cdp=L.CDP_CHOL_F64) == 5
+    assert upd(cdp=L.CDP_JACOBI, iters=-1) == 1
+    assert upd(cg_max=-1) == 1
+    assert upd(tol=-1.0) == 1
+    mp, cim, sp = L.mri_params(), L.cim_params(), L.solve_params(replicas=2)
+    assert lib.l0cim_mri_solve_workspace_bytes(4915, 64, 0) > 64 * 16384 * 9
+    assert lib.l0cim_mri_solve_workspace_bytes(0, 64, 0) == 0
+    solve = lambda mp=mp, sp=sp, ws=FAKE, nbytes=1 << 40, m=10: lib.l0cim_mri_solve(
+        ctypes.byref(mp), m, FAKE, 16384, FAKE, FAKE, ctypes.byref(cim), ctypes.byref(sp), FAKE, FAKE, FAKE, ws,
+        nbytes, None)
+    assert solve(ws=None) == 3
+    assert solve(nbytes=10) == 3
+    assert solve(m=0) == 2
+    assert solve(mp=L.mri_params(cdp=L.CDP_CHOL_F64)) == 5
+    assert solve(mp=L.mri_params(gamma=1e-4), sp=L.solve_params(replicas=2, final_refit_f64=1)) == 5
+    assert solve(sp=L.solve_params(replicas=0)) == 1
 
 
 def test_couplings_rejects_bad_arguments_on_host():

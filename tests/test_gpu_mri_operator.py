@@ -71,7 +71,9 @@ def oracle_trace(op, R, z, c0, eta, prm, steps):
 
 
 @pytest.mark.parametrize("field,P,levels,Rkind", [("CN", 2, 3, "ls"), ("BN", 2, 3, "ls"),
-                                                  ("CN", 1, 1, "random"), ("BN", 3, 3, "random")])
+                                                  ("CN", 1, 1, "random"), ("BN", 3, 3, "random"),
+                                                  ("CN", 1, 0, "random"), ("CN", 1, 2, "random"),
+                                                  ("CN", 1, 4, "random"), ("CN", 1, 7, "random")])
 def test_mri_run_trace_parity(dev, mri_case, field, P, levels, Rkind):
     steps, eta, seed, n = 200, 0.022, 4, 128 * 128
     R = mri_case["R"] if Rkind == "ls" else f32(W.random_r(seed, n, 0.3))
