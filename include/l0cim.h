@@ -321,6 +321,65 @@ l0cim_status l0cim_mri_update_r(int32_t size, int32_t levels, double gamma, cons
                                 int32_t iters, int32_t cg_max_iter, double cg_tol, float* R, int32_t* iters_out,
                                 int32_t* status, void* stream);
 
+/*
+ * CAC-CIM (Positive-P) form: the stochastic CIM the paper compares the
+ * mean-field model against (eq. 5-11), as the sigma-minimiser of Algorithm 1
+ * on the same couplings.  Per spin and replica: mean amplitude mu (eq. 5),
+ * fluctuation variances n, m (eq. 6, 7), amplitude control e (eq. 9); the
+ * field uses the measured amplitudes mu~ = mu + sqrt(g2/(4j)) W (eq. 10):
+ *   R_r h_r = 1/2 (J (mu~ + sqrt(tau)))_r + sqrt(tau) z_r     (eq. 11),
+ *   inj = j e (R h - sqrt(tau) eta^2 / 4)                    (eq. 8).
+ * Forward Euler-Maruyama with time increment dt: one standard normal xi per
+ * spin, replica and step, W taken as its step average xi / sqrt(dt) (noise
+ * increment of eq. 5: sqrt(j g2)(m + n) xi sqrt(dt)), every right-hand side
+ * at step k, pump of eq. 21 at t = k dt.  The normals are counter-based:
+ * SplitMix64 keyed by mix64(seed ^ 0x6E6F6973655F7764), outputs 2 ctr + 1
+ * and 2 ctr + 2 with ctr = (alt << 52) | (k << 32) | (q << 24) | r, two
+ * 53-bit uniforms, Box-Muller in FP64.  A run starts from mu = n = m = 0 and
+ * e = 1 (Algorithm 1) and returns sigma = H(mu) of the last step.
+ */
+typedef struct {
+  double dt;                 /* 0.02 */
+  int32_t n_steps;           /* Euler steps per run, < 2^20 - 1 */
+  double p_thr, d, t_c, t_w; /* pump, eq. 21: 1, 0.4, 4, 2 */
+  double K, j, beta;         /* feedback strength (1 for random data), out-coupling rate, CAC rate */
+  double tau;                /* target amplitude: 0.21 (noise 0.05) or 0.15 (noise 0.1) */
+  double g2;                 /* saturation parameter g^2 (1e-7) */
+} l0cim_cac_params;
+
+void l0cim_cac_params_default(l0cim_cac_params* p);
+
+/*
+ * l0cim_cac_run -- prm->n_steps steps of the CAC-CIM for P replicas (P <= 256)
+ * sharing J (n x n, ldj >= n, zero diagonal) and z (n), both in dtype (F32 or
+ * F64), at threshold eta; alternation index alt (0 .. 2047) and seed key the
+ * noise.  mu, nvar, mvar, e: P x n outputs (final state); sigma: P x n bytes,
+ * H(mu); H (P doubles, may be NULL): the eq. 4 energy of each sigma with
+ * lambda = eta^2 / 2; trace (may be NULL): k x 4 x P x n values (mu, n, m, e
+ * after step k + 1) for k < trace_steps.  ws: at least
+ * l0cim_cac_run_workspace_bytes bytes (two buffers of measured amplitudes and
+ * the energy terms).  One launch per Euler step, each wavefront one row of J.
+ */
+size_t l0cim_cac_run_workspace_bytes(l0cim_dtype dtype, int32_t n, int32_t P);
+l0cim_status l0cim_cac_run(l0cim_dtype dtype, int32_t n, int32_t P, const void* J, int64_t ldj, const void* z,
+                           double eta, const l0cim_cac_params* prm, uint64_t seed, int32_t alt, void* mu,
+                           void* nvar, void* mvar, void* e, uint8_t* sigma, double* H, void* trace,
+                           int32_t trace_steps, int32_t* status, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * l0cim_cac_solve -- Algorithm 1 with the CAC-CIM as the sigma-minimiser:
+ * G, b = gram(A, y); R = b / diag(G); per alternation i < n_outer (at most
+ * 2048): eta_i (eq. 22), J, z from R, l0cim_cac_run(seed, alt = i), the
+ * lowest-energy replica, the Jacobi CDP (dtc, cdp_iters); then the eq. 3
+ * objective into stats.  sp supplies the schedule, replicas, seed and CDP
+ * constants (j_dtype and final_refit_f64 are not used).  ws: at least
+ * l0cim_cac_solve_workspace_bytes bytes.
+ */
+size_t l0cim_cac_solve_workspace_bytes(l0cim_dtype dtype, int32_t m, int32_t n, int32_t P);
+l0cim_status l0cim_cac_solve(l0cim_dtype dtype, int32_t m, int32_t n, const void* A, int64_t lda, const void* y,
+                             const l0cim_cac_params* prm, const l0cim_solve_params* sp, void* R_out,
+                             uint8_t* sigma_out, l0cim_stats* stats, void* ws, size_t ws_bytes, void* stream);
+
 /* Parameters of the MRI-shaped solve. */
 typedef struct {
   int32_t size;              /* image side (128) */
@@ -557,6 +616,33 @@ int32_t l0cim_server_completed(l0cim_server server, l0cim_completion* out, int32
 l0cim_status l0cim_server_info(l0cim_server server, int32_t* active, int32_t* pending, size_t* bytes_in_use,
                                size_t* heap_bytes, int64_t* ticks);
 l0cim_status l0cim_server_destroy(l0cim_server server);
+
+/*
+ * The serving scheduler with no device: the same admission (arrival order,
+ * a free slot, first fit in the arena heap, the step budget when set and
+ * something is resident; the first request that does not fit stops
+ * admission), slot reuse and retirement as l0cim_server_*, on request sizes
+ * alone (l0cim_server_request_bytes), driven by the caller's clock.  For
+ * sizing an arena, choosing slots and a step budget on the host, and testing
+ * the scheduling without a GPU.  A tick admits at t_start, advances every
+ * resident request by one alternation, and retires at t_end those that have
+ * done n_outer.  l0cim_server_sim_resident fills up to `max` entries (tag,
+ * slot, heap offset, alternations done) in resident order and returns the
+ * resident count; free_blocks is the number of free heap extents.
+ */
+typedef struct l0cim_server_sim_s* l0cim_server_sim;
+l0cim_status l0cim_server_sim_create(const l0cim_solve_params* sp, int32_t max_slots, int32_t max_n,
+                                     size_t arena_bytes, l0cim_server_sim* sim);
+l0cim_status l0cim_server_sim_submit(l0cim_server_sim sim, int32_t m, int32_t n, int64_t tag, double t_submit);
+l0cim_status l0cim_server_sim_set_step_budget(l0cim_server_sim sim, size_t bytes);
+l0cim_status l0cim_server_sim_tick(l0cim_server_sim sim, double t_start, double t_end, int32_t* admitted,
+                                   int32_t* completed);
+int32_t l0cim_server_sim_completed(l0cim_server_sim sim, l0cim_completion* out, int32_t max);
+int32_t l0cim_server_sim_resident(l0cim_server_sim sim, int64_t* tags, int32_t* slots, size_t* offsets,
+                                  int32_t* alternations, int32_t max);
+l0cim_status l0cim_server_sim_info(l0cim_server_sim sim, int32_t* active, int32_t* pending, size_t* bytes_in_use,
+                                   size_t* heap_bytes, int32_t* free_blocks);
+l0cim_status l0cim_server_sim_destroy(l0cim_server_sim sim);
 
 /*
  * Tile shape of the single-instance matrix-core run (several replicas): rows

@@ -68,3 +68,39 @@ def initial_state(seed: int, i: int, P: int, N: int, std: float):
     """(c0, e0) for alternation i: c0 = std * normal draws, e0 = 1."""
     c0 = std * standard_normals(seed, i, P, N)
     return c0, np.ones((P, N))
+
+
+# ----------------------------------------------------------------------------
+# Per-step noise of the CAC-CIM stochastic differential equations
+# ----------------------------------------------------------------------------
+#
+# The Positive-P CAC-CIM (eq. 5-11) is driven by a real white noise W_r(t),
+# drawn once per Euler step, spin and replica.  Its normals come from a second
+# SplitMix64 stream whose seed is the finaliser of the solve seed XOR a fixed
+# tag, so that it never overlaps the stream of the initial amplitudes:
+#     s_noise = mix64(seed ^ NOISE_TAG)
+# and the counter of the draw for alternation i, Euler step k, replica q,
+# spin r is
+#     ctr = (i << 52) | (k << 32) | (q << 24) | r
+#     (i < 2^11, k < 2^20, q < 2^8, r < 2^24),
+# with the two uniforms at outputs 2 ctr + 1 and 2 ctr + 2, Box-Muller as above.
+
+NOISE_TAG = 0x6E6F6973655F7764     # "noise_wd" as ASCII bytes
+
+
+def noise_seed(seed: int) -> int:
+    return int(mix64(np.uint64((seed ^ NOISE_TAG) & 0xFFFFFFFFFFFFFFFF)))
+
+
+def step_normals(seed: int, i: int, k: int, P: int, N: int) -> np.ndarray:
+    """(P, N) standard normals of Euler step k of alternation i."""
+    if not (0 <= i < 1 << 11 and 0 <= k < 1 << 20 and 0 < P <= 1 << 8 and 0 < N <= 1 << 24):
+        raise ValueError("noise counter fields out of range")
+    q = np.arange(P, dtype=np.uint64)[:, None]
+    r = np.arange(N, dtype=np.uint64)[None, :]
+    ctr = (np.uint64(i) << np.uint64(52)) | (np.uint64(k) << np.uint64(32)) | (q << np.uint64(24)) | r
+    s = noise_seed(seed)
+    with np.errstate(over="ignore"):
+        u1 = uniform53(splitmix64(s, np.uint64(2) * ctr + np.uint64(1)))
+        u2 = uniform53(splitmix64(s, np.uint64(2) * ctr + np.uint64(2)))
+    return np.sqrt(-2.0 * np.log1p(-u1)) * np.cos(2.0 * np.pi * u2)

@@ -61,6 +61,12 @@ class SolveParams(ctypes.Structure):
     ]
 
 
+class CacParams(ctypes.Structure):
+    _fields_ = [("dt", c_double), ("n_steps", c_int32), ("p_thr", c_double), ("d", c_double), ("t_c", c_double),
+                ("t_w", c_double), ("K", c_double), ("j", c_double), ("beta", c_double), ("tau", c_double),
+                ("g2", c_double)]
+
+
 class MriParams(ctypes.Structure):
     _fields_ = [("size", c_int32), ("levels", c_int32), ("gamma", c_double), ("lasso_iters", c_int32),
                 ("lasso_lam1", c_double), ("cdp", c_int32), ("cg_max_iter", c_int32), ("cg_tol", c_double)]
@@ -152,6 +158,18 @@ def lib():
         L.l0cim_mri_solve.argtypes = [POINTER(MriParams), c_int32, vp, c_int64, vp, vp, POINTER(CimParams),
                                       POINTER(SolveParams), vp, vp, vp, vp, c_size_t, vp]
         L.l0cim_mri_solve.restype = st
+        L.l0cim_cac_params_default.argtypes = [POINTER(CacParams)]
+        L.l0cim_cac_params_default.restype = None
+        L.l0cim_cac_run_workspace_bytes.argtypes = [c_int, c_int32, c_int32]
+        L.l0cim_cac_run_workspace_bytes.restype = c_size_t
+        L.l0cim_cac_run.argtypes = [c_int, c_int32, c_int32, vp, c_int64, vp, c_double, POINTER(CacParams), c_uint64,
+                                    c_int32, vp, vp, vp, vp, vp, vp, vp, c_int32, vp, vp, c_size_t, vp]
+        L.l0cim_cac_run.restype = st
+        L.l0cim_cac_solve_workspace_bytes.argtypes = [c_int, c_int32, c_int32, c_int32]
+        L.l0cim_cac_solve_workspace_bytes.restype = c_size_t
+        L.l0cim_cac_solve.argtypes = [c_int, c_int32, c_int32, vp, c_int64, vp, POINTER(CacParams),
+                                      POINTER(SolveParams), vp, vp, vp, vp, c_size_t, vp]
+        L.l0cim_cac_solve.restype = st
         L.l0cim_select_replica.argtypes = [c_int32, c_int32, vp, vp, vp, vp, vp]
         L.l0cim_select_replica.restype = st
         L.l0cim_update_r_workspace_bytes.argtypes = [c_int, c_int32, c_int]
@@ -190,6 +208,24 @@ def lib():
         L.l0cim_server_request_bytes.restype = c_size_t
         L.l0cim_server_arena_overhead.argtypes = [c_int32, c_int32, POINTER(SolveParams)]
         L.l0cim_server_arena_overhead.restype = c_size_t
+        L.l0cim_server_sim_create.argtypes = [POINTER(SolveParams), c_int32, c_int32, c_size_t, POINTER(c_void_p)]
+        L.l0cim_server_sim_create.restype = st
+        L.l0cim_server_sim_submit.argtypes = [c_void_p, c_int32, c_int32, c_int64, c_double]
+        L.l0cim_server_sim_submit.restype = st
+        L.l0cim_server_sim_set_step_budget.argtypes = [c_void_p, c_size_t]
+        L.l0cim_server_sim_set_step_budget.restype = st
+        L.l0cim_server_sim_tick.argtypes = [c_void_p, c_double, c_double, POINTER(c_int32), POINTER(c_int32)]
+        L.l0cim_server_sim_tick.restype = st
+        L.l0cim_server_sim_completed.argtypes = [c_void_p, POINTER(Completion), c_int32]
+        L.l0cim_server_sim_completed.restype = c_int32
+        L.l0cim_server_sim_resident.argtypes = [c_void_p, POINTER(c_int64), POINTER(c_int32), POINTER(c_size_t),
+                                                POINTER(c_int32), c_int32]
+        L.l0cim_server_sim_resident.restype = c_int32
+        L.l0cim_server_sim_info.argtypes = [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_size_t),
+                                            POINTER(c_size_t), POINTER(c_int32)]
+        L.l0cim_server_sim_info.restype = st
+        L.l0cim_server_sim_destroy.argtypes = [c_void_p]
+        L.l0cim_server_sim_destroy.restype = st
         L.l0cim_server_create.argtypes = [POINTER(CimParams), POINTER(SolveParams), c_int32, c_int32, vp,
                                           c_size_t, vp, POINTER(c_void_p)]
         L.l0cim_server_create.restype = st
@@ -400,6 +436,44 @@ def l0cim_mri_update_r(size: int, levels: int, gamma: float, mask, D, b, sigma, 
                                     iters, cg_max_iter, cg_tol, _ptr(R), _ptr(iters_out), _ptr(status),
                                     _stream(stream)), "l0cim_mri_update_r")
     return R
+
+
+def cac_params(**kw) -> CacParams:
+    """CAC-CIM defaults (random data, noise 0.05) with keyword overrides."""
+    p = CacParams()
+    lib().l0cim_cac_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def l0cim_cac_run(J, z, eta: float, prm: CacParams, seed: int, alt: int, P: int, H=None, trace=None,
+                  trace_steps: int = 0, status=None, ws=None, stream=None):
+    """CAC-CIM run; returns (mu, n, m, e, sigma) as new device tensors."""
+    n = J.shape[0]
+    dt = _dtype_code(J)
+    mu, nv, mv, e = (torch.empty((P, n), dtype=J.dtype, device=J.device) for _ in range(4))
+    sigma = torch.empty((P, n), dtype=torch.uint8, device=J.device)
+    ws = workspace(lib().l0cim_cac_run_workspace_bytes(dt, n, P), J.device) if ws is None else ws
+    _check(lib().l0cim_cac_run(dt, n, P, _ptr(J), _ld(J), _ptr(z), eta, ctypes.byref(prm), seed, alt, _ptr(mu),
+                               _ptr(nv), _ptr(mv), _ptr(e), _ptr(sigma), _ptr(H), _ptr(trace), trace_steps,
+                               _ptr(status), _ptr(ws), ws.numel(), _stream(stream)), "l0cim_cac_run")
+    return mu, nv, mv, e, sigma
+
+
+def l0cim_cac_solve(A, y, prm: CacParams, sp: SolveParams, R_out=None, sigma_out=None, stats=None, ws=None,
+                    stream=None):
+    """Algorithm 1 with the CAC-CIM.  Returns (R, sigma, stats_bytes_tensor)."""
+    m, n = A.shape
+    dt = _dtype_code(A)
+    R_out = torch.empty(n, dtype=A.dtype, device=A.device) if R_out is None else R_out
+    sigma_out = torch.empty(n, dtype=torch.uint8, device=A.device) if sigma_out is None else sigma_out
+    stats = torch.zeros(STATS_BYTES, dtype=torch.uint8, device=A.device) if stats is None else stats
+    ws = workspace(lib().l0cim_cac_solve_workspace_bytes(dt, m, n, sp.replicas), A.device) if ws is None else ws
+    _check(lib().l0cim_cac_solve(dt, m, n, _ptr(A), _ld(A), _ptr(y), ctypes.byref(prm), ctypes.byref(sp),
+                                 _ptr(R_out), _ptr(sigma_out), _ptr(stats), _ptr(ws), ws.numel(), _stream(stream)),
+           "l0cim_cac_solve")
+    return R_out, sigma_out, stats
 
 
 def mri_params(**kw) -> MriParams:

@@ -20,7 +20,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libl0cim.so")
 ARCH = os.environ.get("L0CIM_ARCH", "gfx950")
 
-SOURCES = ["api.hip", "gram.hip", "couplings.hip", "mfcim.hip", "cdp.hip", "batch.hip", "batch_plan.hip", "mfcim_matrix.hip", "chol.hip", "server.hip", "mri.hip", "noalloc.hip", "mri_api.hip"]
+SOURCES = ["api.hip", "gram.hip", "couplings.hip", "mfcim.hip", "cdp.hip", "batch.hip", "batch_plan.hip", "mfcim_matrix.hip", "chol.hip", "server.hip", "mri.hip", "noalloc.hip", "mri_api.hip", "cac.hip"]
 
 CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

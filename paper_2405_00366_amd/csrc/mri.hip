@@ -1019,11 +1019,8 @@ l0cim_status launch_mri_cg(int size, int levels, double gamma, const uint8_t* ma
   const size_t lds = sizeof(MriLds);
   L0_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(mri_cg_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
                              int(lds)));
-  {
-    ProfileScope prof(s);
-    hipLaunchKernelGGL(mri_cg_kernel, dim3(1), dim3(kBS), lds, s, mask, levels, float(gamma), D, incd, b, sigma, R,
-                       max_iter, tol, iters_out, status);
-  }
+  hipLaunchKernelGGL(mri_cg_kernel, dim3(1), dim3(kBS), lds, s, mask, levels, float(gamma), D, incd, b, sigma, R,
+                     max_iter, tol, iters_out, status);
   L0_LAUNCHED("mri_cg_kernel");
   return L0CIM_OK;
 }

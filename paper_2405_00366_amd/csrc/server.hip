@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "batch.h"
+#include "serve_sched.h"
 
 using namespace l0;
 
@@ -119,12 +120,7 @@ struct l0cim_server_s {
   size_t arena_bytes, heap0;
   HeadLayout head;
   hipStream_t stream;
-  std::map<size_t, size_t> free_blocks;   // offset -> bytes, coalesced
-  size_t in_use = 0;
-  size_t step_budget = 0, step_active = 0;
-  std::deque<Req> pending;
-  std::vector<Req> active;
-  std::vector<int> free_slots;
+  ServeSched<Req> q;                      // heap, slots, queue, admission, retirement
   std::vector<l0cim_completion> done;
   void* staging = nullptr;
   size_t staging_bytes = 0;
@@ -135,38 +131,6 @@ struct l0cim_server_s {
 
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  }
-
-  bool alloc(size_t bytes, size_t* off) {
-    for (auto it = free_blocks.begin(); it != free_blocks.end(); ++it) {
-      if (it->second >= bytes) {
-        *off = it->first;
-        const size_t rest = it->second - bytes;
-        const size_t at = it->first + bytes;
-        free_blocks.erase(it);
-        if (rest) free_blocks[at] = rest;
-        in_use += bytes;
-        return true;
-      }
-    }
-    return false;
-  }
-
-  void release(size_t off, size_t bytes) {
-    in_use -= bytes;
-    auto it = free_blocks.emplace(off, bytes).first;
-    auto nx = std::next(it);
-    if (nx != free_blocks.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_blocks.erase(nx);
-    }
-    if (it != free_blocks.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_blocks.erase(it);
-      }
-    }
   }
 
   double eta_of(int alt) const {
@@ -242,29 +206,16 @@ l0cim_status tick(l0cim_server_s* sv, int* n_done) {
   const double t_start = sv->now();
   // admission: arrival order, stop at the first request that does not fit
   // (in memory, or in the step budget unless nothing is resident)
-  while (!sv->pending.empty() && !sv->free_slots.empty()) {
-    Req& r = sv->pending.front();
-    if (sv->step_budget && !sv->active.empty() && sv->step_active + r.cost > sv->step_budget) break;
-    size_t off = 0;
-    if (!sv->alloc(r.bytes, &off)) break;
-    sv->step_active += r.cost;
-    r.off = off;
-    r.slot = sv->free_slots.back();
-    sv->free_slots.pop_back();
-    r.alt = 0;
-    r.t_admit = t_start;
-    Req q = r;
-    sv->pending.pop_front();
-    sv->active.push_back(q);
-    L0_TRY(admit(sv, sv->active.back(), s));
-  }
+  const int added = sv->q.admit(t_start);
+  for (size_t k = sv->q.active.size() - size_t(added); k < sv->q.active.size(); ++k)
+    L0_TRY(admit(sv, sv->q.active[k], s));
   *n_done = 0;
-  if (sv->active.empty()) return L0CIM_OK;
-  const int count = int(sv->active.size());
+  if (sv->q.active.empty()) return L0CIM_OK;
+  const int count = int(sv->q.active.size());
   // tile shape: the largest row block that still gives every CU four tiles
   auto tiles_for = [&](int rb) {
     int64_t t = 0;
-    for (const Req& r : sv->active) t += (r.n + 16 * rb - 1) / (16 * rb);
+    for (const Req& r : sv->q.active) t += (r.n + 16 * rb - 1) / (16 * rb);
     return t;
   };
   int rb = 1;
@@ -283,12 +234,12 @@ l0cim_status tick(l0cim_server_s* sv, int* n_done) {
   int64_t* hst = reinterpret_cast<int64_t*>(h + (sv->head.stp - sv->head.insts));
   std::vector<int> order(count);
   for (int k = 0; k < count; ++k) order[k] = k;
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return sv->active[x].n > sv->active[y].n; });
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return sv->q.active[x].n > sv->q.active[y].n; });
   int nt = 0;
   hrow[0] = 0;
   hst[0] = 0;
   for (int k = 0; k < count; ++k) {
-    const Req& r = sv->active[k];
+    const Req& r = sv->q.active[k];
     hi[k] = sv->make_inst(r);
     hrow[k + 1] = hrow[k] + round_up16(r.n);
     hst[k + 1] = hst[k] + int64_t(sv->P) * hi[k].ld;
@@ -300,7 +251,7 @@ l0cim_status tick(l0cim_server_s* sv, int* n_done) {
   }
   int nret = 0;
   for (int k = 0; k < count; ++k)
-    if (sv->active[k].alt + 1 >= sv->sp.n_outer) hr[nret++] = hi[k];
+    if (sv->q.finishing(sv->q.active[k])) hr[nret++] = hi[k];
   // the staging buffer mirrors the head layout from the instance table on
   BatchDev d{};
   d.count = count;
@@ -347,8 +298,8 @@ l0cim_status tick(l0cim_server_s* sv, int* n_done) {
                                    hr[k].status, sv->arena + sv->head.chol, chol_ws_bytes(sv->max_n), s));
     }
     L0_TRY(launch_bobjective(dr, -1.0, sv->cim.n_steps, 0, sv->P, s));
-    for (const Req& r : sv->active) {
-      if (r.alt + 1 < sv->sp.n_outer) continue;
+    for (const Req& r : sv->q.active) {
+      if (!sv->q.finishing(r)) continue;
       const BInst I = sv->make_inst(r);
       L0_HIP(hipMemcpyAsync(r.R_out, I.R, size_t(r.n) * 4, hipMemcpyDeviceToDevice, s));
       L0_HIP(hipMemcpyAsync(r.sig_out, I.sig, size_t(r.n), hipMemcpyDeviceToDevice, s));
@@ -358,28 +309,19 @@ l0cim_status tick(l0cim_server_s* sv, int* n_done) {
   L0_HIP(hipEventRecord(sv->tick_done, s));
   L0_HIP(hipEventSynchronize(sv->tick_done));
   const double t_end = sv->now();
-  std::vector<Req> keep;
-  keep.reserve(sv->active.size());
-  for (Req& r : sv->active) {
-    if (r.alt + 1 >= sv->sp.n_outer) {
-      l0cim_completion c{};
-      c.tag = r.tag;
-      c.n = r.n;
-      c.m = r.m;
-      c.t_submit = r.t_submit;
-      c.t_admit = r.t_admit;
-      c.t_finish = t_end;
-      sv->done.push_back(c);
-      sv->release(r.off, r.bytes);
-      sv->step_active -= r.cost;
-      sv->free_slots.push_back(r.slot);
-      ++*n_done;
-    } else {
-      ++r.alt;
-      keep.push_back(r);
-    }
+  std::vector<Req> fin;
+  sv->q.retire(fin);
+  for (const Req& r : fin) {
+    l0cim_completion c{};
+    c.tag = r.tag;
+    c.n = r.n;
+    c.m = r.m;
+    c.t_submit = r.t_submit;
+    c.t_admit = r.t_admit;
+    c.t_finish = t_end;
+    sv->done.push_back(c);
   }
-  sv->active.swap(keep);
+  *n_done = int(fin.size());
   ++sv->ticks;
   return L0CIM_OK;
 }
@@ -436,8 +378,7 @@ l0cim_status l0cim_server_create(const l0cim_cim_params* cim, const l0cim_solve_
   sv->heap0 = H.total;
   sv->stream = static_cast<hipStream_t>(stream);
   const size_t heap = (arena_bytes - H.total) / kAlign * kAlign;
-  sv->free_blocks[H.total] = heap;
-  for (int k = max_slots - 1; k >= 0; --k) sv->free_slots.push_back(k);
+  sv->q.init(max_slots, H.total, heap, sp->n_outer);
   sv->staging_bytes = H.stats - H.insts;
   hipError_t he = hipHostMalloc(&sv->staging, sv->staging_bytes, hipHostMallocDefault);
   if (he == hipSuccess) he = hipEventCreateWithFlags(&sv->tick_done, hipEventDisableTiming);
@@ -481,13 +422,13 @@ l0cim_status l0cim_server_submit(l0cim_server sv, int32_t m, int32_t n, const fl
                      sv->arena_bytes - sv->heap0);
   r.t_submit = sv->now();
   r.slot = -1;
-  sv->pending.push_back(r);
+  sv->q.pending.push_back(r);
   return L0CIM_OK;
 }
 
 l0cim_status l0cim_server_set_step_budget(l0cim_server sv, size_t bytes) {
   if (!sv) return set_error(L0CIM_ERR_ARG, "server_set_step_budget: NULL server");
-  sv->step_budget = bytes;
+  sv->q.step_budget = bytes;
   return L0CIM_OK;
 }
 
@@ -512,9 +453,9 @@ int32_t l0cim_server_completed(l0cim_server sv, l0cim_completion* out, int32_t m
 l0cim_status l0cim_server_info(l0cim_server sv, int32_t* active, int32_t* pending, size_t* bytes_in_use,
                                size_t* heap_bytes, int64_t* ticks) {
   if (!sv) return set_error(L0CIM_ERR_ARG, "server_info: NULL server");
-  if (active) *active = int32_t(sv->active.size());
-  if (pending) *pending = int32_t(sv->pending.size());
-  if (bytes_in_use) *bytes_in_use = sv->in_use;
+  if (active) *active = int32_t(sv->q.active.size());
+  if (pending) *pending = int32_t(sv->q.pending.size());
+  if (bytes_in_use) *bytes_in_use = sv->q.in_use;
   if (heap_bytes) *heap_bytes = (sv->arena_bytes - sv->heap0) / kAlign * kAlign;
   if (ticks) *ticks = sv->ticks;
   return L0CIM_OK;
@@ -528,6 +469,143 @@ l0cim_status l0cim_server_destroy(l0cim_server sv) {
   }
   if (sv->staging) (void)hipHostFree(sv->staging);
   delete sv;
+  return L0CIM_OK;
+}
+
+}  // extern "C"
+
+// ---- the scheduler alone: admission, slots and heap with no device -------
+
+namespace {
+
+struct SimReq {
+  int64_t tag;
+  int m, n;
+  size_t bytes, cost, off;
+  int slot, alt;
+  double t_submit, t_admit;
+};
+
+}  // namespace
+
+struct l0cim_server_sim_s {
+  l0cim_solve_params sp;
+  size_t jsz;
+  int P, max_n;
+  size_t heap0;
+  ServeSched<SimReq> q;
+  std::vector<l0cim_completion> done;
+};
+
+extern "C" {
+
+l0cim_status l0cim_server_sim_create(const l0cim_solve_params* sp, int32_t max_slots, int32_t max_n,
+                                     size_t arena_bytes, l0cim_server_sim* out) {
+  if (!sp || !out) return set_error(L0CIM_ERR_ARG, "server_sim_create: NULL pointer");
+  if (max_slots < 1 || max_slots > 4096) return set_error(L0CIM_ERR_ARG, "server_sim_create: max_slots must be 1..4096");
+  if (max_n < 1 || max_n > 12288) return set_error(L0CIM_ERR_SHAPE, "server_sim_create: max_n must be 1..12288");
+  if (sp->replicas < 1 || sp->replicas > 64 || sp->n_outer <= 0 || sp->n_outer >= (1 << 24))
+    return set_error(L0CIM_ERR_ARG, "server_sim_create: replicas 1..64 and a positive n_outer");
+  const l0cim_dtype jdt = l0cim_dtype(sp->j_dtype);
+  if (jdt != L0CIM_F32 && jdt != L0CIM_BF16 && jdt != L0CIM_FP8E4M3)
+    return set_error(L0CIM_ERR_UNSUPPORTED, "server couplings: F32, BF16 or FP8E4M3");
+  const HeadLayout H = head_layout(max_slots, max_n, sp->final_refit_f64 != 0);
+  if (arena_bytes < H.total + kAlign)
+    return set_error(L0CIM_ERR_WORKSPACE, "server_sim_create: arena needs more than %zu bytes", H.total);
+  auto* sim = new l0cim_server_sim_s();
+  sim->sp = *sp;
+  sim->jsz = dtype_size(jdt);
+  sim->P = sp->replicas;
+  sim->max_n = max_n;
+  sim->heap0 = H.total;
+  sim->q.init(max_slots, H.total, (arena_bytes - H.total) / kAlign * kAlign, sp->n_outer);
+  *out = sim;
+  return L0CIM_OK;
+}
+
+l0cim_status l0cim_server_sim_submit(l0cim_server_sim sim, int32_t m, int32_t n, int64_t tag, double t_submit) {
+  if (!sim) return set_error(L0CIM_ERR_ARG, "server_sim_submit: NULL simulation");
+  if (m <= 0 || n <= 0) return set_error(L0CIM_ERR_SHAPE, "server_sim_submit: bad shape");
+  if (n > sim->max_n) return set_error(L0CIM_ERR_SHAPE, "server_sim_submit: n = %d above %d", n, sim->max_n);
+  if (sim->sp.final_refit_f64 && chol_a_ws_bytes(n, m) > chol_ws_bytes(sim->max_n))
+    return set_error(L0CIM_ERR_SHAPE, "server_sim_submit: m = %d too large for the FP64 refit scratch", m);
+  SimReq r{};
+  r.tag = tag;
+  r.m = m;
+  r.n = n;
+  r.bytes = req_layout(m, n, sim->P, sim->jsz).total;
+  r.cost = size_t(round_up16(n)) * size_t(round_up32(n)) * sim->jsz;
+  if (r.bytes > sim->q.heap_bytes)
+    return set_error(L0CIM_ERR_WORKSPACE, "server_sim_submit: request needs %zu bytes, the arena holds %zu", r.bytes,
+                     sim->q.heap_bytes);
+  r.slot = -1;
+  r.t_submit = t_submit;
+  sim->q.pending.push_back(r);
+  return L0CIM_OK;
+}
+
+l0cim_status l0cim_server_sim_set_step_budget(l0cim_server_sim sim, size_t bytes) {
+  if (!sim) return set_error(L0CIM_ERR_ARG, "server_sim_set_step_budget: NULL simulation");
+  sim->q.step_budget = bytes;
+  return L0CIM_OK;
+}
+
+l0cim_status l0cim_server_sim_tick(l0cim_server_sim sim, double t_start, double t_end, int32_t* admitted,
+                                   int32_t* completed) {
+  if (!sim) return set_error(L0CIM_ERR_ARG, "server_sim_tick: NULL simulation");
+  const int added = sim->q.admit(t_start);
+  std::vector<SimReq> fin;
+  if (!sim->q.active.empty()) sim->q.retire(fin);
+  for (const SimReq& r : fin) {
+    l0cim_completion c{};
+    c.tag = r.tag;
+    c.n = r.n;
+    c.m = r.m;
+    c.t_submit = r.t_submit;
+    c.t_admit = r.t_admit;
+    c.t_finish = t_end;
+    sim->done.push_back(c);
+  }
+  if (admitted) *admitted = added;
+  if (completed) *completed = int32_t(fin.size());
+  return L0CIM_OK;
+}
+
+int32_t l0cim_server_sim_completed(l0cim_server_sim sim, l0cim_completion* out, int32_t max) {
+  if (!sim || !out || max <= 0) return 0;
+  const int n = int(std::min<size_t>(sim->done.size(), size_t(max)));
+  std::copy(sim->done.begin(), sim->done.begin() + n, out);
+  sim->done.erase(sim->done.begin(), sim->done.begin() + n);
+  return n;
+}
+
+int32_t l0cim_server_sim_resident(l0cim_server_sim sim, int64_t* tags, int32_t* slots, size_t* offsets,
+                                  int32_t* alternations, int32_t max) {
+  if (!sim) return 0;
+  const int n = int(std::min<size_t>(sim->q.active.size(), size_t(max > 0 ? max : 0)));
+  for (int k = 0; k < n; ++k) {
+    const SimReq& r = sim->q.active[k];
+    if (tags) tags[k] = r.tag;
+    if (slots) slots[k] = r.slot;
+    if (offsets) offsets[k] = r.off - sim->heap0;
+    if (alternations) alternations[k] = r.alt;
+  }
+  return int32_t(sim->q.active.size());
+}
+
+l0cim_status l0cim_server_sim_info(l0cim_server_sim sim, int32_t* active, int32_t* pending, size_t* bytes_in_use,
+                                   size_t* heap_bytes, int32_t* free_blocks) {
+  if (!sim) return set_error(L0CIM_ERR_ARG, "server_sim_info: NULL simulation");
+  if (active) *active = int32_t(sim->q.active.size());
+  if (pending) *pending = int32_t(sim->q.pending.size());
+  if (bytes_in_use) *bytes_in_use = sim->q.in_use;
+  if (heap_bytes) *heap_bytes = sim->q.heap_bytes;
+  if (free_blocks) *free_blocks = int32_t(sim->q.free_blocks.size());
+  return L0CIM_OK;
+}
+
+l0cim_status l0cim_server_sim_destroy(l0cim_server_sim sim) {
+  delete sim;
   return L0CIM_OK;
 }
 
