@@ -972,6 +972,100 @@ def accuracy_bench(args, torch, L, W, dev):
     return out
 
 
+def plain_many_bench(args, torch, L, W, dev):
+    """Plain form with K = --instances independent seeds per step: one
+    l0cim_solve_many call solves them together, so the register-resident CIM
+    runs of all K share one cooperative launch and their exchange round trips
+    overlap.  value counts the spin-steps of the instances whose support equals
+    the stored oracle support."""
+    K = args.instances
+    gold = golden_supports()
+    total = (args.warmup + args.steps) * K
+    seeds = sorted(gold)[:total] if len(gold) >= total else list(range(total))
+    groups = [seeds[i * K:(i + 1) * K] for i in range(args.warmup + args.steps)]
+    data = []
+    for g in groups:
+        insts = [W.plain_gaussian(s) for s in g]
+        A = torch.tensor(np.stack([i.A for i in insts]), dtype=torch.float32, device=dev)
+        y = torch.tensor(np.stack([i.y for i in insts]), dtype=torch.float32, device=dev)
+        data.append((g, A, y))
+    cim = L.cim_params(n_steps=STEPS)
+    sp = L.solve_params(eta_init=0.8, eta_end=0.18, velo=OUTER, n_outer=OUTER)
+    ws = L.workspace(L.l0cim_solve_many_workspace_bytes(L.F32, K, M, N, sp), dev)
+    outs = [(torch.empty((K, N), dtype=torch.float32, device=dev), torch.empty((K, N), dtype=torch.uint8, device=dev),
+             torch.zeros(K * L.STATS_BYTES, dtype=torch.uint8, device=dev)) for _ in groups]
+    stream = torch.cuda.current_stream()
+
+    def run(i):
+        g, A, y = data[i]
+        R, sig, st = outs[i]
+        L.l0cim_solve_many(A, y, g, cim, sp, R_out=R, sigma_out=sig, stats=st, ws=ws, stream=stream)
+
+    for i in range(args.warmup):
+        run(i)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    L.l0cim_profile_begin()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(args.steps):
+        run(args.warmup + k)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    cim_ms, cim_launches = L.l0cim_profile_end()
+    lat = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
+    gpu_ms = ev[0].elapsed_time(ev[-1])
+    match, status_bad = 0, 0
+    for k in range(args.steps):
+        i = args.warmup + k
+        sig = outs[i][1].cpu().numpy()
+        sts = L.read_stats_array(outs[i][2], K)
+        for j, s in enumerate(groups[i]):
+            status_bad += int(sts[j].status_bits != 0)
+            if s in gold and mask_to_int(sig[j]) == gold[s]:
+                match += 1
+    spin_steps = N * P * STEPS * OUTER * K
+    elapsed = max(wall, gpu_ms / 1e3)
+    value = spin_steps * (match / K) / elapsed
+    # one launch runs K instances: (2N + 20) flops per spin-step each
+    per_launch_flops = (2 * N + 20) * N * P * STEPS * K
+    avg_launch_s = (cim_ms / 1e3) / max(cim_launches, 1)
+    achieved = per_launch_flops / avg_launch_s / 1e12
+    return {
+        "metric": METRIC,
+        "value": value,
+        "unit": "spin-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD + f"; {K} instances per step (l0cim_solve_many)", "N": N, "M": M,
+                   "replicas": P, "euler_steps": STEPS, "alternations": OUTER, "instances": K,
+                   "seeds": [s for g in groups[args.warmup:] for s in g]},
+        "support_match": f"{match}/{args.steps * K}",
+        "spin_steps_per_s_all": spin_steps * args.steps / elapsed,
+        "spin_steps_per_s_cim_only": N * P * STEPS * K * cim_launches / (cim_ms / 1e3) if cim_ms > 0 else None,
+        "p50_ms": float(np.percentile(lat, 50)),
+        "p99_ms": float(np.percentile(lat, 99)),
+        "status_nonzero": status_bad,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_VECTOR_PEAK_TFS, "traffic": None,
+                     "kernel": "cim_regs_kernel",
+                     "flops_per_launch": per_launch_flops,
+                     "regime": f"{K} instances' couplings held in registers in one cooperative launch; the step "
+                               "time is set by the exchange of amplitudes between workgroups",
+                     "us_per_euler_step": avg_launch_s * 1e6 / STEPS,
+                     "avg_launch_ms": avg_launch_s * 1e3, "launches": cim_launches},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -1002,6 +1096,9 @@ def main():
                     help="precision / batched forms: alternations instead of 11 / 30 (profiling runs)")
     ap.add_argument("--no-graph", action="store_true",
                     help="batched form: launch the Euler steps one by one (no HIP graph replay)")
+    ap.add_argument("--instances", type=int, default=1,
+                    help="plain form: independent instances solved together per step (l0cim_solve_many; their "
+                         "register-resident CIM runs share one launch)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
@@ -1022,6 +1119,9 @@ def main():
         fn = {"batched": batched_bench, "precision": precision_bench, "serving": serving_bench,
               "accuracy": accuracy_bench}[args.form]
         print(json.dumps(fn(args, torch, L, W, dev)), flush=True)
+        return
+    if args.instances > 1:
+        print(json.dumps(plain_many_bench(args, torch, L, W, dev)), flush=True)
         return
     gold = golden_supports()
     seeds = sorted(gold)[: args.warmup + args.steps] if len(gold) >= args.warmup + args.steps else \

@@ -439,6 +439,26 @@ l0cim_status l0cim_update_r(l0cim_dtype dtype, int32_t n, const void* G, int64_t
                             void* R, int32_t* status, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * l0cim_solve_many -- l0cim_solve on `count` independent instances of the
+ * same m x n shape in lockstep: instance k reads A + k strideA (leading
+ * dimension lda) and y + k stridey (elements of dtype), draws its initial
+ * amplitudes with seeds[k] (host array; sp->seed is not used), and writes
+ * R_out + k n, sigma_out + k n and stats[k]; R_init is b / diag(G) for every
+ * instance.  Every step is l0cim_solve's, so each instance's result is the
+ * one l0cim_solve gives it alone (bitwise).  Where the single-replica FP32
+ * run takes its register-resident form, the CIM runs of all instances share
+ * one cooperative launch, so their exchange round trips overlap; when the
+ * instances do not all fit on the device at once (or another form applies)
+ * they run one after another.  ws: at least l0cim_solve_many_workspace_bytes.
+ */
+size_t l0cim_solve_many_workspace_bytes(l0cim_dtype dtype, int32_t count, int32_t m, int32_t n,
+                                        const l0cim_solve_params* sp);
+l0cim_status l0cim_solve_many(l0cim_dtype dtype, int32_t count, int32_t m, int32_t n, const void* A, int64_t lda,
+                              int64_t strideA, const void* y, int64_t stridey, const uint64_t* seeds,
+                              const l0cim_cim_params* cim, const l0cim_solve_params* sp, void* R_out,
+                              uint8_t* sigma_out, l0cim_stats* stats, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * l0cim_refit_f64 -- the least-squares refit of R on support sigma (the
  * R-minimisation of eq. 3 with sigma fixed; the final step of Algorithm 1 in
  * the precision form), with every quantity taken from A and y in FP64:

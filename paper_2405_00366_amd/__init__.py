@@ -28,6 +28,8 @@ __all__ = [
     "Completion", "l0cim_server_request_bytes", "l0cim_server_arena_overhead", "l0cim_server_create",
     "l0cim_server_clock", "l0cim_server_submit", "l0cim_server_step", "l0cim_server_completed",
     "l0cim_server_info", "l0cim_server_destroy", "l0cim_server_set_step_budget",
+    "l0cim_solve_many", "l0cim_solve_many_workspace_bytes", "l0cim_refit_f64", "l0cim_mfcim_run_noalloc",
+    "l0cim_cac_run", "l0cim_cac_solve", "cac_params", "mri_params",
 ]
 
 F32, F64, BF16, FP8E4M3 = 0, 1, 2, 3
@@ -177,6 +179,11 @@ def lib():
         L.l0cim_update_r.argtypes = [c_int, c_int32, vp, c_int64, vp, vp, c_int, c_double, c_int32,
                                      vp, vp, vp, c_size_t, vp]
         L.l0cim_update_r.restype = st
+        L.l0cim_solve_many_workspace_bytes.argtypes = [c_int, c_int32, c_int32, c_int32, POINTER(SolveParams)]
+        L.l0cim_solve_many_workspace_bytes.restype = c_size_t
+        L.l0cim_solve_many.argtypes = [c_int, c_int32, c_int32, c_int32, vp, c_int64, c_int64, vp, c_int64, vp,
+                                       POINTER(CimParams), POINTER(SolveParams), vp, vp, vp, vp, c_size_t, vp]
+        L.l0cim_solve_many.restype = st
         L.l0cim_refit_f64_workspace_bytes.argtypes = [c_int32, c_int32]
         L.l0cim_refit_f64_workspace_bytes.restype = c_size_t
         L.l0cim_refit_f64.argtypes = [c_int, c_int32, c_int32, vp, c_int64, vp, vp, vp, vp, vp, c_size_t, vp]
@@ -519,6 +526,29 @@ def l0cim_update_r(G, b, sigma, R, cdp: int = CDP_JACOBI, dtc: float = 0.1, iter
     _check(lib().l0cim_update_r(dt, n, _ptr(G), _ld(G), _ptr(b), _ptr(sigma), cdp, dtc, iters, _ptr(R),
                                 _ptr(status), _ptr(ws), ws.numel(), _stream(stream)), "l0cim_update_r")
     return R
+
+
+def l0cim_solve_many_workspace_bytes(dtype: int, count: int, m: int, n: int, sp: SolveParams) -> int:
+    return lib().l0cim_solve_many_workspace_bytes(dtype, count, m, n, ctypes.byref(sp))
+
+
+def l0cim_solve_many(A, y, seeds, cim: CimParams, sp: SolveParams, R_out=None, sigma_out=None, stats=None, ws=None,
+                     stream=None):
+    """l0cim_solve on count stacked instances: A (count, m, n), y (count, m),
+    seeds (count ints).  Returns (R (count, n), sigma (count, n), stats bytes)."""
+    count, m, n = A.shape
+    dt = _dtype_code(A)
+    R_out = torch.empty((count, n), dtype=A.dtype, device=A.device) if R_out is None else R_out
+    sigma_out = torch.empty((count, n), dtype=torch.uint8, device=A.device) if sigma_out is None else sigma_out
+    stats = torch.zeros(count * STATS_BYTES, dtype=torch.uint8, device=A.device) if stats is None else stats
+    need = lib().l0cim_solve_many_workspace_bytes(dt, count, m, n, ctypes.byref(sp))
+    ws = workspace(need, A.device) if ws is None else ws
+    sd = (ctypes.c_uint64 * count)(*[int(v) for v in seeds])
+    _check(lib().l0cim_solve_many(dt, count, m, n, _ptr(A), A.stride(1), A.stride(0), _ptr(y), y.stride(0),
+                                  ctypes.cast(sd, c_void_p), ctypes.byref(cim), ctypes.byref(sp), _ptr(R_out),
+                                  _ptr(sigma_out), _ptr(stats), _ptr(ws), ws.numel(), _stream(stream)),
+           "l0cim_solve_many")
+    return R_out, sigma_out, stats
 
 
 def l0cim_refit_f64_workspace_bytes(m: int, n: int) -> int:

@@ -195,6 +195,52 @@ l0cim_status mfcim_run_checked(l0cim_dtype dtype, int n, int P, l0cim_dtype j_dt
 
 using namespace l0;
 
+namespace {
+
+// Pools of the many-instance solve: every array holds `count` per-instance
+// blocks at a fixed stride, so that one launch can address all instances.
+struct ManyLayout {
+  size_t G, b, J, rs, z, c, e, sig, H, run, cdp, obj, total;
+  size_t sG, sb, sv, sJ, sH, srun, scdp, sobj;   // per-instance strides (bytes; sv in elements)
+};
+
+ManyLayout many_layout(l0cim_dtype dt, int count, int m, int n, int P, l0cim_dtype jdt, bool chol) {
+  ManyLayout L;
+  const size_t ts = dtype_size(dt);
+  L.sG = align_up(size_t(n) * n * ts);
+  L.sb = align_up(size_t(n) * ts);
+  L.sv = align_up(size_t(P) * n * 8) / 8;          // elements, the same for float and double vectors
+  L.sJ = size_t(n) * n;                            // elements (ldj = n)
+  L.sH = align_up(size_t(P) * sizeof(double));
+  L.srun = align_up(mfcim_ws_bytes(dt, n, P));
+  size_t cdp = jacobi_ws_bytes(dt, n);
+  if (chol && chol_a_ws_bytes(n, m) > cdp) cdp = chol_a_ws_bytes(n, m);
+  L.scdp = align_up(cdp);
+  L.sobj = align_up(objective_ws_bytes(m));
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align_up(bytes);
+    return at;
+  };
+  L.G = take(count * L.sG);
+  L.b = take(count * L.sb);
+  L.J = take(count * L.sJ * dtype_size(jdt));
+  L.rs = take(count * L.sv * sizeof(float));
+  L.z = take(count * L.sv * ts);
+  L.c = take(count * L.sv * ts);
+  L.e = take(count * L.sv * ts);
+  L.sig = take(count * L.sv);
+  L.H = take(count * L.sH);
+  L.run = take(count * L.srun);
+  L.cdp = take(count * L.scdp);
+  L.obj = take(count * L.sobj);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
 extern "C" {
 
 int l0cim_version(void) { return L0CIM_VERSION; }
@@ -423,6 +469,116 @@ l0cim_status l0cim_solve(l0cim_dtype dtype, int32_t m, int32_t n, const void* A,
   const int64_t spin_steps = int64_t(n) * P * cim->n_steps * sp->n_outer;
   L0_TRY(launch_objective(dtype, m, n, A, lda, y, sigma_out, R_out, 0.5 * eta * eta, stats, spin_steps,
                           sp->n_outer, obj_ws, L.obj_bytes, s));
+#undef L0_TRY
+  return L0CIM_OK;
+}
+
+size_t l0cim_solve_many_workspace_bytes(l0cim_dtype dtype, int32_t count, int32_t m, int32_t n,
+                                        const l0cim_solve_params* sp) {
+  if (!sp || count <= 0 || m <= 0 || n <= 0 || !is_state_dtype(dtype) || sp->replicas <= 0) return 0;
+  const bool chol = sp->final_refit_f64 || sp->cdp == L0CIM_CDP_CHOL_F64;
+  return many_layout(dtype, count, m, n, sp->replicas, l0cim_dtype(sp->j_dtype), chol).total;
+}
+
+l0cim_status l0cim_solve_many(l0cim_dtype dtype, int32_t count, int32_t m, int32_t n, const void* A, int64_t lda,
+                              int64_t strideA, const void* y, int64_t stridey, const uint64_t* seeds,
+                              const l0cim_cim_params* cim, const l0cim_solve_params* sp, void* R_out,
+                              uint8_t* sigma_out, l0cim_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+  if (!is_state_dtype(dtype)) return set_error(L0CIM_ERR_UNSUPPORTED, "solve_many: dtype %d", int(dtype));
+  l0cim_status st = check_cim(cim);
+  if (st != L0CIM_OK) return st;
+  if (!sp || !seeds) return set_error(L0CIM_ERR_ARG, "solve_many: NULL parameters or seeds");
+  const l0cim_dtype jdt = l0cim_dtype(sp->j_dtype);
+  st = check_jdtype(dtype, jdt);
+  if (st != L0CIM_OK) return st;
+  if (!A || !y || !R_out || !sigma_out || !stats) return set_error(L0CIM_ERR_ARG, "solve_many: NULL pointer");
+  if (count <= 0 || count > 4096) return set_error(L0CIM_ERR_ARG, "solve_many: count must be 1..4096");
+  if (m <= 0 || n <= 0 || n > (1 << 24) || lda < n || strideA < int64_t(m) * lda || stridey < m)
+    return set_error(L0CIM_ERR_SHAPE, "solve_many: bad shape or stride");
+  const int P = sp->replicas;
+  if (P <= 0 || P > (1 << 16)) return set_error(L0CIM_ERR_ARG, "solve_many: replicas out of range");
+  if (sp->n_outer <= 0 || sp->n_outer >= (1 << 24) || sp->velo <= 0)
+    return set_error(L0CIM_ERR_ARG, "solve_many: n_outer and velo must be positive");
+  if (sp->cdp != L0CIM_CDP_JACOBI && sp->cdp != L0CIM_CDP_CHOL_F64)
+    return set_error(L0CIM_ERR_ARG, "solve_many: unknown cdp %d", sp->cdp);
+  if (sp->cdp_iters < 0) return set_error(L0CIM_ERR_ARG, "solve_many: cdp_iters < 0");
+  const bool chol = sp->final_refit_f64 || sp->cdp == L0CIM_CDP_CHOL_F64;
+  const ManyLayout L = many_layout(dtype, count, m, n, P, jdt, chol);
+  if (!ws || ws_bytes < L.total) return set_error(L0CIM_ERR_WORKSPACE, "solve_many: workspace needs %zu bytes", L.total);
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  const size_t ts = dtype_size(dtype);
+  const size_t jsz = dtype_size(jdt);
+  const bool quant = (jdt == L0CIM_BF16 || jdt == L0CIM_FP8E4M3);
+  auto Ak = [&](int k) { return static_cast<const char*>(A) + size_t(k) * strideA * ts; };
+  auto yk = [&](int k) { return static_cast<const char*>(y) + size_t(k) * stridey * ts; };
+  auto Gk = [&](int k) { return base + L.G + k * L.sG; };
+  auto bk = [&](int k) { return base + L.b + k * L.sb; };
+  auto Jk = [&](int k) { return base + L.J + k * L.sJ * jsz; };
+  auto rsk = [&](int k) { return reinterpret_cast<float*>(base + L.rs) + k * L.sv; };
+  auto zk = [&](int k) { return base + L.z + k * L.sv * ts; };
+  auto ck = [&](int k) { return base + L.c + k * L.sv * ts; };
+  auto ek = [&](int k) { return base + L.e + k * L.sv * ts; };
+  auto sigk = [&](int k) { return reinterpret_cast<uint8_t*>(base + L.sig) + k * L.sv; };
+  auto Hk = [&](int k) { return reinterpret_cast<double*>(base + L.H + k * L.sH); };
+  auto runk = [&](int k) { return base + L.run + k * L.srun; };
+  auto cdpk = [&](int k) { return base + L.cdp + k * L.scdp; };
+  auto Rk = [&](int k) { return static_cast<char*>(R_out) + size_t(k) * n * ts; };
+  auto sok = [&](int k) { return sigma_out + size_t(k) * n; };
+#define L0_TRY(x)                  \
+  do {                             \
+    l0cim_status _s = (x);         \
+    if (_s != L0CIM_OK) return _s; \
+  } while (0)
+  for (int k = 0; k < count; ++k) {
+    hipLaunchKernelGGL(stats_init_kernel, dim3(1), dim3(1), 0, s, stats + k);
+    L0_LAUNCHED("stats_init_kernel");
+    L0_TRY(launch_gram(dtype, m, n, Ak(k), lda, yk(k), Gk(k), n, bk(k), s));
+    L0_TRY(launch_r_init(dtype, n, Gk(k), n, bk(k), nullptr, Rk(k), &stats[k].status_bits, s));
+  }
+  // one register-resident launch for all instances where that form applies
+  bool together = dtype == L0CIM_F32 && P == 1 && count > 1;
+  double eta = eta_at(sp, 0);
+  for (int i = 0; i < sp->n_outer; ++i) {
+    eta = eta_at(sp, i);
+    for (int k = 0; k < count; ++k) {
+      L0_TRY(launch_couplings(dtype, n, Gk(k), n, bk(k), Rk(k), jdt, Jk(k), n, rsk(k), zk(k), s));
+      L0_TRY(launch_init_state(dtype, n, P, seeds[k], i, cim->c0_std, ck(k), ek(k), s));
+    }
+    const CimArgs a = make_args(n, P, cim, eta, 0);
+    if (together) {
+      const int64_t sst = int64_t(sizeof(l0cim_stats) / sizeof(int32_t));
+      l0cim_status ms = launch_mfcim_many(jdt, count, n, Jk(0), n, int64_t(L.sJ), quant ? rsk(0) : nullptr,
+                                          reinterpret_cast<const float*>(zk(0)), int64_t(L.sv), a,
+                                          reinterpret_cast<float*>(ck(0)), reinterpret_cast<float*>(ek(0)), sigk(0),
+                                          Hk(0), int64_t(L.sH / sizeof(double)), &stats[0].status_bits, sst, runk(0),
+                                          int64_t(L.srun), s);
+      if (ms == L0CIM_ERR_UNSUPPORTED) together = false;
+      else if (ms != L0CIM_OK) return ms;
+    }
+    if (!together)
+      for (int k = 0; k < count; ++k)
+        L0_TRY(launch_mfcim(dtype, n, P, jdt, Jk(k), n, quant ? rsk(k) : nullptr, zk(k), a, ck(k), ek(k), sigk(k),
+                            Hk(k), nullptr, &stats[k].status_bits, runk(k), L.srun, s));
+    for (int k = 0; k < count; ++k) {
+      L0_TRY(launch_select(n, P, Hk(k), sigk(k), sok(k), &stats[k].selected_replica, &stats[k].H, s));
+      if (sp->cdp == L0CIM_CDP_CHOL_F64)
+        L0_TRY(launch_chol_refit_a(dtype, m, n, Ak(k), lda, yk(k), sok(k), Rk(k), &stats[k].status_bits, cdpk(k),
+                                   L.scdp, s));
+      else
+        L0_TRY(launch_jacobi(dtype, n, Gk(k), n, bk(k), sok(k), sp->dtc, sp->cdp_iters, Rk(k), &stats[k].status_bits,
+                             cdpk(k), L.scdp, s, a.spin_limit));
+    }
+  }
+  const int64_t spin_steps = int64_t(n) * P * cim->n_steps * sp->n_outer;
+  for (int k = 0; k < count; ++k) {
+    if (sp->final_refit_f64)
+      L0_TRY(launch_chol_refit_a(dtype, m, n, Ak(k), lda, yk(k), sok(k), Rk(k), &stats[k].status_bits, cdpk(k),
+                                 L.scdp, s));
+    L0_TRY(launch_objective(dtype, m, n, Ak(k), lda, yk(k), sok(k), Rk(k), 0.5 * eta * eta, stats + k, spin_steps,
+                            sp->n_outer, base + L.obj + k * L.sobj, L.sobj, s));
+  }
 #undef L0_TRY
   return L0CIM_OK;
 }

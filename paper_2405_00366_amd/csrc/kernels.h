@@ -53,6 +53,15 @@ l0cim_status mfcim_run_checked(l0cim_dtype dtype, int n, int P, l0cim_dtype j_dt
                                const float* row_scale, const void* z, double eta, const l0cim_cim_params* prm,
                                void* c, void* e, uint8_t* sigma, double* H, void* trace, int trace_steps,
                                int* status, void* ws, size_t ws_bytes, bool allow_matrix, hipStream_t s);
+// several single-replica FP32 runs of the same n in one register-resident
+// launch: instance i at J + i sJ, per-spin vectors + i sv, run workspace + i
+// sws bytes (each at least mfcim_base_ws_bytes(F32, n, 1)), status + i sst,
+// H + i sh; UNSUPPORTED when that form does not apply (the caller runs them one
+// by one)
+l0cim_status launch_mfcim_many(l0cim_dtype jdt, int count, int n, const void* J, int64_t ldj, int64_t sJ,
+                               const float* rscale, const float* z, int64_t sv, const CimArgs& a, float* c, float* e,
+                               uint8_t* sigma, double* H, int64_t sh, int* status, int64_t sst, void* ws,
+                               int64_t sws, hipStream_t s);
 size_t matrix_ws_bytes(int n, int P, size_t jsize);
 bool matrix_supported(int n, int P, int64_t ldj);
 l0cim_status launch_matrix_run(int n, int P, l0cim_dtype jdt, const void* J, int64_t ldj, const float* rscale,

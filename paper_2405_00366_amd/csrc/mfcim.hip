@@ -322,13 +322,27 @@ constexpr int kFirstPollSleep = 17;
 // and columns u < C, gathers exactly the amplitudes of those columns from the
 // exchange words, multiplies, and the row sums are reduced across the
 // workgroup through LDS.  Wavefront 0 owns the state of the workgroup's rows.
+//
+// Several independent instances of the same n may share one launch (their
+// exchange round trips then overlap): instance i owns workgroups
+// [i G, (i + 1) G), and its couplings, per-spin vectors, run workspace and
+// status word sit at the strides of `mb` from the first instance's.  A single
+// instance has G = the grid and zero strides.
+struct RegsBatch {
+  int G;           // workgroups per instance
+  int64_t sJ;      // elements between the instances' couplings
+  int64_t sv;      // elements between the instances' per-spin vectors (c, e, z, row scales, sigma)
+  int64_t sws;     // bytes between the instances' run workspaces (exchange words, abort word, energies)
+  int64_t sst;     // ints between the instances' status words
+};
+
 template <typename T, typename JT, int FIELD, int R, int C>
 __global__ void __launch_bounds__(512)
 cim_regs_kernel(const JT* __restrict__ J, int64_t ldj, const float* __restrict__ rscale,
                 const T* __restrict__ z, CimArgs a, T* __restrict__ c, T* __restrict__ e,
                 uint8_t* __restrict__ sigma, double* __restrict__ Hpart, T* __restrict__ trace,
                 uint64_t* __restrict__ ll, int* __restrict__ abort_word, int* __restrict__ status,
-                int rpw) {
+                int rpw, RegsBatch mb) {
   using Acc = typename AccT<T>::type;
   constexpr int BS = 512, NW = BS / kWave;
   constexpr int W = LL<T>::kWords;
@@ -336,7 +350,20 @@ cim_regs_kernel(const JT* __restrict__ J, int64_t ldj, const float* __restrict__
   __shared__ int lds_abort;
   const int n = a.n;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-  const int r0 = blockIdx.x * rpw;
+  const int inst = blockIdx.x / mb.G, bx = blockIdx.x - inst * mb.G;
+  if (inst > 0) {
+    J += inst * mb.sJ;
+    if (rscale) rscale += inst * mb.sv;
+    z += inst * mb.sv;
+    c += inst * mb.sv;
+    e += inst * mb.sv;
+    sigma += inst * mb.sv;
+    ll = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(ll) + inst * mb.sws);
+    abort_word = reinterpret_cast<int*>(reinterpret_cast<char*>(abort_word) + inst * mb.sws);
+    if (Hpart) Hpart = reinterpret_cast<double*>(reinterpret_cast<char*>(Hpart) + inst * mb.sws);
+    status += inst * mb.sst;
+  }
+  const int r0 = bx * rpw;
   const int nr = max(0, min(n, r0 + rpw) - r0);
   const size_t slot_words = size_t(n) * W;
 
@@ -463,7 +490,7 @@ cim_regs_kernel(const JT* __restrict__ J, int64_t ldj, const float* __restrict__
         if (lane == 0) {
           double h = 0.0;
           for (int q = 0; q < nr; ++q) h += hrow[q];
-          Hpart[blockIdx.x] = h;
+          Hpart[bx] = h;
         }
       }
     }
@@ -478,7 +505,7 @@ cim_regs_kernel(const JT* __restrict__ J, int64_t ldj, const float* __restrict__
     if (aborted) bits |= L0CIM_ST_TIMEOUT;
     if (bits) raise_status(status, bits);
   }
-  if (aborted && tid == 0 && Hpart) Hpart[blockIdx.x] = NAN;
+  if (aborted && tid == 0 && Hpart) Hpart[bx] = NAN;
 }
 
 struct RunWs {
@@ -548,7 +575,7 @@ l0cim_status run_typed(int n, int P, const JT* J, int64_t ldj, const float* rsca
       if (!rpw && P == 1) {
         const int cols = (n + 511) / 512;
         void (*rk)(const JT*, int64_t, const float*, const T*, CimArgs, T*, T*, uint8_t*, double*, T*,
-                   uint64_t*, int*, int*, int) = nullptr;
+                   uint64_t*, int*, int*, int, RegsBatch) = nullptr;
         if (rpw_cu <= 8 && cols <= 4) rk = cim_regs_kernel<T, JT, FIELD, 8, 4>;
         else if (rpw_cu <= 16 && cols <= 8) rk = cim_regs_kernel<T, JT, FIELD, 16, 8>;
         if (rk) {
@@ -559,8 +586,9 @@ l0cim_status run_typed(int n, int P, const JT* J, int64_t ldj, const float* rsca
           CimArgs args = a;
           const JT* Jp = J;
           int rp = rpw_cu;
+          RegsBatch mb{g, 0, 0, 0, 0};
           void* kargs[] = {&Jp, &ldj, &rscale, &z, &args, &c, &e, &sigma, &w.hpart, &trace,
-                           &w.ll, &w.abort_word, &status, &rp};
+                           &w.ll, &w.abort_word, &status, &rp, &mb};
           {
             ProfileScope prof(s);
             L0_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(rk), dim3(g), dim3(512),
@@ -652,6 +680,60 @@ l0cim_status run_field(int n, int P, const void* J, int64_t ldj, const float* rs
   return run_typed<T, JT, kCN>(n, P, Jp, ldj, rscale, zp, a, cp, ep, sigma, H, tp, status, ws, allow_matrix, s);
 }
 
+// Several single-replica FP32 runs of the same n in one cooperative launch
+// of the register-resident kernel (RegsBatch strides); UNSUPPORTED when the
+// shape has no register-resident form or the instances do not all fit on
+// the device at once.
+template <typename JT, int FIELD>
+l0cim_status regs_many_typed(int count, int n, const JT* J, int64_t ldj, int64_t sJ, const float* rscale,
+                             const float* z, int64_t sv, const CimArgs& a, float* c, float* e, uint8_t* sigma,
+                             double* H, int64_t sh, int* status, int64_t sst, void* ws, int64_t sws, hipStream_t s) {
+  DeviceInfo dev;
+  l0cim_status st = device_info(&dev);
+  if (st != L0CIM_OK) return st;
+  const int rpw_cu = (n + dev.cu_count - 1) / dev.cu_count;
+  const int cols = (n + 511) / 512;
+  // the form l0cim_mfcim_run takes for one such instance (run_typed)
+  const bool small = n <= 256 && resident_layout<float, JT>(n, 1, n).total <= size_t(dev.max_lds);
+  const bool regs_ok = !small && (a.launch == L0CIM_LAUNCH_AUTO || a.launch == L0CIM_LAUNCH_RESIDENT);
+  void (*rk)(const JT*, int64_t, const float*, const float*, CimArgs, float*, float*, uint8_t*, double*, float*,
+             uint64_t*, int*, int*, int, RegsBatch) = nullptr;
+  if (regs_ok && rpw_cu <= 8 && cols <= 4) rk = cim_regs_kernel<float, JT, FIELD, 8, 4>;
+  else if (regs_ok && rpw_cu <= 16 && cols <= 8) rk = cim_regs_kernel<float, JT, FIELD, 16, 8>;
+  if (!rk) return set_error(L0CIM_ERR_UNSUPPORTED, "mfcim_run_many: n = %d has no register-resident form", n);
+  const int g = (n + rpw_cu - 1) / rpw_cu;
+  int per_cu = 0;
+  L0_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(rk), 512, 0));
+  if (int64_t(per_cu) * dev.cu_count < int64_t(count) * g)
+    return set_error(L0CIM_ERR_UNSUPPORTED, "mfcim_run_many: %d instances of %d workgroups exceed %d resident", count,
+                     g, per_cu * dev.cu_count);
+  for (int i = 0; i < count; ++i) {
+    RunWs w = carve_run_ws<float>(static_cast<char*>(ws) + i * sws, n, 1);
+    hipLaunchKernelGGL(ll_clear_kernel, dim3(64), dim3(256), 0, s, w.ll, size_t(2) * n, w.abort_word);
+    L0_LAUNCHED("clear exchange buffer");
+  }
+  RunWs w0 = carve_run_ws<float>(ws, n, 1);
+  CimArgs args = a;
+  args.trace_steps = 0;
+  float* trace = nullptr;
+  int rp = rpw_cu;
+  RegsBatch mb{g, sJ, sv, sws, sst};
+  void* kargs[] = {&J, &ldj, &rscale, &z, &args, &c, &e, &sigma, &w0.hpart, &trace, &w0.ll, &w0.abort_word, &status,
+                   &rp, &mb};
+  {
+    ProfileScope prof(s);
+    L0_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(rk), dim3(g * count), dim3(512), kargs, 0u, s));
+  }
+  if (H) {
+    for (int i = 0; i < count; ++i) {
+      RunWs w = carve_run_ws<float>(static_cast<char*>(ws) + i * sws, n, 1);
+      hipLaunchKernelGGL(reduce_h_kernel, dim3(1), dim3(256), 0, s, w.hpart, g, 1, H + i * sh);
+      L0_LAUNCHED("reduce_h_kernel");
+    }
+  }
+  return L0CIM_OK;
+}
+
 }  // namespace
 
 // Workspace of a run: the exchange words, the abort word, per-workgroup
@@ -694,6 +776,32 @@ l0cim_status launch_mfcim(l0cim_dtype dt, int n, int P, l0cim_dtype jdt, const v
     return run_field<double, double>(n, P, J, ldj, rscale, z, a, c, e, sigma, H, trace, status, ws, am, s);
   }
   return set_error(L0CIM_ERR_UNSUPPORTED, "mfcim_run: dtype %d with coupling dtype %d", int(dt), int(jdt));
+}
+
+l0cim_status launch_mfcim_many(l0cim_dtype jdt, int count, int n, const void* J, int64_t ldj, int64_t sJ,
+                               const float* rscale, const float* z, int64_t sv, const CimArgs& a, float* c, float* e,
+                               uint8_t* sigma, double* H, int64_t sh, int* status, int64_t sst, void* ws,
+                               int64_t sws, hipStream_t s) {
+  const bool bn = a.field == L0CIM_FIELD_BN;
+  switch (jdt) {
+    case L0CIM_F32:
+      return bn ? regs_many_typed<float, kBN>(count, n, (const float*)J, ldj, sJ, nullptr, z, sv, a, c, e, sigma, H,
+                                              sh, status, sst, ws, sws, s)
+                : regs_many_typed<float, kCN>(count, n, (const float*)J, ldj, sJ, nullptr, z, sv, a, c, e, sigma, H,
+                                              sh, status, sst, ws, sws, s);
+    case L0CIM_BF16:
+      return bn ? regs_many_typed<__hip_bfloat16, kBN>(count, n, (const __hip_bfloat16*)J, ldj, sJ, rscale, z, sv, a, c,
+                                                       e, sigma, H, sh, status, sst, ws, sws, s)
+                : regs_many_typed<__hip_bfloat16, kCN>(count, n, (const __hip_bfloat16*)J, ldj, sJ, rscale, z, sv, a, c,
+                                                       e, sigma, H, sh, status, sst, ws, sws, s);
+    case L0CIM_FP8E4M3:
+      return bn ? regs_many_typed<__hip_fp8_e4m3, kBN>(count, n, (const __hip_fp8_e4m3*)J, ldj, sJ, rscale, z, sv, a,
+                                                       c, e, sigma, H, sh, status, sst, ws, sws, s)
+                : regs_many_typed<__hip_fp8_e4m3, kCN>(count, n, (const __hip_fp8_e4m3*)J, ldj, sJ, rscale, z, sv, a,
+                                                       c, e, sigma, H, sh, status, sst, ws, sws, s);
+    default: break;
+  }
+  return set_error(L0CIM_ERR_UNSUPPORTED, "mfcim_run_many: coupling dtype %d", int(jdt));
 }
 
 l0cim_status launch_select(int n, int P, const double* H, const uint8_t* sigma, uint8_t* out,

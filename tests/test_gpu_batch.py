@@ -170,3 +170,38 @@ def test_stepwise_batched_solve_equals_one_call(dev):
     torch.cuda.synchronize()
     L.l0cim_batch_plan_destroy(plan)
     assert torch.equal(R2, ref[0]) and torch.equal(sig2, ref[1]) and torch.equal(stats2, ref[2])
+
+
+@pytest.mark.parametrize("count,n,m,dtype,steps,outer", [(2, 2000, 1000, torch.float32, 2000, 4),
+                                                        (3, 1000, 500, torch.float32, 1000, 3),
+                                                        (3, 64, 32, torch.float64, 1000, 5)])
+def test_solve_many_equals_single_solves(dev, count, n, m, dtype, steps, outer):
+    """l0cim_solve_many on stacked instances gives every instance bitwise the
+    result l0cim_solve gives it alone (the register-resident CIM runs of all
+    instances share one launch where they fit; FP64 runs one by one)."""
+    insts = [W.gaussian_instance(40 + k, n, m, 0.1, 0.01).rounded_f32() for k in range(count)]
+    A = torch.tensor(np.stack([i.A for i in insts]), dtype=dtype, device=dev)
+    y = torch.tensor(np.stack([i.y for i in insts]), dtype=dtype, device=dev)
+    seeds = [100 + k for k in range(count)]
+    cim = L.cim_params(n_steps=steps)
+    jd = L.F64 if dtype == torch.float64 else L.F32
+    sp = L.solve_params(eta_init=0.8, eta_end=0.18, velo=outer, n_outer=outer, replicas=1, j_dtype=jd)
+    L.l0cim_profile_begin()
+    R, sig, stats = L.l0cim_solve_many(A, y, seeds, cim, sp)
+    torch.cuda.synchronize()
+    _, launches = L.l0cim_profile_end()
+    st_many = L.read_stats_array(stats, count)
+    for k in range(count):
+        spk = L.solve_params(eta_init=0.8, eta_end=0.18, velo=outer, n_outer=outer, replicas=1, seed=seeds[k],
+                             j_dtype=jd)
+        Rk, sk, stk = L.l0cim_solve(A[k].contiguous(), y[k].contiguous(), cim, spk)
+        torch.cuda.synchronize()
+        assert torch.equal(sk, sig[k]), f"instance {k}: support differs"
+        assert torch.equal(Rk, R[k]), f"instance {k}: R differs"
+        s1 = L.read_stats(stk)
+        assert (s1.status_bits, s1.selected_replica, s1.support_size) == (
+            st_many[k].status_bits, st_many[k].selected_replica, st_many[k].support_size)
+        assert s1.E == st_many[k].E and s1.H == st_many[k].H
+    print(f"count {count}, n {n}: {launches} CIM launches for {outer} alternations")
+    if dtype == torch.float32 and count == 2:
+        assert launches == outer, "two N = 2000 instances share each register-resident launch"
