@@ -60,8 +60,11 @@ inline bool step_shape_ok(int qb, int rb) {
 }
 
 struct BTile {
-  int inst, row0;
+  int inst, row0;   // inst < 0: an empty tile (its workgroup exits at once)
 };
+
+// XCDs of the device; the dispatcher deals workgroup b to XCD b mod kXcds.
+constexpr int kXcds = 8;
 
 struct BStepArgs {
   int P, n_steps, linear_j, field;

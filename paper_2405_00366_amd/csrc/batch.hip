@@ -178,8 +178,10 @@ __device__ inline T gload(const void* p) {
 typedef unsigned v4u __attribute__((ext_vector_type(4)));
 typedef unsigned v2u __attribute__((ext_vector_type(2)));
 
-// Non-temporal variant: measured faster for the BF16 couplings stream (and
-// slower for FP32 and FP8), so only that path uses it.
+// Non-temporal variant for the couplings stream, which no other workgroup
+// reads in the same step: measured faster for BF16 and for FP32 (batched
+// form: 599 against 638 us per Euler step; within 2% either way for one
+// instance with 64 replicas) and slower for FP8, which keeps plain loads.
 template <typename T>
 __device__ inline T gload_nt(const void* p) {
   return __builtin_nontemporal_load((const __attribute__((address_space(1))) T*)(p));
@@ -251,6 +253,7 @@ bstep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, B
   static_assert(RB * QB * NW <= 128, "partial sums must fit in 128 KB of LDS");
   __shared__ v4f red[NW][RB * QB][64];
   const BTile tl = tiles[blockIdx.x];
+  if (tl.inst < 0) return;
   const BInst I = insts[tl.inst];
   const int n = I.n, ld = I.ld, P = a.P, nch = ld >> 5;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -297,8 +300,8 @@ bstep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, B
     for (int rb = 0; rb < RB; ++rb) {
       const JT* src = pbase[rb] + size_t(c) * 512;
       if constexpr (kF32) {
-        S.a[rb].v0 = gload<v4f>(src);
-        S.a[rb].v1 = gload<v4f>(src + 256);
+        S.a[rb].v0 = gload_nt<v4f>(src);
+        S.a[rb].v1 = gload_nt<v4f>(src + 256);
       } else if constexpr (sizeof(JT) == 2) {
         S.a[rb].v = gload_nt<v4u>(src);
       } else {
@@ -631,17 +634,23 @@ bjac_prep_kernel(const BInst* __restrict__ insts) {
   if (bits) raise_status(I.status, bits);
 }
 
+// Threads of the batched Jacobi kernels: a wavefront per row, sixteen rows of
+// a tile at a time (the step tiles hold 16 to 128 rows).
+constexpr int kJacThreads = 1024;
+constexpr int kJacWaves = kJacThreads / kWave;
+
 // Gc[r][s] = G[r][S[s]] for the rows of one tile (a wavefront per row).
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kJacThreads)
 bjac_compact_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, int rows_per_tile) {
   const BTile tl = tiles[blockIdx.x];
+  if (tl.inst < 0) return;
   const BInst I = insts[tl.inst];
   const int ld = I.ld;
   const int* S = reinterpret_cast<const int*>(I.jw + 3 * ld);
   const int ks = reinterpret_cast<const int*>(I.jw + 5 * ld)[0];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r1 = min(I.n, tl.row0 + rows_per_tile);
-  for (int r = tl.row0 + w; r < r1; r += 4) {
+  for (int r = tl.row0 + w; r < r1; r += kJacWaves) {
     const float* g = I.G + size_t(r) * ld;
     float* gc = I.Gc + size_t(r) * ks;
     for (int s = lane; s < ks; s += kWave) gc[s] = g[S[s]];
@@ -649,10 +658,11 @@ bjac_compact_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ i
 }
 
 // One synchronous sweep over the support rows (support indices of the tile).
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kJacThreads)
 bjac_sweep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, int rows_per_tile, float dtc,
                   int it) {
   const BTile tl = tiles[blockIdx.x];
+  if (tl.inst < 0) return;
   const BInst I = insts[tl.inst];
   const int ld = I.ld;
   const int ks = reinterpret_cast<const int*>(I.jw + 5 * ld)[0];
@@ -663,7 +673,7 @@ bjac_sweep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ ins
   const int* S = reinterpret_cast<const int*>(I.jw + 3 * ld);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int i1 = min(ks, tl.row0 + rows_per_tile);
-  for (int i = tl.row0 + w; i < i1; i += 4) {
+  for (int i = tl.row0 + w; i < i1; i += kJacWaves) {
     const int r = S[i];
     const float* gc = I.Gc + size_t(r) * ks;
     float acc = 0.0f;
@@ -682,10 +692,11 @@ bjac_sweep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ ins
 
 // Every R after K sweeps: the support's from the last sweep, the others from
 // the affine form.
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kJacThreads)
 bjac_final_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, int rows_per_tile, float dtc,
                   int iters) {
   const BTile tl = tiles[blockIdx.x];
+  if (tl.inst < 0) return;
   const BInst I = insts[tl.inst];
   const int ld = I.ld;
   const int ks = reinterpret_cast<const int*>(I.jw + 5 * ld)[0];
@@ -696,7 +707,7 @@ bjac_final_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ ins
   const int r1 = min(I.n, tl.row0 + rows_per_tile);
   float f = 1.0f;
   for (int k = 0; k < iters; ++k) f *= (1.0f - dtc);
-  for (int r = tl.row0 + w; r < r1; r += 4) {
+  for (int r = tl.row0 + w; r < r1; r += kJacWaves) {
     const int pr = pos[r];
     if (pr >= 0) {
       if (lane == 0) I.R[r] = sRK[pr];
@@ -883,14 +894,14 @@ l0cim_status launch_bjacobi(const BatchDev& d, int ntiles, int rows_per_tile, do
   hipLaunchKernelGGL(bjac_prep_kernel, dim3(d.count), dim3(256), 0, s, d.insts);
   L0_LAUNCHED("bjac_prep_kernel");
   if (iters <= 0) return L0CIM_OK;
-  hipLaunchKernelGGL(bjac_compact_kernel, dim3(ntiles), dim3(256), 0, s, d.tiles, d.insts, rows_per_tile);
+  hipLaunchKernelGGL(bjac_compact_kernel, dim3(ntiles), dim3(kJacThreads), 0, s, d.tiles, d.insts, rows_per_tile);
   L0_LAUNCHED("bjac_compact_kernel");
   for (int it = 0; it < iters; ++it) {
-    hipLaunchKernelGGL(bjac_sweep_kernel, dim3(ntiles), dim3(256), 0, s, d.tiles, d.insts, rows_per_tile,
+    hipLaunchKernelGGL(bjac_sweep_kernel, dim3(ntiles), dim3(kJacThreads), 0, s, d.tiles, d.insts, rows_per_tile,
                        float(dtc), it);
     L0_LAUNCHED("bjac_sweep_kernel");
   }
-  hipLaunchKernelGGL(bjac_final_kernel, dim3(ntiles), dim3(256), 0, s, d.tiles, d.insts, rows_per_tile, float(dtc),
+  hipLaunchKernelGGL(bjac_final_kernel, dim3(ntiles), dim3(kJacThreads), 0, s, d.tiles, d.insts, rows_per_tile, float(dtc),
                      iters);
   L0_LAUNCHED("bjac_final_kernel");
   return L0CIM_OK;

@@ -60,17 +60,34 @@ std::map<std::string, int> g_tune;   // shape class -> rows per wavefront block 
 
 int round_up_i(int x, int a) { return (x + a - 1) / a * a; }
 
-// Row tiles of every instance, largest rows-times-columns work first so that
-// the tail of a step is made of small tiles.  Results do not depend on the
-// order: every output row is computed by one wavefront in a fixed k order.
+// Row tiles of every instance.  The dispatcher deals workgroup b to XCD
+// b mod 8, and each XCD has its own L2, so the instances are spread over the
+// XCDs whole (largest first, each to the XCD with the least coupling bytes so
+// far): the amplitudes of an instance are then fetched into one L2 rather
+// than eight.  Workgroup b = 8 i + x takes tile i of XCD x's list (largest
+// work first, so that the tail of a step is made of small tiles); shorter
+// lists are padded with empty tiles (inst = -1), which exit at once.  Results
+// do not depend on the order: every output row is computed by one wavefront
+// in a fixed k order.
 void tile_table(const l0cim_batch_plan_s* p, int rb, std::vector<BTile>& tiles) {
   const int tr = 16 * rb;
   std::vector<int> order(p->count);
   for (int k = 0; k < p->count; ++k) order[k] = k;
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return p->base[x].n > p->base[y].n; });
+  std::vector<BTile> bins[kXcds];
+  double load[kXcds] = {};
+  for (int k : order) {
+    int x = 0;
+    for (int j = 1; j < kXcds; ++j)
+      if (load[j] < load[x]) x = j;
+    load[x] += double(round_up_i(p->base[k].n, tr)) * p->base[k].ld;
+    for (int r0 = 0; r0 < p->base[k].n; r0 += tr) bins[x].push_back(BTile{k, r0});
+  }
+  size_t len = 0;
+  for (auto& b : bins) len = b.size() > len ? b.size() : len;
   tiles.clear();
-  for (int k : order)
-    for (int r0 = 0; r0 < p->base[k].n; r0 += tr) tiles.push_back(BTile{k, r0});
+  for (size_t i = 0; i < len; ++i)
+    for (auto& b : bins) tiles.push_back(i < b.size() ? b[i] : BTile{-1, 0});
 }
 
 struct Pools {
@@ -138,6 +155,7 @@ l0cim_status upload_tables(l0cim_batch_plan_s* p, const BatchDev& d, const Pools
   BInst* hi = reinterpret_cast<BInst*>(h);
   for (int k = 0; k < p->count; ++k) hi[k] = make_inst(p, k, pl);
   for (size_t t = 0; t < tiles.size(); ++t) {
+    if (tiles[t].inst < 0) continue;   // padding
     BInst& I = hi[tiles[t].inst];
     if (tiles[t].row0 == 0) {
       I.tile0 = int(t);
@@ -359,6 +377,7 @@ l0cim_status l0cim_batch_plan_create(int32_t count, const l0cim_instance* inst, 
     p->st_prefix[k + 1] = p->st_prefix[k] + int64_t(p->P) * b.ld;
     p->base[k] = b;
   }
+  p->max_tiles *= kXcds;   // room for the empty tiles that pad the XCD lists (tile_table)
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t at = o;

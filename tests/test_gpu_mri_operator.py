@@ -109,6 +109,9 @@ def test_mri_run_trace_parity(dev, mri_case, field, P, levels, Rkind):
             cp, ep = got[k, 0], got[k, 1]
         flips = sum(int(np.sum((got[k, 0] > 0) != (ref[k, 0] > 0))) for k in range(steps))
         print(f"binarised field: {flips} spin-steps on the other side of zero than in the oracle's trajectory")
+        # measured on MI355X: 0 (P = 2, least-squares R) and 44 of 9.8e6 (P = 3, random R); an FP32
+        # amplitude within rounding of zero may take the other side, and the bound allows 2e-5 of them
+        assert flips <= 2e-5 * steps * n * P, f"{flips} binarised spin-steps differ"
     assert worst <= 1e-5, f"worst normwise error {worst:.3g}"
     cf = c.double().cpu().numpy()
     sg = sig.cpu().numpy()
