@@ -368,6 +368,68 @@ def batched_bench(args, torch, L, W, dev):
     return out
 
 
+def factored_many_bench(args, torch, L, WM, dev, P, steps, outer):
+    """The factored MRI form with K = --instances instances per step: one
+    l0cim_mri_solve_many call solves K seeds (K x 64 workgroups, so that K = 4
+    fills the 256 CUs).  value counts every instance's spin-steps."""
+    K = args.instances
+    pipeline = args.jdtype == "pipeline"
+    gold, gold_R = mri_golden()
+    if pipeline:
+        gold = {k: (v[0], v[2]) for k, v in golden_file("mri_l2").items()}
+    seeds = list(range(args.steps * K))
+    cim = L.cim_params(n_steps=steps, field="BN", K=1.0, d=0.6)
+    n = 128 * 128
+    rows, total, cim_total, launches_total, match = [], 0.0, 0.0, 0, 0
+    for g in range(args.steps):
+        sds = seeds[g * K:(g + 1) * K]
+        print(f"[factored x{K}] building the MRI-shaped instances of seeds {sds}", file=sys.stderr, flush=True)
+        insts = [WM.mri_instance(sd) for sd in sds]
+        if g == 0:
+            factored_many_solve(torch, L, insts, dev, L.cim_params(n_steps=4, field="BN", K=1.0, d=0.6), P, 1, sds,
+                                pipeline)
+        print(f"[factored x{K}] solving ({outer} x {steps} steps)", file=sys.stderr, flush=True)
+        L.l0cim_profile_begin()
+        R, sel, status, dt = factored_many_solve(torch, L, insts, dev, cim, P, outer, sds, pipeline)
+        ms, cnt = L.l0cim_profile_end()
+        total += dt
+        cim_total += ms
+        launches_total += cnt
+        sig_all = sel.cpu().numpy()
+        R_all = R.double().cpu().numpy()
+        for k, sd in enumerate(sds):
+            sig, Rv, inst = sig_all[k], R_all[k], insts[k]
+            rmse = float(np.sqrt(np.mean((Rv * sig - inst.x * inst.xi) ** 2)))
+            ok = sd in gold and mask_to_int(sig) == gold[sd][0] and (steps, outer) == (1000, 11)
+            match += int(ok)
+            rows.append({"seed": sd, "support": int(sig.sum()), "rmse": rmse,
+                         "oracle_rmse": gold[sd][1] if sd in gold else None, "oracle_support_match": ok,
+                         "status": status[k]})
+        print(f"[factored x{K}] seeds {sds}: {dt:.3f} s", file=sys.stderr, flush=True)
+    spin_steps = n * P * steps * outer * len(seeds)
+    run_ms = cim_total / launches_total
+    flops = mri_flops_per_replica_step() * P * K * steps
+    achieved = flops / (run_ms / 1e3) / 1e12
+    return {
+        "metric": METRIC, "value": spin_steps / total, "unit": "spin-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 1, "ms_per_step": total * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{K} MRI-shaped instances per step (seeds as listed, each its own phantom and "
+                               "frequency mask), 128x128, 3-level Haar (N=16384), M=4915, 64 replicas each, BN field, "
+                               "eta 0.8->0.03 over 11 alternations of 1000 steps, factored FP32 couplings, " +
+                               ("MRI pipeline (L2 term, LASSO start, CG CDP)" if pipeline else
+                                "Jacobi CDP in factored form, FP64 Cholesky refit") +
+                               "; one l0cim_mri_solve_many call per step", "instances": K},
+        "couplings": "factored" + (" + MRI pipeline" if pipeline else ""),
+        "support_match": f"{match}/{len(seeds)}", "per_seed": rows,
+        "spin_steps_per_s_cim_only": n * P * K * steps * launches_total / (cim_total / 1e3),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_VECTOR_PEAK_TFS, "traffic": None, "kernel": "mri_cim_kernel<BN>",
+                     "flops_per_replica_step": mri_flops_per_replica_step(), "workgroups": K * P,
+                     "avg_launch_ms": run_ms, "us_per_step": run_ms * 1e3 / steps},
+    }
+
+
 MRI_PIPELINE = dict(gamma=1e-4, lasso_iters=200, lasso_lam1=3e-4, cg_max_iter=10000, cg_tol=1e-5)
 
 
@@ -458,9 +520,34 @@ def precision_cpu_baseline(P: int, seconds_target: float = 15.0):
                       f"in factored form (FP64 NumPy/SciPy DCT), {dt:.1f} s"}
 
 
+def factored_many_solve(torch, L, insts, dev, cim, P, outer, seeds, pipeline=False):
+    """Several MRI-shaped instances through one l0cim_mri_solve_many call
+    (their factored CIM runs, LASSO starts and CDPs as one launch each)."""
+    n = insts[0].N
+    A = torch.tensor(np.stack([i.A for i in insts]), dtype=torch.float32, device=dev)
+    y = torch.tensor(np.stack([i.y for i in insts]), dtype=torch.float32, device=dev)
+    masks = np.zeros((len(insts), n), np.uint8)
+    for k, i in enumerate(insts):
+        masks[k, i.meta["freqs"]] = 1
+    mask = torch.from_numpy(masks).to(dev)
+    mp = L.mri_params(cdp=L.CDP_CG, **MRI_PIPELINE) if pipeline else L.mri_params()
+    sp = L.solve_params(eta_init=0.8, eta_end=0.03, velo=11, n_outer=outer, replicas=P,
+                        final_refit_f64=0 if pipeline else 1)
+    ws = L.workspace(L.lib().l0cim_mri_solve_many_workspace_bytes(len(insts), A.shape[1], P, sp.final_refit_f64), dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    R, sel, stats = L.l0cim_mri_solve_many(mp, A, y, mask, seeds, cim, sp, ws=ws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = L.read_stats_array(stats, len(insts))
+    return R, sel, [x.status_bits for x in st], dt
+
+
 def factored_bench(args, torch, L, W, dev):
     from workloads import mri as WM
     P, steps, outer = 64, args.euler_steps or 1000, args.alternations or 11
+    if args.instances > 1:
+        return factored_many_bench(args, torch, L, WM, dev, P, steps, outer)
     pipeline = args.jdtype == "pipeline"
     gold, gold_R = mri_golden()
     if pipeline:
@@ -1098,7 +1185,8 @@ def main():
                     help="batched form: launch the Euler steps one by one (no HIP graph replay)")
     ap.add_argument("--instances", type=int, default=1,
                     help="plain form: independent instances solved together per step (l0cim_solve_many; their "
-                         "register-resident CIM runs share one launch)")
+                         "register-resident CIM runs share one launch); factored / pipeline precision forms: MRI "
+                         "instances per l0cim_mri_solve_many call")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "

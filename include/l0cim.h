@@ -416,6 +416,27 @@ l0cim_status l0cim_mri_solve(const l0cim_mri_params* mp, int32_t m, const float*
                              void* stream);
 
 /*
+ * l0cim_mri_solve_many -- l0cim_mri_solve on `count` independent MRI-shaped
+ * instances of one shape (Algorithm 1 for each, in lock step): instance k
+ * reads A + k strideA (m x size^2, leading dimension lda; strideA = 0: one A
+ * shared by all), y + k stridey (stridey >= m) and mask + k stride_mask
+ * (stride_mask = 0: one mask shared, as for the slices of one acquisition),
+ * draws its initial amplitudes with seeds[k] (host array; sp->seed is not
+ * used), and writes R_out + k size^2, sigma_out + k size^2 and stats[k].
+ * The factored CIM runs of all instances are one launch (count x replicas
+ * workgroups, one per CU, so that several instances fill the device), and so
+ * are the LASSO starts and the CDPs; each instance's result is the one
+ * l0cim_mri_solve gives it alone (bitwise).  ws: at least
+ * l0cim_mri_solve_many_workspace_bytes(count, m, replicas, final_refit_f64).
+ */
+size_t l0cim_mri_solve_many_workspace_bytes(int32_t count, int32_t m, int32_t P, int32_t final_refit_f64);
+l0cim_status l0cim_mri_solve_many(const l0cim_mri_params* mp, int32_t count, int32_t m, const float* A, int64_t lda,
+                                  int64_t strideA, const float* y, int64_t stridey, const uint8_t* mask,
+                                  int64_t stride_mask, const uint64_t* seeds, const l0cim_cim_params* cim,
+                                  const l0cim_solve_params* sp, float* R_out, uint8_t* sigma_out, l0cim_stats* stats,
+                                  void* ws, size_t ws_bytes, void* stream);
+
+/*
  * l0cim_select_replica -- q* = argmin_q H[q] (lowest q on ties, NaN never
  * chosen unless all are NaN) and sigma_out = sigma[q*] (n bytes).
  * q_out (int32, may be NULL) receives q*.

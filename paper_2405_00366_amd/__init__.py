@@ -29,7 +29,7 @@ __all__ = [
     "l0cim_server_clock", "l0cim_server_submit", "l0cim_server_step", "l0cim_server_completed",
     "l0cim_server_info", "l0cim_server_destroy", "l0cim_server_set_step_budget",
     "l0cim_solve_many", "l0cim_solve_many_workspace_bytes", "l0cim_refit_f64", "l0cim_mfcim_run_noalloc",
-    "l0cim_cac_run", "l0cim_cac_solve", "cac_params", "mri_params",
+    "l0cim_cac_run", "l0cim_cac_solve", "cac_params", "mri_params", "l0cim_mri_solve", "l0cim_mri_solve_many",
 ]
 
 F32, F64, BF16, FP8E4M3 = 0, 1, 2, 3
@@ -160,6 +160,12 @@ def lib():
         L.l0cim_mri_solve.argtypes = [POINTER(MriParams), c_int32, vp, c_int64, vp, vp, POINTER(CimParams),
                                       POINTER(SolveParams), vp, vp, vp, vp, c_size_t, vp]
         L.l0cim_mri_solve.restype = st
+        L.l0cim_mri_solve_many_workspace_bytes.argtypes = [c_int32, c_int32, c_int32, c_int32]
+        L.l0cim_mri_solve_many_workspace_bytes.restype = c_size_t
+        L.l0cim_mri_solve_many.argtypes = [POINTER(MriParams), c_int32, c_int32, vp, c_int64, c_int64, vp, c_int64, vp,
+                                           c_int64, vp, POINTER(CimParams), POINTER(SolveParams), vp, vp, vp, vp,
+                                           c_size_t, vp]
+        L.l0cim_mri_solve_many.restype = st
         L.l0cim_cac_params_default.argtypes = [POINTER(CacParams)]
         L.l0cim_cac_params_default.restype = None
         L.l0cim_cac_run_workspace_bytes.argtypes = [c_int, c_int32, c_int32]
@@ -503,6 +509,29 @@ def l0cim_mri_solve(mp: MriParams, A, y, mask, cim: CimParams, sp: SolveParams, 
     _check(lib().l0cim_mri_solve(ctypes.byref(mp), m, _ptr(A), _ld(A), _ptr(y), _ptr(mask), ctypes.byref(cim),
                                  ctypes.byref(sp), _ptr(R_out), _ptr(sigma_out), _ptr(stats), _ptr(ws), ws.numel(),
                                  _stream(stream)), "l0cim_mri_solve")
+    return R_out, sigma_out, stats
+
+
+def l0cim_mri_solve_many(mp: MriParams, A, y, mask, seeds, cim: CimParams, sp: SolveParams, R_out=None,
+                         sigma_out=None, stats=None, ws=None, stream=None):
+    """l0cim_mri_solve on stacked instances: A (count, m, n) or (m, n) shared, y (count, m), mask (count, n) or (n,)
+    shared, seeds (count ints).  Returns (R (count, n), sigma (count, n), stats bytes)."""
+    count, m = y.shape
+    n = A.shape[-1]
+    shared_a = A.dim() == 2
+    R_out = torch.empty((count, n), dtype=torch.float32, device=A.device) if R_out is None else R_out
+    sigma_out = torch.empty((count, n), dtype=torch.uint8, device=A.device) if sigma_out is None else sigma_out
+    stats = torch.zeros(count * STATS_BYTES, dtype=torch.uint8, device=A.device) if stats is None else stats
+    need = lib().l0cim_mri_solve_many_workspace_bytes(count, m, sp.replicas, sp.final_refit_f64)
+    ws = workspace(need, A.device) if ws is None else ws
+    sd = (ctypes.c_uint64 * count)(*[int(v) for v in seeds])
+    lda = A.stride(0) if shared_a else A.stride(1)
+    strideA = 0 if shared_a else A.stride(0)
+    smask = 0 if mask.dim() == 1 else mask.stride(0)
+    _check(lib().l0cim_mri_solve_many(ctypes.byref(mp), count, m, _ptr(A), lda, strideA, _ptr(y), y.stride(0),
+                                      _ptr(mask), smask, ctypes.cast(sd, c_void_p), ctypes.byref(cim),
+                                      ctypes.byref(sp), _ptr(R_out), _ptr(sigma_out), _ptr(stats), _ptr(ws),
+                                      ws.numel(), _stream(stream)), "l0cim_mri_solve_many")
     return R_out, sigma_out, stats
 
 

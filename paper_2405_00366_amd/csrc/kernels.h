@@ -15,22 +15,36 @@ l0cim_status launch_couplings(l0cim_dtype dt, int n, const void* G, int64_t ldg,
                               void* z, hipStream_t s);
 l0cim_status launch_init_state(l0cim_dtype dt, int n, int P, uint64_t seed, int alt, double std,
                                void* c, void* e, hipStream_t s);
+// Several MRI-shaped instances of one launch: instance k's arrays sit at k
+// times these strides (elements) from the first instance's.  One instance:
+// all zero.
+struct MriStrides {
+  int64_t mask;     // sampling masks (bytes)
+  int64_t vec;      // per-spin vectors: R, b, the selected support
+  int64_t D;        // diagonals D (elements; read with the launch's incd)
+  int64_t state;    // replica arrays c, e, sigma (P * n)
+  int64_t H;        // replica energies (P)
+  int64_t status;   // status words (ints)
+  int64_t it;       // CG iteration counts (ints)
+};
 l0cim_status launch_mri_mfcim(int size, int levels, int P, const uint8_t* mask, const float* R,
                               const float* D, int64_t incd, const float* b, double gamma, const CimArgs& a, float* c,
-                              float* e, uint8_t* sigma, double* H, float* trace, int* status, hipStream_t s);
+                              float* e, uint8_t* sigma, double* H, float* trace, int* status, hipStream_t s,
+                              int count = 1, const MriStrides& ms = MriStrides{});
 l0cim_status launch_mri_l2_diag(int size, int levels, double gamma, const float* D_in, int64_t incd, float* D_out,
                                 hipStream_t s);
 l0cim_status launch_mri_lasso(int size, int levels, double gamma, const uint8_t* mask, const float* b, double lam1,
-                              int iters, float* R_out, hipStream_t s);
+                              int iters, float* R_out, hipStream_t s, int count = 1,
+                              const MriStrides& ms = MriStrides{});
 l0cim_status launch_mri_jacobi(int size, int levels, double gamma, const uint8_t* mask, const float* D,
                                int64_t incd, const float* b, const uint8_t* sigma, float* R, int iters, double dtc,
-                               int* status, hipStream_t s);
+                               int* status, hipStream_t s, int count = 1, const MriStrides& ms = MriStrides{});
 l0cim_status launch_mri_aty_colnorm(int m, int n, const float* A, int64_t lda, const float* y, float* b, float* D,
                                     hipStream_t s);
 l0cim_status launch_mri_r_init(int n, const float* b, const float* D, float* R, int* status, hipStream_t s);
 l0cim_status launch_mri_cg(int size, int levels, double gamma, const uint8_t* mask, const float* D, int64_t incd,
                            const float* b, const uint8_t* sigma, float* R, int max_iter, double tol, int* iters_out,
-                           int* status, hipStream_t s);
+                           int* status, hipStream_t s, int count = 1, const MriStrides& ms = MriStrides{});
 l0cim_status launch_r_init(l0cim_dtype dt, int n, const void* G, int64_t ldg, const void* b,
                            const void* R_init, void* R, int* status, hipStream_t s);
 // the same, also writing the diagonal G_rr to D_out (n, may be NULL)

@@ -48,8 +48,8 @@ constexpr int kQuads = (kS / 2) * (kS / 2) / kBS;   // Haar quads per thread at 
 static_assert(kRows * 16 <= 32, "mask bits of a thread's column frequencies fit one word");
 
 struct MriLds {
-  float A[kS * kLd];
-  float B[kS * kLd];
+  float A[kS * kLd];   // the image; the row pass's output is stored back into it transposed
+  float Rv[kS * kS];   // R of the run's spins (read-only), in LDS rather than registers
   float2 tw[kS];     // exp(-2 pi i m / 128)
   float2 ph[kS];     // exp(-i pi k / 256)
   double red[kBS / kWave];
@@ -409,7 +409,7 @@ __device__ void gram_apply(MriLds& s, float (&u)[kPer], int levels, uint32_t mbi
     __syncthreads();
   }
   // rows: DCT-II along each image row, rows g and g + 64 as one complex FFT;
-  // the result is stored transposed in B
+  // once every row is in registers the result is stored transposed in A
   constexpr int H = kS / 2;
   static_assert(kBS / 8 == H, "one 8-lane group per row pair");
   {
@@ -421,16 +421,16 @@ __device__ void gram_apply(MriLds& s, float (&u)[kPer], int levels, uint32_t mbi
 #pragma unroll
       for (int p = 0; p < 8; ++p) {
         const int k = 2 * n2 + h + 16 * brev<3>(p);
-        s.B[k * kLd + g] = ya[h * 8 + p];
-        s.B[k * kLd + g + H] = yb[h * 8 + p];
+        s.A[k * kLd + g] = ya[h * 8 + p];
+        s.A[k * kLd + g + H] = yb[h * 8 + p];
       }
     __syncthreads();
   }
-  // columns kc = g and g + 64 (rows of B): DCT-II, mask, DCT-III
+  // columns kc = g and g + 64 (rows of the transposed A): DCT-II, mask, DCT-III
   {
     float ya[16], yb[16];
-    float* ra = s.B + g * kLd;
-    float* rb = s.B + (g + H) * kLd;
+    float* ra = s.A + g * kLd;
+    float* rb = s.A + (g + H) * kLd;
     dct_fwd2(ra, rb, ra, rb, n2, s, ya, yb);
     if (gamma == 0.0f) {
 #pragma unroll
@@ -593,20 +593,31 @@ __global__ void __launch_bounds__(kBS)
 mri_cim_kernel(const uint8_t* __restrict__ mask, const float* __restrict__ R, const float* __restrict__ D, int64_t incd,
                const float* __restrict__ b, float gamma, CimArgs a, int levels, float* __restrict__ c,
                float* __restrict__ e, uint8_t* __restrict__ sigma, double* __restrict__ H,
-               float* __restrict__ trace, int* __restrict__ status) {
+               float* __restrict__ trace, int* __restrict__ status, MriStrides ms) {
   extern __shared__ __align__(16) unsigned char smem[];
   MriLds& s = *reinterpret_cast<MriLds*>(smem);
   const int t = threadIdx.x, q = blockIdx.x, n = kS * kS;
+  if (const int k = blockIdx.y) {   // instance k of a many-instance launch
+    mask += k * ms.mask;
+    R += k * ms.vec;
+    b += k * ms.vec;
+    D += k * ms.D;
+    c += k * ms.state;
+    e += k * ms.state;
+    sigma += k * ms.state;
+    if (H) H += k * ms.H;
+    status += k * ms.status;
+  }
   const uint32_t mbits = init_tables(s, mask, t);
   const double lj = a.linear_j ? a.j : 0.0;
   fill_lin(s.lin, 0, a.n_steps, a.dt, a.p_thr, a.d, a.t_c, a.t_w, lj);
-  float cv[kPer], ev[kPer], Rv[kPer];
+  float cv[kPer], ev[kPer];
 #pragma unroll
   for (int i = 0; i < kPer; ++i) {
     const int r = t + kBS * i;
     cv[i] = c[size_t(q) * n + r];
     ev[i] = e[size_t(q) * n + r];
-    Rv[i] = R[r];
+    s.Rv[r] = R[r];
   }
   __syncthreads();
   const float st = float(sqrt(a.tau)), half_st = float(0.5 * sqrt(a.tau));
@@ -623,7 +634,7 @@ mri_cim_kernel(const uint8_t* __restrict__ mask, const float* __restrict__ R, co
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
       const float x = bn ? (cv[i] > 0.0f ? 1.0f : 0.0f) : (cv[i] + st) * 0.25f;
-      u[i] = Rv[i] * x;
+      u[i] = s.Rv[t + kBS * i] * x;
     }
     float dq[kPer], zb[kPer];
     gram_apply(s, u, levels, mbits, gamma, opaque_tid(), D, incd, b, dq, zb);
@@ -635,7 +646,7 @@ mri_cim_kernel(const uint8_t* __restrict__ mask, const float* __restrict__ R, co
     for (int i = 0; i < kPer; ++i) {
       const int r = tk + kBS * i;
       const float x = bn ? (cv[i] > 0.0f ? 1.0f : 0.0f) : (cv[i] + st) * 0.25f;
-      const float Rr = Rv[i];
+      const float Rr = s.Rv[r];
       const float y = -Rr * u[i] + (dq[i] * Rr * Rr) * x;    // (J x)_r, zero diagonal
       const float zr = Rr * zb[i];                           // z = R o b
       const float phi = bn ? half_st * (y + zr) : y + half_st * zr;
@@ -663,7 +674,7 @@ mri_cim_kernel(const uint8_t* __restrict__ mask, const float* __restrict__ R, co
     c[size_t(q) * n + r] = cv[i];
     e[size_t(q) * n + r] = ev[i];
     sigma[size_t(q) * n + r] = cv[i] > 0.0f ? 1 : 0;
-    u[i] = cv[i] > 0.0f ? Rv[i] : 0.0f;
+    u[i] = cv[i] > 0.0f ? s.Rv[r] : 0.0f;
     if (!(isfinite(cv[i]) && isfinite(ev[i]))) bits |= L0CIM_ST_NONFINITE;
     else if (fabsf(cv[i]) > 1e3f) bits |= L0CIM_ST_BLOWUP;
   }
@@ -677,9 +688,9 @@ mri_cim_kernel(const uint8_t* __restrict__ mask, const float* __restrict__ R, co
     for (int i = 0; i < kPer; ++i) {
       const int r = tf + kBS * i;
       if (cv[i] > 0.0f) {
-        const double Rr = Rv[i];
+        const double Rr = s.Rv[r];
         const double js = -Rr * double(u[i]) + double(D[r * incd]) * Rr * Rr;   // (J sigma)_r
-        hs += -0.5 * js - double(Rv[i] * b[r]) + lam;
+        hs += -0.5 * js - double(s.Rv[r] * b[r]) + lam;
       }
     }
     // fixed-order reduction: wavefront partials, then wavefront 0
@@ -757,10 +768,15 @@ __device__ double block_sum(MriLds& s, double v) {
 // step 1 / (1 + 32 gamma), G_gamma applied in factored form.  One workgroup.
 __global__ void __launch_bounds__(kBS)
 mri_lasso_kernel(const uint8_t* __restrict__ mask, int levels, float gamma, const float* __restrict__ b,
-                 double lam1, int iters, float* __restrict__ R_out) {
+                 double lam1, int iters, float* __restrict__ R_out, MriStrides ms) {
   extern __shared__ __align__(16) unsigned char smem[];
   MriLds& s = *reinterpret_cast<MriLds*>(smem);
   const int t = threadIdx.x;
+  if (const int k = blockIdx.x) {   // instance k
+    mask += k * ms.mask;
+    b += k * ms.vec;
+    R_out += k * ms.vec;
+  }
   const uint32_t mbits = init_tables(s, mask, t);
   __syncthreads();
   const double stepd = 1.0 / (1.0 + 32.0 * double(gamma));
@@ -797,10 +813,19 @@ mri_lasso_kernel(const uint8_t* __restrict__ mask, int levels, float gamma, cons
 __global__ void __launch_bounds__(kBS)
 mri_cg_kernel(const uint8_t* __restrict__ mask, int levels, float gamma, const float* __restrict__ D, int64_t incd,
               const float* __restrict__ b, const uint8_t* __restrict__ sigma, float* __restrict__ R, int max_iter,
-              double tol, int* __restrict__ iters_out, int* __restrict__ status) {
+              double tol, int* __restrict__ iters_out, int* __restrict__ status, MriStrides ms) {
   extern __shared__ __align__(16) unsigned char smem[];
   MriLds& s = *reinterpret_cast<MriLds*>(smem);
   const int t = threadIdx.x;
+  if (const int k = blockIdx.x) {   // instance k
+    mask += k * ms.mask;
+    D += k * ms.D;
+    b += k * ms.vec;
+    sigma += k * ms.vec;
+    R += k * ms.vec;
+    if (iters_out) iters_out += k * ms.it;
+    status += k * ms.status;
+  }
   const uint32_t mbits = init_tables(s, mask, t);
   __syncthreads();
   uint32_t sb = 0;
@@ -885,10 +910,18 @@ mri_cg_kernel(const uint8_t* __restrict__ mask, int levels, float gamma, const f
 __global__ void __launch_bounds__(kBS)
 mri_jacobi_kernel(const uint8_t* __restrict__ mask, int levels, float gamma, const float* __restrict__ D,
                   int64_t incd, const float* __restrict__ b, const uint8_t* __restrict__ sigma, float* __restrict__ R,
-                  int iters, float dtc, int* __restrict__ status) {
+                  int iters, float dtc, int* __restrict__ status, MriStrides ms) {
   extern __shared__ __align__(16) unsigned char smem[];
   MriLds& s = *reinterpret_cast<MriLds*>(smem);
   const int t = threadIdx.x;
+  if (const int k = blockIdx.x) {   // instance k
+    mask += k * ms.mask;
+    D += k * ms.D;
+    b += k * ms.vec;
+    sigma += k * ms.vec;
+    R += k * ms.vec;
+    status += k * ms.status;
+  }
   const uint32_t mbits = init_tables(s, mask, t);
   __syncthreads();
   uint32_t sb = 0;
@@ -950,18 +983,21 @@ size_t mri_lds_bytes() { return sizeof(MriLds); }
 
 l0cim_status launch_mri_mfcim(int size, int levels, int P, const uint8_t* mask, const float* R,
                               const float* D, int64_t incd, const float* b, double gamma, const CimArgs& a, float* c,
-                              float* e, uint8_t* sigma, double* H, float* trace, int* status, hipStream_t s) {
+                              float* e, uint8_t* sigma, double* H, float* trace, int* status, hipStream_t s,
+                              int count, const MriStrides& ms) {
   if (size != kS) return set_error(L0CIM_ERR_UNSUPPORTED, "mri_mfcim_run: image side %d (128 supported)", size);
+  if (count < 1 || count > 65535 || (count > 1 && trace))
+    return set_error(L0CIM_ERR_ARG, "mri_mfcim_run: %d instances (a trace needs one)", count);
   const size_t lds = sizeof(MriLds);
   void (*k)(const uint8_t*, const float*, const float*, int64_t, const float*, float, CimArgs, int, float*, float*,
-            uint8_t*, double*, float*, int*) =
+            uint8_t*, double*, float*, int*, MriStrides) =
       a.field == L0CIM_FIELD_BN ? mri_cim_kernel<int(L0CIM_FIELD_BN)> : mri_cim_kernel<int(L0CIM_FIELD_CN)>;
   L0_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
                              int(lds)));
   {
     ProfileScope prof(s);
-    hipLaunchKernelGGL(k, dim3(P), dim3(kBS), lds, s, mask, R, D, incd, b, float(gamma), a, levels, c, e, sigma, H,
-                       trace, status);
+    hipLaunchKernelGGL(k, dim3(P, count), dim3(kBS), lds, s, mask, R, D, incd, b, float(gamma), a, levels, c, e,
+                       sigma, H, trace, status, ms);
   }
   L0_LAUNCHED("mri_cim_kernel");
   return L0CIM_OK;
@@ -976,25 +1012,26 @@ l0cim_status launch_mri_l2_diag(int size, int levels, double gamma, const float*
 }
 
 l0cim_status launch_mri_lasso(int size, int levels, double gamma, const uint8_t* mask, const float* b, double lam1,
-                              int iters, float* R_out, hipStream_t s) {
+                              int iters, float* R_out, hipStream_t s, int count, const MriStrides& ms) {
   if (size != kS) return set_error(L0CIM_ERR_UNSUPPORTED, "mri_lasso: image side %d (128 supported)", size);
   const size_t lds = sizeof(MriLds);
   L0_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(mri_lasso_kernel),
                              hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-  hipLaunchKernelGGL(mri_lasso_kernel, dim3(1), dim3(kBS), lds, s, mask, levels, float(gamma), b, lam1, iters, R_out);
+  hipLaunchKernelGGL(mri_lasso_kernel, dim3(count), dim3(kBS), lds, s, mask, levels, float(gamma), b, lam1, iters,
+                     R_out, ms);
   L0_LAUNCHED("mri_lasso_kernel");
   return L0CIM_OK;
 }
 
 l0cim_status launch_mri_jacobi(int size, int levels, double gamma, const uint8_t* mask, const float* D,
                                int64_t incd, const float* b, const uint8_t* sigma, float* R, int iters, double dtc,
-                               int* status, hipStream_t s) {
+                               int* status, hipStream_t s, int count, const MriStrides& ms) {
   if (size != kS) return set_error(L0CIM_ERR_UNSUPPORTED, "mri_cdp: image side %d (128 supported)", size);
   const size_t lds = sizeof(MriLds);
   L0_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(mri_jacobi_kernel),
                              hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-  hipLaunchKernelGGL(mri_jacobi_kernel, dim3(1), dim3(kBS), lds, s, mask, levels, float(gamma), D, incd, b, sigma, R,
-                     iters, float(dtc), status);
+  hipLaunchKernelGGL(mri_jacobi_kernel, dim3(count), dim3(kBS), lds, s, mask, levels, float(gamma), D, incd, b, sigma,
+                     R, iters, float(dtc), status, ms);
   L0_LAUNCHED("mri_jacobi_kernel");
   return L0CIM_OK;
 }
@@ -1014,13 +1051,13 @@ l0cim_status launch_mri_r_init(int n, const float* b, const float* D, float* R, 
 
 l0cim_status launch_mri_cg(int size, int levels, double gamma, const uint8_t* mask, const float* D, int64_t incd,
                            const float* b, const uint8_t* sigma, float* R, int max_iter, double tol, int* iters_out,
-                           int* status, hipStream_t s) {
+                           int* status, hipStream_t s, int count, const MriStrides& ms) {
   if (size != kS) return set_error(L0CIM_ERR_UNSUPPORTED, "mri_cdp_cg: image side %d (128 supported)", size);
   const size_t lds = sizeof(MriLds);
   L0_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(mri_cg_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
                              int(lds)));
-  hipLaunchKernelGGL(mri_cg_kernel, dim3(1), dim3(kBS), lds, s, mask, levels, float(gamma), D, incd, b, sigma, R,
-                     max_iter, tol, iters_out, status);
+  hipLaunchKernelGGL(mri_cg_kernel, dim3(count), dim3(kBS), lds, s, mask, levels, float(gamma), D, incd, b, sigma, R,
+                     max_iter, tol, iters_out, status, ms);
   L0_LAUNCHED("mri_cg_kernel");
   return L0CIM_OK;
 }

@@ -87,6 +87,68 @@ MriSolveLayout mri_solve_layout(int m, int P, bool refit) {
   return L;
 }
 
+// The argument checks of Algorithm 1 on the MRI-shaped operator (one
+// instance or several of one shape).
+l0cim_status check_mri_solve(const l0cim_mri_params* mp, int m, int64_t lda, const l0cim_cim_params* cim,
+                             const l0cim_solve_params* sp, const char* who) {
+  if (!mp || !sp) return set_error(L0CIM_ERR_ARG, "%s: NULL parameters", who);
+  l0cim_status st = check_geometry(mp->size, mp->levels, who);
+  if (st != L0CIM_OK) return st;
+  st = check_cim_params(cim, who);
+  if (st != L0CIM_OK) return st;
+  const int n = mp->size * mp->size;
+  if (m <= 0 || lda < n) return set_error(L0CIM_ERR_SHAPE, "%s: bad shape", who);
+  const int P = sp->replicas;
+  if (P <= 0 || P > (1 << 16)) return set_error(L0CIM_ERR_ARG, "%s: replicas out of range", who);
+  if (sp->n_outer <= 0 || sp->n_outer >= (1 << 24) || sp->velo <= 0)
+    return set_error(L0CIM_ERR_ARG, "%s: n_outer and velo must be positive", who);
+  if (!(mp->gamma >= 0.0) || mp->lasso_iters < 0 || !(mp->lasso_lam1 >= 0.0))
+    return set_error(L0CIM_ERR_ARG, "%s: gamma, lasso_iters and lasso_lam1 must be >= 0", who);
+  if (mp->cdp == L0CIM_CDP_JACOBI) {
+    if (sp->cdp_iters < 0) return set_error(L0CIM_ERR_ARG, "%s: cdp_iters < 0", who);
+  } else if (mp->cdp == L0CIM_CDP_CG) {
+    if (mp->cg_max_iter < 0 || !(mp->cg_tol >= 0.0)) return set_error(L0CIM_ERR_ARG, "%s: bad CG limits", who);
+  } else {
+    return set_error(L0CIM_ERR_UNSUPPORTED, "%s: cdp %d (Jacobi or CG)", who, mp->cdp);
+  }
+  if (sp->final_refit_f64 && mp->gamma != 0.0)
+    return set_error(L0CIM_ERR_UNSUPPORTED, "%s: the FP64 refit is the unregularised least squares (gamma = 0)", who);
+  return L0CIM_OK;
+}
+
+// Pools of the many-instance solve: each array holds the `count` instances'
+// blocks back to back, so that one launch can address every instance at a
+// fixed stride.
+struct MriManyLayout {
+  size_t b, D0, D, c, e, sig, H, its, obj, chol, total;
+  size_t sobj, schol;   // bytes of one instance's objective scratch and of the refit scratch
+};
+
+MriManyLayout mri_many_layout(int count, int m, int P, bool refit) {
+  const size_t n = size_t(kSide) * kSide;
+  MriManyLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align_up(bytes);
+    return at;
+  };
+  L.sobj = align_up(objective_ws_bytes(m));
+  L.schol = refit ? align_up(chol_a_ws_bytes(int(n), m)) : 0;
+  L.b = take(count * n * 4);
+  L.D0 = take(count * n * 4);
+  L.D = take(count * n * 4);
+  L.c = take(count * size_t(P) * n * 4);
+  L.e = take(count * size_t(P) * n * 4);
+  L.sig = take(count * size_t(P) * n);
+  L.H = take(count * size_t(P) * 8);
+  L.its = take(count * sizeof(int));
+  L.obj = take(count * L.sobj);
+  L.chol = take(L.schol);   // the refits run one after another on the stream and share it
+  L.total = o;
+  return L;
+}
+
 }  // namespace
 }  // namespace l0
 
@@ -176,29 +238,11 @@ l0cim_status l0cim_mri_solve(const l0cim_mri_params* mp, int32_t m, const float*
                              const uint8_t* mask, const l0cim_cim_params* cim, const l0cim_solve_params* sp,
                              float* R_out, uint8_t* sigma_out, l0cim_stats* stats, void* ws, size_t ws_bytes,
                              void* stream) {
-  if (!mp || !sp) return set_error(L0CIM_ERR_ARG, "mri_solve: NULL parameters");
-  l0cim_status st = check_geometry(mp->size, mp->levels, "mri_solve");
+  l0cim_status st = check_mri_solve(mp, m, lda, cim, sp, "mri_solve");
   if (st != L0CIM_OK) return st;
-  st = check_cim_params(cim, "mri_solve");
-  if (st != L0CIM_OK) return st;
-  const int n = mp->size * mp->size;
   if (!A || !y || !mask || !R_out || !sigma_out || !stats) return set_error(L0CIM_ERR_ARG, "mri_solve: NULL pointer");
-  if (m <= 0 || lda < n) return set_error(L0CIM_ERR_SHAPE, "mri_solve: bad shape");
+  const int n = mp->size * mp->size;
   const int P = sp->replicas;
-  if (P <= 0 || P > (1 << 16)) return set_error(L0CIM_ERR_ARG, "mri_solve: replicas out of range");
-  if (sp->n_outer <= 0 || sp->n_outer >= (1 << 24) || sp->velo <= 0)
-    return set_error(L0CIM_ERR_ARG, "mri_solve: n_outer and velo must be positive");
-  if (!(mp->gamma >= 0.0) || mp->lasso_iters < 0 || !(mp->lasso_lam1 >= 0.0))
-    return set_error(L0CIM_ERR_ARG, "mri_solve: gamma, lasso_iters and lasso_lam1 must be >= 0");
-  if (mp->cdp == L0CIM_CDP_JACOBI) {
-    if (sp->cdp_iters < 0) return set_error(L0CIM_ERR_ARG, "mri_solve: cdp_iters < 0");
-  } else if (mp->cdp == L0CIM_CDP_CG) {
-    if (mp->cg_max_iter < 0 || !(mp->cg_tol >= 0.0)) return set_error(L0CIM_ERR_ARG, "mri_solve: bad CG limits");
-  } else {
-    return set_error(L0CIM_ERR_UNSUPPORTED, "mri_solve: cdp %d (Jacobi or CG)", mp->cdp);
-  }
-  if (sp->final_refit_f64 && mp->gamma != 0.0)
-    return set_error(L0CIM_ERR_UNSUPPORTED, "mri_solve: the FP64 refit is the unregularised least squares (gamma = 0)");
   const MriSolveLayout L = mri_solve_layout(m, P, sp->final_refit_f64 != 0);
   if (!ws || ws_bytes < L.total) return set_error(L0CIM_ERR_WORKSPACE, "mri_solve: workspace needs %zu bytes", L.total);
 
@@ -248,6 +292,103 @@ l0cim_status l0cim_mri_solve(const l0cim_mri_params* mp, int32_t m, const float*
   const int64_t spin_steps = int64_t(n) * P * cim->n_steps * sp->n_outer;
   L0_TRY(launch_objective(L0CIM_F32, m, n, A, lda, y, sigma_out, R_out, 0.5 * eta * eta, stats, spin_steps,
                           sp->n_outer, base + L.obj, objective_ws_bytes(m), s));
+#undef L0_TRY
+  return L0CIM_OK;
+}
+
+size_t l0cim_mri_solve_many_workspace_bytes(int32_t count, int32_t m, int32_t P, int32_t final_refit_f64) {
+  if (count <= 0 || m <= 0 || P <= 0) return 0;
+  return mri_many_layout(count, m, P, final_refit_f64 != 0).total;
+}
+
+l0cim_status l0cim_mri_solve_many(const l0cim_mri_params* mp, int32_t count, int32_t m, const float* A, int64_t lda,
+                                  int64_t strideA, const float* y, int64_t stridey, const uint8_t* mask,
+                                  int64_t stride_mask, const uint64_t* seeds, const l0cim_cim_params* cim,
+                                  const l0cim_solve_params* sp, float* R_out, uint8_t* sigma_out, l0cim_stats* stats,
+                                  void* ws, size_t ws_bytes, void* stream) {
+  l0cim_status st = check_mri_solve(mp, m, lda, cim, sp, "mri_solve_many");
+  if (st != L0CIM_OK) return st;
+  if (!A || !y || !mask || !seeds || !R_out || !sigma_out || !stats)
+    return set_error(L0CIM_ERR_ARG, "mri_solve_many: NULL pointer");
+  const int n = mp->size * mp->size;
+  if (count <= 0 || count > 4096) return set_error(L0CIM_ERR_ARG, "mri_solve_many: count must be 1..4096");
+  if (strideA < 0 || (strideA > 0 && strideA < int64_t(m) * lda) || stridey < m ||
+      (stride_mask != 0 && stride_mask < n))
+    return set_error(L0CIM_ERR_SHAPE, "mri_solve_many: bad stride");
+  const int P = sp->replicas;
+  const bool refit = sp->final_refit_f64 != 0;
+  const MriManyLayout L = mri_many_layout(count, m, P, refit);
+  if (!ws || ws_bytes < L.total)
+    return set_error(L0CIM_ERR_WORKSPACE, "mri_solve_many: workspace needs %zu bytes", L.total);
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  float* b = reinterpret_cast<float*>(base + L.b);
+  float* D0 = reinterpret_cast<float*>(base + L.D0);
+  float* D = mp->gamma != 0.0 ? reinterpret_cast<float*>(base + L.D) : D0;
+  float* c = reinterpret_cast<float*>(base + L.c);
+  float* e = reinterpret_cast<float*>(base + L.e);
+  uint8_t* sig = reinterpret_cast<uint8_t*>(base + L.sig);
+  double* H = reinterpret_cast<double*>(base + L.H);
+  int* its = reinterpret_cast<int*>(base + L.its);
+  const size_t pn = size_t(P) * n;
+  auto Ak = [&](int k) { return A + size_t(k) * strideA; };
+  auto yk = [&](int k) { return y + size_t(k) * stridey; };
+  MriStrides ms;
+  ms.mask = stride_mask;
+  ms.vec = n;
+  ms.D = n;
+  ms.state = int64_t(pn);
+  ms.H = P;
+  ms.status = int64_t(sizeof(l0cim_stats) / sizeof(int32_t));
+  ms.it = 1;
+#define L0_TRY(x)                  \
+  do {                             \
+    l0cim_status _s = (x);         \
+    if (_s != L0CIM_OK) return _s; \
+  } while (0)
+  for (int k = 0; k < count; ++k) {
+    hipLaunchKernelGGL(mri_stats_init_kernel, dim3(1), dim3(1), 0, s, stats + k);
+    L0_LAUNCHED("mri_stats_init_kernel");
+    L0_TRY(launch_mri_aty_colnorm(m, n, Ak(k), lda, yk(k), b + size_t(k) * n, D0 + size_t(k) * n, s));
+    if (mp->gamma != 0.0)
+      L0_TRY(launch_mri_l2_diag(mp->size, mp->levels, mp->gamma, D0 + size_t(k) * n, 1, D + size_t(k) * n, s));
+    if (mp->lasso_iters <= 0)
+      L0_TRY(launch_mri_r_init(n, b + size_t(k) * n, D + size_t(k) * n, R_out + size_t(k) * n, &stats[k].status_bits,
+                               s));
+  }
+  if (mp->lasso_iters > 0)
+    L0_TRY(launch_mri_lasso(mp->size, mp->levels, mp->gamma, mask, b, mp->lasso_lam1, mp->lasso_iters, R_out, s,
+                            count, ms));
+  double eta = sp->eta_init;
+  for (int i = 0; i < sp->n_outer; ++i) {
+    const double v = sp->eta_init * (1.0 - double(i) / double(sp->velo));
+    eta = v > sp->eta_end ? v : sp->eta_end;
+    for (int k = 0; k < count; ++k)
+      L0_TRY(launch_init_state(L0CIM_F32, n, P, seeds[k], i, cim->c0_std, c + k * pn, e + k * pn, s));
+    const CimArgs a = mri_args(n, P, cim, eta, 0);
+    L0_TRY(launch_mri_mfcim(mp->size, mp->levels, P, mask, R_out, D, 1, b, mp->gamma, a, c, e, sig, H, nullptr,
+                            &stats[0].status_bits, s, count, ms));
+    for (int k = 0; k < count; ++k)
+      L0_TRY(launch_select(n, P, H + size_t(k) * P, sig + k * pn, sigma_out + size_t(k) * n,
+                           &stats[k].selected_replica, &stats[k].H, s));
+    if (mp->cdp == L0CIM_CDP_CG)
+      L0_TRY(launch_mri_cg(mp->size, mp->levels, mp->gamma, mask, D, 1, b, sigma_out, R_out, mp->cg_max_iter,
+                           mp->cg_tol, its, &stats[0].status_bits, s, count, ms));
+    else
+      L0_TRY(launch_mri_jacobi(mp->size, mp->levels, mp->gamma, mask, D, 1, b, sigma_out, R_out, sp->cdp_iters,
+                               sp->dtc, &stats[0].status_bits, s, count, ms));
+  }
+  const int64_t spin_steps = int64_t(n) * P * cim->n_steps * sp->n_outer;
+  for (int k = 0; k < count; ++k) {
+    float* Rk = R_out + size_t(k) * n;
+    uint8_t* sk = sigma_out + size_t(k) * n;
+    if (refit)
+      L0_TRY(launch_chol_refit_a(L0CIM_F32, m, n, Ak(k), lda, yk(k), sk, Rk, &stats[k].status_bits,
+                                 base + L.chol, L.schol, s));
+    L0_TRY(launch_objective(L0CIM_F32, m, n, Ak(k), lda, yk(k), sk, Rk, 0.5 * eta * eta, stats + k, spin_steps,
+                            sp->n_outer, base + L.obj + k * L.sobj, L.sobj, s));
+  }
 #undef L0_TRY
   return L0CIM_OK;
 }

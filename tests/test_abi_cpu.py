@@ -128,6 +128,19 @@ def test_mri_pipeline_entry_points_reject_bad_arguments_on_host():
     assert solve(mp=L.mri_params(cdp=L.CDP_CHOL_F64)) == 5
     assert solve(mp=L.mri_params(gamma=1e-4), sp=L.solve_params(replicas=2, final_refit_f64=1)) == 5
     assert solve(sp=L.solve_params(replicas=0)) == 1
+    assert lib.l0cim_mri_solve_many_workspace_bytes(4, 4915, 64, 0) > 4 * 64 * 16384 * 9
+    assert lib.l0cim_mri_solve_many_workspace_bytes(0, 4915, 64, 0) == 0
+    seeds = (ctypes.c_uint64 * 4)(1, 2, 3, 4)
+    many = lambda count=4, sA=10 * 16384, sy=10, sm=16384, sd=seeds, ws=FAKE, nbytes=1 << 40: \
+        lib.l0cim_mri_solve_many(ctypes.byref(mp), count, 10, FAKE, 16384, sA, FAKE, sy, FAKE, sm,
+                                 ctypes.cast(sd, ctypes.c_void_p) if sd is not None else None, ctypes.byref(cim),
+                                 ctypes.byref(sp), FAKE, FAKE, FAKE, ws, nbytes, None)
+    assert many(sd=None) == 1
+    assert many(count=0) == 1
+    assert many(sA=-1) == 2 and many(sA=5) == 2
+    assert many(sy=9) == 2
+    assert many(sm=100) == 2
+    assert many(ws=None) == 3 and many(nbytes=10) == 3
 
 
 def test_couplings_rejects_bad_arguments_on_host():
