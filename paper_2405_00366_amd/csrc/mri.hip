@@ -122,6 +122,16 @@ __device__ __forceinline__ int opaque_tid() {
   return t;
 }
 
+// Slot of element (k1, n2) of the FFT transpose in a row's storage: 16 groups
+// of 8, group k1 shifted by k1 / 2 slots (at most slot 134, inside the row's
+// 136-float stride).  Lane n2 of an 8-lane group writes (k1, n2) for one k1
+// at a time and reads (2 n2 + h, q) for one q at a time; unshifted, those
+// reads put the 64 lanes of a wavefront (8 groups, rows 8 banks apart) on 8
+// banks, shifted on 64 distinct ones, and both sides keep one address per
+// lane plus constant offsets.
+__device__ __forceinline__ int tslot(int k1, int n2) { return k1 * 8 + n2 + (k1 >> 1); }
+static_assert(15 * 8 + 7 + 15 / 2 < kLd, "transpose slots stay inside the row's stride");
+
 // Position in a length-128 row of element m of the reordered DCT sequence:
 // v[m] = x[2m] for m < 64, x[255 - 2m] otherwise.
 __device__ __forceinline__ int perm_col(int m) { return m < kS / 2 ? 2 * m : 2 * kS - 1 - 2 * m; }
@@ -151,8 +161,8 @@ __device__ __forceinline__ void dct_fwd2(const float* srca, const float* srcb, f
   for (int p = 0; p < 16; ++p) {
     const int k1 = brev<4>(p);
     const float2 t = s.tw[(n2 * k1) & (kS - 1)];
-    scr_re[k1 * 8 + n2] = re[p] * t.x - im[p] * t.y;
-    scr_im[k1 * 8 + n2] = re[p] * t.y + im[p] * t.x;
+    scr_re[tslot(k1, n2)] = re[p] * t.x - im[p] * t.y;
+    scr_im[tslot(k1, n2)] = re[p] * t.y + im[p] * t.x;
   }
   wave_sync();
   float zr[16], zi[16];
@@ -162,8 +172,8 @@ __device__ __forceinline__ void dct_fwd2(const float* srca, const float* srcb, f
     float r8[8], i8[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      r8[q] = scr_re[k1 * 8 + q];
-      i8[q] = scr_im[k1 * 8 + q];
+      r8[q] = scr_re[tslot(k1, q)];
+      i8[q] = scr_im[tslot(k1, q)];
     }
     dif<8, -1>(r8, i8);
 #pragma unroll
@@ -241,16 +251,16 @@ __device__ __forceinline__ void dct_inv2(const float (&wa)[16], const float (&wp
     for (int p = 0; p < 8; ++p) {
       const int q = brev<3>(p);          // n2 of this output
       const float2 t = s.tw[(q * k1) & (kS - 1)];   // conj twiddle
-      scr_re[k1 * 8 + q] = r8[p] * t.x + i8[p] * t.y;
-      scr_im[k1 * 8 + q] = i8[p] * t.x - r8[p] * t.y;
+      scr_re[tslot(k1, q)] = r8[p] * t.x + i8[p] * t.y;
+      scr_im[tslot(k1, q)] = i8[p] * t.x - r8[p] * t.y;
     }
   }
   wave_sync();
   float re[16], im[16];
 #pragma unroll
   for (int k1 = 0; k1 < 16; ++k1) {
-    re[k1] = scr_re[k1 * 8 + n2];
-    im[k1] = scr_im[k1 * 8 + n2];
+    re[k1] = scr_re[tslot(k1, n2)];
+    im[k1] = scr_im[tslot(k1, n2)];
   }
   wave_sync();
   dif<16, 1>(re, im);
