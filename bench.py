@@ -170,6 +170,7 @@ def percentiles(v):
 
 
 BATCH_SEED, BATCH_COUNT, BATCH_P, BATCH_STEPS, BATCH_OUTER = 7, 256, 16, 1000, 30
+SERVE_HOST_REQUESTS = 200
 BATCH_WORKLOAD = ("batched Gaussian L0RBCS: 256 instances (batch seed 7), N log-uniform [256, 4096], alpha U[0.3, 0.7], "
                   "sparsity U[0.05, 0.2], N(0,1) values, A iid N(0,1/M), noise std 0.01, 16 replicas each, "
                   "1000 Euler steps x 30 alternations, eta 0.8->0.18 (velo 30), Jacobi CDP 100 sweeps, FP32 "
@@ -702,11 +703,11 @@ def precision_bench(args, torch, L, W, dev):
 
 def serving_cpu_baseline(specs, P, seconds_target: float = 15.0):
     """The FP64 oracle on a bounded sample of the serving stream: the first
-    alternation of every 20th request (Euler step count cut so that the sample
-    takes about `seconds_target` seconds)."""
+    alternation of every 20th of the first 200 requests (Euler step count cut
+    so that the sample takes about `seconds_target` seconds)."""
     from oracle import mfcim as O
 
-    sample = list(range(0, len(specs), 20))
+    sample = list(range(0, min(len(specs), SERVE_HOST_REQUESTS), 20))
     insts = {k: specs[k].build().rounded_f32() for k in sample}
 
     def timed(n_steps):
@@ -731,10 +732,19 @@ def serving_bench(args, torch, L, W, dev):
     data, truth = [], []
     print(f"[serving] drawing {len(specs)} requests", file=sys.stderr, flush=True)
     for k, s in enumerate(specs):
-        inst = s.build()
-        data.append((torch.tensor(inst.A, dtype=torch.float32, device=dev),
-                     torch.tensor(inst.y, dtype=torch.float32, device=dev)))
-        truth.append((inst.x, inst.xi))
+        if k < SERVE_HOST_REQUESTS:
+            # the first 200 from the NumPy generator (the oracle's stored results are on these)
+            inst = s.build()
+            data.append((torch.tensor(inst.A, dtype=torch.float32, device=dev),
+                         torch.tensor(inst.y, dtype=torch.float32, device=dev)))
+            truth.append((inst.x, inst.xi))
+        else:
+            # the rest of a long stream drawn on the device (same law, other draws)
+            A, y, _x, _xi = W.gaussian_instance_device(s.seed, s.N, s.M, s.a, s.nu, dev)
+            data.append((A, y))
+            truth.append(None)
+        if (k + 1) % 250 == 0:
+            print(f"[serving] {k + 1}/{len(specs)} requests drawn", file=sys.stderr, flush=True)
     max_n = max(s.N for s in specs)
     outs = [(torch.empty(s.N, device=dev), torch.empty(s.N, dtype=torch.uint8, device=dev),
              torch.zeros(L.STATS_BYTES, dtype=torch.uint8, device=dev)) for s in specs]
@@ -778,10 +788,25 @@ def serving_bench(args, torch, L, W, dev):
 
     total_spin = sum(s.N for s in specs) * P * steps * outer
     total_bytes = sum(step_bytes(s.N, P, 4) for s in specs) * (steps + 1) * outer
-    # saturation: every request present at t = 0
-    print(f"[serving] {len(specs)} requests, arena {arena_bytes / 1e9:.1f} GB; saturation run", file=sys.stderr,
-          flush=True)
-    makespan, lat_sat, cim_ms, ticks = serve([0.0] * len(specs))
+    runs = []
+    if args.ref_thr > 0:
+        # rates relative to a saturation throughput measured in an earlier run (a long stream
+        # then fits one process: one arrival rate per run); value is this run's throughput
+        thr = args.ref_thr
+        frac = args.rates[0]
+        print(f"[serving] {len(specs)} requests, arena {arena_bytes / 1e9:.1f} GB; Poisson arrivals at {frac} x "
+              f"{thr:.2f} req/s", file=sys.stderr, flush=True)
+        arr = W.poisson_arrivals(args.seed, len(specs), frac * thr)
+        makespan, lat, cim_ms, ticks = serve(list(arr))
+        p50, p99 = percentiles(lat)
+        runs.append({"rate_frac": frac, "arrival_rate": frac * thr, "req_per_s": len(specs) / makespan,
+                     "p50_s": p50, "p99_s": p99, "ticks": ticks})
+        args.rates = []
+    else:
+        # saturation: every request present at t = 0
+        print(f"[serving] {len(specs)} requests, arena {arena_bytes / 1e9:.1f} GB; saturation run",
+              file=sys.stderr, flush=True)
+        makespan, lat_sat, cim_ms, ticks = serve([0.0] * len(specs))
     # the sampled requests against the oracle's stored supports (saturation run)
     gold = golden_file("serving") if args.seed == 0 else {}
     sample = [k for k in sorted(gold) if k < len(specs)]
@@ -795,9 +820,10 @@ def serving_bench(args, torch, L, W, dev):
         drmse = max(drmse, abs(rm - gold[k][2]))
         per.append({"request": k, "N": specs[k].N, "identical": bool(ok), "rmse": rm, "oracle_rmse": gold[k][2]})
     sat_bits = [outs[k][1].clone() for k in range(len(specs))]
-    thr = len(specs) / makespan
-    runs = [{"rate_frac": "saturation", "req_per_s": thr, "p50_s": percentiles(lat_sat)[0],
-             "p99_s": percentiles(lat_sat)[1], "ticks": ticks}]
+    if args.ref_thr <= 0:
+        thr = len(specs) / makespan
+        runs = [{"rate_frac": "saturation", "req_per_s": thr, "p50_s": percentiles(lat_sat)[0],
+                 "p99_s": percentiles(lat_sat)[1], "ticks": ticks}]
     achieved = total_bytes / (cim_ms / 1e3) / 1e9
     for frac in args.rates:
         print(f"[serving] Poisson arrivals at {frac} x {thr:.2f} req/s", file=sys.stderr, flush=True)
@@ -848,7 +874,8 @@ def serving_bench(args, torch, L, W, dev):
                                "FP32 couplings, continuous batching (one alternation per tick)",
                    "requests": len(specs), "max_slots": args.slots, "arena_GB": arena_bytes / 1e9,
                    "step_budget_MB": args.step_budget_mb or None},
-        "requests_per_s": thr, "runs": runs,
+        "requests_per_s": len(specs) / makespan, "runs": runs,
+        "reference_saturation_req_per_s": args.ref_thr if args.ref_thr > 0 else None,
         "support_match": f"{match}/{len(sample)} sampled requests (every 4th) identical to the FP64 oracle",
         "max_abs_rmse_diff_vs_oracle": drmse if sample else None, "per_request": per,
         "single_instance_path": {"requests_measured": k_plain, "req_per_s": plain_thr, "spin_steps_per_s": plain_spin,
@@ -1169,6 +1196,9 @@ def main():
     ap.add_argument("--slots", type=int, default=48, help="serving form: resident requests at most")
     ap.add_argument("--rates", type=float, nargs="*", default=[0.5, 0.9],
                     help="serving form: Poisson arrival rates as fractions of the saturation throughput")
+    ap.add_argument("--ref-thr", type=float, default=0.0,
+                    help="serving form: skip the saturation run and take this throughput (req/s) as the reference "
+                         "of the first --rates value (one rate per run; for long streams)")
     ap.add_argument("--plain-sample", type=int, default=-1,
                     help="serving form: requests timed on the single-instance path (-1: all, 0: none)")
     ap.add_argument("--step-budget-mb", type=float, default=300.0,
