@@ -36,6 +36,11 @@ Usage:  python tests/golden/make_oracle_supports.py {small|plain|mri} FIRST LAST
           0.18 over 30 alternations of 1000 steps, inputs rounded to FP32.
           FIRST/LAST index the sample (0..49); the key is the request index.
 
+  cac   : the CAC-CIM (Positive-P, eq. 5-11) as the sigma-minimiser at the
+          plain shape (N = 2000, M = 1000, inputs rounded to FP32), default
+          CAC parameters, 8 replicas, eta 0.8 -> 0.18 over 30 alternations of
+          1000 steps, Jacobi CDP, no refit.
+
   prec_f64 | prec_bf16 | prec_fp8 : the precision-form study at the plain
           shape (N = 2000, M = 1000, Bernoulli(0.1), noise 0.01, inputs rounded
           to FP32), 16 replicas, eta 0.8 -> 0.18 over 30 alternations of 1000
@@ -158,8 +163,22 @@ def one_multi(name, key):
     return key, int(res.sigma.sum()), O.rmse(res.sigma, res.R, inst.x, inst.xi), bitmask_hex(res.sigma), dt
 
 
+CAC_OUTER = O.OuterParams(eta_init=0.8, eta_end=0.18, velo=30, n_outer=30, replicas=8)
+
+
+def one_cac(seed):
+    from oracle import cac as C
+    inst = W.plain_gaussian(seed).rounded_f32()
+    t = time.perf_counter()
+    res = C.solve(inst.A, inst.y, C.CacParams(n_steps=1000), O.with_params(CAC_OUTER, seed=seed), keep_history=False)
+    dt = time.perf_counter() - t
+    return seed, int(res.sigma.sum()), O.rmse(res.sigma, res.R, inst.x, inst.xi), bitmask_hex(res.sigma), dt
+
+
 def one(args):
     name, seed = args
+    if name == "cac":
+        return one_cac(seed)
     if name == "mri":
         return one_mri(seed)
     if name == "mri_f32in":
