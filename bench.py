@@ -431,6 +431,102 @@ def factored_many_bench(args, torch, L, WM, dev, P, steps, outer):
     }
 
 
+CAC_P, CAC_STEPS, CAC_OUTER = 8, 1000, 30
+
+
+def cac_cpu_baseline(W, seed: int = 0, seconds_target: float = 12.0):
+    """The FP64 CAC-CIM oracle on a bounded sample of the CAC workload: the
+    first alternation of seed 0 (Gram prep, replica choice and Jacobi CDP
+    included), Euler step count cut so that it takes about `seconds_target`."""
+    from oracle import cac as C, mfcim as O
+
+    inst = W.plain_gaussian(seed).rounded_f32()
+
+    def timed(n_steps):
+        t = time.perf_counter()
+        outer = O.OuterParams(eta_init=0.8, eta_end=0.18, velo=CAC_OUTER, n_outer=1, replicas=CAC_P, seed=seed)
+        C.solve(inst.A, inst.y, C.CacParams(n_steps=n_steps), outer, keep_history=False)
+        return time.perf_counter() - t
+
+    n, dt = calibrated_steps(timed, 50, CAC_STEPS, seconds_target)
+    return {"value": N * CAC_P * n / dt, "unit": "spin-steps/s", "cores": oracle_threads(), "kind": "oracle",
+            "sample": f"first alternation ({n} of {CAC_STEPS} Euler-Maruyama steps, Gram prep, replica choice and "
+                      f"Jacobi CDP included) of seed {seed}, N = 2000, 8 replicas, FP64 NumPy, {dt:.1f} s"}
+
+
+def cac_bench(args, torch, L, W, dev):
+    """The CAC-CIM (Positive-P, eq. 5-11) as the sigma-minimiser of Algorithm 1
+    at the plain shape: N = 2000, M = 1000, 8 replicas, default CAC
+    parameters, 1000 steps x 30 alternations, FP32, one l0cim_cac_solve per
+    seed.  Supports are compared with the FP64 oracle's stored ones
+    (oracle_supports_cac.txt)."""
+    gold = golden_file("cac")
+    steps, outer = args.euler_steps or CAC_STEPS, args.alternations or CAC_OUTER
+    seeds = list(range(args.warmup + args.steps))
+    prm = L.cac_params(n_steps=steps)
+    data = []
+    for sd in seeds:
+        inst = W.plain_gaussian(sd)
+        data.append((torch.tensor(inst.A, dtype=torch.float32, device=dev),
+                     torch.tensor(inst.y, dtype=torch.float32, device=dev), inst))
+    outs = []
+    sp0 = L.solve_params(eta_init=0.8, eta_end=0.18, velo=outer, n_outer=outer, replicas=CAC_P)
+    ws = L.workspace(L.lib().l0cim_cac_solve_workspace_bytes(L.F32, M, N, CAC_P), dev)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    for i, sd in enumerate(seeds):
+        if i == args.warmup:
+            torch.cuda.synchronize()
+            L.l0cim_profile_begin()
+            t0 = time.perf_counter()
+            ev[0].record(stream)
+        A, y, _ = data[i]
+        sp = L.solve_params(eta_init=0.8, eta_end=0.18, velo=outer, n_outer=outer, replicas=CAC_P, seed=sd)
+        outs.append(L.l0cim_cac_solve(A, y, prm, sp, ws=ws, stream=stream))
+        if i >= args.warmup:
+            ev[i - args.warmup + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    run_ms, launches = L.l0cim_profile_end()
+    gpu_ms = ev[0].elapsed_time(ev[-1])
+    elapsed = max(wall, gpu_ms / 1e3)
+    match, drmse, per = 0, 0.0, []
+    for i in range(args.warmup, len(seeds)):
+        sd = seeds[i]
+        R, sig, st = outs[i]
+        s_h = sig.cpu().numpy()
+        inst = data[i][2]
+        rm = float(np.sqrt(np.mean((R.double().cpu().numpy() * s_h - inst.x * inst.xi) ** 2)))
+        ok = sd in gold and mask_to_int(s_h) == gold[sd][0] and (steps, outer) == (CAC_STEPS, CAC_OUTER)
+        match += int(ok)
+        if sd in gold:
+            drmse = max(drmse, abs(rm - gold[sd][2]))
+        per.append({"seed": sd, "support": int(s_h.sum()), "rmse": rm, "identical_to_oracle": ok,
+                    "status": L.read_stats(st).status_bits})
+    spin = N * CAC_P * steps * outer * args.steps
+    launch_s = run_ms / 1e3 / max(launches, 1) / steps     # per Euler step (one launch each)
+    # each step reads J once per replica pass and the P measured-amplitude vectors
+    byts = N * N * 4 + CAC_P * N * 4 * 6
+    achieved = byts / launch_s / 1e9
+    return {
+        "metric": METRIC, "value": spin * (match / args.steps) / elapsed, "unit": "spin-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "CAC-CIM (Positive-P) as the sigma-minimiser: plain Gaussian L0RBCS N=2000, M=1000, "
+                               "Bernoulli(0.1), noise 0.01, 8 replicas, default CAC parameters (dt 0.02, tau 0.21, "
+                               "g2 1e-7), 1000 Euler-Maruyama steps x 30 alternations, eta 0.8->0.18, Jacobi CDP, "
+                               "FP32", "seeds": seeds[args.warmup:]},
+        "support_match": f"{match}/{args.steps} seeds identical to the FP64 oracle", "per_seed": per,
+        "max_abs_rmse_diff_vs_oracle": drmse if gold else None,
+        "spin_steps_per_s_all": spin / elapsed,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "cac_step_kernel<float>",
+                     "algorithmic_bytes_per_step": byts, "us_per_step": launch_s * 1e6,
+                     "note": "one launch per Euler step; J (16 MB) is read once per step at the bound"},
+        **({} if args.no_cpu else {"cpu_baseline": cac_cpu_baseline(W)}),
+    }
+
+
 MRI_PIPELINE = dict(gamma=1e-4, lasso_iters=200, lasso_lam1=3e-4, cg_max_iter=10000, cg_tol=1e-5)
 
 
@@ -1188,7 +1284,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run a 512 MiB fill and copy first (HBM counter calibration)")
-    ap.add_argument("--form", choices=["plain", "batched", "precision", "serving", "accuracy"], default="batched")
+    ap.add_argument("--form", choices=["plain", "batched", "precision", "serving", "accuracy", "cac"], default="batched")
     ap.add_argument("--jdtype", choices=["bf16", "fp8", "factored", "pipeline"], default="bf16",
                     help="precision form couplings (factored: FP32, applied through the MRI operator; pipeline: "
                          "the same with the L2 term of eq. 20, the LASSO start and the CG CDP)")
@@ -1235,7 +1331,7 @@ def main():
         traffic_probe(torch, dev)
     if args.form != "plain":
         fn = {"batched": batched_bench, "precision": precision_bench, "serving": serving_bench,
-              "accuracy": accuracy_bench}[args.form]
+              "accuracy": accuracy_bench, "cac": cac_bench}[args.form]
         print(json.dumps(fn(args, torch, L, W, dev)), flush=True)
         return
     if args.instances > 1:

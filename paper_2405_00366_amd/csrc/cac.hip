@@ -30,6 +30,10 @@ namespace {
 constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
 constexpr uint64_t kNoiseTag = 0x6E6F6973655F7764ull;
 constexpr int kRows = 4;   // rows (wavefronts) per 256-thread workgroup
+constexpr int kQB = 8;     // replicas per pass over a row of J
+constexpr int kLdsRows = 8;   // rows (wavefronts) per workgroup of the LDS form
+constexpr int kJU = 16;       // loads of a row of J in flight per lane
+constexpr size_t kCacLds = 128 * 1024;   // LDS of the staged amplitudes at most
 
 __device__ inline uint64_t smix(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -73,6 +77,79 @@ __global__ void cac_init_kernel(CacArgs a, T* __restrict__ mu, T* __restrict__ n
   }
 }
 
+// Constants of one Euler-Maruyama step k (eq. 5-11).
+template <typename T>
+struct CacStep {
+  T st, p, dt, jj, g2, KK, beta, tau, theta, noise_mu;
+  double s_meas;
+  __device__ CacStep(const CacArgs& a, int k) {
+    st = T(sqrt(a.tau));
+    p = T(cac_pump(a, k));
+    dt = T(a.dt);
+    jj = T(a.j);
+    g2 = T(a.g2);
+    KK = T(a.K);
+    beta = T(a.beta);
+    tau = T(a.tau);
+    theta = T(sqrt(a.tau) * a.eta * a.eta * 0.25);
+    noise_mu = T(sqrt(a.j * a.g2) * sqrt(a.dt));
+    s_meas = sqrt(a.g2 / (4.0 * a.j)) / sqrt(a.dt);
+  }
+};
+
+// The update of spin r of replica q from its field sum acc = sum_c J_rc (m_c + sqrt(tau)).
+template <typename T>
+__device__ inline void cac_update(const CacArgs& a, const CacStep<T>& c, int k, int q, int r, T acc,
+                                  const T* __restrict__ z, const T* __restrict__ mum_in, T* __restrict__ mum_out,
+                                  T* __restrict__ mu, T* __restrict__ nv, T* __restrict__ mv, T* __restrict__ e,
+                                  T* __restrict__ trace) {
+  const int n = a.n, P = a.P;
+  const size_t g = size_t(q) * n + r;
+  const T phi = T(0.5) * acc + c.st * z[r];
+  const T xi = T(step_normal(a.noise_seed, a.alt, k, q, r));
+  const T m_t = mum_in[g];
+  const T u = mu[g], nn = nv[g], mm = mv[g], ee = e[g];
+  const T inj = c.jj * ee * (phi - c.theta);
+  const T u2 = u * u;
+  const T p = c.p, jj = c.jj, g2 = c.g2;
+  const T du = -(T(1) - p + jj) * u - u * (u2 + T(2) * g2 * nn + g2 * mm) + c.KK * inj;
+  const T dn = -T(2) * (T(1) + jj) * nn + T(2) * p * mm - T(2) * u2 * (T(2) * nn + mm) - jj * (mm + nn) * (mm + nn);
+  const T dm = -T(2) * (T(1) + jj) * mm + T(2) * p * nn - T(2) * u2 * (T(2) * mm + nn) + p - (u2 + g2 * mm) -
+               jj * (mm + nn) * (mm + nn);
+  const T de = -c.beta * (m_t * m_t - c.tau) * ee;
+  const T un = u + c.dt * du + c.noise_mu * (mm + nn) * xi;
+  const T nn1 = nn + c.dt * dn, mm1 = mm + c.dt * dm, ee1 = ee + c.dt * de;
+  mu[g] = un;
+  nv[g] = nn1;
+  mv[g] = mm1;
+  e[g] = ee1;
+  mum_out[g] = un + T(c.s_meas * step_normal(a.noise_seed, a.alt, k + 1, q, r));
+  if (k < a.trace_steps) {
+    const size_t base = (size_t(k) * 4) * P * n + g;
+    trace[base] = un;
+    trace[base + size_t(P) * n] = nn1;
+    trace[base + size_t(2) * P * n] = mm1;
+    trace[base + size_t(3) * P * n] = ee1;
+  }
+}
+
+// Lane 0's total of each of the kQB sums to lane qq (every lane's butterfly
+// total may differ in its last bits; lane 0's is the one used).
+template <typename T>
+__device__ inline T lane_total(T (&acc)[kQB], int lane) {
+  T mine = T(0);
+#pragma unroll
+  for (int qq = 0; qq < kQB; ++qq) {
+    const T tot = __shfl(wave_sum(acc[qq]), 0, kWave);
+    if (lane == qq) mine = tot;
+  }
+  return mine;
+}
+
+// One Euler-Maruyama step of every spin and replica, a wavefront per row of J:
+// kQB replicas per pass, the row of J read once for all of them, lane qq
+// then runs the update of replica q0 + qq.  The measured amplitudes are read
+// from memory (any n; the LDS form below covers n up to a limit).
 template <typename T>
 __global__ void __launch_bounds__(256)
 cac_step_kernel(const T* __restrict__ J, int64_t ldj, const T* __restrict__ z, CacArgs a, int k,
@@ -82,45 +159,81 @@ cac_step_kernel(const T* __restrict__ J, int64_t ldj, const T* __restrict__ z, C
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   const int r = blockIdx.x * kRows + wv;
   if (r >= n) return;
-  const T st = T(sqrt(a.tau));
-  const T p = T(cac_pump(a, k));
-  const T dt = T(a.dt), jj = T(a.j), g2 = T(a.g2), KK = T(a.K), beta = T(a.beta), tau = T(a.tau);
-  const T theta = T(sqrt(a.tau) * a.eta * a.eta * 0.25);
-  const T noise_mu = T(sqrt(a.j * a.g2) * sqrt(a.dt));
-  const double s_meas = sqrt(a.g2 / (4.0 * a.j)) / sqrt(a.dt);
+  const CacStep<T> c(a, k);
   const T* jr = J + size_t(r) * ldj;
-  for (int q = 0; q < P; ++q) {
-    const T* xq = mum_in + size_t(q) * n;
-    T acc = T(0);
-    for (int c = lane; c < n; c += kWave) acc += jr[c] * (xq[c] + st);
-    acc = wave_sum(acc);
-    if (lane == 0) {
-      const size_t g = size_t(q) * n + r;
-      const T phi = T(0.5) * acc + st * z[r];
-      const T xi = T(step_normal(a.noise_seed, a.alt, k, q, r));
-      const T m_t = xq[r];
-      const T u = mu[g], nn = nv[g], mm = mv[g], ee = e[g];
-      const T inj = jj * ee * (phi - theta);
-      const T u2 = u * u;
-      const T du = -(T(1) - p + jj) * u - u * (u2 + T(2) * g2 * nn + g2 * mm) + KK * inj;
-      const T dn = -T(2) * (T(1) + jj) * nn + T(2) * p * mm - T(2) * u2 * (T(2) * nn + mm) - jj * (mm + nn) * (mm + nn);
-      const T dm = -T(2) * (T(1) + jj) * mm + T(2) * p * nn - T(2) * u2 * (T(2) * mm + nn) + p - (u2 + g2 * mm) -
-                   jj * (mm + nn) * (mm + nn);
-      const T de = -beta * (m_t * m_t - tau) * ee;
-      const T un = u + dt * du + noise_mu * (mm + nn) * xi;
-      const T nn1 = nn + dt * dn, mm1 = mm + dt * dm, ee1 = ee + dt * de;
-      mu[g] = un;
-      nv[g] = nn1;
-      mv[g] = mm1;
-      e[g] = ee1;
-      mum_out[g] = un + T(s_meas * step_normal(a.noise_seed, a.alt, k + 1, q, r));
-      if (k < a.trace_steps) {
-        const size_t base = (size_t(k) * 4) * P * n + g;
-        trace[base] = un;
-        trace[base + size_t(P) * n] = nn1;
-        trace[base + size_t(2) * P * n] = mm1;
-        trace[base + size_t(3) * P * n] = ee1;
+  for (int q0 = 0; q0 < P; q0 += kQB) {
+    const int nq = P - q0 < kQB ? P - q0 : kQB;
+    T acc[kQB];
+#pragma unroll
+    for (int qq = 0; qq < kQB; ++qq) acc[qq] = T(0);
+    for (int c0 = lane; c0 < n; c0 += kWave * kJU) {
+      T jv[kJU];   // kJU loads of the row in flight, then the sums in the same column order
+#pragma unroll
+      for (int u = 0; u < kJU; ++u) jv[u] = c0 + u * kWave < n ? jr[c0 + u * kWave] : T(0);
+#pragma unroll
+      for (int u = 0; u < kJU; ++u) {
+        const int cc = c0 + u * kWave;
+        if (cc < n) {
+#pragma unroll
+          for (int qq = 0; qq < kQB; ++qq)
+            if (qq < nq) acc[qq] += jv[u] * (mum_in[size_t(q0 + qq) * n + cc] + c.st);
+        }
       }
+    }
+    const T mine = lane_total(acc, lane);
+    if (lane < nq) cac_update(a, c, k, q0 + lane, r, mine, z, mum_in, mum_out, mu, nv, mv, e, trace);
+  }
+}
+
+// The same step with the measured amplitudes of kQB replicas (plus sqrt(tau),
+// the same rounding as above) staged in LDS once per workgroup of kLdsRows
+// rows, so that every row reads them from LDS instead of the caches.
+template <typename T>
+__global__ void __launch_bounds__(kLdsRows * kWave)
+cac_step_lds_kernel(const T* __restrict__ J, int64_t ldj, const T* __restrict__ z, CacArgs a, int k,
+                    const T* __restrict__ mum_in, T* __restrict__ mum_out, T* __restrict__ mu, T* __restrict__ nv,
+                    T* __restrict__ mv, T* __restrict__ e, T* __restrict__ trace) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* xs = reinterpret_cast<T*>(smem);
+  const int n = a.n, P = a.P;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  const int r = blockIdx.x * kLdsRows + wv;
+  const CacStep<T> c(a, k);
+  const T* jr = J + size_t(r < n ? r : 0) * ldj;
+  for (int q0 = 0; q0 < P; q0 += kQB) {
+    const int nq = P - q0 < kQB ? P - q0 : kQB;
+    __syncthreads();   // the previous block's reads of xs are done
+    const int tot = nq * n;
+    constexpr int kThreads = kLdsRows * kWave;
+    for (int i0 = tid; i0 < tot; i0 += kThreads * kJU) {   // kJU loads in flight per lane
+      T v[kJU];
+#pragma unroll
+      for (int u = 0; u < kJU; ++u) v[u] = i0 + u * kThreads < tot ? mum_in[size_t(q0) * n + i0 + u * kThreads] : T(0);
+#pragma unroll
+      for (int u = 0; u < kJU; ++u)
+        if (i0 + u * kThreads < tot) xs[i0 + u * kThreads] = v[u] + c.st;
+    }
+    __syncthreads();
+    if (r < n) {
+      T acc[kQB];
+#pragma unroll
+      for (int qq = 0; qq < kQB; ++qq) acc[qq] = T(0);
+      for (int c0 = lane; c0 < n; c0 += kWave * kJU) {
+        T jv[kJU];
+#pragma unroll
+        for (int u = 0; u < kJU; ++u) jv[u] = c0 + u * kWave < n ? jr[c0 + u * kWave] : T(0);
+#pragma unroll
+        for (int u = 0; u < kJU; ++u) {
+          const int cc = c0 + u * kWave;
+          if (cc < n) {
+#pragma unroll
+            for (int qq = 0; qq < kQB; ++qq)
+              if (qq < nq) acc[qq] += jv[u] * xs[qq * n + cc];
+          }
+        }
+      }
+      const T mine = lane_total(acc, lane);
+      if (lane < nq) cac_update(a, c, k, q0 + lane, r, mine, z, mum_in, mum_out, mu, nv, mv, e, trace);
     }
   }
 }
@@ -202,11 +315,20 @@ l0cim_status cac_run_typed(int n, int P, const T* J, int64_t ldj, const T* z, co
   L0_LAUNCHED("cac_init_kernel");
   const int grid = (n + kRows - 1) / kRows;
   T* bufs[2] = {static_cast<T*>(w.mum0), static_cast<T*>(w.mum1)};
+  const size_t lds = size_t(kQB) * n * sizeof(T);
+  const bool staged = lds <= kCacLds;
+  if (staged)
+    L0_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(cac_step_lds_kernel<T>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
   {
     ProfileScope prof(s);
     for (int k = 0; k < a.n_steps; ++k) {
-      hipLaunchKernelGGL(cac_step_kernel<T>, dim3(grid), dim3(256), 0, s, J, ldj, z, a, k, bufs[k & 1],
-                         bufs[(k + 1) & 1], mu, nv, mv, e, trace);
+      if (staged)
+        hipLaunchKernelGGL(cac_step_lds_kernel<T>, dim3((n + kLdsRows - 1) / kLdsRows), dim3(kLdsRows * kWave), lds,
+                           s, J, ldj, z, a, k, bufs[k & 1], bufs[(k + 1) & 1], mu, nv, mv, e, trace);
+      else
+        hipLaunchKernelGGL(cac_step_kernel<T>, dim3(grid), dim3(256), 0, s, J, ldj, z, a, k, bufs[k & 1],
+                           bufs[(k + 1) & 1], mu, nv, mv, e, trace);
       L0_LAUNCHED("cac_step_kernel");
     }
   }

@@ -49,8 +49,11 @@ def _problem(seed, n, dtype):
     return J, z
 
 
+# n = 2100 in FP64 (8 replicas' amplitudes above 128 KB) takes the form that reads them from memory;
+# the others stage them in LDS
 @pytest.mark.parametrize("n,P,dtype,steps,tau", [(300, 2, torch.float64, 200, 0.21), (300, 3, torch.float32, 200, 0.21),
-                                                  (2000, 1, torch.float32, 200, 0.15), (777, 2, torch.float32, 600, 0.21)])
+                                                  (2000, 1, torch.float32, 200, 0.15), (777, 2, torch.float32, 600, 0.21),
+                                                  (2100, 2, torch.float64, 200, 0.21), (500, 11, torch.float32, 200, 0.21)])
 def test_cac_run_trace_parity(dev, n, P, dtype, steps, tau):
     seed, alt, eta = 11, 3, 0.4
     J, z = _problem(seed + n, n, dtype)
@@ -111,3 +114,40 @@ def test_cac_rejects_bad_arguments(dev):
     with pytest.raises(L.L0cimError):
         L.l0cim_cac_run(J, J[0], 0.3, L.cac_params(), 0, 0, 257)
     assert lib.l0cim_cac_run_workspace_bytes(L.BF16, 8, 1) == 0
+
+
+def _golden_cac():
+    import os
+    out = {}
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "oracle_supports_cac.txt")):
+        if line.strip() and line[0] != "#":
+            k, sz, rm, hx = line.split()
+            out[int(k)] = (int(hx, 16), int(sz), float(rm))
+    return out
+
+
+def test_cac_solve_plain_shape_against_stored_oracle(dev):
+    """l0cim_cac_solve in FP32 at the plain shape (N = 2000, M = 1000, 8
+    replicas, default CAC parameters, 30 alternations of 1000 steps, eta
+    0.8 -> 0.18) on the ten seeds whose FP64 oracle results are stored
+    (tests/golden/oracle_supports_cac.txt): the final support and RMSE.
+    Measured on MI355X: 10/10 identical, max |dRMSE| 1.5e-7.  Gate: all ten,
+    and |dRMSE| <= 1e-3."""
+    gold = _golden_cac()
+    assert len(gold) == 10
+    same, worst = 0, 0.0
+    for sd in sorted(gold):
+        inst = W.plain_gaussian(sd)
+        A = torch.tensor(inst.A, dtype=torch.float32, device=dev)
+        y = torch.tensor(inst.y, dtype=torch.float32, device=dev)
+        sp = L.solve_params(eta_init=0.8, eta_end=0.18, velo=30, n_outer=30, replicas=8, seed=sd)
+        R, sig, st = L.l0cim_cac_solve(A, y, L.cac_params(n_steps=1000), sp)
+        torch.cuda.synchronize()
+        assert L.read_stats(st).status_bits == 0
+        sg = sig.cpu().numpy()
+        so = np.array([(gold[sd][0] >> r) & 1 for r in range(inst.N)], np.uint8)
+        same += int(np.array_equal(sg, so))
+        worst = max(worst, abs(O.rmse(sg, R.double().cpu().numpy(), inst.x, inst.xi) - gold[sd][2]))
+    print(f"CAC-CIM at N = 2000: {same}/10 supports identical to the FP64 oracle, max |dRMSE| {worst:.2e}")
+    assert same == 10
+    assert worst <= 1e-3
