@@ -33,7 +33,10 @@ constexpr int kRows = 4;   // rows (wavefronts) per 256-thread workgroup
 constexpr int kQB = 8;     // replicas per pass over a row of J
 constexpr int kLdsRows = 8;   // rows (wavefronts) per workgroup of the LDS form
 constexpr int kJU = 16;       // loads of a row of J in flight per lane
-constexpr size_t kCacLds = 128 * 1024;   // LDS of the staged amplitudes at most
+// The LDS form holds a whole row of J in registers and the kQB replicas'
+// amplitudes in LDS: n up to 2048 (FP32) / 1024 (FP64), 64 KB of LDS.
+template <typename T>
+constexpr int kCacMaxN() { return sizeof(T) == 4 ? 2048 : 1024; }
 
 __device__ inline uint64_t smix(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -199,7 +202,13 @@ cac_step_lds_kernel(const T* __restrict__ J, int64_t ldj, const T* __restrict__ 
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
   const int r = blockIdx.x * kLdsRows + wv;
   const CacStep<T> c(a, k);
+  // the whole row of J in registers (columns lane + 64 u), requested before
+  // the staging so that its latency is spent under it; it serves every pass
+  constexpr int kCols = kCacMaxN<T>() / kWave;
   const T* jr = J + size_t(r < n ? r : 0) * ldj;
+  T jv[kCols];
+#pragma unroll
+  for (int u = 0; u < kCols; ++u) jv[u] = lane + u * kWave < n ? jr[lane + u * kWave] : T(0);
   for (int q0 = 0; q0 < P; q0 += kQB) {
     const int nq = P - q0 < kQB ? P - q0 : kQB;
     __syncthreads();   // the previous block's reads of xs are done
@@ -218,13 +227,26 @@ cac_step_lds_kernel(const T* __restrict__ J, int64_t ldj, const T* __restrict__ 
       T acc[kQB];
 #pragma unroll
       for (int qq = 0; qq < kQB; ++qq) acc[qq] = T(0);
-      for (int c0 = lane; c0 < n; c0 += kWave * kJU) {
-        T jv[kJU];
+      if (nq == kQB) {
+        // a full block, one replica at a time: the LDS reads of its columns
+        // issue together (the same column order per lane as below); a lane
+        // past the row's end adds J = 0 times a valid entry (its index
+        // clamped), which leaves the sum unchanged
+        const int uend = (n + kWave - 1) / kWave;
 #pragma unroll
-        for (int u = 0; u < kJU; ++u) jv[u] = c0 + u * kWave < n ? jr[c0 + u * kWave] : T(0);
+        for (int qq = 0; qq < kQB; ++qq) {
+          const T* xq = xs + qq * n;
 #pragma unroll
-        for (int u = 0; u < kJU; ++u) {
-          const int cc = c0 + u * kWave;
+          for (int u = 0; u < kCols; ++u) {
+            if (u >= uend) break;
+            const int cc = lane + u * kWave < n ? lane + u * kWave : n - 1;
+            acc[qq] += jv[u] * xq[cc];
+          }
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < kCols; ++u) {
+          const int cc = lane + u * kWave;
           if (cc < n) {
 #pragma unroll
             for (int qq = 0; qq < kQB; ++qq)
@@ -316,7 +338,7 @@ l0cim_status cac_run_typed(int n, int P, const T* J, int64_t ldj, const T* z, co
   const int grid = (n + kRows - 1) / kRows;
   T* bufs[2] = {static_cast<T*>(w.mum0), static_cast<T*>(w.mum1)};
   const size_t lds = size_t(kQB) * n * sizeof(T);
-  const bool staged = lds <= kCacLds;
+  const bool staged = n <= kCacMaxN<T>();
   if (staged)
     L0_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(cac_step_lds_kernel<T>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
