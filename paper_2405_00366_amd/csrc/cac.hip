@@ -100,18 +100,12 @@ struct CacStep {
   }
 };
 
-// The update of spin r of replica q from its field sum acc = sum_c J_rc (m_c + sqrt(tau)).
+// One Euler-Maruyama step of (mu, n, m, e) of one spin and replica from its
+// field sum acc = sum_c J_rc (m_c + sqrt(tau)), its Zeeman term zr, its
+// measured amplitude m_t and the normal xi of the step (eq. 5-11).
 template <typename T>
-__device__ inline void cac_update(const CacArgs& a, const CacStep<T>& c, int k, int q, int r, T acc,
-                                  const T* __restrict__ z, const T* __restrict__ mum_in, T* __restrict__ mum_out,
-                                  T* __restrict__ mu, T* __restrict__ nv, T* __restrict__ mv, T* __restrict__ e,
-                                  T* __restrict__ trace) {
-  const int n = a.n, P = a.P;
-  const size_t g = size_t(q) * n + r;
-  const T phi = T(0.5) * acc + c.st * z[r];
-  const T xi = T(step_normal(a.noise_seed, a.alt, k, q, r));
-  const T m_t = mum_in[g];
-  const T u = mu[g], nn = nv[g], mm = mv[g], ee = e[g];
+__device__ inline void cac_advance(const CacStep<T>& c, T acc, T zr, T m_t, T xi, T& u, T& nn, T& mm, T& ee) {
+  const T phi = T(0.5) * acc + c.st * zr;
   const T inj = c.jj * ee * (phi - c.theta);
   const T u2 = u * u;
   const T p = c.p, jj = c.jj, g2 = c.g2;
@@ -122,18 +116,39 @@ __device__ inline void cac_update(const CacArgs& a, const CacStep<T>& c, int k, 
   const T de = -c.beta * (m_t * m_t - c.tau) * ee;
   const T un = u + c.dt * du + c.noise_mu * (mm + nn) * xi;
   const T nn1 = nn + c.dt * dn, mm1 = mm + c.dt * dm, ee1 = ee + c.dt * de;
-  mu[g] = un;
-  nv[g] = nn1;
-  mv[g] = mm1;
-  e[g] = ee1;
-  mum_out[g] = un + T(c.s_meas * step_normal(a.noise_seed, a.alt, k + 1, q, r));
+  u = un;
+  nn = nn1;
+  mm = mm1;
+  ee = ee1;
+}
+
+template <typename T>
+__device__ inline void cac_trace(const CacArgs& a, int k, size_t g, T u, T nn, T mm, T ee, T* __restrict__ trace) {
   if (k < a.trace_steps) {
-    const size_t base = (size_t(k) * 4) * P * n + g;
-    trace[base] = un;
-    trace[base + size_t(P) * n] = nn1;
-    trace[base + size_t(2) * P * n] = mm1;
-    trace[base + size_t(3) * P * n] = ee1;
+    const size_t base = (size_t(k) * 4) * a.P * a.n + g;
+    trace[base] = u;
+    trace[base + size_t(a.P) * a.n] = nn;
+    trace[base + size_t(2) * a.P * a.n] = mm;
+    trace[base + size_t(3) * a.P * a.n] = ee;
   }
+}
+
+// The update of spin r of replica q, state read from and written to memory.
+template <typename T>
+__device__ inline void cac_update(const CacArgs& a, const CacStep<T>& c, int k, int q, int r, T acc,
+                                  const T* __restrict__ z, const T* __restrict__ mum_in, T* __restrict__ mum_out,
+                                  T* __restrict__ mu, T* __restrict__ nv, T* __restrict__ mv, T* __restrict__ e,
+                                  T* __restrict__ trace) {
+  const size_t g = size_t(q) * a.n + r;
+  const T xi = T(step_normal(a.noise_seed, a.alt, k, q, r));
+  T u = mu[g], nn = nv[g], mm = mv[g], ee = e[g];
+  cac_advance(c, acc, z[r], mum_in[g], xi, u, nn, mm, ee);
+  mu[g] = u;
+  nv[g] = nn;
+  mv[g] = mm;
+  e[g] = ee;
+  mum_out[g] = u + T(c.s_meas * step_normal(a.noise_seed, a.alt, k + 1, q, r));
+  cac_trace(a, k, g, u, nn, mm, ee, trace);
 }
 
 // Lane 0's total of each of the kQB sums to lane qq (every lane's butterfly
@@ -260,6 +275,135 @@ cac_step_lds_kernel(const T* __restrict__ J, int64_t ldj, const T* __restrict__ 
   }
 }
 
+// The whole run in one cooperative launch (every workgroup resident), for
+// P <= kQB replicas and n up to kCacMaxN: each workgroup keeps its kLdsRows
+// rows of J in registers and lane q of wavefront w the state (mu, n, m, e)
+// of row w, replica q; the measured amplitudes of step k travel between
+// workgroups as step-tagged words (flag k + 1, two slots by step parity).
+// Per step every workgroup gathers all P n of them into LDS (plus
+// sqrt(tau)), forms its rows' sums exactly as cac_step_lds_kernel does,
+// advances its owned states and publishes the measured amplitudes of step
+// k + 1.  A slot is rewritten only after every workgroup has gathered the
+// step it held (a workgroup cannot finish step k + 1 before every other has
+// published it).  Every wait is bounded; a timeout raises the abort word
+// and every workgroup leaves the loop.
+template <typename T>
+__global__ void __launch_bounds__(kLdsRows * kWave)
+cac_resident_kernel(const T* __restrict__ J, int64_t ldj, const T* __restrict__ z, CacArgs a,
+                    const T* __restrict__ mum0, T* __restrict__ mu, T* __restrict__ nv, T* __restrict__ mv,
+                    T* __restrict__ e, T* __restrict__ trace, uint64_t* __restrict__ ll, int* __restrict__ abort_word,
+                    int* __restrict__ status) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* xs = reinterpret_cast<T*>(smem);
+  __shared__ int lds_abort;
+  constexpr int W = LL<T>::kWords;
+  constexpr int kThreads = kLdsRows * kWave;
+  constexpr int kCols = kCacMaxN<T>() / kWave;
+  const int n = a.n, P = a.P;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  const int r = blockIdx.x * kLdsRows + wv;
+  const bool valid = r < n;
+  const size_t slot = size_t(P) * n * W;
+  const T* jr = J + size_t(valid ? r : 0) * ldj;
+  T jv[kCols];
+#pragma unroll
+  for (int u = 0; u < kCols; ++u) jv[u] = lane + u * kWave < n ? jr[lane + u * kWave] : T(0);
+  const bool own = valid && lane < P;
+  const size_t g = own ? size_t(lane) * n + r : 0;
+  T su = T(0), sn = T(0), sm = T(0), se = T(0), mt = T(0), zr = T(0);
+  if (own) {
+    su = mu[g];
+    sn = nv[g];
+    sm = mv[g];
+    se = e[g];
+    mt = mum0[g];
+    zr = z[r];
+    LL<T>::put(ll + g * W, mt, 1u);
+  }
+  if (tid == 0) lds_abort = 0;
+  __syncthreads();
+  bool aborted = false;
+  const int tot = P * n;
+  for (int k = 0; k < a.n_steps; ++k) {
+    const CacStep<T> c(a, k);
+    const uint64_t* src = ll + size_t(k & 1) * slot;
+    const uint32_t flag = uint32_t(k + 1);
+    bool ok = true;
+    for (int i0 = tid; i0 < tot && ok; i0 += kThreads * kJU) {   // kJU words in flight per lane
+      uint64_t w[kJU][W];
+#pragma unroll
+      for (int u = 0; u < kJU; ++u) {
+        const int idx = i0 + u * kThreads;
+#pragma unroll
+        for (int v = 0; v < W; ++v) w[u][v] = idx < tot ? ll_load(src + size_t(idx) * W + v) : (uint64_t(flag) << 32);
+      }
+#pragma unroll
+      for (int u = 0; u < kJU; ++u) {
+        const int idx = i0 + u * kThreads;
+        if (idx < tot && ok) {
+#pragma unroll
+          for (int v = 0; v < W; ++v)
+            if (ok) ok = ll_wait(src + size_t(idx) * W + v, flag, w[u][v], kDefaultSpinLimit, abort_word);
+          if (ok) xs[idx] = ll_decode<T>(w[u]) + c.st;
+        }
+      }
+    }
+    if (!ok) {
+      lds_abort = 1;
+      __hip_atomic_store(abort_word, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    if (lds_abort) {
+      aborted = true;
+      break;
+    }
+    if (valid) {
+      T acc[kQB];
+#pragma unroll
+      for (int qq = 0; qq < kQB; ++qq) acc[qq] = T(0);
+      if (P == kQB) {
+        const int uend = (n + kWave - 1) / kWave;
+#pragma unroll
+        for (int qq = 0; qq < kQB; ++qq) {
+          const T* xq = xs + qq * n;
+#pragma unroll
+          for (int u = 0; u < kCols; ++u) {
+            if (u >= uend) break;
+            const int cc = lane + u * kWave < n ? lane + u * kWave : n - 1;
+            acc[qq] += jv[u] * xq[cc];
+          }
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < kCols; ++u) {
+          const int cc = lane + u * kWave;
+          if (cc < n) {
+#pragma unroll
+            for (int qq = 0; qq < kQB; ++qq)
+              if (qq < P) acc[qq] += jv[u] * xs[qq * n + cc];
+          }
+        }
+      }
+      const T mine = lane_total(acc, lane);
+      if (own) {
+        const T xi = T(step_normal(a.noise_seed, a.alt, k, lane, r));
+        cac_advance(c, mine, zr, mt, xi, su, sn, sm, se);
+        mt = su + T(c.s_meas * step_normal(a.noise_seed, a.alt, k + 1, lane, r));
+        LL<T>::put(ll + size_t((k + 1) & 1) * slot + g * W, mt, uint32_t(k + 2));
+        cac_trace(a, k, g, su, sn, sm, se, trace);
+      }
+    }
+    __syncthreads();   // every read of xs is done before the next gather
+  }
+  if (own) {
+    mu[g] = su;
+    nv[g] = sn;
+    mv[g] = sm;
+    e[g] = se;
+  }
+  if (aborted && tid == 0) raise_status(status, L0CIM_ST_TIMEOUT);
+}
+
 // sigma = H(mu) and the per-row terms of the eq. 4 energy
 // sigma_r (-1/2 (J sigma)_r - z_r + lambda) of every replica.
 template <typename T>
@@ -313,15 +457,23 @@ uint64_t host_mix64(uint64_t zz) {
 struct CacWs {
   void *mum0, *mum1;
   double* hrow;
+  uint64_t* ll;     // exchange words of the resident form: 2 slots x P n values
+  int* abort_word;
 };
+
+size_t cac_ll_words(l0cim_dtype dt, int n, int P) { return 2 * size_t(n) * P * (dt == L0CIM_F64 ? 2 : 1); }
 
 CacWs cac_ws(void* ws, l0cim_dtype dt, int n, int P) {
   char* b = static_cast<char*>(ws);
   const size_t v = align_up(size_t(n) * P * dtype_size(dt));
+  const size_t h = align_up(size_t(n) * P * sizeof(double));
+  const size_t l = align_up(cac_ll_words(dt, n, P) * sizeof(uint64_t));
   CacWs w;
   w.mum0 = b;
   w.mum1 = b + v;
   w.hrow = reinterpret_cast<double*>(b + 2 * v);
+  w.ll = reinterpret_cast<uint64_t*>(b + 2 * v + h);
+  w.abort_word = reinterpret_cast<int*>(b + 2 * v + h + l);
   return w;
 }
 
@@ -337,6 +489,39 @@ l0cim_status cac_run_typed(int n, int P, const T* J, int64_t ldj, const T* z, co
   L0_LAUNCHED("cac_init_kernel");
   const int grid = (n + kRows - 1) / kRows;
   T* bufs[2] = {static_cast<T*>(w.mum0), static_cast<T*>(w.mum1)};
+  // the whole run in one launch when every workgroup can be resident
+  if (P <= kQB && n <= kCacMaxN<T>()) {
+    const size_t rlds = size_t(P) * n * sizeof(T);
+    const int rgrid = (n + kLdsRows - 1) / kLdsRows;
+    const void* rk = reinterpret_cast<const void*>(cac_resident_kernel<T>);
+    L0_HIP(hipFuncSetAttribute(rk, hipFuncAttributeMaxDynamicSharedMemorySize, int(rlds)));
+    DeviceInfo dev;
+    l0cim_status st = device_info(&dev);
+    if (st != L0CIM_OK) return st;
+    int per_cu = 0;
+    L0_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, rk, kLdsRows * kWave, rlds));
+    if (int64_t(per_cu) * dev.cu_count >= rgrid) {
+      hipLaunchKernelGGL(ll_clear_kernel, dim3(64), dim3(256), 0, s, w.ll, cac_ll_words(dt, n, P), w.abort_word);
+      L0_LAUNCHED("clear exchange buffer");
+      const T* m0 = static_cast<const T*>(w.mum0);
+      CacArgs aa = a;
+      uint64_t* llp = w.ll;
+      int* abw = w.abort_word;
+      void* kargs[] = {&J, &ldj, &z, &aa, &m0, &mu, &nv, &mv, &e, &trace, &llp, &abw, &status};
+      {
+        ProfileScope prof(s);
+        L0_HIP(hipLaunchCooperativeKernel(rk, dim3(rgrid), dim3(kLdsRows * kWave), kargs, unsigned(rlds), s));
+      }
+      hipLaunchKernelGGL(cac_sigma_energy_kernel<T>, dim3(grid), dim3(256), 0, s, J, ldj, z, n, P,
+                         0.5 * a.eta * a.eta, mu, e, sigma, w.hrow, status);
+      L0_LAUNCHED("cac_sigma_energy_kernel");
+      if (H) {
+        hipLaunchKernelGGL(cac_energy_reduce_kernel, dim3(P), dim3(256), 0, s, n, w.hrow, H);
+        L0_LAUNCHED("cac_energy_reduce_kernel");
+      }
+      return L0CIM_OK;
+    }
+  }
   const size_t lds = size_t(kQB) * n * sizeof(T);
   const bool staged = n <= kCacMaxN<T>();
   if (staged)
@@ -396,7 +581,8 @@ l0cim_status check_cac(const l0cim_cac_params* p, const char* who) {
 }
 
 size_t cac_run_ws_bytes(l0cim_dtype dt, int n, int P) {
-  return 2 * align_up(size_t(n) * P * dtype_size(dt)) + align_up(size_t(n) * P * sizeof(double));
+  return 2 * align_up(size_t(n) * P * dtype_size(dt)) + align_up(size_t(n) * P * sizeof(double)) +
+         align_up(cac_ll_words(dt, n, P) * sizeof(uint64_t)) + align_up(sizeof(int));
 }
 
 l0cim_status launch_cac_run(l0cim_dtype dt, int n, int P, const void* J, int64_t ldj, const void* z, const CacArgs& a,
