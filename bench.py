@@ -888,6 +888,8 @@ def serving_bench(args, torch, L, W, dev):
     if args.ref_thr > 0:
         # rates relative to a saturation throughput measured in an earlier run (a long stream
         # then fits one process: one arrival rate per run); value is this run's throughput
+        if len(args.rates) != 1:
+            raise SystemExit("--ref-thr takes exactly one --rates value")
         thr = args.ref_thr
         frac = args.rates[0]
         print(f"[serving] {len(specs)} requests, arena {arena_bytes / 1e9:.1f} GB; Poisson arrivals at {frac} x "
