@@ -34,15 +34,29 @@ struct BInst {
 };
 
 // Panel layout of the couplings: rows in panels of 16 (the row count padded
-// to n16, a multiple of 16), columns in chunks of 32 (ld); block (p, c)
-// holds J[16 p, 16 p + 16) x [32 c, 32 c + 32) as 512 consecutive elements
-// in the order the matrix-core operands are loaded, so that each wavefront
-// load reads one contiguous run:
+// to n16 = 16 np, a multiple of 16), columns in chunks of 32 (ld); block
+// (p, c) holds J[16 p, 16 p + 16) x [32 c, 32 c + 32) as 512 consecutive
+// elements in the order the matrix-core operands are loaded, so that each
+// wavefront load reads one contiguous run:
 //   4-byte elements: (li, 8 lk + 4 h + u) at ((16 h + li) * 4 + lk) * 4 + u
 //   1- and 2-byte:   (li, 8 lk + t)       at (4 li + lk) * 8 + t
-__host__ __device__ inline size_t jpanel_offset(int r, int j, int ld, int esize) {
+// Panels go in groups of kPanelGroup (the last group holds the rest): group
+// g holds chunk c of its gs panels side by side, so that a row tile of up to
+// kPanelGroup panels (aligned to its size) reads one contiguous run of
+// gs blocks per chunk: block (p, c) starts at
+//   (kPanelGroup g nch + c gs + p mod kPanelGroup) 512,  g = p / kPanelGroup.
+constexpr int kPanelGroup = 8;
+__host__ __device__ inline int jpanel_group_size(int p, int np) {
+  const int rest = np - (p / kPanelGroup) * kPanelGroup;
+  return rest < kPanelGroup ? rest : kPanelGroup;
+}
+__host__ __device__ inline size_t jpanel_block(int p, int c, int nch, int np) {
+  const int g = p / kPanelGroup;
+  return (size_t(g) * kPanelGroup * nch + size_t(c) * jpanel_group_size(p, np) + size_t(p % kPanelGroup)) * 512;
+}
+__host__ __device__ inline size_t jpanel_offset(int r, int j, int ld, int np, int esize) {
   const int li = r & 15, jj = j & 31, lk = jj >> 3, t = jj & 7;
-  const size_t blk = (size_t(r >> 4) * size_t(ld >> 5) + size_t(j >> 5)) * 512;
+  const size_t blk = jpanel_block(r >> 4, j >> 5, ld >> 5, np);
   if (esize == 4) return blk + size_t(((16 * (t >> 2) + li) * 4 + lk) * 4 + (t & 3));
   return blk + size_t((4 * li + lk) * 8 + t);
 }

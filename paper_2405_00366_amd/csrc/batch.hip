@@ -71,10 +71,10 @@ bcouplings_kernel(const BInst* __restrict__ insts, const int64_t* __restrict__ r
   const int k = find_inst(row_prefix, count, blockIdx.x);
   const BInst I = insts[k];
   const int r = int(blockIdx.x - row_prefix[k]);
-  const int n = I.n, ld = I.ld;
+  const int n = I.n, ld = I.ld, np = (n + 15) / 16;
   JT* J = static_cast<JT*>(I.J);
   if (r >= n) {
-    for (int j = threadIdx.x; j < ld; j += 256) J[jpanel_offset(r, j, ld, int(sizeof(JT)))] = JT(0.0f);
+    for (int j = threadIdx.x; j < ld; j += 256) J[jpanel_offset(r, j, ld, np, int(sizeof(JT)))] = JT(0.0f);
     return;
   }
   const float* G = I.G + size_t(r) * ld;
@@ -82,7 +82,7 @@ bcouplings_kernel(const BInst* __restrict__ insts, const int64_t* __restrict__ r
   const float Rr = R[r];
   if constexpr (sizeof(JT) == 4) {
     for (int j = threadIdx.x; j < ld; j += 256)
-      J[jpanel_offset(r, j, ld, 4)] = (j < n && j != r) ? -(G[j] * (Rr * R[j])) : 0.0f;
+      J[jpanel_offset(r, j, ld, np, 4)] = (j < n && j != r) ? -(G[j] * (Rr * R[j])) : 0.0f;
     if (threadIdx.x == 0) {
       I.z[r] = Rr * I.b[r];
       I.rs[r] = 1.0f;
@@ -103,7 +103,7 @@ bcouplings_kernel(const BInst* __restrict__ insts, const int64_t* __restrict__ r
     const float scale = red[0] > 0.0f ? red[0] / qmax : 1.0f;
     for (int j = threadIdx.x; j < ld; j += 256) {
       float v = (j < n && j != r) ? -(G[j] * (Rr * R[j])) / scale : 0.0f;
-      const size_t o = jpanel_offset(r, j, ld, int(sizeof(JT)));
+      const size_t o = jpanel_offset(r, j, ld, np, int(sizeof(JT)));
       if constexpr (sizeof(JT) == 2) J[o] = __float2bfloat16(v);
       else J[o] = __hip_fp8_e4m3(fminf(fmaxf(v, -448.0f), 448.0f));
     }
@@ -271,11 +271,18 @@ bstep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, B
 
   // Rows of panels past the instance and replicas past P read valid
   // addresses of panel p0 / replica 0 instead; their sums are never used.
-  const JT* pbase[RB];
+  // The tile's panels lie in one panel group (RB divides kPanelGroup and p0
+  // is a multiple of RB): chunk c of panel p0 + rb is block gs c + rb of the
+  // group, after the group's base.
+  static_assert(kPanelGroup % RB == 0, "row tiles within one panel group");
+  const int np = (n + 15) / 16;
+  const int cstride = jpanel_group_size(p0, np) * 512;
+  const JT* gbase = J + size_t(p0 / kPanelGroup) * kPanelGroup * nch * 512;
+  int poff[RB];
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
     const int pp = (p0 + rb) * 16 < n ? p0 + rb : p0;
-    pbase[rb] = J + size_t(pp) * nch * 512 + lane_off;
+    poff[rb] = (pp % kPanelGroup) * 512 + lane_off;
   }
   bool qon[QB];
   const float* cbase[QB];
@@ -298,7 +305,7 @@ bstep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, B
   auto load = [&](int c, St& S) {
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
-      const JT* src = pbase[rb] + size_t(c) * 512;
+      const JT* src = gbase + (size_t(c * cstride) + poff[rb]);
       if constexpr (kF32) {
         S.a[rb].v0 = gload_nt<v4f>(src);
         S.a[rb].v1 = gload_nt<v4f>(src + 256);

@@ -47,22 +47,22 @@ mat_setup_kernel(BInst I, BTile* __restrict__ tiles, int ntiles, int tr, BInst* 
 template <typename JT>
 __global__ void __launch_bounds__(256)
 mat_copyJ_kernel(const JT* __restrict__ J, int64_t ldj, JT* __restrict__ Jp, int n, int ld) {
-  const int r = blockIdx.y;
+  const int r = blockIdx.y, np = (n + 15) / 16;
   for (int j0 = 8 * (blockIdx.x * 256 + threadIdx.x); j0 < ld; j0 += 8 * gridDim.x * 256) {
     JT v[8];
 #pragma unroll
     for (int t = 0; t < 8; ++t) v[t] = (r < n && j0 + t < n) ? J[size_t(r) * ldj + j0 + t] : JT(0.0f);
     if constexpr (sizeof(JT) == 4) {
-      *reinterpret_cast<float4*>(Jp + jpanel_offset(r, j0, ld, 4)) =
+      *reinterpret_cast<float4*>(Jp + jpanel_offset(r, j0, ld, np, 4)) =
           make_float4(float(v[0]), float(v[1]), float(v[2]), float(v[3]));
-      *reinterpret_cast<float4*>(Jp + jpanel_offset(r, j0 + 4, ld, 4)) =
+      *reinterpret_cast<float4*>(Jp + jpanel_offset(r, j0 + 4, ld, np, 4)) =
           make_float4(float(v[4]), float(v[5]), float(v[6]), float(v[7]));
     } else {
       struct alignas(8 * sizeof(JT)) Run { JT e[8]; };
       Run run;
 #pragma unroll
       for (int t = 0; t < 8; ++t) run.e[t] = v[t];
-      *reinterpret_cast<Run*>(Jp + jpanel_offset(r, j0, ld, int(sizeof(JT)))) = run;
+      *reinterpret_cast<Run*>(Jp + jpanel_offset(r, j0, ld, np, int(sizeof(JT)))) = run;
     }
   }
 }
