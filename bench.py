@@ -1241,8 +1241,13 @@ def plain_many_bench(args, torch, L, W, dev):
     spin_steps = N * P * STEPS * OUTER * K
     elapsed = max(wall, gpu_ms / 1e3)
     value = spin_steps * (match / K) / elapsed
-    # one launch runs K instances: (2N + 20) flops per spin-step each
-    per_launch_flops = (2 * N + 20) * N * P * STEPS * K
+    # (2N + 20) flops per spin-step; the K instances of a call share one
+    # launch when the device holds all their workgroups at once, else the
+    # library runs them one launch each: count instances per launch from
+    # the launches actually made
+    cim_runs = K * OUTER * args.steps
+    per_launch = cim_runs / max(cim_launches, 1)
+    per_launch_flops = (2 * N + 20) * N * P * STEPS * per_launch
     avg_launch_s = (cim_ms / 1e3) / max(cim_launches, 1)
     achieved = per_launch_flops / avg_launch_s / 1e12
     return {
@@ -1263,7 +1268,7 @@ def plain_many_bench(args, torch, L, W, dev):
                    "seeds": [s for g in groups[args.warmup:] for s in g]},
         "support_match": f"{match}/{args.steps * K}",
         "spin_steps_per_s_all": spin_steps * args.steps / elapsed,
-        "spin_steps_per_s_cim_only": N * P * STEPS * K * cim_launches / (cim_ms / 1e3) if cim_ms > 0 else None,
+        "spin_steps_per_s_cim_only": N * P * STEPS * cim_runs / (cim_ms / 1e3) if cim_ms > 0 else None,
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
         "status_nonzero": status_bad,
@@ -1271,8 +1276,10 @@ def plain_many_bench(args, torch, L, W, dev):
                      "frac": achieved / FP32_VECTOR_PEAK_TFS, "traffic": None,
                      "kernel": "cim_regs_kernel",
                      "flops_per_launch": per_launch_flops,
-                     "regime": f"{K} instances' couplings held in registers in one cooperative launch; the step "
-                               "time is set by the exchange of amplitudes between workgroups",
+                     "instances_per_launch": per_launch,
+                     "regime": f"{per_launch:g} instances' couplings held in registers per cooperative launch "
+                               f"({K} per call); the step time is set by the exchange of amplitudes between "
+                               "workgroups",
                      "us_per_euler_step": avg_launch_s * 1e6 / STEPS,
                      "avg_launch_ms": avg_launch_s * 1e3, "launches": cim_launches},
     }
