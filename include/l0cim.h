@@ -357,8 +357,13 @@ void l0cim_cac_params_default(l0cim_cac_params* p);
  * H(mu); H (P doubles, may be NULL): the eq. 4 energy of each sigma with
  * lambda = eta^2 / 2; trace (may be NULL): k x 4 x P x n values (mu, n, m, e
  * after step k + 1) for k < trace_steps.  ws: at least
- * l0cim_cac_run_workspace_bytes bytes (two buffers of measured amplitudes and
- * the energy terms).  One launch per Euler step, each wavefront one row of J.
+ * l0cim_cac_run_workspace_bytes bytes (two buffers of measured amplitudes,
+ * the energy terms and the exchange words of the one-launch form).  Each
+ * wavefront owns one row of J.  With P <= 8 and n <= 2048 (F32; 1024 in
+ * F64), when the device holds the n / 8 workgroups at once, the whole run is
+ * one cooperative launch (rows of J in registers, the measured amplitudes of
+ * each step exchanged between workgroups as step-tagged words); otherwise
+ * one launch per Euler step.
  */
 size_t l0cim_cac_run_workspace_bytes(l0cim_dtype dtype, int32_t n, int32_t P);
 l0cim_status l0cim_cac_run(l0cim_dtype dtype, int32_t n, int32_t P, const void* J, int64_t ldj, const void* z,
