@@ -50,6 +50,12 @@ __host__ __device__ inline int jpanel_group_size(int p, int np) {
   const int rest = np - (p / kPanelGroup) * kPanelGroup;
   return rest < kPanelGroup ? rest : kPanelGroup;
 }
+// First element of panel group p / kPanelGroup: a row tile of RB panels
+// (RB dividing kPanelGroup) starting at panel p0 finds chunk c of its panel
+// p0 + rb at jpanel_group_base(p0, nch) + (c gs + (p0 + rb) mod kPanelGroup) 512.
+__host__ __device__ inline size_t jpanel_group_base(int p0, int nch) {
+  return size_t(p0 / kPanelGroup) * kPanelGroup * nch * 512;
+}
 __host__ __device__ inline size_t jpanel_block(int p, int c, int nch, int np) {
   const int g = p / kPanelGroup;
   return (size_t(g) * kPanelGroup * nch + size_t(c) * jpanel_group_size(p, np) + size_t(p % kPanelGroup)) * 512;

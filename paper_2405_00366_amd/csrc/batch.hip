@@ -277,7 +277,7 @@ bstep_kernel(const BTile* __restrict__ tiles, const BInst* __restrict__ insts, B
   static_assert(kPanelGroup % RB == 0, "row tiles within one panel group");
   const int np = (n + 15) / 16;
   const int cstride = jpanel_group_size(p0, np) * 512;
-  const JT* gbase = J + size_t(p0 / kPanelGroup) * kPanelGroup * nch * 512;
+  const JT* gbase = J + jpanel_group_base(p0, nch);
   int poff[RB];
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {

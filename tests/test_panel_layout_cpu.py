@@ -7,8 +7,10 @@ hipcc as host code (no device needed):
     512 + panel-in-group * 512) equal jpanel_block for every aligned row
     tile of 1, 2, 4 and 8 panels and every chunk, clamped rows included.
 
-The second check restates the address arithmetic of bstep_kernel; a layout
-change that one side misses fails here, on the CPU, before any GPU run.
+The second check uses the helpers bstep_kernel forms its addresses with
+(jpanel_group_base, jpanel_group_size) and the kernel's own clamping of
+rows past n; a layout change that one side misses fails here, on the CPU,
+before any GPU run.
 """
 import os
 import shutil
@@ -41,7 +43,7 @@ int main() {
     for (int RB : {1, 2, 4, 8}) {
       for (int p0 = 0; p0 < np; p0 += RB) {
         const int cstride = jpanel_group_size(p0, np) * 512;
-        const size_t gbase = size_t(p0 / kPanelGroup) * kPanelGroup * nch * 512;
+        const size_t gbase = jpanel_group_base(p0, nch);
         for (int rb = 0; rb < RB; ++rb) {
           const int pp = (p0 + rb) * 16 < n ? p0 + rb : p0;
           for (int c = 0; c < nch; ++c) {
